@@ -1,0 +1,192 @@
+/*
+ * pic355 — electromagnetic particle-in-cell time step for MI355X (gfx950).
+ *
+ * C ABI of the hot path.  The operations follow the paper's statement of the
+ * PIC problem ("Porting WarpX to GPU-accelerated platforms", arXiv
+ * 2101.12149): relativistic charged macro-particles coupled to Maxwell's
+ * equations (Sec. 1); one particle container per species holding per-particle
+ * arrays (Sec. 2.2); field components on the Yee staggering, B on cell faces
+ * and E, J on cell edges (Sec. 2.4); and the particle operations field
+ * gathering, particle pushing and current deposition (Sec. 2.2), with the
+ * Yee FDTD solver, Esirkepov deposition and third-order shapes (Sec. 4.1.1),
+ * energy-conserving gathering (Sec. 4.2) and particle binning / sorting by a
+ * counting sort (Sec. 3.4.2).
+ *
+ * Conventions shared by every entry point
+ *   - Every array pointer is a DEVICE pointer owned by the caller.  Structs
+ *     are host memory and are only read during the call.  The library never
+ *     keeps a pointer after returning and never allocates device memory.
+ *   - Every call is asynchronous on `stream` (a hipStream_t; NULL = the null
+ *     stream), except where a status has to be read back (pic_step reads a
+ *     device error word at its end and so synchronises the stream).
+ *   - Grid: n[3] cells, periodic in all three directions, spacing d[3].
+ *     Field arrays hold n0*n1*n2 values, x fastest: index i + n0*(j + n1*k).
+ *     Staggering of element [i,j,k] (in cells):
+ *       E_x, J_x (i+1/2, j, k)   E_y, J_y (i, j+1/2, k)   E_z, J_z (i, j, k+1/2)
+ *       B_x (i, j+1/2, k+1/2)    B_y (i+1/2, j, k+1/2)    B_z (i+1/2, j+1/2, k)
+ *   - Particle position in cell units x/d = cell + off with cell an int32 in
+ *     [0, n) and off in [0, 1) of the grid dtype (split precision).  u = gamma v.
+ *   - dtype PIC_F32: fields, offsets, momenta, weights and source map are
+ *     float; PIC_F64: double.  Energy/charge reductions are always FP64.
+ *   - State at step n is (x^n, u^{n-1/2}, E^n, B^n).
+ *
+ * Errors: every argument check is synchronous and runs before any launch; on
+ * a non-OK status no output has been touched.  pic_last_error() returns a
+ * thread-local message.  No C++ exception crosses this ABI.
+ */
+#ifndef PIC355_PIC_H
+#define PIC355_PIC_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#if defined(__GNUC__)
+#define PIC_API __attribute__((visibility("default")))
+#else
+#define PIC_API
+#endif
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef enum {
+    PIC_OK = 0,
+    PIC_E_INVALID = 1,     /* null pointer, bad size, inconsistent argument */
+    PIC_E_CFL = 2,         /* c dt > 1/sqrt(sum 1/d^2): Yee step unstable */
+    PIC_E_UNSUPPORTED = 3, /* order not in {1,3}, dtype unknown, tile too big */
+    PIC_E_WORKSPACE = 4,   /* workspace missing or smaller than pic_workspace_bytes */
+    PIC_E_STATE = 5,       /* corrupt particle state found on the device */
+    PIC_E_DEVICE = 6       /* a HIP call failed */
+} pic_status;
+
+typedef enum { PIC_F32 = 0, PIC_F64 = 1 } pic_dtype;
+
+typedef struct {
+    int32_t n[3];     /* cells per direction (periodic) */
+    double d[3];      /* cell size */
+    double dt;        /* time step */
+    double c;         /* speed of light */
+    double eps0;      /* vacuum permittivity; mu0 = 1/(eps0 c^2) */
+    int32_t order;    /* shape-function order: 1 (cloud in cell) or 3 (cubic) */
+    int32_t dtype;    /* pic_dtype */
+    int32_t tile[3];  /* sort/tile size in cells, each in [1,16] dividing n;
+                         0 = the largest divisor of n not above 8 */
+    int32_t slack;    /* cells of halo slack around a tile for particles that
+                         drifted since the last sort; -1 = automatic */
+} pic_grid;
+
+typedef struct {
+    int64_t n;          /* number of particles */
+    int32_t *cell[3];   /* int32[n] cell index per direction */
+    void *off[3];       /* T[n] in-cell offset in [0,1) */
+    void *u[3];         /* T[n] momentum per mass, gamma v */
+    void *w;            /* T[n] weights, or NULL for the constant w0 (sorted
+                           along with the other arrays) */
+    double w0;          /* weight used when w == NULL */
+    double q, m;        /* charge and mass of one physical particle */
+} pic_species;
+
+typedef struct {
+    void *E[3], *B[3], *J[3];   /* T[n0*n1*n2] each */
+} pic_fields;
+
+typedef struct {
+    int32_t k_plane;    /* < 0: no source */
+    const void *amp;    /* T[n0*n1] device map, x fastest */
+    const double *g;    /* HOST double[n_g]; g[step] multiplies the map */
+    int64_t n_g;        /* steps outside [0, n_g) use g = 0 */
+} pic_source;
+/* A soft source: after the E update of step `step`,
+ * E_x[i, j, k_plane] += amp[i + n0*j] * g[step].  The paper's laser stage
+ * (Sec. 4.2) injects a laser; this plane source is the periodic-box stand-in. */
+
+typedef struct {
+    void *lx[3];   /* T[n] dL/d(position in cell units) */
+    void *lu[3];   /* T[n] dL/du */
+    void *lE[3];   /* T[n0*n1*n2] dL/dE */
+    void *lB[3];   /* T[n0*n1*n2] dL/dB */
+} pic_adjoint;
+
+/* Bytes of device workspace needed by pic_sort_tiles, pic_step,
+ * pic_step_adjoint and pic_reduce for this grid and particle count. */
+PIC_API size_t pic_workspace_bytes(const pic_grid *grid, int64_t n_particles);
+
+/* Number of tiles the library uses for this grid (the length of tile_start
+ * is this plus one); 0 if the grid is invalid.  With tile[d] == 0 the tile
+ * edge starts at 8 and is halved until the LDS regions fit one workgroup. */
+PIC_API int64_t pic_tile_count(const pic_grid *grid);
+
+/* Particle binning and sorting by counting sort (Sec. 3.4.2: binning computes
+ * a permutation that assigns particles to bins; sorting reorders the data).
+ * The key is the tile-major cell index: tiles of grid->tile cells in
+ * lexicographic (x fastest) order, cells x-fastest inside a tile.
+ * Reorders every array of `sp` in place (stable within a cell is NOT
+ * guaranteed), writes tile_start[t] = first particle of tile t for
+ * t in [0, ntiles] (tile_start[ntiles] = n), and, if perm != NULL,
+ * perm[j] = index before the sort of the particle now at j.
+ * tile_start: int32[ntiles+1] device.  perm: int32[n] device or NULL.
+ * Particles with a cell outside [0,n) or an offset outside [0,1) make the
+ * call return PIC_E_STATE (this call synchronises the stream to read it). */
+PIC_API pic_status pic_sort_tiles(const pic_grid *grid, pic_species *sp, int32_t *tile_start, int32_t *perm,
+                          void *ws, size_t ws_bytes, void *stream);
+
+/* Field gather (Sec. 3.1, Sec. 4.2): E and B at every particle, each
+ * component interpolated from its own staggered location with the
+ * order-`order` B-spline in all three directions.  Ep, Bp: T[n] x 3 outputs. */
+PIC_API pic_status pic_gather(const pic_grid *grid, const pic_species *sp, const pic_fields *f, void *const Ep[3],
+                      void *const Bp[3], void *stream);
+
+/* Relativistic Boris push u^{n-1/2} -> u^{n+1/2} with the given per-particle
+ * fields, then the position update x += dt u/gamma with periodic wrap. */
+PIC_API pic_status pic_push(const pic_grid *grid, pic_species *sp, void *const Ep[3], void *const Bp[3], void *stream);
+
+/* Esirkepov charge-conserving current deposition (Sec. 3.4.1, 4.1.1):
+ * J += current of the particles moving from `before` to `after` (same n,
+ * same order of particles, displacement below one cell per direction). */
+PIC_API pic_status pic_deposit(const pic_grid *grid, const pic_species *before, const pic_species *after, pic_fields *f,
+                       void *stream);
+
+/* One Yee FDTD step (Sec. 2.4, 4.1.1): B -= dt/2 curl E; E += dt (c^2 curl B
+ * - J/eps0); source; B -= dt/2 curl E.  J is read, not modified. */
+PIC_API pic_status pic_yee(const pic_grid *grid, pic_fields *f, const pic_source *src, int64_t step, void *stream);
+
+/* nsteps full PIC steps from step index step0: [sort] -> gather + Boris push
+ * + position update + Esirkepov deposit (one fused tile kernel, Sec. 3.1) ->
+ * Yee update.  Sorting happens before the first step of the call and before
+ * every step whose index is a multiple of sort_every when sort_every > 0;
+ * with sort_every == 0 the binning already in tile_start is used, and with
+ * tile_start == NULL as well the particles are processed without tiles.
+ * On return J holds the current of the last step.  diag (optional, device
+ * double[nsteps][5]) receives pic_reduce's five values after every step.
+ * Synchronises the stream at the end to read the device error word. */
+PIC_API pic_status pic_step(const pic_grid *grid, pic_species *sp, pic_fields *f, const pic_source *src, int64_t step0,
+                    int32_t nsteps, int32_t sort_every, int32_t *tile_start, void *ws, size_t ws_bytes,
+                    double *diag, void *stream);
+
+/* Hand-written adjoint of step `step`: state_n / fields_n are the inputs of
+ * that forward step (no sort in between); lam holds dL/d(state n+1) on entry
+ * and dL/d(state n) on return; dA (device double[n0*n1], or NULL) accumulates
+ * dL/d(source map).  Field part: transpose of the Yee step (the periodic
+ * forward difference is minus the transpose of the backward one).  Particle
+ * part: transpose of the deposit (a gather of the current adjoint), of the
+ * position update, of the Boris push and of the gather (a scatter). */
+PIC_API pic_status pic_step_adjoint(const pic_grid *grid, const pic_species *state_n, const pic_fields *fields_n,
+                            const pic_source *src, int64_t step, pic_adjoint *lam, double *dA, void *ws,
+                            size_t ws_bytes, void *stream);
+
+/* FP64 reductions (Sec. 2.6): out[0] = dV/2 sum eps0|E|^2,
+ * out[1] = dV/2 sum |B|^2/mu0, out[2] = sum w m c^2 (gamma-1),
+ * out[3] = sum q w, out[4] = sum w m u_z.  sp may be NULL (out[2..4] = 0).
+ * out: device double[5].  Needs the workspace. */
+PIC_API pic_status pic_reduce(const pic_grid *grid, const pic_species *sp, const pic_fields *f, double *out, void *ws,
+                      size_t ws_bytes, void *stream);
+
+/* Message for the last non-OK status of the calling thread. */
+PIC_API const char *pic_last_error(void);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* PIC355_PIC_H */

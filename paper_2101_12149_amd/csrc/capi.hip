@@ -1,0 +1,794 @@
+// C-ABI entry points of the EM-PIC library (declared in include/pic.h).
+//
+// Every call validates its arguments on the host before any launch, maps
+// the caller's device pointers into kernel-argument structs, and launches
+// asynchronously on the caller's stream.  The library allocates no device
+// memory: scratch space comes from the caller's workspace, carved at fixed
+// 256-byte-aligned offsets.
+#include <cmath>
+#include <cstdio>
+#include <cstring>
+#include <string>
+
+#include "pic.h"
+#include "pic_types.hpp"
+
+using namespace pic;
+
+namespace {
+
+thread_local std::string g_msg;
+
+pic_status fail(pic_status s, const std::string &m)
+{
+    g_msg = m;
+    return s;
+}
+
+pic_status hip_fail(hipError_t e, const char *where)
+{
+    g_msg = std::string(where) + ": " + hipGetErrorString(e);
+    return PIC_E_DEVICE;
+}
+
+#define PIC_HIP(call)                                   \
+    do {                                                \
+        hipError_t e_ = (call);                         \
+        if (e_ != hipSuccess)                           \
+            return hip_fail(e_, #call);                 \
+    } while (0)
+
+// error word of the calls that take no workspace (their device-side state
+// checks are not reported; see pic.h)
+__device__ int g_sink_err;
+
+int *sink_err()
+{
+    int *p = nullptr;
+    if (hipGetSymbolAddress(reinterpret_cast<void **>(&p), HIP_SYMBOL(g_sink_err)) != hipSuccess)
+        return nullptr;
+    return p;
+}
+
+// LDS bytes one workgroup may use; gfx950 has 160 KiB per CU, which is also
+// what a host without a visible device assumes
+int lds_limit()
+{
+    int dev = 0, v = 0;
+    if (hipGetDevice(&dev) != hipSuccess)
+        return 160 * 1024;
+    if (hipDeviceGetAttribute(&v, hipDeviceAttributeMaxSharedMemoryPerBlock, dev) != hipSuccess || v <= 0)
+        return 160 * 1024;
+    return v;
+}
+
+struct GridInfo {
+    int n[3];
+    int64_t ncell;
+    int order;
+    int dtype;
+    size_t tsize;
+    TileGeo tg;
+    int ntiles;
+    int tile_cells;
+};
+
+void region_extents(int order, TileGeo &tg)
+{
+    const int s = tg.slack;
+    const int gl = order == 3 ? 2 : 1;   // gather halo below the tile
+    for (int d = 0; d < 3; ++d) {
+        tg.rf[d] = tg.t[d] + 2 * s + (order == 3 ? 4 : 2);
+        tg.rj[d] = tg.t[d] + 2 * s + (order == 3 ? 5 : 3);
+    }
+    tg.lo_f = s + gl;
+    tg.lo_j = s + gl;
+}
+
+size_t lds_bytes(const GridInfo &gi)
+{
+    const size_t rf = (size_t)gi.tg.rf[0] * gi.tg.rf[1] * gi.tg.rf[2];
+    const size_t rj = (size_t)gi.tg.rj[0] * gi.tg.rj[1] * gi.tg.rj[2];
+    return (6 * rf + 3 * rj) * gi.tsize;
+}
+
+pic_status check_grid(const pic_grid *g, GridInfo &gi)
+{
+    if (!g)
+        return fail(PIC_E_INVALID, "grid is NULL");
+    int64_t nc = 1;
+    for (int d = 0; d < 3; ++d) {
+        if (g->n[d] < 4)
+            return fail(PIC_E_INVALID, "grid n[d] must be >= 4");
+        if (!(g->d[d] > 0) || !std::isfinite(g->d[d]))
+            return fail(PIC_E_INVALID, "grid spacing must be positive and finite");
+        gi.n[d] = g->n[d];
+        nc *= g->n[d];
+    }
+    if (nc >= (int64_t(1) << 31))
+        return fail(PIC_E_INVALID, "grid has 2^31 cells or more");
+    gi.ncell = nc;
+    if (!(g->dt > 0) || !(g->c > 0) || !(g->eps0 > 0) || !std::isfinite(g->dt) || !std::isfinite(g->c) ||
+        !std::isfinite(g->eps0))
+        return fail(PIC_E_INVALID, "dt, c and eps0 must be positive and finite");
+    if (g->order != 1 && g->order != 3)
+        return fail(PIC_E_UNSUPPORTED, "shape order must be 1 or 3");
+    if (g->dtype != PIC_F32 && g->dtype != PIC_F64)
+        return fail(PIC_E_UNSUPPORTED, "dtype must be PIC_F32 or PIC_F64");
+    const double inv = 1.0 / (g->d[0] * g->d[0]) + 1.0 / (g->d[1] * g->d[1]) + 1.0 / (g->d[2] * g->d[2]);
+    if (g->c * g->dt * std::sqrt(inv) > 1.0 + 1e-12)
+        return fail(PIC_E_CFL, "c dt exceeds the Yee CFL limit 1/sqrt(sum 1/d^2)");
+    gi.order = g->order;
+    gi.dtype = g->dtype;
+    gi.tsize = g->dtype == PIC_F64 ? sizeof(double) : sizeof(float);
+    // tiles
+    bool auto_tile[3];
+    for (int d = 0; d < 3; ++d) {
+        int t = g->tile[d];
+        auto_tile[d] = (t == 0);
+        if (t == 0) {   // largest divisor of n not above 8
+            t = 8;
+            while (g->n[d] % t != 0)
+                --t;
+        }
+        if (t < 1 || t > 16 || g->n[d] % t != 0)
+            return fail(PIC_E_INVALID, "tile size must be in [1,16] and divide n");
+        gi.tg.t[d] = t;
+    }
+    if (g->slack < -1 || g->slack > 2)
+        return fail(PIC_E_INVALID, "slack must be -1 (automatic) or in [0,2]");
+    gi.tg.slack = g->slack < 0 ? 0 : g->slack;
+    region_extents(gi.order, gi.tg);
+    const size_t limit = (size_t)lds_limit();
+    // an automatic tile shrinks until its LDS regions fit one workgroup
+    while (lds_bytes(gi) > limit) {
+        int dmax = -1;
+        for (int d = 0; d < 3; ++d)
+            if (auto_tile[d] && gi.tg.t[d] >= 4 && gi.tg.t[d] % 2 == 0 &&
+                (dmax < 0 || gi.tg.t[d] > gi.tg.t[dmax]))
+                dmax = d;
+        if (dmax < 0)
+            break;
+        gi.tg.t[dmax] /= 2;
+        region_extents(gi.order, gi.tg);
+    }
+    if (lds_bytes(gi) > limit)
+        return fail(PIC_E_UNSUPPORTED, "tile plus halo does not fit in LDS; use a smaller tile or slack");
+    int nt = 1;
+    for (int d = 0; d < 3; ++d) {
+        gi.tg.nt[d] = gi.n[d] / gi.tg.t[d];
+        nt *= gi.tg.nt[d];
+    }
+    gi.ntiles = nt;
+    gi.tile_cells = gi.tg.t[0] * gi.tg.t[1] * gi.tg.t[2];
+    gi.tg.xcd_map = (nt % 8 == 0) ? 1 : 0;
+    return PIC_OK;
+}
+
+pic_status check_species(const pic_species *s, const char *name)
+{
+    if (!s)
+        return fail(PIC_E_INVALID, std::string(name) + " is NULL");
+    if (s->n < 0 || s->n >= (int64_t(1) << 31) - 1)
+        return fail(PIC_E_INVALID, std::string(name) + ": particle count must be in [0, 2^31-1)");
+    if (s->n > 0)
+        for (int d = 0; d < 3; ++d)
+            if (!s->cell[d] || !s->off[d] || !s->u[d])
+                return fail(PIC_E_INVALID, std::string(name) + ": NULL particle array");
+    if (!(s->m > 0) || !std::isfinite(s->m) || !std::isfinite(s->q) || !std::isfinite(s->w0))
+        return fail(PIC_E_INVALID, std::string(name) + ": m must be positive and q, w0 finite");
+    return PIC_OK;
+}
+
+pic_status check_fields(const pic_fields *f, bool need_j)
+{
+    if (!f)
+        return fail(PIC_E_INVALID, "fields is NULL");
+    for (int d = 0; d < 3; ++d)
+        if (!f->E[d] || !f->B[d] || (need_j && !f->J[d]))
+            return fail(PIC_E_INVALID, "NULL field array");
+    return PIC_OK;
+}
+
+// workspace layout
+struct WsLayout {
+    size_t err, counts, bsum, key, rank, scell, soff, su, sw, hatE, partials, total;
+};
+
+size_t al(size_t x)
+{
+    return (x + 255) & ~size_t(255);
+}
+
+WsLayout layout(const GridInfo &gi, int64_t np)
+{
+    WsLayout L{};
+    size_t o = 0;
+    const size_t n = (size_t)(np > 0 ? np : 0);
+    L.err = o;
+    o += 256;
+    L.counts = o;
+    o += al(sizeof(int) * ((size_t)gi.ncell + 1));
+    L.bsum = o;
+    o += al(sizeof(int) * ((size_t)scan_blocks(gi.ncell + 1) + 1));
+    L.key = o;
+    o += al(sizeof(int) * n);
+    L.rank = o;
+    o += al(sizeof(int) * n);
+    L.scell = o;
+    o += 3 * al(sizeof(int) * n);
+    L.soff = o;
+    o += 3 * al(gi.tsize * n);
+    L.su = o;
+    o += 3 * al(gi.tsize * n);
+    L.sw = o;
+    o += al(gi.tsize * n);
+    L.hatE = o;
+    o += 3 * al(gi.tsize * (size_t)gi.ncell);
+    L.partials = o;
+    o += al(sizeof(double) * 5 * (size_t)reduce_max_blocks());
+    L.total = o;
+    return L;
+}
+
+pic_status check_ws(const GridInfo &gi, int64_t np, void *ws, size_t ws_bytes, WsLayout &L)
+{
+    L = layout(gi, np);
+    if (!ws)
+        return fail(PIC_E_WORKSPACE, "workspace is NULL");
+    if ((reinterpret_cast<uintptr_t>(ws) & 255) != 0)
+        return fail(PIC_E_WORKSPACE, "workspace must be 256-byte aligned");
+    if (ws_bytes < L.total)
+        return fail(PIC_E_WORKSPACE, "workspace smaller than pic_workspace_bytes()");
+    return PIC_OK;
+}
+
+template <typename T>
+PConst<T> make_const(const pic_grid *g, const pic_species *s)
+{
+    PConst<T> pc{};
+    for (int d = 0; d < 3; ++d) {
+        pc.n[d] = g->n[d];
+        pc.dtd[d] = (T)(g->dt / g->d[d]);
+        const int p = (d + 1) % 3, q = (d + 2) % 3;
+        pc.jk[d] = s ? (T)(-s->q / (g->dt * g->d[p] * g->d[q])) : T(0);
+    }
+    pc.h = s ? (T)(s->q * g->dt / (2.0 * s->m)) : T(0);
+    pc.inv_c2 = (T)(1.0 / (g->c * g->c));
+    pc.w0 = s ? (T)s->w0 : T(0);
+    pc.lj = (T)(-g->dt / g->eps0);
+    return pc;
+}
+
+template <typename T>
+PArr<T> parr(const pic_species *s)
+{
+    PArr<T> a{};
+    for (int d = 0; d < 3; ++d) {
+        a.cell[d] = s->cell[d];
+        a.off[d] = static_cast<T *>(s->off[d]);
+        a.u[d] = static_cast<T *>(s->u[d]);
+    }
+    a.w = static_cast<T *>(s->w);
+    a.n = s->n;
+    return a;
+}
+
+template <typename T>
+PArr<T> parr_ws(char *ws, const WsLayout &L, const pic_species *s)
+{
+    PArr<T> a{};
+    const size_t n = (size_t)s->n;
+    for (int d = 0; d < 3; ++d) {
+        a.cell[d] = reinterpret_cast<int *>(ws + L.scell + d * al(sizeof(int) * n));
+        a.off[d] = reinterpret_cast<T *>(ws + L.soff + d * al(sizeof(T) * n));
+        a.u[d] = reinterpret_cast<T *>(ws + L.su + d * al(sizeof(T) * n));
+    }
+    a.w = s->w ? reinterpret_cast<T *>(ws + L.sw) : nullptr;
+    a.n = s->n;
+    return a;
+}
+
+template <typename T>
+FieldPtrs<T> fptrs(const pic_fields *f)
+{
+    FieldPtrs<T> p{};
+    for (int d = 0; d < 3; ++d) {
+        p.E[d] = static_cast<T *>(f->E[d]);
+        p.B[d] = static_cast<T *>(f->B[d]);
+        p.J[d] = static_cast<T *>(f->J[d]);
+    }
+    return p;
+}
+
+double src_g(const pic_source *src, int64_t step)
+{
+    if (!src || src->k_plane < 0 || !src->g || step < 0 || step >= src->n_g)
+        return 0.0;
+    return src->g[step];
+}
+
+pic_status check_source(const pic_source *src, const GridInfo &gi)
+{
+    if (!src || src->k_plane < 0)
+        return PIC_OK;
+    if (src->k_plane >= gi.n[2])
+        return fail(PIC_E_INVALID, "source k_plane outside the grid");
+    if (!src->amp)
+        return fail(PIC_E_INVALID, "source amp is NULL");
+    if (src->n_g > 0 && !src->g)
+        return fail(PIC_E_INVALID, "source g is NULL");
+    return PIC_OK;
+}
+
+// One Yee step: B -= dt/2 curlE; E += dt (c^2 curlB - J/eps0) + source;
+// B -= dt/2 curlE.  zero_j clears J as it is consumed.
+template <typename T>
+pic_status yee_step(const pic_grid *g, const GridInfo &gi, const FieldPtrs<T> &f, const pic_source *src,
+                    int64_t step, bool zero_j, hipStream_t st)
+{
+    CurlArgs<T> b{};
+    for (int d = 0; d < 3; ++d) {
+        b.out[d] = f.B[d];
+        b.in[d] = f.B[d];
+        b.src[d] = f.E[d];
+        b.n[d] = gi.n[d];
+    }
+    b.cx = (T)(-0.5 * g->dt / g->d[0]);
+    b.cy = (T)(-0.5 * g->dt / g->d[1]);
+    b.cz = (T)(-0.5 * g->dt / g->d[2]);
+    b.kplane = -1;
+    CurlArgs<T> e{};
+    for (int d = 0; d < 3; ++d) {
+        e.out[d] = f.E[d];
+        e.in[d] = f.E[d];
+        e.src[d] = f.B[d];
+        e.J[d] = f.J[d];
+        e.n[d] = gi.n[d];
+    }
+    const double c2 = g->c * g->c;
+    e.cx = (T)(c2 * g->dt / g->d[0]);
+    e.cy = (T)(c2 * g->dt / g->d[1]);
+    e.cz = (T)(c2 * g->dt / g->d[2]);
+    e.jc = (T)(-g->dt / g->eps0);
+    e.zero_j = zero_j ? 1 : 0;
+    e.kplane = -1;
+    if (src && src->k_plane >= 0) {
+        e.kplane = src->k_plane;
+        e.amp = static_cast<const T *>(src->amp);
+        e.ag = (T)src_g(src, step);
+    }
+    PIC_HIP(launch_curl<T>(true, b, st));
+    PIC_HIP(launch_curl<T>(false, e, st));
+    PIC_HIP(launch_curl<T>(true, b, st));
+    return PIC_OK;
+}
+
+template <typename T>
+pic_status do_sort(const GridInfo &gi, const pic_species *sp, char *ws, const WsLayout &L, int *tile_start,
+                   int *perm, hipStream_t st, PArr<T> &sorted)
+{
+    int *err = reinterpret_cast<int *>(ws + L.err);
+    int *counts = reinterpret_cast<int *>(ws + L.counts);
+    int *bsum = reinterpret_cast<int *>(ws + L.bsum);
+    int *key = reinterpret_cast<int *>(ws + L.key);
+    int *rank = reinterpret_cast<int *>(ws + L.rank);
+    const PArr<T> in = parr<T>(sp);
+    sorted = parr_ws<T>(ws, L, sp);
+    PIC_HIP(launch_fill<int>(counts, gi.ncell + 1, 0, st));
+    PIC_HIP(launch_bin_count<T>(in, gi.tg, counts, key, rank, err, st));
+    PIC_HIP(launch_scan(counts, gi.ncell, bsum, st));
+    PIC_HIP(launch_tile_start(counts, gi.tile_cells, gi.ntiles, sp->n, tile_start, st));
+    PIC_HIP(launch_scatter<T>(in, sorted, key, rank, counts, perm, st));
+    return PIC_OK;
+}
+
+template <typename T>
+pic_status sort_tiles_t(const pic_grid *g, const GridInfo &gi, pic_species *sp, int32_t *tile_start, int32_t *perm,
+                        void *ws, const WsLayout &L, hipStream_t st)
+{
+    char *w = static_cast<char *>(ws);
+    int *err = reinterpret_cast<int *>(w + L.err);
+    PIC_HIP(launch_fill<int>(err, 1, 0, st));
+    // the state check runs before anything is reordered
+    {
+        int *counts = reinterpret_cast<int *>(w + L.counts);
+        int *key = reinterpret_cast<int *>(w + L.key);
+        int *rank = reinterpret_cast<int *>(w + L.rank);
+        PIC_HIP(launch_fill<int>(counts, gi.ncell + 1, 0, st));
+        PIC_HIP(launch_bin_count<T>(parr<T>(sp), gi.tg, counts, key, rank, err, st));
+        int herr = 0;
+        PIC_HIP(hipMemcpyAsync(&herr, err, sizeof(int), hipMemcpyDeviceToHost, st));
+        PIC_HIP(hipStreamSynchronize(st));
+        if (herr)
+            return fail(PIC_E_STATE, "particle with a cell outside the grid or an offset outside [0,1)");
+    }
+    PArr<T> sorted;
+    pic_status s = do_sort<T>(gi, sp, w, L, tile_start, perm, st, sorted);
+    if (s != PIC_OK)
+        return s;
+    const size_t n = (size_t)sp->n;
+    for (int d = 0; d < 3; ++d) {
+        PIC_HIP(hipMemcpyAsync(sp->cell[d], sorted.cell[d], n * sizeof(int), hipMemcpyDeviceToDevice, st));
+        PIC_HIP(hipMemcpyAsync(sp->off[d], sorted.off[d], n * sizeof(T), hipMemcpyDeviceToDevice, st));
+        PIC_HIP(hipMemcpyAsync(sp->u[d], sorted.u[d], n * sizeof(T), hipMemcpyDeviceToDevice, st));
+    }
+    if (sp->w)
+        PIC_HIP(hipMemcpyAsync(sp->w, sorted.w, n * sizeof(T), hipMemcpyDeviceToDevice, st));
+    (void)g;
+    return PIC_OK;
+}
+
+template <typename T>
+pic_status reduce_t(const pic_grid *g, const GridInfo &gi, const pic_species *sp, const pic_fields *f, double *out,
+                    char *ws, const WsLayout &L, hipStream_t st)
+{
+    const double dV = g->d[0] * g->d[1] * g->d[2];
+    const double mu0 = 1.0 / (g->eps0 * g->c * g->c);
+    double scale[7];
+    scale[0] = 0.5 * dV * g->eps0;
+    scale[1] = 0.5 * dV / mu0;
+    scale[2] = sp ? sp->m * g->c * g->c : 0.0;
+    scale[3] = sp ? sp->q : 0.0;
+    scale[4] = sp ? sp->m : 0.0;
+    scale[5] = 1.0 / (g->c * g->c);
+    scale[6] = sp ? sp->w0 : 0.0;
+    PArr<T> a{};
+    if (sp)
+        a = parr<T>(sp);
+    PIC_HIP(launch_reduce<T>(sp ? &a : nullptr, fptrs<T>(f), gi.ncell, reinterpret_cast<double *>(ws + L.partials),
+                             reduce_max_blocks(), scale, out, st));
+    return PIC_OK;
+}
+
+template <typename T>
+pic_status step_t(const pic_grid *g, const GridInfo &gi, pic_species *sp, pic_fields *f, const pic_source *src,
+                  int64_t step0, int32_t nsteps, int32_t sort_every, int32_t *tile_start, void *ws,
+                  const WsLayout &L, double *diag, hipStream_t st)
+{
+    char *w = static_cast<char *>(ws);
+    int *err = reinterpret_cast<int *>(w + L.err);
+    const PConst<T> pc = make_const<T>(g, sp);
+    const FieldPtrs<T> fp = fptrs<T>(f);
+    const PArr<T> user = parr<T>(sp);
+    PIC_HIP(launch_fill<int>(err, 1, 0, st));
+    for (int d = 0; d < 3; ++d)
+        PIC_HIP(launch_fill<T>(fp.J[d], gi.ncell, T(0), st));
+    for (int32_t it = 0; it < nsteps; ++it) {
+        const int64_t step = step0 + it;
+        const bool sort_now = sort_every > 0 && (it == 0 || step % sort_every == 0);
+        if (sort_now && sp->n > 0) {
+            PArr<T> sorted;
+            pic_status s = do_sort<T>(gi, sp, w, L, tile_start, nullptr, st, sorted);
+            if (s != PIC_OK)
+                return s;
+            PIC_HIP(launch_particles_tile<T>(gi.order, pc, gi.tg, sorted, user, fp, tile_start, err, st));
+        } else if (tile_start && sp->n > 0) {
+            PIC_HIP(launch_particles_tile<T>(gi.order, pc, gi.tg, user, user, fp, tile_start, err, st));
+        } else {
+            PIC_HIP(launch_particles_global<T>(gi.order, pc, user, fp, err, st));
+        }
+        pic_status s = yee_step<T>(g, gi, fp, src, step, it + 1 < nsteps, st);
+        if (s != PIC_OK)
+            return s;
+        if (diag) {
+            s = reduce_t<T>(g, gi, sp, f, diag + 5 * (int64_t)it, w, L, st);
+            if (s != PIC_OK)
+                return s;
+        }
+    }
+    int herr = 0;
+    PIC_HIP(hipMemcpyAsync(&herr, err, sizeof(int), hipMemcpyDeviceToHost, st));
+    PIC_HIP(hipStreamSynchronize(st));
+    if (herr)
+        return fail(PIC_E_STATE, "corrupt particle state (cell, offset, momentum or a displacement >= 1 cell)");
+    return PIC_OK;
+}
+
+template <typename T>
+pic_status adjoint_t(const pic_grid *g, const GridInfo &gi, const pic_species *sp, const pic_fields *f,
+                     const pic_source *src, int64_t step, pic_adjoint *lam, double *dA, void *ws, const WsLayout &L,
+                     hipStream_t st)
+{
+    char *w = static_cast<char *>(ws);
+    int *err = reinterpret_cast<int *>(w + L.err);
+    T *hat[3];
+    T *lE[3], *lB[3], *lx[3], *lu[3];
+    for (int d = 0; d < 3; ++d) {
+        hat[d] = reinterpret_cast<T *>(w + L.hatE + d * al(sizeof(T) * (size_t)gi.ncell));
+        lE[d] = static_cast<T *>(lam->lE[d]);
+        lB[d] = static_cast<T *>(lam->lB[d]);
+        lx[d] = static_cast<T *>(lam->lx[d]);
+        lu[d] = static_cast<T *>(lam->lu[d]);
+    }
+    const double c2 = g->c * g->c;
+    // hatE = lE - dt/2 curl_b(lB);  dA += g(step) hatE_x[k_plane]
+    CurlArgs<T> a{};
+    for (int d = 0; d < 3; ++d) {
+        a.out[d] = hat[d];
+        a.in[d] = lE[d];
+        a.src[d] = lB[d];
+        a.n[d] = gi.n[d];
+    }
+    a.cx = (T)(-0.5 * g->dt / g->d[0]);
+    a.cy = (T)(-0.5 * g->dt / g->d[1]);
+    a.cz = (T)(-0.5 * g->dt / g->d[2]);
+    a.kplane = -1;
+    if (src && src->k_plane >= 0 && dA) {
+        a.kplane = src->k_plane;
+        a.dA = dA;
+        a.dag = src_g(src, step);
+    }
+    PIC_HIP(launch_curl<T>(false, a, st));
+    // lB += dt c^2 curl_f(hatE)
+    CurlArgs<T> b{};
+    for (int d = 0; d < 3; ++d) {
+        b.out[d] = lB[d];
+        b.in[d] = lB[d];
+        b.src[d] = hat[d];
+        b.n[d] = gi.n[d];
+    }
+    b.cx = (T)(c2 * g->dt / g->d[0]);
+    b.cy = (T)(c2 * g->dt / g->d[1]);
+    b.cz = (T)(c2 * g->dt / g->d[2]);
+    b.kplane = -1;
+    PIC_HIP(launch_curl<T>(true, b, st));
+    // lE = hatE - dt/2 curl_b(lB)
+    CurlArgs<T> e{};
+    for (int d = 0; d < 3; ++d) {
+        e.out[d] = lE[d];
+        e.in[d] = hat[d];
+        e.src[d] = lB[d];
+        e.n[d] = gi.n[d];
+    }
+    e.cx = a.cx;
+    e.cy = a.cy;
+    e.cz = a.cz;
+    e.kplane = -1;
+    PIC_HIP(launch_curl<T>(false, e, st));
+    // particles: deposit, position, Boris and gather transposes
+    if (sp->n > 0) {
+        const PConst<T> pc = make_const<T>(g, sp);
+        PIC_HIP(launch_adjoint_particles<T>(gi.order, pc, parr<T>(sp), fptrs<T>(f), hat, lx, lu, lE, lB, err, st));
+    }
+    return PIC_OK;
+}
+
+pic_status check_vec3(void *const v[3], const char *name)
+{
+    if (!v)
+        return fail(PIC_E_INVALID, std::string(name) + " is NULL");
+    for (int d = 0; d < 3; ++d)
+        if (!v[d])
+            return fail(PIC_E_INVALID, std::string(name) + " has a NULL component");
+    return PIC_OK;
+}
+
+}  // namespace
+
+// ---------------------------------------------------------------------------
+// exported entry points
+
+#define PIC_TRY(expr)                      \
+    do {                                   \
+        pic_status s_ = (expr);            \
+        if (s_ != PIC_OK)                  \
+            return s_;                     \
+    } while (0)
+
+extern "C" {
+
+size_t pic_workspace_bytes(const pic_grid *grid, int64_t n_particles)
+{
+    GridInfo gi;
+    if (check_grid(grid, gi) != PIC_OK)
+        return 0;
+    return layout(gi, n_particles).total;
+}
+
+int64_t pic_tile_count(const pic_grid *grid)
+{
+    GridInfo gi;
+    if (check_grid(grid, gi) != PIC_OK)
+        return 0;
+    return gi.ntiles;
+}
+
+pic_status pic_sort_tiles(const pic_grid *grid, pic_species *sp, int32_t *tile_start, int32_t *perm, void *ws,
+                          size_t ws_bytes, void *stream)
+{
+    try {
+        GridInfo gi;
+        WsLayout L;
+        PIC_TRY(check_grid(grid, gi));
+        PIC_TRY(check_species(sp, "species"));
+        if (!tile_start)
+            return fail(PIC_E_INVALID, "tile_start is NULL");
+        PIC_TRY(check_ws(gi, sp->n, ws, ws_bytes, L));
+        hipStream_t st = static_cast<hipStream_t>(stream);
+        if (gi.dtype == PIC_F64)
+            return sort_tiles_t<double>(grid, gi, sp, tile_start, perm, ws, L, st);
+        return sort_tiles_t<float>(grid, gi, sp, tile_start, perm, ws, L, st);
+    } catch (...) {
+        return fail(PIC_E_DEVICE, "unexpected host exception");
+    }
+}
+
+pic_status pic_gather(const pic_grid *grid, const pic_species *sp, const pic_fields *f, void *const Ep[3],
+                      void *const Bp[3], void *stream)
+{
+    GridInfo gi;
+    PIC_TRY(check_grid(grid, gi));
+    PIC_TRY(check_species(sp, "species"));
+    PIC_TRY(check_fields(f, false));
+    PIC_TRY(check_vec3(Ep, "Ep"));
+    PIC_TRY(check_vec3(Bp, "Bp"));
+    int *err = sink_err();
+    if (!err)
+        return fail(PIC_E_DEVICE, "cannot resolve the device error word");
+    hipStream_t st = static_cast<hipStream_t>(stream);
+    if (gi.dtype == PIC_F64) {
+        double *e[3], *b[3];
+        for (int d = 0; d < 3; ++d) {
+            e[d] = static_cast<double *>(Ep[d]);
+            b[d] = static_cast<double *>(Bp[d]);
+        }
+        PIC_HIP(launch_gather<double>(gi.order, make_const<double>(grid, sp), parr<double>(sp), fptrs<double>(f), e,
+                                      b, err, st));
+    } else {
+        float *e[3], *b[3];
+        for (int d = 0; d < 3; ++d) {
+            e[d] = static_cast<float *>(Ep[d]);
+            b[d] = static_cast<float *>(Bp[d]);
+        }
+        PIC_HIP(launch_gather<float>(gi.order, make_const<float>(grid, sp), parr<float>(sp), fptrs<float>(f), e, b,
+                                     err, st));
+    }
+    return PIC_OK;
+}
+
+pic_status pic_push(const pic_grid *grid, pic_species *sp, void *const Ep[3], void *const Bp[3], void *stream)
+{
+    GridInfo gi;
+    PIC_TRY(check_grid(grid, gi));
+    PIC_TRY(check_species(sp, "species"));
+    PIC_TRY(check_vec3(Ep, "Ep"));
+    PIC_TRY(check_vec3(Bp, "Bp"));
+    int *err = sink_err();
+    if (!err)
+        return fail(PIC_E_DEVICE, "cannot resolve the device error word");
+    hipStream_t st = static_cast<hipStream_t>(stream);
+    if (gi.dtype == PIC_F64) {
+        double *e[3], *b[3];
+        for (int d = 0; d < 3; ++d) {
+            e[d] = static_cast<double *>(Ep[d]);
+            b[d] = static_cast<double *>(Bp[d]);
+        }
+        PIC_HIP(launch_push<double>(make_const<double>(grid, sp), parr<double>(sp), e, b, err, st));
+    } else {
+        float *e[3], *b[3];
+        for (int d = 0; d < 3; ++d) {
+            e[d] = static_cast<float *>(Ep[d]);
+            b[d] = static_cast<float *>(Bp[d]);
+        }
+        PIC_HIP(launch_push<float>(make_const<float>(grid, sp), parr<float>(sp), e, b, err, st));
+    }
+    return PIC_OK;
+}
+
+pic_status pic_deposit(const pic_grid *grid, const pic_species *before, const pic_species *after, pic_fields *f,
+                       void *stream)
+{
+    GridInfo gi;
+    PIC_TRY(check_grid(grid, gi));
+    PIC_TRY(check_species(before, "before"));
+    PIC_TRY(check_species(after, "after"));
+    if (before->n != after->n)
+        return fail(PIC_E_INVALID, "before and after hold different particle counts");
+    if (!f)
+        return fail(PIC_E_INVALID, "fields is NULL");
+    for (int d = 0; d < 3; ++d)
+        if (!f->J[d])
+            return fail(PIC_E_INVALID, "NULL current array");
+    int *err = sink_err();
+    if (!err)
+        return fail(PIC_E_DEVICE, "cannot resolve the device error word");
+    hipStream_t st = static_cast<hipStream_t>(stream);
+    if (gi.dtype == PIC_F64)
+        PIC_HIP(launch_deposit<double>(gi.order, make_const<double>(grid, before), parr<double>(before),
+                                       parr<double>(after), fptrs<double>(f), err, st));
+    else
+        PIC_HIP(launch_deposit<float>(gi.order, make_const<float>(grid, before), parr<float>(before),
+                                      parr<float>(after), fptrs<float>(f), err, st));
+    return PIC_OK;
+}
+
+pic_status pic_yee(const pic_grid *grid, pic_fields *f, const pic_source *src, int64_t step, void *stream)
+{
+    GridInfo gi;
+    PIC_TRY(check_grid(grid, gi));
+    PIC_TRY(check_fields(f, true));
+    PIC_TRY(check_source(src, gi));
+    hipStream_t st = static_cast<hipStream_t>(stream);
+    if (gi.dtype == PIC_F64)
+        return yee_step<double>(grid, gi, fptrs<double>(f), src, step, false, st);
+    return yee_step<float>(grid, gi, fptrs<float>(f), src, step, false, st);
+}
+
+pic_status pic_step(const pic_grid *grid, pic_species *sp, pic_fields *f, const pic_source *src, int64_t step0,
+                    int32_t nsteps, int32_t sort_every, int32_t *tile_start, void *ws, size_t ws_bytes,
+                    double *diag, void *stream)
+{
+    try {
+        GridInfo gi;
+        WsLayout L;
+        PIC_TRY(check_grid(grid, gi));
+        PIC_TRY(check_species(sp, "species"));
+        PIC_TRY(check_fields(f, true));
+        PIC_TRY(check_source(src, gi));
+        if (nsteps < 0)
+            return fail(PIC_E_INVALID, "nsteps must be >= 0");
+        if (sort_every < 0)
+            return fail(PIC_E_INVALID, "sort_every must be >= 0");
+        if (sort_every > 0 && !tile_start)
+            return fail(PIC_E_INVALID, "sorting needs a tile_start array");
+        PIC_TRY(check_ws(gi, sp->n, ws, ws_bytes, L));
+        hipStream_t st = static_cast<hipStream_t>(stream);
+        if (gi.dtype == PIC_F64)
+            return step_t<double>(grid, gi, sp, f, src, step0, nsteps, sort_every, tile_start, ws, L, diag, st);
+        return step_t<float>(grid, gi, sp, f, src, step0, nsteps, sort_every, tile_start, ws, L, diag, st);
+    } catch (...) {
+        return fail(PIC_E_DEVICE, "unexpected host exception");
+    }
+}
+
+pic_status pic_step_adjoint(const pic_grid *grid, const pic_species *state_n, const pic_fields *fields_n,
+                            const pic_source *src, int64_t step, pic_adjoint *lam, double *dA, void *ws,
+                            size_t ws_bytes, void *stream)
+{
+    try {
+        GridInfo gi;
+        WsLayout L;
+        PIC_TRY(check_grid(grid, gi));
+        PIC_TRY(check_species(state_n, "state_n"));
+        PIC_TRY(check_fields(fields_n, false));
+        PIC_TRY(check_source(src, gi));
+        if (!lam)
+            return fail(PIC_E_INVALID, "adjoint state is NULL");
+        for (int d = 0; d < 3; ++d)
+            if (!lam->lE[d] || !lam->lB[d] || (state_n->n > 0 && (!lam->lx[d] || !lam->lu[d])))
+                return fail(PIC_E_INVALID, "NULL adjoint array");
+        PIC_TRY(check_ws(gi, state_n->n, ws, ws_bytes, L));
+        hipStream_t st = static_cast<hipStream_t>(stream);
+        if (gi.dtype == PIC_F64)
+            return adjoint_t<double>(grid, gi, state_n, fields_n, src, step, lam, dA, ws, L, st);
+        return adjoint_t<float>(grid, gi, state_n, fields_n, src, step, lam, dA, ws, L, st);
+    } catch (...) {
+        return fail(PIC_E_DEVICE, "unexpected host exception");
+    }
+}
+
+pic_status pic_reduce(const pic_grid *grid, const pic_species *sp, const pic_fields *f, double *out, void *ws,
+                      size_t ws_bytes, void *stream)
+{
+    GridInfo gi;
+    WsLayout L;
+    PIC_TRY(check_grid(grid, gi));
+    if (sp)
+        PIC_TRY(check_species(sp, "species"));
+    PIC_TRY(check_fields(f, false));
+    if (!out)
+        return fail(PIC_E_INVALID, "out is NULL");
+    PIC_TRY(check_ws(gi, sp ? sp->n : 0, ws, ws_bytes, L));
+    hipStream_t st = static_cast<hipStream_t>(stream);
+    if (gi.dtype == PIC_F64)
+        return reduce_t<double>(grid, gi, sp, f, out, static_cast<char *>(ws), L, st);
+    return reduce_t<float>(grid, gi, sp, f, out, static_cast<char *>(ws), L, st);
+}
+
+const char *pic_last_error(void)
+{
+    return g_msg.c_str();
+}
+
+}  // extern "C"

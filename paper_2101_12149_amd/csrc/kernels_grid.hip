@@ -1,0 +1,428 @@
+// Grid kernels of the EM-PIC step for gfx950: the Yee curl updates (and
+// their transposes), the counting sort that bins particles by tile-major
+// cell (Sec. 3.4.2), and the FP64 reductions (Sec. 2.6).  All of them are
+// bound by HBM bandwidth: coalesced x-fastest access, one pass per update.
+#include "pic_types.hpp"
+
+namespace pic {
+
+// ---------------------------------------------------------------------------
+// Curl updates.  Forward differences take edge-centred vectors to faces,
+// backward differences take face-centred vectors to edges (Sec. 2.4, Yee):
+//   curl_f(S)_x = (S_z[j+1] - S_z)/dy - (S_y[k+1] - S_y)/dz      (cyclic)
+//   curl_b(S)_x = (S_z - S_z[j-1])/dy - (S_y - S_y[k-1])/dz
+// The coefficients cx, cy, cz already hold (scale / d).
+
+template <typename T, bool FWD>
+__global__ void __launch_bounds__(256) k_curl(CurlArgs<T> a)
+{
+    const int i = blockIdx.x * blockDim.x + threadIdx.x;
+    const int j = blockIdx.y;
+    const int k = blockIdx.z;
+    const int n0 = a.n[0], n1 = a.n[1], n2 = a.n[2];
+    if (i >= n0)
+        return;
+    const int64_t o = i + (int64_t)n0 * (j + (int64_t)n1 * k);
+    int64_t xs, ys, zs;   // neighbour offsets (+1 for forward, -1 for backward), periodic
+    if (FWD) {
+        xs = (i + 1 < n0) ? 1 : 1 - n0;
+        ys = (j + 1 < n1) ? n0 : (int64_t)n0 * (1 - n1);
+        zs = (k + 1 < n2) ? (int64_t)n0 * n1 : (int64_t)n0 * n1 * (1 - n2);
+    } else {
+        xs = (i > 0) ? -1 : n0 - 1;
+        ys = (j > 0) ? -(int64_t)n0 : (int64_t)n0 * (n1 - 1);
+        zs = (k > 0) ? -(int64_t)n0 * n1 : (int64_t)n0 * n1 * (n2 - 1);
+    }
+    const T *Sx = a.src[0], *Sy = a.src[1], *Sz = a.src[2];
+    T dx_sy, dx_sz, dy_sx, dy_sz, dz_sx, dz_sy;
+    if (FWD) {
+        dx_sy = Sy[o + xs] - Sy[o];
+        dx_sz = Sz[o + xs] - Sz[o];
+        dy_sx = Sx[o + ys] - Sx[o];
+        dy_sz = Sz[o + ys] - Sz[o];
+        dz_sx = Sx[o + zs] - Sx[o];
+        dz_sy = Sy[o + zs] - Sy[o];
+    } else {
+        dx_sy = Sy[o] - Sy[o + xs];
+        dx_sz = Sz[o] - Sz[o + xs];
+        dy_sx = Sx[o] - Sx[o + ys];
+        dy_sz = Sz[o] - Sz[o + ys];
+        dz_sx = Sx[o] - Sx[o + zs];
+        dz_sy = Sy[o] - Sy[o + zs];
+    }
+    T vx = a.in[0][o] + (a.cy * dy_sz - a.cz * dz_sy);
+    T vy = a.in[1][o] + (a.cz * dz_sx - a.cx * dx_sz);
+    T vz = a.in[2][o] + (a.cx * dx_sy - a.cy * dy_sx);
+    if (a.J[0]) {
+        vx += a.jc * a.J[0][o];
+        vy += a.jc * a.J[1][o];
+        vz += a.jc * a.J[2][o];
+        if (a.zero_j) {
+            a.J[0][o] = T(0);
+            a.J[1][o] = T(0);
+            a.J[2][o] = T(0);
+        }
+    }
+    if (k == a.kplane) {
+        if (a.amp)
+            vx += a.amp[i + (int64_t)n0 * j] * a.ag;
+        if (a.dA)
+            a.dA[i + (int64_t)n0 * j] += a.dag * (double)vx;
+    }
+    a.out[0][o] = vx;
+    a.out[1][o] = vy;
+    a.out[2][o] = vz;
+}
+
+template <typename T>
+hipError_t launch_curl(bool forward, const CurlArgs<T> &a, hipStream_t st)
+{
+    const int bx = a.n[0] >= 256 ? 256 : (a.n[0] >= 128 ? 128 : 64);
+    dim3 grid((a.n[0] + bx - 1) / bx, a.n[1], a.n[2]);
+    if (forward)
+        hipLaunchKernelGGL((k_curl<T, true>), grid, dim3(bx), 0, st, a);
+    else
+        hipLaunchKernelGGL((k_curl<T, false>), grid, dim3(bx), 0, st, a);
+    return hipGetLastError();
+}
+
+template <typename T>
+__global__ void k_fill(T *p, int64_t n, T v)
+{
+    for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x)
+        p[i] = v;
+}
+
+template <typename T>
+hipError_t launch_fill(T *p, int64_t n, T v, hipStream_t st)
+{
+    if (n <= 0)
+        return hipSuccess;
+    int64_t b = (n + 255) / 256;
+    if (b > 65536)
+        b = 65536;
+    hipLaunchKernelGGL((k_fill<T>), dim3((unsigned)b), dim3(256), 0, st, p, n, v);
+    return hipGetLastError();
+}
+
+// ---------------------------------------------------------------------------
+// Counting sort by tile-major cell key (Sec. 3.4.2).  Pass 1 computes each
+// particle's key and its rank inside the key's bin with one atomic increment
+// per particle; an exclusive scan of the bin counts gives bin offsets; pass 2
+// scatters every particle to offset[key] + rank.
+
+template <typename T>
+__global__ void __launch_bounds__(256) k_bin_count(PArr<T> sp, TileGeo tg, int n0, int n1, int n2, int *counts,
+                                                   int *key, int *rank, int *err)
+{
+    const int64_t p = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (p >= sp.n)
+        return;
+    int c[3] = {sp.cell[0][p], sp.cell[1][p], sp.cell[2][p]};
+    const int n[3] = {n0, n1, n2};
+    bool ok = true;
+#pragma unroll
+    for (int d = 0; d < 3; ++d) {
+        const T f = sp.off[d][p];
+        ok = ok && c[d] >= 0 && c[d] < n[d] && f >= T(0) && f < T(1);
+        c[d] = c[d] < 0 ? 0 : (c[d] >= n[d] ? n[d] - 1 : c[d]);   // keep the key in range
+    }
+    if (!ok)
+        atomicOr(err, 1);
+    const int tx = c[0] / tg.t[0], ty = c[1] / tg.t[1], tz = c[2] / tg.t[2];
+    const int lx = c[0] - tx * tg.t[0], ly = c[1] - ty * tg.t[1], lz = c[2] - tz * tg.t[2];
+    const int tile = tx + tg.nt[0] * (ty + tg.nt[1] * tz);
+    const int kk = tile * (tg.t[0] * tg.t[1] * tg.t[2]) + lx + tg.t[0] * (ly + tg.t[1] * lz);
+    key[p] = kk;
+    rank[p] = atomicAdd(counts + kk, 1);
+}
+
+template <typename T>
+hipError_t launch_bin_count(const PArr<T> &sp, const TileGeo &tg, int *counts, int *key, int *rank, int *err,
+                            hipStream_t st)
+{
+    if (sp.n == 0)
+        return hipSuccess;
+    const int n0 = tg.t[0] * tg.nt[0], n1 = tg.t[1] * tg.nt[1], n2 = tg.t[2] * tg.nt[2];
+    hipLaunchKernelGGL((k_bin_count<T>), dim3((unsigned)((sp.n + 255) / 256)), dim3(256), 0, st, sp, tg, n0, n1, n2,
+                       counts, key, rank, err);
+    return hipGetLastError();
+}
+
+template <typename T>
+__global__ void __launch_bounds__(256) k_scatter(PArr<T> in, PArr<T> out, const int *key, const int *rank,
+                                                 const int *offsets, int *perm)
+{
+    const int64_t p = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (p >= in.n)
+        return;
+    const int64_t q = (int64_t)offsets[key[p]] + rank[p];
+#pragma unroll
+    for (int d = 0; d < 3; ++d) {
+        out.cell[d][q] = in.cell[d][p];
+        out.off[d][q] = in.off[d][p];
+        out.u[d][q] = in.u[d][p];
+    }
+    if (in.w)
+        out.w[q] = in.w[p];
+    if (perm)
+        perm[q] = (int)p;
+}
+
+template <typename T>
+hipError_t launch_scatter(const PArr<T> &in, const PArr<T> &out, const int *key, const int *rank,
+                          const int *offsets, int *perm, hipStream_t st)
+{
+    if (in.n == 0)
+        return hipSuccess;
+    hipLaunchKernelGGL((k_scatter<T>), dim3((unsigned)((in.n + 255) / 256)), dim3(256), 0, st, in, out, key, rank,
+                       offsets, perm);
+    return hipGetLastError();
+}
+
+// Exclusive scan of int32 in three passes (block sums, scan of the sums,
+// block-local rescan with the block offset).  Each block covers SCAN_CHUNK
+// elements, 16 per thread.
+static constexpr int SCAN_T = 256;
+static constexpr int SCAN_PER = 16;
+static constexpr int SCAN_CHUNK = SCAN_T * SCAN_PER;
+
+int64_t scan_blocks(int64_t n)
+{
+    return (n + SCAN_CHUNK - 1) / SCAN_CHUNK;
+}
+
+// inclusive block scan of one value per thread; returns the block total
+__device__ inline int block_incl_scan(int v, int *sh)
+{
+    const int tid = threadIdx.x;
+    sh[tid] = v;
+    __syncthreads();
+    for (int off = 1; off < SCAN_T; off <<= 1) {
+        int add = tid >= off ? sh[tid - off] : 0;
+        __syncthreads();
+        sh[tid] += add;
+        __syncthreads();
+    }
+    return sh[tid];
+}
+
+__global__ void __launch_bounds__(SCAN_T) k_scan_reduce(const int *data, int64_t n, int *bsum)
+{
+    __shared__ int sh[SCAN_T];
+    const int64_t base = (int64_t)blockIdx.x * SCAN_CHUNK + (int64_t)threadIdx.x * SCAN_PER;
+    int s = 0;
+#pragma unroll
+    for (int e = 0; e < SCAN_PER; ++e)
+        if (base + e < n)
+            s += data[base + e];
+    const int incl = block_incl_scan(s, sh);
+    if (threadIdx.x == SCAN_T - 1)
+        bsum[blockIdx.x] = incl;
+}
+
+// one workgroup scans the block sums (exclusive), chunk by chunk
+__global__ void __launch_bounds__(SCAN_T) k_scan_top(int *bsum, int64_t nb)
+{
+    __shared__ int sh[SCAN_T];
+    int carry = 0;
+    for (int64_t base = 0; base < nb; base += (int64_t)SCAN_T * SCAN_PER) {
+        const int64_t b0 = base + (int64_t)threadIdx.x * SCAN_PER;
+        int loc[SCAN_PER];
+        int s = 0;
+#pragma unroll
+        for (int e = 0; e < SCAN_PER; ++e) {
+            loc[e] = (b0 + e < nb) ? bsum[b0 + e] : 0;
+            s += loc[e];
+        }
+        const int incl = block_incl_scan(s, sh);
+        int run = carry + incl - s;
+#pragma unroll
+        for (int e = 0; e < SCAN_PER; ++e) {
+            if (b0 + e < nb)
+                bsum[b0 + e] = run;
+            run += loc[e];
+        }
+        const int total = sh[SCAN_T - 1];
+        __syncthreads();
+        carry += total;
+    }
+}
+
+__global__ void __launch_bounds__(SCAN_T) k_scan_down(int *data, int64_t n, const int *bsum)
+{
+    __shared__ int sh[SCAN_T];
+    const int64_t base = (int64_t)blockIdx.x * SCAN_CHUNK + (int64_t)threadIdx.x * SCAN_PER;
+    int loc[SCAN_PER];
+    int s = 0;
+#pragma unroll
+    for (int e = 0; e < SCAN_PER; ++e) {
+        loc[e] = (base + e < n) ? data[base + e] : 0;
+        s += loc[e];
+    }
+    const int incl = block_incl_scan(s, sh);
+    int run = bsum[blockIdx.x] + incl - s;
+#pragma unroll
+    for (int e = 0; e < SCAN_PER; ++e) {
+        if (base + e < n)
+            data[base + e] = run;
+        run += loc[e];
+    }
+}
+
+hipError_t launch_scan(int *data, int64_t n, int *bsum, hipStream_t st)
+{
+    if (n <= 0)
+        return hipSuccess;
+    const int64_t nb = scan_blocks(n);
+    hipLaunchKernelGGL(k_scan_reduce, dim3((unsigned)nb), dim3(SCAN_T), 0, st, data, n, bsum);
+    hipLaunchKernelGGL(k_scan_top, dim3(1), dim3(SCAN_T), 0, st, bsum, nb);
+    hipLaunchKernelGGL(k_scan_down, dim3((unsigned)nb), dim3(SCAN_T), 0, st, data, n, bsum);
+    return hipGetLastError();
+}
+
+__global__ void k_tile_start(const int *offsets, int tile_cells, int ntiles, int64_t np, int *tile_start)
+{
+    const int t = blockIdx.x * blockDim.x + threadIdx.x;
+    if (t < ntiles)
+        tile_start[t] = offsets[(int64_t)t * tile_cells];
+    else if (t == ntiles)
+        tile_start[t] = (int)np;
+}
+
+hipError_t launch_tile_start(const int *offsets, int tile_cells, int ntiles, int64_t np, int *tile_start,
+                             hipStream_t st)
+{
+    hipLaunchKernelGGL(k_tile_start, dim3((unsigned)((ntiles + 1 + 255) / 256)), dim3(256), 0, st, offsets,
+                       tile_cells, ntiles, np, tile_start);
+    return hipGetLastError();
+}
+
+// ---------------------------------------------------------------------------
+// FP64 reductions in one pass over cells and particles (Sec. 2.6: several
+// reductions in a single launch).  Blocks [0, nbf) sum |E|^2 and |B|^2 over
+// cells, blocks [nbf, nbf+nbp) sum w (gamma-1), w and w u_z over particles;
+// each block writes its five partial sums, and one final block adds them in
+// block order (deterministic) and applies the physical scale factors.
+
+static constexpr int RED_T = 256;
+static constexpr int RED_MAX_BLOCKS = 4096;
+
+int reduce_max_blocks()
+{
+    return RED_MAX_BLOCKS;
+}
+
+__device__ inline double wave_sum(double v)
+{
+    for (int off = 32; off > 0; off >>= 1)
+        v += __shfl_down(v, off, 64);
+    return v;
+}
+
+__device__ inline void block_sum5(double *v, double *sh, double *dst)
+{
+    const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
+#pragma unroll
+    for (int k = 0; k < 5; ++k) {
+        const double s = wave_sum(v[k]);
+        if (lane == 0)
+            sh[wv * 5 + k] = s;
+    }
+    __syncthreads();
+    if (threadIdx.x < 5) {
+        double s = 0;
+        for (int w = 0; w < RED_T / 64; ++w)
+            s += sh[w * 5 + threadIdx.x];
+        dst[threadIdx.x] = s;
+    }
+}
+
+template <typename T>
+__global__ void __launch_bounds__(RED_T) k_reduce(PArr<T> sp, int has_sp, FieldPtrs<T> f, int64_t ncell, int nbf,
+                                                  int nbp, double inv_c2, double w0, double *partials)
+{
+    __shared__ double sh[(RED_T / 64) * 5];
+    double v[5] = {0, 0, 0, 0, 0};
+    if ((int)blockIdx.x < nbf) {
+        for (int64_t i = (int64_t)blockIdx.x * RED_T + threadIdx.x; i < ncell; i += (int64_t)nbf * RED_T) {
+#pragma unroll
+            for (int m = 0; m < 3; ++m) {
+                const double e = (double)f.E[m][i], b = (double)f.B[m][i];
+                v[0] += e * e;
+                v[1] += b * b;
+            }
+        }
+    } else if (has_sp) {
+        const int bb = blockIdx.x - nbf;
+        for (int64_t p = (int64_t)bb * RED_T + threadIdx.x; p < sp.n; p += (int64_t)nbp * RED_T) {
+            const double ux = sp.u[0][p], uy = sp.u[1][p], uz = sp.u[2][p];
+            const double w = sp.w ? (double)sp.w[p] : w0;
+            const double uu = (ux * ux + uy * uy + uz * uz) * inv_c2;
+            const double gm = sqrt(1.0 + uu);
+            v[2] += w * uu / (gm + 1.0);   // gamma - 1 without cancellation
+            v[3] += w;
+            v[4] += w * uz;
+        }
+    }
+    block_sum5(v, sh, partials + 5 * (int64_t)blockIdx.x);
+}
+
+__global__ void __launch_bounds__(RED_T) k_reduce_final(const double *partials, int nb, double s0, double s1,
+                                                        double s2, double s3, double s4, double *out)
+{
+    __shared__ double sh[(RED_T / 64) * 5];
+    // each thread sums a contiguous range of blocks in order
+    const int per = (nb + RED_T - 1) / RED_T;
+    double v[5] = {0, 0, 0, 0, 0};
+    for (int b = threadIdx.x * per; b < (threadIdx.x + 1) * per && b < nb; ++b)
+#pragma unroll
+        for (int k = 0; k < 5; ++k)
+            v[k] += partials[5 * b + k];
+    __shared__ double tot[5];
+    block_sum5(v, sh, tot);
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        out[0] = s0 * tot[0];
+        out[1] = s1 * tot[1];
+        out[2] = s2 * tot[2];
+        out[3] = s3 * tot[3];
+        out[4] = s4 * tot[4];
+    }
+}
+
+template <typename T>
+hipError_t launch_reduce(const PArr<T> *sp, const FieldPtrs<T> &f, int64_t ncell, double *partials, int max_blocks,
+                         const double scale[7], double *out, hipStream_t st)
+{
+    // scale[0..4]: factors of the five sums; scale[5] = 1/c^2; scale[6] = w0
+    int nbf = (int)((ncell + RED_T * 8 - 1) / (RED_T * 8));
+    int nbp = sp ? (int)((sp->n + RED_T * 8 - 1) / (RED_T * 8)) : 0;
+    const int half = max_blocks / 2;
+    nbf = nbf < 1 ? 1 : (nbf > half ? half : nbf);
+    nbp = nbp > half ? half : nbp;
+    PArr<T> s{};
+    if (sp)
+        s = *sp;
+    hipLaunchKernelGGL((k_reduce<T>), dim3(nbf + nbp), dim3(RED_T), 0, st, s, sp ? 1 : 0, f, ncell, nbf, nbp,
+                       scale[5], scale[6], partials);
+    hipLaunchKernelGGL(k_reduce_final, dim3(1), dim3(RED_T), 0, st, partials, nbf + nbp, scale[0], scale[1], scale[2],
+                       scale[3], scale[4], out);
+    return hipGetLastError();
+}
+
+#define PIC_GINST(T)                                                                                             \
+    template hipError_t launch_curl<T>(bool, const CurlArgs<T> &, hipStream_t);                                   \
+    template hipError_t launch_fill<T>(T *, int64_t, T, hipStream_t);                                             \
+    template hipError_t launch_bin_count<T>(const PArr<T> &, const TileGeo &, int *, int *, int *, int *,         \
+                                            hipStream_t);                                                         \
+    template hipError_t launch_scatter<T>(const PArr<T> &, const PArr<T> &, const int *, const int *, const int *, \
+                                          int *, hipStream_t);                                                    \
+    template hipError_t launch_reduce<T>(const PArr<T> *, const FieldPtrs<T> &, int64_t, double *, int,           \
+                                         const double[7], double *, hipStream_t);
+
+PIC_GINST(float)
+PIC_GINST(double)
+template hipError_t launch_fill<int>(int *, int64_t, int, hipStream_t);
+
+}  // namespace pic

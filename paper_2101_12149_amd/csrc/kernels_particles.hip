@@ -1,0 +1,677 @@
+// Particle kernels of the EM-PIC step for gfx950.
+//
+//  k_particles_tile   one workgroup per tile: E and B of the tile plus the
+//                     gather halo are staged in LDS, the current of the tile
+//                     plus the deposit halo is accumulated in LDS with LDS
+//                     atomics and flushed with one global atomic per touched
+//                     value (a single-GPU analogue of the paper's guard-cell
+//                     FillBoundary / SumBoundary, Sec. 2.4).  Particles are
+//                     gathered, pushed, moved and deposited in one pass, so
+//                     per-particle fields are never stored (Sec. 3.1).
+//  k_particles_global the same fused step without tiles (global memory and
+//                     global atomics, the paper's GPU deposition, Sec. 3.4.1)
+//  k_gather / k_push / k_deposit   the separate operations
+//  k_adjoint_particles             transpose of the particle part of a step
+#include "pic_device.hpp"
+#include "pic_types.hpp"
+
+namespace pic {
+
+template <typename T>
+__device__ inline void gatomic_add(T *p, T v)
+{
+    unsafeAtomicAdd(p, v);
+}
+
+template <typename T>
+__device__ inline void latomic_add(T *p, T v)
+{
+    __hip_atomic_fetch_add(p, v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
+}
+
+__device__ inline int wrap_once(int v, int n)
+{
+    return v < 0 ? v + n : (v >= n ? v - n : v);
+}
+
+__device__ inline int wrap_any(int v, int n)
+{
+    int r = v % n;
+    return r < 0 ? r + n : r;
+}
+
+template <typename T>
+__device__ inline bool finite3(const T *u)
+{
+    return isfinite(u[0]) && isfinite(u[1]) && isfinite(u[2]);
+}
+
+// Load a particle and check its state; returns false (and flags err) for a
+// cell outside [0,n), an offset outside [0,1) or a non-finite momentum.
+template <typename T>
+__device__ inline bool load_particle(const PArr<T> &in, int64_t p, const int *n, int *c, T *f, T *u, int *err)
+{
+    bool ok = true;
+#pragma unroll
+    for (int d = 0; d < 3; ++d) {
+        c[d] = in.cell[d][p];
+        f[d] = in.off[d][p];
+        u[d] = in.u[d][p];
+        ok = ok && c[d] >= 0 && c[d] < n[d] && f[d] >= T(0) && f[d] < T(1);
+    }
+    ok = ok && finite3(u);
+    if (!ok)
+        atomicOr(err, 1);
+    return ok;
+}
+
+template <typename T>
+__device__ inline void copy_particle(const PArr<T> &in, const PArr<T> &out, int64_t p)
+{
+    if (in.cell[0] == out.cell[0])
+        return;
+#pragma unroll
+    for (int d = 0; d < 3; ++d) {
+        out.cell[d][p] = in.cell[d][p];
+        out.off[d][p] = in.off[d][p];
+        out.u[d][p] = in.u[d][p];
+    }
+    if (out.w)
+        out.w[p] = in.w[p];
+}
+
+// ---------------------------------------------------------------------------
+// One particle through gather -> Boris -> move -> Esirkepov.  With LOCAL the
+// particle lies in the LDS regions (positions l[] relative to the tile);
+// otherwise everything is read and scattered in global memory.
+template <typename T, int O, bool LOCAL>
+__device__ inline void particle_step(const PConst<T> &pc, const PArr<T> &in, const PArr<T> &out,
+                                     const FieldPtrs<T> &fp, const FieldSrc<T> &fsrc, int64_t p, const int *c,
+                                     const T *f, const T *u, const int *l, int lo_f, const int *sf, int lo_j,
+                                     const int *sj, T *sJ, int rjvol, int *err)
+{
+    constexpr int NW = Shape<O, T>::NW;
+    const int gs[3] = {1, pc.n[0], pc.n[0] * pc.n[1]};
+    AxisW<O, T> aw[3];
+    int on[3][NW], os[3][NW];
+#pragma unroll
+    for (int d = 0; d < 3; ++d) {
+        axis_weights<O>(f[d], aw[d]);
+        if (LOCAL) {
+            axis_offsets_local<NW>(l[d] + lo_f, aw[d].bn, sf[d], on[d]);
+            axis_offsets_local<NW>(l[d] + lo_f, aw[d].bs, sf[d], os[d]);
+        } else {
+            axis_offsets_global<NW>(c[d], aw[d].bn, pc.n[d], gs[d], on[d]);
+            axis_offsets_global<NW>(c[d], aw[d].bs, pc.n[d], gs[d], os[d]);
+        }
+    }
+    T E[3], B[3];
+    gather_eb<O>(fsrc, aw, on, os, E, B);
+
+    BorisTape<T> tp;
+    T u1[3];
+    boris(pc.h, pc.inv_c2, u, E, B, u1, tp);
+    const T ig = T(1) / sqrt(T(1) + (u1[0] * u1[0] + u1[1] * u1[1] + u1[2] * u1[2]) * pc.inv_c2);
+    T f1[3];
+    int kap[3];
+    bool ok = true;
+#pragma unroll
+    for (int d = 0; d < 3; ++d) {
+        const T disp = pc.dtd[d] * u1[d] * ig;
+        ok = ok && fabs(disp) < T(1);
+        move_axis(f[d], disp, f1[d], kap[d]);
+    }
+    if (!ok) {
+        atomicOr(err, 2);
+        copy_particle(in, out, p);
+        return;
+    }
+    const T w = in.w ? in.w[p] : pc.w0;
+    EskAxis<O, T> e[3];
+    T K[3];
+    int jo[3][NW + 1];
+#pragma unroll
+    for (int d = 0; d < 3; ++d) {
+        esk_axis<O>(f[d], f1[d], kap[d], e[d]);
+        K[d] = pc.jk[d] * w;
+        if (LOCAL)
+            axis_offsets_local<NW + 1>(l[d] + lo_j, e[d].lo, sj[d], jo[d]);
+        else
+            axis_offsets_global<NW + 1>(c[d], e[d].lo, pc.n[d], gs[d], jo[d]);
+    }
+    if (LOCAL) {
+        esk_scatter<O>(e, jo, K, [&](int m, int idx, T v) { latomic_add(sJ + m * rjvol + idx, v); });
+    } else {
+        esk_scatter<O>(e, jo, K, [&](int m, int idx, T v) { gatomic_add(fp.J[m] + idx, v); });
+    }
+#pragma unroll
+    for (int d = 0; d < 3; ++d) {
+        out.cell[d][p] = wrap_once(c[d] + kap[d], pc.n[d]);
+        out.off[d][p] = f1[d];
+        out.u[d][p] = u1[d];
+    }
+    if (out.w && out.w != in.w)
+        out.w[p] = in.w[p];
+}
+
+// ---------------------------------------------------------------------------
+template <typename T, int O>
+__global__ void __launch_bounds__(256) k_particles_tile(PConst<T> pc, TileGeo tg, PArr<T> in, PArr<T> out,
+                                                        FieldPtrs<T> fp, const int *__restrict__ tile_start,
+                                                        int *err)
+{
+    extern __shared__ __align__(16) unsigned char smem_raw[];
+    T *sF = reinterpret_cast<T *>(smem_raw);
+    const int rfx = tg.rf[0], rfy = tg.rf[1];
+    const int rfvol = rfx * rfy * tg.rf[2];
+    const int rjx = tg.rj[0], rjy = tg.rj[1];
+    const int rjvol = rjx * rjy * tg.rj[2];
+    T *sJ = sF + 6 * rfvol;
+
+    const int ntiles = tg.nt[0] * tg.nt[1] * tg.nt[2];
+    int t = blockIdx.x;
+    if (tg.xcd_map)
+        t = (t & 7) * (ntiles >> 3) + (t >> 3);
+    const int tx = t % tg.nt[0], ty = (t / tg.nt[0]) % tg.nt[1], tz = t / (tg.nt[0] * tg.nt[1]);
+    const int t0[3] = {tx * tg.t[0], ty * tg.t[1], tz * tg.t[2]};
+    const int64_t N = in.n;
+    int64_t ps = tile_start[t], pe = tile_start[t + 1];
+    ps = ps < 0 ? 0 : (ps > N ? N : ps);
+    pe = pe < ps ? ps : (pe > N ? N : pe);
+    if (pe <= ps)
+        return;   // uniform across the workgroup
+
+    const int tid = threadIdx.x, nth = blockDim.x;
+    for (int r = tid; r < rfvol; r += nth) {
+        const int rx = r % rfx, ry = (r / rfx) % rfy, rz = r / (rfx * rfy);
+        const int gx = wrap_any(t0[0] - tg.lo_f + rx, pc.n[0]);
+        const int gy = wrap_any(t0[1] - tg.lo_f + ry, pc.n[1]);
+        const int gz = wrap_any(t0[2] - tg.lo_f + rz, pc.n[2]);
+        const int gi = gx + pc.n[0] * (gy + pc.n[1] * gz);
+#pragma unroll
+        for (int m = 0; m < 3; ++m) {
+            sF[m * rfvol + r] = fp.E[m][gi];
+            sF[(3 + m) * rfvol + r] = fp.B[m][gi];
+        }
+    }
+    for (int r = tid; r < 3 * rjvol; r += nth)
+        sJ[r] = T(0);
+    __syncthreads();
+
+    FieldSrc<T> lf, gf;
+#pragma unroll
+    for (int m = 0; m < 3; ++m) {
+        lf.c[m] = sF + m * rfvol;
+        lf.c[3 + m] = sF + (3 + m) * rfvol;
+        gf.c[m] = fp.E[m];
+        gf.c[3 + m] = fp.B[m];
+    }
+    const int sf[3] = {1, rfx, rfx * rfy};
+    const int sj[3] = {1, rjx, rjx * rjy};
+    const int np = (int)(pe - ps);
+    const int per = (np + nth - 1) / nth;
+    // each thread takes a contiguous run of the tile's particles, so the
+    // lanes of a wave sit in different cells and their LDS atomics rarely
+    // hit the same address
+    for (int it = 0; it < per; ++it) {
+        const int j = tid * per + it;
+        if (j < np) {
+            const int64_t p = ps + j;
+            int c[3];
+            T f[3], u[3];
+            if (!load_particle(in, p, pc.n, c, f, u, err)) {
+                copy_particle(in, out, p);
+            } else {
+                int l[3];
+                bool inside = true;
+#pragma unroll
+                for (int d = 0; d < 3; ++d) {
+                    int v = c[d] - t0[d];
+                    if (v < -tg.slack)
+                        v += pc.n[d];
+                    else if (v >= tg.t[d] + tg.slack)
+                        v -= pc.n[d];
+                    l[d] = v;
+                    inside = inside && v >= -tg.slack && v < tg.t[d] + tg.slack;
+                }
+                if (inside)
+                    particle_step<T, O, true>(pc, in, out, fp, lf, p, c, f, u, l, tg.lo_f, sf, tg.lo_j, sj, sJ,
+                                              rjvol, err);
+                else
+                    particle_step<T, O, false>(pc, in, out, fp, gf, p, c, f, u, l, tg.lo_f, sf, tg.lo_j, sj, sJ,
+                                               rjvol, err);
+            }
+        }
+    }
+    __syncthreads();
+    for (int r = tid; r < 3 * rjvol; r += nth) {
+        const T v = sJ[r];
+        if (v != T(0)) {
+            const int m = r / rjvol, rr = r - m * rjvol;
+            const int rx = rr % rjx, ry = (rr / rjx) % rjy, rz = rr / (rjx * rjy);
+            const int gx = wrap_any(t0[0] - tg.lo_j + rx, pc.n[0]);
+            const int gy = wrap_any(t0[1] - tg.lo_j + ry, pc.n[1]);
+            const int gz = wrap_any(t0[2] - tg.lo_j + rz, pc.n[2]);
+            gatomic_add(fp.J[m] + gx + pc.n[0] * (gy + pc.n[1] * gz), v);
+        }
+    }
+}
+
+template <typename T, int O>
+__global__ void __launch_bounds__(256) k_particles_global(PConst<T> pc, PArr<T> sp, FieldPtrs<T> fp, int *err)
+{
+    const int64_t p = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (p >= sp.n)
+        return;
+    int c[3];
+    T f[3], u[3];
+    if (!load_particle(sp, p, pc.n, c, f, u, err))
+        return;
+    FieldSrc<T> gf;
+#pragma unroll
+    for (int m = 0; m < 3; ++m) {
+        gf.c[m] = fp.E[m];
+        gf.c[3 + m] = fp.B[m];
+    }
+    const int z3[3] = {0, 0, 0};
+    particle_step<T, O, false>(pc, sp, sp, fp, gf, p, c, f, u, z3, 0, z3, 0, z3, nullptr, 0, err);
+}
+
+template <typename T, int O>
+__global__ void __launch_bounds__(256) k_gather(PConst<T> pc, PArr<T> sp, FieldPtrs<T> fp, T *Ex, T *Ey, T *Ez,
+                                                T *Bx, T *By, T *Bz, int *err)
+{
+    constexpr int NW = Shape<O, T>::NW;
+    const int64_t p = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (p >= sp.n)
+        return;
+    int c[3];
+    T f[3];
+    T E[3] = {T(0), T(0), T(0)}, B[3] = {T(0), T(0), T(0)};
+    bool ok = true;
+#pragma unroll
+    for (int d = 0; d < 3; ++d) {
+        c[d] = sp.cell[d][p];
+        f[d] = sp.off[d][p];
+        ok = ok && c[d] >= 0 && c[d] < pc.n[d] && f[d] >= T(0) && f[d] < T(1);
+    }
+    if (!ok)
+        atomicOr(err, 1);
+    if (ok) {
+        const int gs[3] = {1, pc.n[0], pc.n[0] * pc.n[1]};
+        AxisW<O, T> aw[3];
+        int on[3][NW], os[3][NW];
+#pragma unroll
+        for (int d = 0; d < 3; ++d) {
+            axis_weights<O>(f[d], aw[d]);
+            axis_offsets_global<NW>(c[d], aw[d].bn, pc.n[d], gs[d], on[d]);
+            axis_offsets_global<NW>(c[d], aw[d].bs, pc.n[d], gs[d], os[d]);
+        }
+        FieldSrc<T> gf;
+#pragma unroll
+        for (int m = 0; m < 3; ++m) {
+            gf.c[m] = fp.E[m];
+            gf.c[3 + m] = fp.B[m];
+        }
+        gather_eb<O>(gf, aw, on, os, E, B);
+    }
+    Ex[p] = E[0];
+    Ey[p] = E[1];
+    Ez[p] = E[2];
+    Bx[p] = B[0];
+    By[p] = B[1];
+    Bz[p] = B[2];
+}
+
+template <typename T>
+__global__ void __launch_bounds__(256) k_push(PConst<T> pc, PArr<T> sp, const T *Ex, const T *Ey, const T *Ez,
+                                              const T *Bx, const T *By, const T *Bz, int *err)
+{
+    const int64_t p = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (p >= sp.n)
+        return;
+    int c[3];
+    T f[3], u[3];
+    if (!load_particle(sp, p, pc.n, c, f, u, err))
+        return;
+    const T E[3] = {Ex[p], Ey[p], Ez[p]}, B[3] = {Bx[p], By[p], Bz[p]};
+    BorisTape<T> tp;
+    T u1[3];
+    boris(pc.h, pc.inv_c2, u, E, B, u1, tp);
+    const T ig = T(1) / sqrt(T(1) + (u1[0] * u1[0] + u1[1] * u1[1] + u1[2] * u1[2]) * pc.inv_c2);
+    T f1[3];
+    int kap[3];
+    bool ok = true;
+#pragma unroll
+    for (int d = 0; d < 3; ++d) {
+        const T disp = pc.dtd[d] * u1[d] * ig;
+        ok = ok && fabs(disp) < T(1);
+        move_axis(f[d], disp, f1[d], kap[d]);
+    }
+    if (!ok) {
+        atomicOr(err, 2);
+        return;
+    }
+#pragma unroll
+    for (int d = 0; d < 3; ++d) {
+        sp.cell[d][p] = wrap_once(c[d] + kap[d], pc.n[d]);
+        sp.off[d][p] = f1[d];
+        sp.u[d][p] = u1[d];
+    }
+}
+
+template <typename T, int O>
+__global__ void __launch_bounds__(256) k_deposit(PConst<T> pc, PArr<T> b, PArr<T> a, FieldPtrs<T> fp, int *err)
+{
+    constexpr int NW = Shape<O, T>::NW;
+    const int64_t p = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (p >= b.n)
+        return;
+    int c0[3], c1[3], kap[3];
+    T f0[3], f1[3], u[3];
+    if (!load_particle(b, p, pc.n, c0, f0, u, err))
+        return;
+    bool ok = true;
+#pragma unroll
+    for (int d = 0; d < 3; ++d) {
+        c1[d] = a.cell[d][p];
+        f1[d] = a.off[d][p];
+        int k = c1[d] - c0[d];
+        if (k > pc.n[d] / 2)
+            k -= pc.n[d];
+        if (k < -(pc.n[d] / 2))
+            k += pc.n[d];
+        kap[d] = k;
+        ok = ok && k >= -1 && k <= 1 && c1[d] >= 0 && c1[d] < pc.n[d] && f1[d] >= T(0) && f1[d] < T(1);
+    }
+    if (!ok) {
+        atomicOr(err, 4);
+        return;
+    }
+    const T w = b.w ? b.w[p] : pc.w0;
+    const int gs[3] = {1, pc.n[0], pc.n[0] * pc.n[1]};
+    EskAxis<O, T> e[3];
+    T K[3];
+    int jo[3][NW + 1];
+#pragma unroll
+    for (int d = 0; d < 3; ++d) {
+        esk_axis<O>(f0[d], f1[d], kap[d], e[d]);
+        K[d] = pc.jk[d] * w;
+        axis_offsets_global<NW + 1>(c0[d], e[d].lo, pc.n[d], gs[d], jo[d]);
+    }
+    esk_scatter<O>(e, jo, K, [&](int m, int idx, T v) { gatomic_add(fp.J[m] + idx, v); });
+}
+
+// ---------------------------------------------------------------------------
+// Transpose of the particle part of one step.  The forward quantities are
+// recomputed from the state at step n with the same device functions as the
+// forward kernels, so the reverse sweep follows exactly the forward rounding.
+template <typename T, int O>
+__global__ void __launch_bounds__(256)
+    k_adjoint_particles(PConst<T> pc, PArr<T> sp, FieldPtrs<T> fp, const T *hE0, const T *hE1, const T *hE2,
+                        T *lx0, T *lx1, T *lx2, T *lu0, T *lu1, T *lu2, T *lE0, T *lE1, T *lE2, T *lB0, T *lB1,
+                        T *lB2, int *err)
+{
+    constexpr int NW = Shape<O, T>::NW;
+    const int64_t p = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (p >= sp.n)
+        return;
+    int c[3];
+    T f[3], u[3];
+    if (!load_particle(sp, p, pc.n, c, f, u, err))
+        return;
+    const int gs[3] = {1, pc.n[0], pc.n[0] * pc.n[1]};
+    AxisW<O, T> aw[3];
+    int on[3][NW], os[3][NW];
+#pragma unroll
+    for (int d = 0; d < 3; ++d) {
+        axis_weights<O>(f[d], aw[d]);
+        axis_offsets_global<NW>(c[d], aw[d].bn, pc.n[d], gs[d], on[d]);
+        axis_offsets_global<NW>(c[d], aw[d].bs, pc.n[d], gs[d], os[d]);
+    }
+    FieldSrc<T> gf;
+#pragma unroll
+    for (int m = 0; m < 3; ++m) {
+        gf.c[m] = fp.E[m];
+        gf.c[3 + m] = fp.B[m];
+    }
+    T E[3], B[3];
+    gather_eb<O>(gf, aw, on, os, E, B);
+    BorisTape<T> tp;
+    T u1[3];
+    boris(pc.h, pc.inv_c2, u, E, B, u1, tp);
+    const T ig = T(1) / sqrt(T(1) + (u1[0] * u1[0] + u1[1] * u1[1] + u1[2] * u1[2]) * pc.inv_c2);
+    T f1[3];
+    int kap[3];
+    bool ok = true;
+#pragma unroll
+    for (int d = 0; d < 3; ++d) {
+        const T disp = pc.dtd[d] * u1[d] * ig;
+        ok = ok && fabs(disp) < T(1);
+        move_axis(f[d], disp, f1[d], kap[d]);
+    }
+    if (!ok) {
+        atomicOr(err, 2);
+        return;
+    }
+    // deposit transpose: phi = <lJ, J_p>, lJ = (-dt/eps0) hatE
+    const T w = sp.w ? sp.w[p] : pc.w0;
+    EskAxis<O, T> e[3];
+    T dS0[3][NW + 1], dDS1[3][NW + 1];
+    T K[3];
+    int jo[3][NW + 1];
+#pragma unroll
+    for (int d = 0; d < 3; ++d) {
+        esk_axis<O>(f[d], f1[d], kap[d], e[d]);
+        esk_axis_deriv<O>(f[d], f1[d], kap[d], dS0[d], dDS1[d]);
+        K[d] = pc.jk[d] * w * pc.lj;
+        axis_offsets_global<NW + 1>(c[d], e[d].lo, pc.n[d], gs[d], jo[d]);
+    }
+    const T *hE[3] = {hE0, hE1, hE2};
+    T g0[3], g1[3];
+    esk_gather_adjoint<O>(e, dS0, dDS1, jo, K, [&](int m, int idx) { return hE[m][idx]; }, g0, g1);
+    T *LX[3] = {lx0, lx1, lx2}, *LU[3] = {lu0, lu1, lu2};
+    T lxa[3], lxb[3], v[3];
+    T uv = T(0);
+#pragma unroll
+    for (int d = 0; d < 3; ++d) {
+        lxb[d] = LX[d][p] + g1[d];                 // dL/dx^{n+1} incl. the deposit
+        lxa[d] = g0[d] + lxb[d];                   // x^{n+1} = x^n + disp
+        v[d] = pc.dtd[d] * lxb[d];
+        uv += u1[d] * v[d];
+    }
+    // d(u/gamma)/du = I/gamma - u u^T / (gamma^3 c^2)
+    T ub[3];
+    const T ig3 = ig * ig * ig * pc.inv_c2 * uv;
+#pragma unroll
+    for (int d = 0; d < 3; ++d)
+        ub[d] = LU[d][p] + v[d] * ig - u1[d] * ig3;
+    T u0b[3], Eb[3], Bb[3];
+    boris_adjoint(pc.h, pc.inv_c2, B, tp, ub, u0b, Eb, Bb);
+    // gather transpose: scatter S * (Eb, Bb) and add the shape gradient
+    T dn[3][NW], ds[3][NW];
+#pragma unroll
+    for (int d = 0; d < 3; ++d)
+        axis_dweights<O>(f[d], dn[d], ds[d]);
+    T *LE[3] = {lE0, lE1, lE2}, *LB[3] = {lB0, lB1, lB2};
+    // component staggering: E_x(s,n,n) E_y(n,s,n) E_z(n,n,s) B_x(n,s,s) B_y(s,n,s) B_z(s,s,n)
+    const bool stag[6][3] = {{1, 0, 0}, {0, 1, 0}, {0, 0, 1}, {0, 1, 1}, {1, 0, 1}, {1, 1, 0}};
+#pragma unroll
+    for (int comp = 0; comp < 6; ++comp) {
+        const T vb = comp < 3 ? Eb[comp] : Bb[comp - 3];
+        const T *F = gf.c[comp];
+        T *L = comp < 3 ? LE[comp] : LB[comp - 3];
+        const T *wx = stag[comp][0] ? aw[0].ws : aw[0].wn;
+        const T *wy = stag[comp][1] ? aw[1].ws : aw[1].wn;
+        const T *wz = stag[comp][2] ? aw[2].ws : aw[2].wn;
+        const T *dx = stag[comp][0] ? ds[0] : dn[0];
+        const T *dy = stag[comp][1] ? ds[1] : dn[1];
+        const T *dz = stag[comp][2] ? ds[2] : dn[2];
+        const int *xo = stag[comp][0] ? os[0] : on[0];
+        const int *yo = stag[comp][1] ? os[1] : on[1];
+        const int *zo = stag[comp][2] ? os[2] : on[2];
+        T gx = T(0), gy = T(0), gz = T(0);
+#pragma unroll
+        for (int k = 0; k < NW; ++k)
+#pragma unroll
+            for (int j = 0; j < NW; ++j) {
+                const int rowo = yo[j] + zo[k];
+                T ax = T(0), adx = T(0);
+#pragma unroll
+                for (int i = 0; i < NW; ++i) {
+                    const T val = F[rowo + xo[i]];
+                    ax += wx[i] * val;
+                    adx += dx[i] * val;
+                    gatomic_add(L + rowo + xo[i], wx[i] * wy[j] * wz[k] * vb);
+                }
+                gx += adx * wy[j] * wz[k];
+                gy += ax * dy[j] * wz[k];
+                gz += ax * wy[j] * dz[k];
+            }
+        lxa[0] += vb * gx;
+        lxa[1] += vb * gy;
+        lxa[2] += vb * gz;
+    }
+#pragma unroll
+    for (int d = 0; d < 3; ++d) {
+        LX[d][p] = lxa[d];
+        LU[d][p] = u0b[d];
+    }
+}
+
+// ---------------------------------------------------------------------------
+// launchers
+
+static inline unsigned nblk(int64_t n, int b)
+{
+    return (unsigned)((n + b - 1) / b);
+}
+
+template <typename T>
+size_t tile_lds_bytes(int, const TileGeo &tg)
+{
+    const size_t rf = (size_t)tg.rf[0] * tg.rf[1] * tg.rf[2];
+    const size_t rj = (size_t)tg.rj[0] * tg.rj[1] * tg.rj[2];
+    return (6 * rf + 3 * rj) * sizeof(T);
+}
+
+template <typename T, int O>
+static hipError_t launch_tile_o(const PConst<T> &pc, const TileGeo &tg, const PArr<T> &in, const PArr<T> &out,
+                                const FieldPtrs<T> &f, const int *tile_start, int *err, hipStream_t st)
+{
+    const size_t lds = tile_lds_bytes<T>(O, tg);
+    static bool attr_set = false;
+    if (!attr_set) {
+        // allow more than the default dynamic LDS per workgroup
+        hipFuncSetAttribute(reinterpret_cast<const void *>(&k_particles_tile<T, O>),
+                            hipFuncAttributeMaxDynamicSharedMemorySize, 160 * 1024);
+        attr_set = true;
+    }
+    const unsigned ntiles = (unsigned)(tg.nt[0] * tg.nt[1] * tg.nt[2]);
+    hipLaunchKernelGGL((k_particles_tile<T, O>), dim3(ntiles), dim3(256), lds, st, pc, tg, in, out, f, tile_start,
+                       err);
+    return hipGetLastError();
+}
+
+template <typename T>
+hipError_t launch_particles_tile(int order, const PConst<T> &pc, const TileGeo &tg, const PArr<T> &in,
+                                 const PArr<T> &out, const FieldPtrs<T> &f, const int *tile_start, int *err,
+                                 hipStream_t st)
+{
+    return order == 1 ? launch_tile_o<T, 1>(pc, tg, in, out, f, tile_start, err, st)
+                      : launch_tile_o<T, 3>(pc, tg, in, out, f, tile_start, err, st);
+}
+
+template <typename T>
+hipError_t launch_particles_global(int order, const PConst<T> &pc, const PArr<T> &sp, const FieldPtrs<T> &f,
+                                   int *err, hipStream_t st)
+{
+    if (sp.n == 0)
+        return hipSuccess;
+    if (order == 1)
+        hipLaunchKernelGGL((k_particles_global<T, 1>), dim3(nblk(sp.n, 256)), dim3(256), 0, st, pc, sp, f, err);
+    else
+        hipLaunchKernelGGL((k_particles_global<T, 3>), dim3(nblk(sp.n, 256)), dim3(256), 0, st, pc, sp, f, err);
+    return hipGetLastError();
+}
+
+template <typename T>
+hipError_t launch_gather(int order, const PConst<T> &pc, const PArr<T> &sp, const FieldPtrs<T> &f, T *const Ep[3],
+                         T *const Bp[3], int *err, hipStream_t st)
+{
+    if (sp.n == 0)
+        return hipSuccess;
+    if (order == 1)
+        hipLaunchKernelGGL((k_gather<T, 1>), dim3(nblk(sp.n, 256)), dim3(256), 0, st, pc, sp, f, Ep[0], Ep[1],
+                           Ep[2], Bp[0], Bp[1], Bp[2], err);
+    else
+        hipLaunchKernelGGL((k_gather<T, 3>), dim3(nblk(sp.n, 256)), dim3(256), 0, st, pc, sp, f, Ep[0], Ep[1],
+                           Ep[2], Bp[0], Bp[1], Bp[2], err);
+    return hipGetLastError();
+}
+
+template <typename T>
+hipError_t launch_push(const PConst<T> &pc, const PArr<T> &sp, T *const Ep[3], T *const Bp[3], int *err,
+                       hipStream_t st)
+{
+    if (sp.n == 0)
+        return hipSuccess;
+    hipLaunchKernelGGL((k_push<T>), dim3(nblk(sp.n, 256)), dim3(256), 0, st, pc, sp, Ep[0], Ep[1], Ep[2], Bp[0],
+                       Bp[1], Bp[2], err);
+    return hipGetLastError();
+}
+
+template <typename T>
+hipError_t launch_deposit(int order, const PConst<T> &pc, const PArr<T> &before, const PArr<T> &after,
+                          const FieldPtrs<T> &f, int *err, hipStream_t st)
+{
+    if (before.n == 0)
+        return hipSuccess;
+    if (order == 1)
+        hipLaunchKernelGGL((k_deposit<T, 1>), dim3(nblk(before.n, 256)), dim3(256), 0, st, pc, before, after, f,
+                           err);
+    else
+        hipLaunchKernelGGL((k_deposit<T, 3>), dim3(nblk(before.n, 256)), dim3(256), 0, st, pc, before, after, f,
+                           err);
+    return hipGetLastError();
+}
+
+template <typename T>
+hipError_t launch_adjoint_particles(int order, const PConst<T> &pc, const PArr<T> &sp, const FieldPtrs<T> &f,
+                                    T *const hatE[3], T *const lx[3], T *const lu[3], T *const lE[3],
+                                    T *const lB[3], int *err, hipStream_t st)
+{
+    if (sp.n == 0)
+        return hipSuccess;
+    if (order == 1)
+        hipLaunchKernelGGL((k_adjoint_particles<T, 1>), dim3(nblk(sp.n, 256)), dim3(256), 0, st, pc, sp, f,
+                           hatE[0], hatE[1], hatE[2], lx[0], lx[1], lx[2], lu[0], lu[1], lu[2], lE[0], lE[1],
+                           lE[2], lB[0], lB[1], lB[2], err);
+    else
+        hipLaunchKernelGGL((k_adjoint_particles<T, 3>), dim3(nblk(sp.n, 256)), dim3(256), 0, st, pc, sp, f,
+                           hatE[0], hatE[1], hatE[2], lx[0], lx[1], lx[2], lu[0], lu[1], lu[2], lE[0], lE[1],
+                           lE[2], lB[0], lB[1], lB[2], err);
+    return hipGetLastError();
+}
+
+#define PIC_INST(T)                                                                                               \
+    template size_t tile_lds_bytes<T>(int, const TileGeo &);                                                       \
+    template hipError_t launch_particles_tile<T>(int, const PConst<T> &, const TileGeo &, const PArr<T> &,         \
+                                                 const PArr<T> &, const FieldPtrs<T> &, const int *, int *,        \
+                                                 hipStream_t);                                                     \
+    template hipError_t launch_particles_global<T>(int, const PConst<T> &, const PArr<T> &, const FieldPtrs<T> &,  \
+                                                   int *, hipStream_t);                                            \
+    template hipError_t launch_gather<T>(int, const PConst<T> &, const PArr<T> &, const FieldPtrs<T> &,            \
+                                         T *const[3], T *const[3], int *, hipStream_t);                            \
+    template hipError_t launch_push<T>(const PConst<T> &, const PArr<T> &, T *const[3], T *const[3], int *,        \
+                                       hipStream_t);                                                               \
+    template hipError_t launch_deposit<T>(int, const PConst<T> &, const PArr<T> &, const PArr<T> &,                \
+                                          const FieldPtrs<T> &, int *, hipStream_t);                               \
+    template hipError_t launch_adjoint_particles<T>(int, const PConst<T> &, const PArr<T> &, const FieldPtrs<T> &, \
+                                                    T *const[3], T *const[3], T *const[3], T *const[3],            \
+                                                    T *const[3], int *, hipStream_t);
+
+PIC_INST(float)
+PIC_INST(double)
+
+}  // namespace pic

@@ -1,0 +1,120 @@
+// Kernel-argument structs and launcher declarations shared by the HIP
+// translation units of the library (host and device side).
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stddef.h>
+#include <stdint.h>
+
+namespace pic {
+
+// Per-step constants of the particle update, in the working precision T.
+template <typename T>
+struct PConst {
+    int n[3];
+    T dtd[3];      // dt / d_d: displacement in cells per unit velocity
+    T h;           // q dt / (2 m)
+    T inv_c2;      // 1 / c^2
+    T jk[3];       // -q / (dt d_p d_q): Esirkepov prefactor per unit weight
+    T w0;          // weight when the species has no weight array
+    T lj;          // -dt / eps0: current adjoint from the field adjoint
+};
+
+// Structure-of-arrays particle storage.
+template <typename T>
+struct PArr {
+    int *cell[3];
+    T *off[3];
+    T *u[3];
+    T *w;          // may be null
+    int64_t n;
+};
+
+template <typename T>
+struct FieldPtrs {
+    T *E[3], *B[3], *J[3];
+};
+
+// Tile decomposition of the grid and the LDS regions of one tile: fields
+// with the gather halo (lo_f cells below, extent rf) and current with the
+// deposit halo (lo_j, rj).  `slack` extra cells on each side keep particles
+// that drifted since the last sort on the LDS path.
+struct TileGeo {
+    int t[3];      // tile size in cells
+    int nt[3];     // tiles per direction
+    int slack;
+    int lo_f, rf[3];
+    int lo_j, rj[3];
+    int xcd_map;   // spread consecutive tiles so each XCD gets a contiguous block
+};
+
+// Arguments of the curl-update kernel:
+//   out = in + (cx,cy,cz)-weighted curl(src)  [forward or backward differences]
+//         + jc * J                       (J may be null; zero_j clears J)
+//   out_x[kplane] += amp * ag            (plane source, amp may be null)
+//   dA[i + n0 j] += dag * out_x[kplane]  (source adjoint, dA may be null)
+template <typename T>
+struct CurlArgs {
+    T *out[3];
+    const T *in[3];
+    const T *src[3];
+    T cx, cy, cz;
+    T *J[3];
+    T jc;
+    int zero_j;
+    const T *amp;
+    T ag;
+    int kplane;
+    double *dA;
+    double dag;
+    int n[3];
+};
+
+// ---------------------------------------------------------------------------
+// launchers (return hipSuccess or the launch error)
+
+template <typename T>
+hipError_t launch_particles_tile(int order, const PConst<T> &pc, const TileGeo &tg, const PArr<T> &in,
+                                 const PArr<T> &out, const FieldPtrs<T> &f, const int *tile_start, int *err,
+                                 hipStream_t st);
+template <typename T>
+hipError_t launch_particles_global(int order, const PConst<T> &pc, const PArr<T> &sp, const FieldPtrs<T> &f,
+                                   int *err, hipStream_t st);
+template <typename T>
+hipError_t launch_gather(int order, const PConst<T> &pc, const PArr<T> &sp, const FieldPtrs<T> &f, T *const Ep[3],
+                         T *const Bp[3], int *err, hipStream_t st);
+template <typename T>
+hipError_t launch_push(const PConst<T> &pc, const PArr<T> &sp, T *const Ep[3], T *const Bp[3], int *err,
+                       hipStream_t st);
+template <typename T>
+hipError_t launch_deposit(int order, const PConst<T> &pc, const PArr<T> &before, const PArr<T> &after,
+                          const FieldPtrs<T> &f, int *err, hipStream_t st);
+template <typename T>
+hipError_t launch_adjoint_particles(int order, const PConst<T> &pc, const PArr<T> &sp, const FieldPtrs<T> &f,
+                                    T *const hatE[3], T *const lx[3], T *const lu[3], T *const lE[3],
+                                    T *const lB[3], int *err, hipStream_t st);
+template <typename T>
+size_t tile_lds_bytes(int order, const TileGeo &tg);
+
+template <typename T>
+hipError_t launch_curl(bool forward, const CurlArgs<T> &a, hipStream_t st);
+template <typename T>
+hipError_t launch_fill(T *p, int64_t n, T v, hipStream_t st);
+template <typename T>
+hipError_t launch_bin_count(const PArr<T> &sp, const TileGeo &tg, int *counts, int *key, int *rank, int *err,
+                            hipStream_t st);
+template <typename T>
+hipError_t launch_scatter(const PArr<T> &in, const PArr<T> &out, const int *key, const int *rank,
+                          const int *offsets, int *perm, hipStream_t st);
+hipError_t launch_scan(int *data, int64_t n, int *block_sums, hipStream_t st);
+hipError_t launch_tile_start(const int *offsets, int tile_cells, int ntiles, int64_t nparticles, int *tile_start,
+                             hipStream_t st);
+template <typename T>
+hipError_t launch_reduce(const PArr<T> *sp, const FieldPtrs<T> &f, int64_t ncell, double *partials,
+                         int max_blocks, const double scale[7], double *out, hipStream_t st);
+
+// blocks used by the scan for n elements, and by the reduction
+int64_t scan_blocks(int64_t n);
+int reduce_max_blocks();
+
+}  // namespace pic

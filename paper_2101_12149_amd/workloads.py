@@ -32,7 +32,7 @@ class Grid:
     c: float = 1.0
     eps0: float = 1.0
     order: int = 3      # shape-function order: 1 or 3
-    tile: tuple = (8, 8, 8)
+    tile: tuple = (0, 0, 0)   # sort/LDS tile edge per direction (0: library default)
     slack: int = -1     # halo slack of the tiled particle kernel (-1: automatic)
 
     @property
@@ -186,7 +186,7 @@ def draw_species(cell, u_th, w0, seed, dtype=torch.float64, device="cpu", w=None
                    None if w is None else w.to(dtype).contiguous(), float(w0), q, m)
 
 
-def plasma_grid(n, order, omega_p_dt=0.1, cfl=0.99, tile=(8, 8, 8)) -> Grid:
+def plasma_grid(n, order, omega_p_dt=0.1, cfl=0.99, tile=(0, 0, 0)) -> Grid:
     """Cubic cells sized so that dt sits at `cfl` of the 3D Yee limit."""
     dt = float(omega_p_dt)
     dx = math.sqrt(3.0) * dt / cfl
@@ -197,7 +197,7 @@ def plasma_grid(n, order, omega_p_dt=0.1, cfl=0.99, tile=(8, 8, 8)) -> Grid:
 # named workloads
 
 def uniform_plasma(n=(32, 32, 32), ppc=8, u_th=0.01, order=1, nsteps=10, dtype="f64", seed=1001,
-                   sort_every=4, device="cpu", shuffle=False, name=None, tile=(8, 8, 8)) -> Workload:
+                   sort_every=4, device="cpu", shuffle=False, name=None, tile=(0, 0, 0)) -> Workload:
     """Periodic uniform electron plasma (n0 = 1) over an immobile ion background."""
     grid = plasma_grid(n, order, tile=tile)
     tdt = torch.float64 if dtype == "f64" else torch.float32
@@ -213,7 +213,7 @@ def uniform_plasma(n=(32, 32, 32), ppc=8, u_th=0.01, order=1, nsteps=10, dtype="
 
 def laser_plasma(n=(128, 128, 1024), ppc=2, order=3, nsteps=500, dtype="f32", seed=1003, sort_every=4,
                  device="cpu", a0=2.0, waist_lambda=20.0, fwhm_periods=10.0, n0=0.01, ramp=(32, 132),
-                 k_source=2, cells_per_lambda=16, width_lambda=80.0, name=None, tile=(8, 8, 8)) -> Workload:
+                 k_source=2, cells_per_lambda=16, width_lambda=80.0, name=None, tile=(0, 0, 0)) -> Workload:
     """Laser wakefield stage: x-polarised Gaussian pulse from a soft source near
     z-min into a plasma with a linear up-ramp; cold electrons, immobile ions.
     omega_L = 1, lambda = 2 pi, n_crit = 1."""
@@ -254,7 +254,7 @@ def laser_plasma(n=(128, 128, 1024), ppc=2, order=3, nsteps=500, dtype="f32", se
 
 
 def differentiable(n=(64, 64, 64), ppc=4, u_th=0.05, order=3, nsteps=20, dtype="f64", seed=1004,
-                   checkpoint_every=5, amp0=1e-3, period=16, device="cpu", name=None, tile=(8, 8, 8)) -> Workload:
+                   checkpoint_every=5, amp0=1e-3, period=16, device="cpu", name=None, tile=(0, 0, 0)) -> Workload:
     """Periodic plasma with a transverse E_x amplitude map on the plane k = 0,
     driven as sin(2 pi n / period); the loss is the final field energy."""
     grid = plasma_grid(n, order, tile=tile)

@@ -1,0 +1,108 @@
+"""Host-side checks of the C ABI (no GPU needed): the library loads, exports
+every symbol include/pic.h declares, and rejects bad arguments before any
+launch with the documented status."""
+import ctypes as C
+import os
+import re
+
+import pytest
+
+from paper_2101_12149_amd import _lib
+from paper_2101_12149_amd import workloads as wl
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+
+
+def _declared():
+    text = open(os.path.join(ROOT, "include", "pic.h")).read()
+    return re.findall(r"PIC_API\s+[\w\s\*]+?\b(pic_\w+)\s*\(", text)
+
+
+def test_header_declares_the_entry_points():
+    names = set(_declared())
+    for n in ("pic_sort_tiles", "pic_gather", "pic_push", "pic_deposit", "pic_yee", "pic_step",
+              "pic_step_adjoint", "pic_reduce", "pic_workspace_bytes", "pic_last_error", "pic_tile_count"):
+        assert n in names
+    assert names == set(_lib.EXPORTS)
+
+
+def test_library_exports_every_declared_symbol():
+    lib = _lib.load()
+    for n in _declared():
+        assert hasattr(lib, n), n
+
+
+def _grid(**kw):
+    g = wl.plasma_grid((16, 16, 16), 3)
+    for k, v in kw.items():
+        setattr(g, k, v)
+    return g
+
+
+def test_workspace_bytes_grows_with_particles_and_rejects_bad_grids():
+    g = _grid()
+    a = _lib.pic_workspace_bytes(g, "f64", 0)
+    b = _lib.pic_workspace_bytes(g, "f64", 1000)
+    c = _lib.pic_workspace_bytes(g, "f32", 1000)
+    assert a > 0 and b > a and c < b
+    assert _lib.pic_workspace_bytes(_grid(order=2), "f64", 10) == 0
+    assert _lib.pic_workspace_bytes(_grid(n=(3, 16, 16)), "f64", 10) == 0
+    assert _lib.pic_tile_count(_grid(tile=(8, 8, 8)), "f64") in (8, 16, 32, 64)
+
+
+def _raw_call_step(grid, dtype="f64"):
+    lib = _lib.load()
+    g = _lib.make_grid(grid, dtype)
+    sp = _lib.pic_species()
+    sp.n = 0
+    sp.m, sp.q = 1.0, -1.0
+    f = _lib.pic_fields()
+    for m in range(3):
+        f.E[m] = f.B[m] = f.J[m] = 0x1000      # never dereferenced: validation fails first
+    src = _lib.pic_source()
+    src.k_plane = -1
+    st = lib.pic_step(C.byref(g), C.byref(sp), C.byref(f), C.byref(src), 0, 1, 0, None, None, 0, None, None)
+    return st, lib.pic_last_error().decode()
+
+
+def test_cfl_violation_is_rejected():
+    g = _grid()
+    g.dt = g.d[0] / (3 ** 0.5) * 1.01
+    st, msg = _raw_call_step(g)
+    assert st == 2 and "CFL" in msg
+
+
+def test_unsupported_order_and_dtype():
+    st, _ = _raw_call_step(_grid(order=2))
+    assert st == 3
+    lib = _lib.load()
+    g = _lib.make_grid(_grid(), "f64")
+    g.dtype = 7
+    assert lib.pic_workspace_bytes(C.byref(g), 10) == 0
+
+
+def test_missing_workspace_and_null_pointers():
+    st, msg = _raw_call_step(_grid())
+    assert st == 4 and "workspace" in msg
+    lib = _lib.load()
+    g = _lib.make_grid(_grid(), "f64")
+    assert lib.pic_step(C.byref(g), None, None, None, 0, 1, 0, None, None, 0, None, None) == 1
+    sp = _lib.pic_species()
+    sp.n = 5
+    sp.m = 1.0
+    assert lib.pic_gather(C.byref(g), C.byref(sp), None, (C.c_void_p * 3)(), (C.c_void_p * 3)(), None) == 1
+    assert "NULL" in lib.pic_last_error().decode()
+
+
+def test_bad_tile_and_negative_steps():
+    st, msg = _raw_call_step(_grid(tile=(5, 8, 8)))
+    assert st == 1 and "tile" in msg
+    lib = _lib.load()
+    g = _lib.make_grid(_grid(), "f64")
+    sp = _lib.pic_species()
+    sp.m = 1.0
+    f = _lib.pic_fields()
+    for m in range(3):
+        f.E[m] = f.B[m] = f.J[m] = 0x1000
+    assert lib.pic_step(C.byref(g), C.byref(sp), C.byref(f), None, 0, -1, 0, None, None, 0, None, None) == 1
+    assert lib.pic_step(C.byref(g), C.byref(sp), C.byref(f), None, 0, 1, 4, None, None, 0, None, None) == 1

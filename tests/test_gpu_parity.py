@@ -1,0 +1,342 @@
+"""Parity of the HIP path (through the C ABI) with the FP64 oracle.
+
+FP64: results within 1e-12 relative (rel-L2 over the compared array, or max
+error over the array's scale).  FP32 split precision: rel-L2 of E, B, J
+<= 1e-5 after one step and a charge-conservation residual <= 1e-6, the oracle
+starting from the FP32 state upcast exactly to FP64.  Sizes span several
+tiles with a ragged last tile where the grid allows it.
+"""
+import numpy as np
+import pytest
+import torch
+
+import oracle
+from paper_2101_12149_amd import _lib
+from paper_2101_12149_amd import workloads as wl
+from pic_cases import (NS, dev, max_rel, particle_table, random_fields, random_species, rel_l2, tdtype)
+
+pytestmark = pytest.mark.gpu
+
+F64_TOL = 1e-12
+
+
+def _grid(n=(12, 16, 20), order=3):
+    return wl.plasma_grid(n, order)
+
+
+def _cpu(t):
+    return t.detach().cpu().to(torch.float64).numpy()
+
+
+# ---------------------------------------------------------------------------
+# separate operations
+
+@pytest.mark.parametrize("order", [1, 3])
+@pytest.mark.parametrize("dtype", ["f64", "f32"])
+def test_gather_matches_oracle(order, dtype):
+    g = _grid(order=order)
+    sp = random_species(g, 5000, 11, dtype=dtype)
+    f = random_fields(g, 12, dtype=dtype)
+    Ep, Bp = _lib.pic_gather(g, dev(sp), dev(f))
+    torch.cuda.synchronize()
+    oE, oB = oracle.gather(g, sp.numpy(), f.numpy())
+    tol = F64_TOL if dtype == "f64" else 2e-6
+    assert max_rel(_cpu(Ep), oE) < tol
+    assert max_rel(_cpu(Bp), oB) < tol
+
+
+@pytest.mark.parametrize("dtype", ["f64", "f32"])
+def test_push_matches_oracle(dtype):
+    g = _grid()
+    sp = random_species(g, 5000, 21, u_th=0.3, dtype=dtype)
+    rng = np.random.default_rng(22)
+    Ep = torch.tensor(rng.normal(0, 2.0, (3, 5000)), dtype=tdtype(dtype))
+    Bp = torch.tensor(rng.normal(0, 5.0, (3, 5000)), dtype=tdtype(dtype))
+    d_sp = dev(sp)
+    _lib.pic_push(g, d_sp, dev(Ep), dev(Bp))
+    torch.cuda.synchronize()
+    o = sp.numpy()
+    oracle.push(g, o, np.ascontiguousarray(_cpu(Ep)), np.ascontiguousarray(_cpu(Bp)))
+    tol = F64_TOL if dtype == "f64" else 2e-6
+    assert max_rel(_cpu(d_sp.u), o.u) < tol
+    # positions: compare unwrapped (cell + offset) differences
+    gx = d_sp.cell.cpu().numpy() + _cpu(d_sp.off)
+    ox = o.cell + o.off
+    dxy = np.abs(gx - ox)
+    dxy = np.minimum(dxy, np.abs(dxy - np.array(g.n)[:, None]))
+    assert dxy.max() < (1e-13 if dtype == "f64" else 2e-6)
+
+
+def _displaced(g, sp, seed, amp=0.9):
+    """Copy of sp moved by a random displacement below one cell."""
+    rng = np.random.default_rng(seed)
+    o = sp.numpy()
+    xi = o.off + rng.uniform(-amp, amp, o.off.shape)
+    k = np.floor(xi)
+    off = xi - k
+    off = np.where(off >= 1, 0.0, off)
+    cell = (o.cell + k.astype(np.int32)) % np.array(g.n, dtype=np.int32)[:, None]
+    after = wl.Species(torch.tensor(cell.astype(np.int32)), torch.tensor(off), sp.u.to(torch.float64),
+                       None if sp.w is None else sp.w.to(torch.float64), sp.w0, sp.q, sp.m)
+    return after.to(dtype=sp.off.dtype)
+
+
+@pytest.mark.parametrize("order", [1, 3])
+@pytest.mark.parametrize("dtype", ["f64", "f32"])
+def test_deposit_matches_oracle_and_conserves_charge(order, dtype):
+    g = _grid(order=order)
+    before = random_species(g, 4000, 31, dtype=dtype)
+    after = _displaced(g, before, 32)
+    f = random_fields(g, 33, dtype=dtype)
+    f.J.zero_()
+    df = dev(f)
+    _lib.pic_deposit(g, dev(before), dev(after), df)
+    torch.cuda.synchronize()
+    of = f.numpy()
+    ob, oa = before.numpy(), after.numpy()
+    oracle.deposit(g, ob, oa, of)
+    J = _cpu(df.J)
+    assert rel_l2(J, of.J) < (F64_TOL if dtype == "f64" else 1e-5)
+    # continuity with an FP64 charge density of the same positions
+    rho0, rho1 = oracle.rho(g, ob), oracle.rho(g, oa)
+    drho = (rho1 - rho0) / g.dt
+    divJ = sum((J[m] - np.roll(J[m], 1, axis=2 - m)) / g.d[m] for m in range(3))
+    assert np.linalg.norm(drho + divJ) / np.linalg.norm(drho) < (1e-13 if dtype == "f64" else 1e-6)
+
+
+@pytest.mark.parametrize("dtype", ["f64", "f32"])
+def test_yee_matches_oracle_with_source(dtype):
+    g = _grid((16, 12, 20))
+    f = random_fields(g, 41, dtype=dtype, with_j=True)
+    amp = torch.randn((12, 16), dtype=torch.float64, generator=torch.Generator().manual_seed(42))
+    src = wl.Source(5, amp.to(tdtype(dtype)), np.array([0.3, -1.2, 0.7]))
+    df = dev(f)
+    for step in range(3):
+        _lib.pic_yee(g, df, src.to(device="cuda"), step)
+    torch.cuda.synchronize()
+    of = f.numpy()
+    osrc = src.numpy()
+    for step in range(3):
+        oracle.yee(g, of, osrc, step)
+    tol = F64_TOL if dtype == "f64" else 1e-5
+    assert rel_l2(_cpu(df.E), of.E) < tol
+    assert rel_l2(_cpu(df.B), of.B) < tol
+    assert np.array_equal(_cpu(df.J), of.J)   # J is read-only in pic_yee
+
+
+@pytest.mark.parametrize("dtype", ["f64", "f32"])
+def test_reduce_matches_oracle(dtype):
+    g = _grid()
+    sp = random_species(g, 7000, 51, u_th=0.4, dtype=dtype)
+    f = random_fields(g, 52, dtype=dtype)
+    ws = _lib.workspace(g, dtype, sp.n)
+    out = _lib.pic_reduce(g, dev(sp), dev(f), ws)
+    torch.cuda.synchronize()
+    want = oracle.reduce(g, sp.numpy(), f.numpy())
+    np.testing.assert_allclose(out.cpu().numpy(), want, rtol=1e-13, atol=0)
+
+
+# ---------------------------------------------------------------------------
+# sort
+
+def test_sort_tiles_is_a_binning_permutation():
+    g = wl.plasma_grid((16, 24, 8), 3)
+    sp = random_species(g, 20000, 61, dtype="f32")
+    d = dev(sp)
+    nt = _lib.pic_tile_count(g, "f32")
+    ts = torch.empty(nt + 1, dtype=torch.int32, device="cuda")
+    perm = torch.empty(sp.n, dtype=torch.int32, device="cuda")
+    ws = _lib.workspace(g, "f32", sp.n)
+    _lib.pic_sort_tiles(g, d, ts, ws, perm=perm)
+    torch.cuda.synchronize()
+    p = perm.cpu().numpy().astype(np.int64)
+    assert np.array_equal(np.sort(p), np.arange(sp.n))
+    # data moved with the permutation
+    assert torch.equal(d.cell.cpu(), sp.cell[:, p])
+    assert torch.equal(d.off.cpu(), sp.off[:, p])
+    assert torch.equal(d.u.cpu(), sp.u[:, p])
+    assert torch.equal(d.w.cpu(), sp.w[p])
+    # tile-major cell keys are non-decreasing; tile_start is the histogram prefix
+    tx, ty, tz = 8, 8, 8
+    c = d.cell.cpu().numpy().astype(np.int64)
+    tile = (c[0] // tx) + (g.n[0] // tx) * ((c[1] // ty) + (g.n[1] // ty) * (c[2] // tz))
+    local = (c[0] % tx) + tx * ((c[1] % ty) + ty * (c[2] % tz))
+    key = tile * (tx * ty * tz) + local
+    assert np.all(np.diff(key) >= 0)
+    hist = np.bincount(tile, minlength=nt)
+    assert nt == (g.n[0] // tx) * (g.n[1] // ty) * (g.n[2] // tz)
+    want = np.concatenate([[0], np.cumsum(hist)])
+    assert np.array_equal(ts.cpu().numpy(), want)
+
+
+def test_sort_rejects_corrupt_state_without_touching_it():
+    g = wl.plasma_grid((16, 16, 16), 3)
+    sp = random_species(g, 1000, 62, dtype="f64")
+    sp.off[1, 17] = 1.0            # an offset outside [0,1)
+    d = dev(sp)
+    ts = torch.empty(_lib.pic_tile_count(g, "f64") + 1, dtype=torch.int32, device="cuda")
+    ws = _lib.workspace(g, "f64", sp.n)
+    with pytest.raises(_lib.PicError) as ei:
+        _lib.pic_sort_tiles(g, d, ts, ws)
+    assert ei.value.name == "PIC_E_STATE"
+    assert torch.equal(d.off.cpu(), sp.off)
+
+
+# ---------------------------------------------------------------------------
+# full steps
+
+def _run_gpu_steps(w, nsteps, sort_every, tiled=True, tile_start=None, diag=False):
+    g = w.grid
+    sp, f = dev(w.species), dev(w.fields)
+    src = w.source.to(device="cuda") if w.source is not None else None
+    ws = _lib.workspace(g, w.dtype, sp.n)
+    ts = None
+    if tiled:
+        ts = tile_start if tile_start is not None else torch.zeros(_lib.pic_tile_count(g, w.dtype) + 1,
+                                                                   dtype=torch.int32, device="cuda")
+    dg = torch.zeros((nsteps, 5), dtype=torch.float64, device="cuda") if diag else None
+    _lib.pic_step(g, sp, f, src, 0, nsteps, sort_every, ts, ws, dg)
+    torch.cuda.synchronize()
+    return sp, f, dg
+
+
+def _run_oracle(w, nsteps):
+    sp, f = w.species.numpy(), w.fields.numpy()
+    src = w.source.numpy() if w.source is not None else None
+    diag = oracle.step(w.grid, sp, f, src, 0, nsteps)
+    return sp, f, diag
+
+
+def test_uniform32_order1_f64_ten_steps_matches_oracle():
+    """32^3 periodic uniform plasma, 8 ppc, u_th = 0.01c, CIC, FP64, 10 steps,
+    sorted every 4 steps: fields and the particle set within 1e-12."""
+    w = wl.named("uniform32_o1_f64")
+    gsp, gf, gdiag = _run_gpu_steps(w, w.nsteps, w.sort_every, diag=True)
+    osp, of, odiag = _run_oracle(w, w.nsteps)
+    for name in ("E", "B", "J"):
+        assert rel_l2(_cpu(getattr(gf, name)), getattr(of, name)) < F64_TOL, name
+    gt, ot = particle_table(gsp), particle_table(osp)
+    assert np.array_equal(gt[:, :3], ot[:, :3])
+    assert rel_l2(gt[:, 3:6], ot[:, 3:6]) < F64_TOL
+    assert rel_l2(gt[:, 6:], ot[:, 6:]) < F64_TOL
+    np.testing.assert_allclose(gdiag.cpu().numpy(), odiag, rtol=1e-10)
+
+
+@pytest.mark.parametrize("sort_every", [1, 3])
+def test_order3_tiled_f64_matches_oracle(sort_every):
+    """Order 3 with a random initial field: tiles of 8 with a ragged grid
+    (24 = 3 tiles, 20 -> tile 5), several sorts, LDS and fallback paths."""
+    w = wl.uniform_plasma((16, 24, 20), 3, 0.1, 3, 6, "f64", 71, sort_every, shuffle=True)
+    f0 = random_fields(w.grid, 72, scale=0.05)
+    w.fields = f0
+    gsp, gf, _ = _run_gpu_steps(w, w.nsteps, sort_every)
+    osp, of, _ = _run_oracle(w, w.nsteps)
+    for name in ("E", "B", "J"):
+        assert rel_l2(_cpu(getattr(gf, name)), getattr(of, name)) < F64_TOL, name
+    gt, ot = particle_table(gsp), particle_table(osp)
+    assert np.array_equal(gt[:, :3], ot[:, :3])
+    assert rel_l2(gt[:, 3:], ot[:, 3:]) < F64_TOL
+
+
+def test_untiled_step_matches_oracle_particle_by_particle():
+    w = wl.uniform_plasma((16, 16, 16), 2, 0.1, 3, 4, "f64", 73, 0, shuffle=True)
+    w.fields = random_fields(w.grid, 74, scale=0.05)
+    gsp, gf, _ = _run_gpu_steps(w, w.nsteps, 0, tiled=False)
+    osp, of, _ = _run_oracle(w, w.nsteps)
+    assert np.array_equal(gsp.cell.cpu().numpy(), osp.cell)
+    assert max_rel(_cpu(gsp.off), osp.off) < 1e-13
+    assert max_rel(_cpu(gsp.u), osp.u) < F64_TOL
+    for name in ("E", "B", "J"):
+        assert rel_l2(_cpu(getattr(gf, name)), getattr(of, name)) < F64_TOL, name
+
+
+def test_stale_binning_uses_the_fallback_path_correctly():
+    """Sort once, then step many times without re-sorting at a high thermal
+    speed: particles leave their tile's LDS region and take the global path."""
+    w = wl.uniform_plasma((16, 16, 16), 2, 0.3, 3, 8, "f64", 75, 0, shuffle=True)
+    g = w.grid
+    sp = dev(w.species)
+    ts = torch.zeros(_lib.pic_tile_count(g, "f64") + 1, dtype=torch.int32, device="cuda")
+    ws = _lib.workspace(g, "f64", sp.n)
+    _lib.pic_sort_tiles(g, sp, ts, ws)
+    torch.cuda.synchronize()
+    w2 = wl.Workload(w.name, g, wl.Species(sp.cell.cpu(), sp.off.cpu(), sp.u.cpu(), None, sp.w0, sp.q, sp.m),
+                     w.fields, None, 8, 0, "f64", 75)
+    gsp, gf, _ = _run_gpu_steps(w2, 8, 0, tiled=True, tile_start=ts)
+    osp, of, _ = _run_oracle(w2, 8)
+    assert np.array_equal(gsp.cell.cpu().numpy(), osp.cell)
+    assert max_rel(_cpu(gsp.u), osp.u) < F64_TOL
+    for name in ("E", "B", "J"):
+        assert rel_l2(_cpu(getattr(gf, name)), getattr(of, name)) < F64_TOL, name
+
+
+def test_f32_split_precision_one_step_bounds():
+    """FP32 fields/momenta with int32 cell + FP32 offset: rel-L2 of E, B, J
+    <= 1e-5 after one step against the oracle started from the same FP32
+    state, and charge-conservation residual <= 1e-6 with rho in FP64."""
+    w = wl.uniform_plasma((32, 32, 32), 8, 0.05, 3, 1, "f32", 81, 1)
+    w.fields = random_fields(w.grid, 82, scale=0.02, dtype="f32")
+    before = w.species.numpy()
+    gsp, gf, _ = _run_gpu_steps(w, 1, 1)
+    osp, of, _ = _run_oracle(w, 1)
+    for name in ("E", "B", "J"):
+        r = rel_l2(_cpu(getattr(gf, name)), getattr(of, name))
+        assert r < 1e-5, (name, r)
+    g = w.grid
+    after = gsp.numpy()
+    rho0, rho1 = oracle.rho(g, before), oracle.rho(g, after)
+    drho = (rho1 - rho0) / g.dt
+    J = _cpu(gf.J)
+    divJ = sum((J[m] - np.roll(J[m], 1, axis=2 - m)) / g.d[m] for m in range(3))
+    res = np.linalg.norm(drho + divJ) / np.linalg.norm(drho)
+    assert res < 1e-6, res
+
+
+def test_laser_plasma_reduced_with_empty_tiles_and_source():
+    """Laser workload shape at reduced size: vacuum tiles without particles,
+    a density up-ramp with per-particle weights, the soft source."""
+    w = wl.laser_plasma((16, 16, 96), 2, 3, 40, "f64", 91, 4, ramp=(32, 60), k_source=2, cells_per_lambda=16,
+                        width_lambda=4.0)
+    gsp, gf, _ = _run_gpu_steps(w, w.nsteps, w.sort_every)
+    osp, of, _ = _run_oracle(w, w.nsteps)
+    for name in ("E", "B", "J"):
+        assert rel_l2(_cpu(getattr(gf, name)), getattr(of, name)) < F64_TOL, name
+    gt, ot = particle_table(gsp), particle_table(osp)
+    assert np.array_equal(gt[:, :3], ot[:, :3])
+    assert rel_l2(gt[:, 3:], ot[:, 3:]) < F64_TOL
+
+
+def test_zero_particles_and_edge_offsets():
+    g = wl.plasma_grid((8, 8, 8), 3)
+    # no particles: the step is a pure field solve
+    empty = wl.Species(torch.zeros((3, 0), dtype=torch.int32), torch.zeros((3, 0)), torch.zeros((3, 0)), None,
+                       1.0)
+    f = random_fields(g, 92)
+    w = wl.Workload("empty", g, empty, f, None, 2, 1, "f64", 0)
+    _, gf, _ = _run_gpu_steps(w, 2, 1)
+    _, of, _ = _run_oracle(w, 2)
+    assert rel_l2(_cpu(gf.E), of.E) < F64_TOL
+    # offsets at 0 and just below 1, crossing the periodic seam
+    n = 6
+    cell = torch.tensor([[0, 7, 7, 0, 3, 7], [0, 7, 0, 7, 3, 7], [7, 0, 7, 0, 3, 7]], dtype=torch.int32)
+    one_m = float(np.nextafter(1.0, 0.0))
+    off = torch.tensor([[0.0, one_m, one_m, 0.0, 0.5, one_m]] * 3, dtype=torch.float64)
+    u = torch.tensor([[-0.5, 0.5, 0.5, -0.5, 0.0, 0.9], [0.4, 0.3, -0.4, 0.2, 0.0, 0.1],
+                      [0.1, -0.2, 0.3, -0.6, 0.0, 0.2]], dtype=torch.float64)
+    sp = wl.Species(cell, off, u, None, 0.3)
+    w = wl.Workload("edges", g, sp, random_fields(g, 93), None, 3, 1, "f64", 0)
+    gsp, gf, _ = _run_gpu_steps(w, 3, 1)
+    osp, of, _ = _run_oracle(w, 3)
+    for name in ("E", "B", "J"):
+        assert rel_l2(_cpu(getattr(gf, name)), getattr(of, name)) < F64_TOL, name
+    gt, ot = particle_table(gsp), particle_table(osp)
+    assert np.array_equal(gt[:, :3], ot[:, :3])
+    assert np.abs(gt[:, 3:] - ot[:, 3:]).max() < 1e-13
+
+
+def test_corrupt_momentum_reports_state_error():
+    w = wl.uniform_plasma((8, 8, 8), 1, 0.05, 3, 1, "f64", 94, 1)
+    w.species.u[0, 5] = float("nan")
+    with pytest.raises(_lib.PicError) as ei:
+        _run_gpu_steps(w, 1, 1)
+    assert ei.value.name == "PIC_E_STATE"
