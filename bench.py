@@ -1,0 +1,211 @@
+"""Throughput benchmark of the EM-PIC step on one MI355X.
+
+One step = sort (every 4 steps, amortised) + fused gather/Boris/position/
+Esirkepov tile kernel + Yee update + FP64 reductions, over a 256^3 periodic
+uniform plasma with 8 particles per cell (134,217,728 particles), order-3
+shapes, u_th = 0.05c, in split precision (int32 cell + FP32 offset, FP32
+fields and momenta).  Companion measurements on the same GPU: the same
+workload in FP64, and one adjoint step against one forward step.  Inputs are
+seeded synthetic particles drawn on the device; nothing is read from disk.
+
+Prints one JSON line.  Kernel times come from HIP events the library records
+on the launch stream (pic_timing); the CPU baseline is the FP64 oracle timed
+on a bounded sample on the host cores.
+"""
+import argparse
+import json
+import math
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+if ROOT not in sys.path:
+    sys.path.insert(0, ROOT)
+
+METRIC = "particle-steps/s (gather+push+deposit+Yee), FP32 vs FP64, fwd vs adjoint"
+HBM_PEAK_GBS = 8000.0
+
+
+def log(*a):
+    print(*a, file=sys.stderr, flush=True)
+
+
+def particle_bytes(n, tsize, has_w):
+    # state read + written once: 3 int32 cells, 3 offsets, 3 momenta (+ weight read)
+    return n * (2 * (3 * 4 + 6 * tsize) + (tsize if has_w else 0))
+
+
+def field_bytes(ncell, tsize):
+    # E, B read once and J read+written once per cell
+    return ncell * (6 * tsize + 6 * tsize)
+
+
+def run_forward(w, steps, warmup, sort_every, label):
+    import torch
+    from paper_2101_12149_amd import _lib
+    g = w.grid
+    sp, f = w.species, w.fields
+    dtype = w.dtype
+    ws = _lib.workspace(g, dtype, sp.n)
+    ts = torch.zeros(_lib.pic_tile_count(g, dtype) + 1, dtype=torch.int32, device="cuda")
+    diag = torch.zeros((max(steps, warmup, 1), 5), dtype=torch.float64, device="cuda")
+    log(f"[{label}] warmup {warmup} steps, {sp.n} particles")
+    _lib.pic_step(g, sp, f, None, 0, warmup, sort_every, ts, ws, diag[:max(warmup, 1)])
+    torch.cuda.synchronize()
+    _lib.pic_timing(True)
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    e0.record()
+    _lib.pic_step(g, sp, f, None, warmup, steps, sort_every, ts, ws, diag[:steps])
+    e1.record()
+    torch.cuda.synchronize()
+    wall = time.perf_counter() - t0
+    kt = _lib.pic_timing(False)
+    ev_ms = e0.elapsed_time(e1)
+    log(f"[{label}] {steps} steps: {ev_ms:.2f} ms (events), {wall * 1e3:.2f} ms (wall)")
+    return dict(ms=ev_ms, wall_ms=wall * 1e3, kernels=kt, diag=diag[:steps].cpu().numpy(), ws=ws, ts=ts)
+
+
+def run_adjoint(w, nrep):
+    import torch
+    from paper_2101_12149_amd import _lib
+    g = w.grid
+    sp, f = w.species, w.fields
+    ws = _lib.workspace(g, w.dtype, sp.n)
+
+    class Lam:
+        pass
+    lam = Lam()
+    tdt = sp.off.dtype
+    lam.lx = torch.zeros_like(sp.off)
+    lam.lu = torch.zeros_like(sp.u)
+    lam.lE = f.E.clone()
+    lam.lB = f.B.clone()
+    dA = None
+    _lib.pic_step_adjoint(g, sp, f, None, 0, lam, dA, ws)   # warm
+    torch.cuda.synchronize()
+    _lib.pic_timing(True)
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    e0.record()
+    for r in range(nrep):
+        _lib.pic_step_adjoint(g, sp, f, None, r, lam, dA, ws)
+    e1.record()
+    torch.cuda.synchronize()
+    kt = _lib.pic_timing(False)
+    del tdt
+    return dict(ms=e0.elapsed_time(e1), kernels=kt)
+
+
+def cpu_baseline():
+    """FP64 oracle on a bounded sample of the same workload shape."""
+    import oracle
+    from paper_2101_12149_amd import workloads as wl
+    n = (48, 48, 48)
+    ppc, nsteps = 8, 2
+    w = wl.uniform_plasma(n, ppc, 0.05, 3, nsteps, "f64", 1002, 4)
+    sp, f = w.species.numpy(), w.fields.numpy()
+    oracle.step(w.grid, sp, f, None, 0, 1)   # warm (page-in, thread start)
+    t0 = time.perf_counter()
+    oracle.step(w.grid, sp, f, None, 1, nsteps)
+    dt = time.perf_counter() - t0
+    npart = sp.cell.shape[1]
+    return {"value": npart * nsteps / dt, "unit": "particle-steps/s", "cores": oracle.num_threads(),
+            "kind": "oracle",
+            "sample": f"uniform plasma {n[0]}^3, {ppc} ppc ({npart} particles), order 3, FP64, {nsteps} steps "
+                      f"after 1 warm-up step ({dt:.1f} s)"}
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=40)
+    ap.add_argument("--warmup", type=int, default=4)
+    ap.add_argument("--workload", default="uniform256_o3_f32")
+    ap.add_argument("--sort-every", type=int, default=None)
+    ap.add_argument("--no-fp64", action="store_true")
+    ap.add_argument("--no-adjoint", action="store_true")
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--tile", type=int, default=0)
+    ap.add_argument("--slack", type=int, default=-1)
+    args = ap.parse_args()
+    if args.gpus != 1:
+        print(json.dumps({"error": "this build runs on one GPU; --gpus must be 1 "
+                                   "(multi-GPU sharding is described in DESIGN.md, not built)"}))
+        sys.exit(2)
+
+    import torch
+    from paper_2101_12149_amd import _lib
+    from paper_2101_12149_amd import workloads as wl
+    _lib.load()
+    torch.cuda.set_device(0)
+
+    w = wl.named(args.workload, device="cuda")
+    if args.tile:
+        w.grid.tile = (args.tile,) * 3
+    w.grid.slack = args.slack
+    sort_every = w.sort_every if args.sort_every is None else args.sort_every
+    g = w.grid
+    npart, ncell = w.species.n, g.ncells
+    tsize = 4 if w.dtype == "f32" else 8
+    fw = run_forward(w, args.steps, args.warmup, sort_every, w.dtype)
+    ms_step = fw["ms"] / args.steps
+    value = npart * args.steps / (fw["ms"] * 1e-3)
+
+    # dominant kernel: the fused tile kernel (gather + push + deposit)
+    pk_ms, pk_n = fw["kernels"]["particles"]
+    pk_avg = pk_ms / max(pk_n, 1)
+    alg_bytes = particle_bytes(npart, tsize, w.species.w is not None) + field_bytes(ncell, tsize)
+    achieved = alg_bytes / (pk_avg * 1e-3) / 1e9
+    roofline = {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": None,
+                "kernel": "k_particles_tile", "avg_ms": round(pk_avg, 4),
+                "alg_bytes_per_launch": int(alg_bytes),
+                "alg_bytes_per_particle": round(alg_bytes / npart, 2)}
+    breakdown = {k: {"ms_per_step": round(v[0] / args.steps, 4), "launch_groups": v[1]}
+                 for k, v in fw["kernels"].items() if v[1]}
+
+    out = {"metric": METRIC, "value": value, "unit": "particle-steps/s", "n_gpus": 1, "steps": args.steps,
+           "warmup": args.warmup, "ms_per_step": ms_step, "higher_is_better": True, "scaling": "weak",
+           "vs_baseline": None, "dtype": w.dtype, "data": "synthetic",
+           "config": {"workload": w.name, "cells": list(g.n), "particles": npart, "ppc": w.meta.get("ppc"),
+                      "order": g.order, "u_th": w.meta.get("u_th"), "sort_every": sort_every,
+                      "precision": "int32 cell + FP32 offset, FP32 fields/momenta, FP64 reductions"
+                      if w.dtype == "f32" else "FP64"},
+           "kernels": breakdown, "roofline": roofline}
+    fwd_diag_last = fw["diag"][-1].tolist()
+    out["diag_last"] = fwd_diag_last
+
+    if not args.no_adjoint:
+        nrep = max(3, min(10, args.steps // 4))
+        adj = run_adjoint(w, nrep)
+        adj_ms = adj["ms"] / nrep
+        out["adjoint"] = {"ms_per_step": adj_ms, "particle_steps_per_s": npart / (adj_ms * 1e-3),
+                          "ratio_adjoint_over_forward": adj_ms / ms_step,
+                          "ratio_with_replay": (adj_ms + ms_step) / ms_step,
+                          "kernels": {k: round(v[0] / nrep, 4) for k, v in adj["kernels"].items() if v[1]}}
+    del w, fw
+    torch.cuda.empty_cache()
+
+    if not args.no_fp64 and args.workload.endswith("_f32"):
+        w64 = wl.named(args.workload[:-4] + "_f64", device="cuda")
+        w64.grid.slack = args.slack
+        k64 = max(4, args.steps // 2)
+        fw64 = run_forward(w64, k64, 2, sort_every, "f64")
+        v64 = w64.species.n * k64 / (fw64["ms"] * 1e-3)
+        pk64 = fw64["kernels"]["particles"]
+        out["fp64"] = {"value": v64, "ms_per_step": fw64["ms"] / k64, "steps": k64,
+                       "particles_kernel_ms": pk64[0] / max(pk64[1], 1),
+                       "ratio_f32_over_f64": value / v64}
+        del w64, fw64
+        torch.cuda.empty_cache()
+
+    if not args.no_cpu_baseline:
+        log("[cpu] timing the oracle on a bounded sample")
+        out["cpu_baseline"] = cpu_baseline()
+    print(json.dumps(out), flush=True)
+
+
+if __name__ == "__main__":
+    main()

@@ -175,12 +175,31 @@ PIC_API pic_status pic_step_adjoint(const pic_grid *grid, const pic_species *sta
                             const pic_source *src, int64_t step, pic_adjoint *lam, double *dA, void *ws,
                             size_t ws_bytes, void *stream);
 
+/* Field-energy loss and the seed of the reverse sweep: out[0] (device double)
+ * receives L = U_E + U_B (pic_reduce's out[0] + out[1]); lam->lE = s eps0 dV E,
+ * lam->lB = s dV B / mu0 (the gradient of s L), and lam->lx, lam->lu are
+ * zeroed for n_particles particles.  s scales the seed (the incoming
+ * gradient of a composite loss).  Needs the workspace. */
+PIC_API pic_status pic_energy_loss(const pic_grid *grid, const pic_fields *f, int64_t n_particles, double s,
+                                   pic_adjoint *lam, double *out, void *ws, size_t ws_bytes, void *stream);
+
 /* FP64 reductions (Sec. 2.6): out[0] = dV/2 sum eps0|E|^2,
  * out[1] = dV/2 sum |B|^2/mu0, out[2] = sum w m c^2 (gamma-1),
  * out[3] = sum q w, out[4] = sum w m u_z.  sp may be NULL (out[2..4] = 0).
  * out: device double[5].  Needs the workspace. */
 PIC_API pic_status pic_reduce(const pic_grid *grid, const pic_species *sp, const pic_fields *f, double *out, void *ws,
                       size_t ws_bytes, void *stream);
+
+/* Kernel timing with HIP events recorded on the caller's stream around the
+ * launches of pic_step and pic_step_adjoint, by category:
+ *   0 sort (binning + scan + scatter)   1 fused particle kernel
+ *   2 Yee field update                  3 FP64 reductions
+ *   4 adjoint field transposes          5 adjoint particle kernel
+ * Completes the pending measurements (synchronising on their events),
+ * writes the accumulated milliseconds and launch counts of the first n
+ * categories to ms / count (either may be NULL), resets the accumulators and
+ * then turns timing on (enable != 0) or off.  Off by default. */
+PIC_API pic_status pic_timing(int enable, double *ms, int64_t *count, int n);
 
 /* Message for the last non-OK status of the calling thread. */
 PIC_API const char *pic_last_error(void);

@@ -67,6 +67,7 @@ def _load():
                 build()
             lib = C.CDLL(_SO)
             P = C.POINTER
+            lib.or_num_threads.restype = C.c_int
             lib.or_shape.restype = C.c_double
             lib.or_shape.argtypes = [C.c_int, C.c_double]
             lib.or_dshape.restype = C.c_double
@@ -163,6 +164,10 @@ def _vec3(arrs):
     for m in range(3):
         v[m] = _ptr(_f64(arrs[m], "vector component"))
     return v
+
+
+def num_threads():
+    return int(_load().or_num_threads())
 
 
 def shape(order, r):

@@ -73,6 +73,16 @@ typedef struct {
     double *lx[3], *lu[3], *lE[3], *lB[3];
 } or_adjoint;
 
+/* Threads the oracle's parallel loops use. */
+int or_num_threads(void)
+{
+#ifdef _OPENMP
+    return omp_get_max_threads();
+#else
+    return 1;
+#endif
+}
+
 /* ------------------------------------------------------------------ */
 /* indexing                                                            */
 

@@ -50,7 +50,8 @@ class pic_adjoint(C.Structure):
 
 
 EXPORTS = ("pic_workspace_bytes", "pic_tile_count", "pic_sort_tiles", "pic_gather", "pic_push", "pic_deposit",
-           "pic_yee", "pic_step", "pic_step_adjoint", "pic_reduce", "pic_last_error")
+           "pic_yee", "pic_step", "pic_step_adjoint", "pic_reduce", "pic_energy_loss", "pic_timing", "pic_last_error")
+TIMING_CATEGORIES = ("sort", "particles", "yee", "reduce", "adjoint_fields", "adjoint_particles")
 
 _lock = threading.Lock()
 _lib = None
@@ -92,6 +93,11 @@ def load():
             lib.pic_reduce.restype = C.c_int
             lib.pic_reduce.argtypes = [P(pic_grid), P(pic_species), P(pic_fields), C.c_void_p, C.c_void_p,
                                        C.c_size_t, C.c_void_p]
+            lib.pic_energy_loss.restype = C.c_int
+            lib.pic_energy_loss.argtypes = [P(pic_grid), P(pic_fields), C.c_int64, C.c_double, P(pic_adjoint),
+                                            C.c_void_p, C.c_void_p, C.c_size_t, C.c_void_p]
+            lib.pic_timing.restype = C.c_int
+            lib.pic_timing.argtypes = [C.c_int, C.c_void_p, C.c_void_p, C.c_int]
             lib.pic_last_error.restype = C.c_char_p
             lib.pic_last_error.argtypes = []
             _lib = lib
@@ -102,6 +108,8 @@ def load():
 # marshalling
 
 def _dtype_code(dtype):
+    if isinstance(dtype, int) and dtype in (PIC_F32, PIC_F64):
+        return dtype
     if dtype in ("f64", torch.float64):
         return PIC_F64
     if dtype in ("f32", torch.float32):
@@ -274,17 +282,23 @@ def pic_step(grid, sp, fields, src, step0, nsteps, sort_every, tile_start, ws, d
     del keep
 
 
+def make_adjoint(lam, code):
+    a = pic_adjoint()
+    n = int(lam.lx.shape[1]) if lam.lx is not None else 0
+    for m in range(3):
+        a.lx[m] = _ptr(lam.lx[m], _tdtype(code), "lx") if n > 0 else None
+        a.lu[m] = _ptr(lam.lu[m], _tdtype(code), "lu") if n > 0 else None
+        a.lE[m] = _ptr(lam.lE[m], _tdtype(code), "lE")
+        a.lB[m] = _ptr(lam.lB[m], _tdtype(code), "lB")
+    return a
+
+
 def pic_step_adjoint(grid, sp, fields, src, step, lam, dA, ws):
     """lam: object with lx, lu (3, N) and lE, lB (3, nz, ny, nx) device tensors."""
     code = _dtype_code(sp.off.dtype)
     g, s, f = make_grid(grid, code), make_species(sp, code), make_fields(fields, code, need_j=False)
     so, keep = make_source(src, code)
-    a = pic_adjoint()
-    for m in range(3):
-        a.lx[m] = _ptr(lam.lx[m], _tdtype(code), "lx")
-        a.lu[m] = _ptr(lam.lu[m], _tdtype(code), "lu")
-        a.lE[m] = _ptr(lam.lE[m], _tdtype(code), "lE")
-        a.lB[m] = _ptr(lam.lB[m], _tdtype(code), "lB")
+    a = make_adjoint(lam, code)
     wp, wn = _ws_ptr(ws)
     _check(load().pic_step_adjoint(C.byref(g), C.byref(s), C.byref(f), C.byref(so), int(step), C.byref(a),
                                    _ptr(dA, torch.float64, "dA") if dA is not None else None, wp, wn, _stream()))
@@ -301,6 +315,31 @@ def pic_reduce(grid, sp, fields, ws, out=None):
     _check(load().pic_reduce(C.byref(g), C.byref(s) if s is not None else None, C.byref(f),
                              _ptr(out, torch.float64, "out"), wp, wn, _stream()))
     return out
+
+
+def pic_energy_loss(grid, fields, lam, ws, seed=1.0, out=None):
+    """L = U_E + U_B into out (device float64 [1]) and the seed of the reverse
+    sweep into lam (lE, lB scaled fields; lx, lu zeroed)."""
+    code = _dtype_code(fields.E.dtype)
+    if out is None:
+        out = torch.empty(1, dtype=torch.float64, device=fields.E.device)
+    g, f = make_grid(grid, code), make_fields(fields, code, need_j=False)
+    a = make_adjoint(lam, code)
+    n = int(lam.lx.shape[1]) if lam.lx is not None else 0
+    wp, wn = _ws_ptr(ws)
+    _check(load().pic_energy_loss(C.byref(g), C.byref(f), n, float(seed), C.byref(a),
+                                  _ptr(out, torch.float64, "out"), wp, wn, _stream()))
+    return out
+
+
+def pic_timing(enable):
+    """Read and reset the per-category kernel times, then switch timing on or
+    off.  Returns {category: (milliseconds, launches)}."""
+    n = len(TIMING_CATEGORIES)
+    ms = (C.c_double * n)()
+    cnt = (C.c_int64 * n)()
+    _check(load().pic_timing(1 if enable else 0, C.cast(ms, C.c_void_p), C.cast(cnt, C.c_void_p), n))
+    return {k: (ms[i], cnt[i]) for i, k in enumerate(TIMING_CATEGORIES)}
 
 
 def pic_last_error():

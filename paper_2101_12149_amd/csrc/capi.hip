@@ -8,7 +8,9 @@
 #include <cmath>
 #include <cstdio>
 #include <cstring>
+#include <mutex>
 #include <string>
+#include <vector>
 
 #include "pic.h"
 #include "pic_types.hpp"
@@ -31,12 +33,88 @@ pic_status hip_fail(hipError_t e, const char *where)
     return PIC_E_DEVICE;
 }
 
+#define PIC_TRY_S(expr)                                 \
+    do {                                                \
+        pic_status s_ = (expr);                         \
+        if (s_ != PIC_OK)                               \
+            return s_;                                  \
+    } while (0)
+
 #define PIC_HIP(call)                                   \
     do {                                                \
         hipError_t e_ = (call);                         \
         if (e_ != hipSuccess)                           \
             return hip_fail(e_, #call);                 \
     } while (0)
+
+// ---------------------------------------------------------------------------
+// optional kernel timing (pic_timing): event pairs recorded around launches
+constexpr int NCAT = 6;
+struct Timer {
+    bool on = false;
+    struct Pending {
+        int cat;
+        hipEvent_t a, b;
+    };
+    std::vector<Pending> pending;
+    std::vector<hipEvent_t> pool;
+    double ms[NCAT] = {};
+    int64_t cnt[NCAT] = {};
+};
+Timer g_timer;
+std::mutex g_timer_mu;
+
+hipEvent_t timer_event()
+{
+    if (!g_timer.pool.empty()) {
+        hipEvent_t e = g_timer.pool.back();
+        g_timer.pool.pop_back();
+        return e;
+    }
+    hipEvent_t e = nullptr;
+    if (hipEventCreate(&e) != hipSuccess)
+        return nullptr;
+    return e;
+}
+
+// records an event pair around the launches made while it is alive
+struct TimedScope {
+    int cat;
+    hipStream_t st;
+    hipEvent_t a = nullptr, b = nullptr;
+    TimedScope(int c, hipStream_t s) : cat(c), st(s)
+    {
+        std::lock_guard<std::mutex> lk(g_timer_mu);
+        if (!g_timer.on)
+            return;
+        a = timer_event();
+        b = timer_event();
+        if (a && b)
+            hipEventRecord(a, st);
+    }
+    ~TimedScope()
+    {
+        if (!a || !b)
+            return;
+        hipEventRecord(b, st);
+        std::lock_guard<std::mutex> lk(g_timer_mu);
+        g_timer.pending.push_back({cat, a, b});
+    }
+};
+
+void timer_flush()
+{
+    for (auto &p : g_timer.pending) {
+        float ms = 0.f;
+        if (hipEventSynchronize(p.b) == hipSuccess && hipEventElapsedTime(&ms, p.a, p.b) == hipSuccess) {
+            g_timer.ms[p.cat] += ms;
+            g_timer.cnt[p.cat] += 1;
+        }
+        g_timer.pool.push_back(p.a);
+        g_timer.pool.push_back(p.b);
+    }
+    g_timer.pending.clear();
+}
 
 // error word of the calls that take no workspace (their device-side state
 // checks are not reported; see pic.h)
@@ -89,7 +167,8 @@ size_t lds_bytes(const GridInfo &gi)
 {
     const size_t rf = (size_t)gi.tg.rf[0] * gi.tg.rf[1] * gi.tg.rf[2];
     const size_t rj = (size_t)gi.tg.rj[0] * gi.tg.rj[1] * gi.tg.rj[2];
-    return (6 * rf + 3 * rj) * gi.tsize;
+    // fields in the working precision, the current tile in FP64
+    return ((6 * rf * gi.tsize + 15) & ~size_t(15)) + 3 * rj * sizeof(double);
 }
 
 pic_status check_grid(const pic_grid *g, GridInfo &gi)
@@ -137,9 +216,14 @@ pic_status check_grid(const pic_grid *g, GridInfo &gi)
     }
     if (g->slack < -1 || g->slack > 2)
         return fail(PIC_E_INVALID, "slack must be -1 (automatic) or in [0,2]");
-    gi.tg.slack = g->slack < 0 ? 0 : g->slack;
-    region_extents(gi.order, gi.tg);
     const size_t limit = (size_t)lds_limit();
+    // automatic slack: one cell when the regions still fit one workgroup
+    gi.tg.slack = g->slack < 0 ? 1 : g->slack;
+    region_extents(gi.order, gi.tg);
+    if (g->slack < 0 && lds_bytes(gi) > limit) {
+        gi.tg.slack = 0;
+        region_extents(gi.order, gi.tg);
+    }
     // an automatic tile shrinks until its LDS regions fit one workgroup
     while (lds_bytes(gi) > limit) {
         int dmax = -1;
@@ -192,7 +276,7 @@ pic_status check_fields(const pic_fields *f, bool need_j)
 
 // workspace layout
 struct WsLayout {
-    size_t err, counts, bsum, key, rank, scell, soff, su, sw, hatE, partials, total;
+    size_t err, counts, bsum, key, rank, scell, soff, su, sw, hatE, partials, red5, total;
 };
 
 size_t al(size_t x)
@@ -227,6 +311,8 @@ WsLayout layout(const GridInfo &gi, int64_t np)
     o += 3 * al(gi.tsize * (size_t)gi.ncell);
     L.partials = o;
     o += al(sizeof(double) * 5 * (size_t)reduce_max_blocks());
+    L.red5 = o;
+    o += 256;
     L.total = o;
     return L;
 }
@@ -459,19 +545,30 @@ pic_status step_t(const pic_grid *g, const GridInfo &gi, pic_species *sp, pic_fi
         const bool sort_now = sort_every > 0 && (it == 0 || step % sort_every == 0);
         if (sort_now && sp->n > 0) {
             PArr<T> sorted;
-            pic_status s = do_sort<T>(gi, sp, w, L, tile_start, nullptr, st, sorted);
-            if (s != PIC_OK)
-                return s;
+            {
+                TimedScope ts(0, st);
+                pic_status s = do_sort<T>(gi, sp, w, L, tile_start, nullptr, st, sorted);
+                if (s != PIC_OK)
+                    return s;
+            }
+            TimedScope ts(1, st);
             PIC_HIP(launch_particles_tile<T>(gi.order, pc, gi.tg, sorted, user, fp, tile_start, err, st));
         } else if (tile_start && sp->n > 0) {
+            TimedScope ts(1, st);
             PIC_HIP(launch_particles_tile<T>(gi.order, pc, gi.tg, user, user, fp, tile_start, err, st));
         } else {
+            TimedScope ts(1, st);
             PIC_HIP(launch_particles_global<T>(gi.order, pc, user, fp, err, st));
         }
-        pic_status s = yee_step<T>(g, gi, fp, src, step, it + 1 < nsteps, st);
+        pic_status s;
+        {
+            TimedScope ts(2, st);
+            s = yee_step<T>(g, gi, fp, src, step, it + 1 < nsteps, st);
+        }
         if (s != PIC_OK)
             return s;
         if (diag) {
+            TimedScope ts(3, st);
             s = reduce_t<T>(g, gi, sp, f, diag + 5 * (int64_t)it, w, L, st);
             if (s != PIC_OK)
                 return s;
@@ -519,8 +616,6 @@ pic_status adjoint_t(const pic_grid *g, const GridInfo &gi, const pic_species *s
         a.dA = dA;
         a.dag = src_g(src, step);
     }
-    PIC_HIP(launch_curl<T>(false, a, st));
-    // lB += dt c^2 curl_f(hatE)
     CurlArgs<T> b{};
     for (int d = 0; d < 3; ++d) {
         b.out[d] = lB[d];
@@ -532,7 +627,6 @@ pic_status adjoint_t(const pic_grid *g, const GridInfo &gi, const pic_species *s
     b.cy = (T)(c2 * g->dt / g->d[1]);
     b.cz = (T)(c2 * g->dt / g->d[2]);
     b.kplane = -1;
-    PIC_HIP(launch_curl<T>(true, b, st));
     // lE = hatE - dt/2 curl_b(lB)
     CurlArgs<T> e{};
     for (int d = 0; d < 3; ++d) {
@@ -545,11 +639,39 @@ pic_status adjoint_t(const pic_grid *g, const GridInfo &gi, const pic_species *s
     e.cy = a.cy;
     e.cz = a.cz;
     e.kplane = -1;
-    PIC_HIP(launch_curl<T>(false, e, st));
+    {
+        TimedScope tf(4, st);
+        PIC_HIP(launch_curl<T>(false, a, st));   // hatE
+        PIC_HIP(launch_curl<T>(true, b, st));    // lB += dt c^2 curl_f(hatE)
+        PIC_HIP(launch_curl<T>(false, e, st));   // lE = hatE - dt/2 curl_b(lB)
+    }
     // particles: deposit, position, Boris and gather transposes
     if (sp->n > 0) {
+        TimedScope tp(5, st);
         const PConst<T> pc = make_const<T>(g, sp);
         PIC_HIP(launch_adjoint_particles<T>(gi.order, pc, parr<T>(sp), fptrs<T>(f), hat, lx, lu, lE, lB, err, st));
+    }
+    return PIC_OK;
+}
+
+template <typename T>
+pic_status energy_loss_t(const pic_grid *g, const GridInfo &gi, const pic_fields *f, int64_t np, double s,
+                         pic_adjoint *lam, double *out, char *ws, const WsLayout &L, hipStream_t st)
+{
+    double *red5 = reinterpret_cast<double *>(ws + L.red5);
+    PIC_TRY_S(reduce_t<T>(g, gi, nullptr, f, red5, ws, L, st));
+    PIC_HIP(launch_sum2(red5, out, st));
+    const double dV = g->d[0] * g->d[1] * g->d[2];
+    const double mu0 = 1.0 / (g->eps0 * g->c * g->c);
+    for (int d = 0; d < 3; ++d) {
+        PIC_HIP(launch_scale<T>(static_cast<T *>(lam->lE[d]), static_cast<const T *>(f->E[d]), gi.ncell,
+                                (T)(s * g->eps0 * dV), st));
+        PIC_HIP(launch_scale<T>(static_cast<T *>(lam->lB[d]), static_cast<const T *>(f->B[d]), gi.ncell,
+                                (T)(s * dV / mu0), st));
+        if (np > 0) {
+            PIC_HIP(launch_fill<T>(static_cast<T *>(lam->lx[d]), np, T(0), st));
+            PIC_HIP(launch_fill<T>(static_cast<T *>(lam->lu[d]), np, T(0), st));
+        }
     }
     return PIC_OK;
 }
@@ -784,6 +906,47 @@ pic_status pic_reduce(const pic_grid *grid, const pic_species *sp, const pic_fie
     if (gi.dtype == PIC_F64)
         return reduce_t<double>(grid, gi, sp, f, out, static_cast<char *>(ws), L, st);
     return reduce_t<float>(grid, gi, sp, f, out, static_cast<char *>(ws), L, st);
+}
+
+pic_status pic_timing(int enable, double *ms, int64_t *count, int n)
+{
+    std::lock_guard<std::mutex> lk(g_timer_mu);
+    timer_flush();
+    for (int c = 0; c < n && c < NCAT; ++c) {
+        if (ms)
+            ms[c] = g_timer.ms[c];
+        if (count)
+            count[c] = g_timer.cnt[c];
+    }
+    for (int c = 0; c < NCAT; ++c) {
+        g_timer.ms[c] = 0.0;
+        g_timer.cnt[c] = 0;
+    }
+    g_timer.on = enable != 0;
+    return PIC_OK;
+}
+
+pic_status pic_energy_loss(const pic_grid *grid, const pic_fields *f, int64_t n_particles, double s,
+                           pic_adjoint *lam, double *out, void *ws, size_t ws_bytes, void *stream)
+{
+    GridInfo gi;
+    WsLayout L;
+    PIC_TRY(check_grid(grid, gi));
+    PIC_TRY(check_fields(f, false));
+    if (!lam || !out)
+        return fail(PIC_E_INVALID, "lam and out must not be NULL");
+    if (n_particles < 0)
+        return fail(PIC_E_INVALID, "n_particles must be >= 0");
+    for (int d = 0; d < 3; ++d)
+        if (!lam->lE[d] || !lam->lB[d] || (n_particles > 0 && (!lam->lx[d] || !lam->lu[d])))
+            return fail(PIC_E_INVALID, "NULL adjoint array");
+    if (!std::isfinite(s))
+        return fail(PIC_E_INVALID, "seed scale must be finite");
+    PIC_TRY(check_ws(gi, 0, ws, ws_bytes, L));
+    hipStream_t st = static_cast<hipStream_t>(stream);
+    if (gi.dtype == PIC_F64)
+        return energy_loss_t<double>(grid, gi, f, n_particles, s, lam, out, static_cast<char *>(ws), L, st);
+    return energy_loss_t<float>(grid, gi, f, n_particles, s, lam, out, static_cast<char *>(ws), L, st);
 }
 
 const char *pic_last_error(void)

@@ -105,6 +105,37 @@ hipError_t launch_fill(T *p, int64_t n, T v, hipStream_t st)
     return hipGetLastError();
 }
 
+template <typename T>
+__global__ void k_scale(T *out, const T *in, int64_t n, T a)
+{
+    for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x)
+        out[i] = a * in[i];
+}
+
+template <typename T>
+hipError_t launch_scale(T *out, const T *in, int64_t n, T a, hipStream_t st)
+{
+    if (n <= 0)
+        return hipSuccess;
+    int64_t b = (n + 255) / 256;
+    if (b > 65536)
+        b = 65536;
+    hipLaunchKernelGGL((k_scale<T>), dim3((unsigned)b), dim3(256), 0, st, out, in, n, a);
+    return hipGetLastError();
+}
+
+__global__ void k_sum2(const double *in, double *out)
+{
+    if (threadIdx.x == 0 && blockIdx.x == 0)
+        out[0] = in[0] + in[1];
+}
+
+hipError_t launch_sum2(const double *in, double *out, hipStream_t st)
+{
+    hipLaunchKernelGGL(k_sum2, dim3(1), dim3(64), 0, st, in, out);
+    return hipGetLastError();
+}
+
 // ---------------------------------------------------------------------------
 // Counting sort by tile-major cell key (Sec. 3.4.2).  Pass 1 computes each
 // particle's key and its rank inside the key's bin with one atomic increment
@@ -414,6 +445,7 @@ hipError_t launch_reduce(const PArr<T> *sp, const FieldPtrs<T> &f, int64_t ncell
 #define PIC_GINST(T)                                                                                             \
     template hipError_t launch_curl<T>(bool, const CurlArgs<T> &, hipStream_t);                                   \
     template hipError_t launch_fill<T>(T *, int64_t, T, hipStream_t);                                             \
+    template hipError_t launch_scale<T>(T *, const T *, int64_t, T, hipStream_t);                                 \
     template hipError_t launch_bin_count<T>(const PArr<T> &, const TileGeo &, int *, int *, int *, int *,         \
                                             hipStream_t);                                                         \
     template hipError_t launch_scatter<T>(const PArr<T> &, const PArr<T> &, const int *, const int *, const int *, \

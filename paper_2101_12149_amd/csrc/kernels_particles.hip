@@ -17,6 +17,11 @@
 
 namespace pic {
 
+// threads per tile workgroup: at 8 particles per cell and 8^3-cell tiles each
+// thread takes about one cell's particles, so neighbouring lanes touch
+// neighbouring LDS words
+constexpr int TILE_THREADS = 512;
+
 template <typename T>
 __device__ inline void gatomic_add(T *p, T v)
 {
@@ -88,7 +93,7 @@ template <typename T, int O, bool LOCAL>
 __device__ inline void particle_step(const PConst<T> &pc, const PArr<T> &in, const PArr<T> &out,
                                      const FieldPtrs<T> &fp, const FieldSrc<T> &fsrc, int64_t p, const int *c,
                                      const T *f, const T *u, const int *l, int lo_f, const int *sf, int lo_j,
-                                     const int *sj, T *sJ, int rjvol, int *err)
+                                     const int *sj, double *sJ, int rjvol, int *err)
 {
     constexpr int NW = Shape<O, T>::NW;
     const int gs[3] = {1, pc.n[0], pc.n[0] * pc.n[1]};
@@ -140,9 +145,10 @@ __device__ inline void particle_step(const PConst<T> &pc, const PArr<T> &in, con
             axis_offsets_global<NW + 1>(c[d], e[d].lo, pc.n[d], gs[d], jo[d]);
     }
     if (LOCAL) {
-        esk_scatter<O>(e, jo, K, [&](int m, int idx, T v) { latomic_add(sJ + m * rjvol + idx, v); });
+        esk_scatter<O, T, double>(e, jo, K,
+                                  [&](int m, int idx, double v) { latomic_add(sJ + m * rjvol + idx, v); });
     } else {
-        esk_scatter<O>(e, jo, K, [&](int m, int idx, T v) { gatomic_add(fp.J[m] + idx, v); });
+        esk_scatter<O, T, T>(e, jo, K, [&](int m, int idx, T v) { gatomic_add(fp.J[m] + idx, v); });
     }
 #pragma unroll
     for (int d = 0; d < 3; ++d) {
@@ -156,7 +162,7 @@ __device__ inline void particle_step(const PConst<T> &pc, const PArr<T> &in, con
 
 // ---------------------------------------------------------------------------
 template <typename T, int O>
-__global__ void __launch_bounds__(256) k_particles_tile(PConst<T> pc, TileGeo tg, PArr<T> in, PArr<T> out,
+__global__ void __launch_bounds__(TILE_THREADS) k_particles_tile(PConst<T> pc, TileGeo tg, PArr<T> in, PArr<T> out,
                                                         FieldPtrs<T> fp, const int *__restrict__ tile_start,
                                                         int *err)
 {
@@ -166,7 +172,8 @@ __global__ void __launch_bounds__(256) k_particles_tile(PConst<T> pc, TileGeo tg
     const int rfvol = rfx * rfy * tg.rf[2];
     const int rjx = tg.rj[0], rjy = tg.rj[1];
     const int rjvol = rjx * rjy * tg.rj[2];
-    T *sJ = sF + 6 * rfvol;
+    // the current tile accumulates in FP64 (fast LDS atomics), after the fields
+    double *sJ = reinterpret_cast<double *>(smem_raw + ((6 * rfvol * sizeof(T) + 15) & ~size_t(15)));
 
     const int ntiles = tg.nt[0] * tg.nt[1] * tg.nt[2];
     int t = blockIdx.x;
@@ -195,7 +202,7 @@ __global__ void __launch_bounds__(256) k_particles_tile(PConst<T> pc, TileGeo tg
         }
     }
     for (int r = tid; r < 3 * rjvol; r += nth)
-        sJ[r] = T(0);
+        sJ[r] = 0.0;
     __syncthreads();
 
     FieldSrc<T> lf, gf;
@@ -245,7 +252,7 @@ __global__ void __launch_bounds__(256) k_particles_tile(PConst<T> pc, TileGeo tg
     }
     __syncthreads();
     for (int r = tid; r < 3 * rjvol; r += nth) {
-        const T v = sJ[r];
+        const T v = (T)sJ[r];
         if (v != T(0)) {
             const int m = r / rjvol, rr = r - m * rjvol;
             const int rx = rr % rjx, ry = (rr / rjx) % rjy, rz = rr / (rjx * rjy);
@@ -399,7 +406,7 @@ __global__ void __launch_bounds__(256) k_deposit(PConst<T> pc, PArr<T> b, PArr<T
         K[d] = pc.jk[d] * w;
         axis_offsets_global<NW + 1>(c0[d], e[d].lo, pc.n[d], gs[d], jo[d]);
     }
-    esk_scatter<O>(e, jo, K, [&](int m, int idx, T v) { gatomic_add(fp.J[m] + idx, v); });
+    esk_scatter<O, T, T>(e, jo, K, [&](int m, int idx, T v) { gatomic_add(fp.J[m] + idx, v); });
 }
 
 // ---------------------------------------------------------------------------
@@ -552,7 +559,7 @@ size_t tile_lds_bytes(int, const TileGeo &tg)
 {
     const size_t rf = (size_t)tg.rf[0] * tg.rf[1] * tg.rf[2];
     const size_t rj = (size_t)tg.rj[0] * tg.rj[1] * tg.rj[2];
-    return (6 * rf + 3 * rj) * sizeof(T);
+    return ((6 * rf * sizeof(T) + 15) & ~size_t(15)) + 3 * rj * sizeof(double);
 }
 
 template <typename T, int O>
@@ -568,7 +575,7 @@ static hipError_t launch_tile_o(const PConst<T> &pc, const TileGeo &tg, const PA
         attr_set = true;
     }
     const unsigned ntiles = (unsigned)(tg.nt[0] * tg.nt[1] * tg.nt[2]);
-    hipLaunchKernelGGL((k_particles_tile<T, O>), dim3(ntiles), dim3(256), lds, st, pc, tg, in, out, f, tile_start,
+    hipLaunchKernelGGL((k_particles_tile<T, O>), dim3(ntiles), dim3(TILE_THREADS), lds, st, pc, tg, in, out, f, tile_start,
                        err);
     return hipGetLastError();
 }

@@ -302,7 +302,8 @@ template <int O, typename T>
 struct EskAxis {
     static constexpr int NW = Shape<O, T>::NW;
     T S0[NW + 1], DS[NW + 1];
-    int lo;   // first window node relative to the old cell
+    int lo;       // first window node relative to the old cell
+    bool cross;   // the particle changed cell along this axis
 };
 
 template <int O, typename T>
@@ -317,6 +318,7 @@ __device__ inline void esk_axis(T d0, T d1, int kappa, EskAxis<O, T> &e)
         e.S0[a] = T(0);
         e.DS[a] = T(0);
     }
+    e.cross = kappa != 0;
     if (kappa == 0) {
         S::q(d0, d1, qa);
         const T dd = d1 - d0;
@@ -393,9 +395,12 @@ __device__ inline void esk_axis_deriv(T d0, T d1, int kappa, T *dS0, T *dDS1)
 // P_m the running sum of DS_m along m and
 // C = S0p S0q + DSp S0q/2 + S0p DSq/2 + DSp DSq/3
 // (the Esirkepov weight (S0p S0q + S1p S1q)/3 + (S1p S0q + S0p S1q)/6
-// rewritten in S0 and DS).  `add(m, index, value)` performs the scatter;
-// jo[d][a] are the index offsets of window node a along axis d.
-template <int O, typename T, typename AddFn>
+// rewritten in S0 and DS).  The products K P C are formed in the
+// accumulator type A (double for the LDS current tile, whose FP64 atomics
+// are far faster than FP32 ones on gfx950).  `add(m, index, value)`
+// performs the scatter; jo[d][a] are the index offsets of window node a
+// along axis d.
+template <int O, typename T, typename A, typename AddFn>
 __device__ inline void esk_scatter(const EskAxis<O, T> *e, const int (*jo)[Shape<O, T>::NW + 1], const T *K,
                                    AddFn &&add)
 {
@@ -404,23 +409,33 @@ __device__ inline void esk_scatter(const EskAxis<O, T> *e, const int (*jo)[Shape
 #pragma unroll
     for (int m = 0; m < 3; ++m) {
         const int p = (m + 1) % 3, q = (m + 2) % 3;
-        T P[NW];
+        A P[NW];
         T run = T(0);
 #pragma unroll
         for (int a = 0; a < NW; ++a) {
             run += e[m].DS[a];
-            P[a] = K[m] * run;
+            P[a] = (A)(K[m] * run);
         }
+        // A particle that stays in its cell along an axis has S0 = DS = 0 at
+        // the window's last node, and along m its running sum closes to zero
+        // one node earlier: those entries are zero and are not scattered.
+        // The rim of the window is touched only by cell-crossing particles.
+        const bool xm = e[m].cross, xp = e[p].cross, xq = e[q].cross;
 #pragma unroll
         for (int c = 0; c <= NW; ++c) {
 #pragma unroll
             for (int b = 0; b <= NW; ++b) {
-                const T C = e[p].S0[b] * (e[q].S0[c] + half * e[q].DS[c]) +
-                            e[p].DS[b] * (half * e[q].S0[c] + third * e[q].DS[c]);
+                if ((c == NW && !xq) || (b == NW && !xp))
+                    continue;
+                const A C = (A)(e[p].S0[b] * (e[q].S0[c] + half * e[q].DS[c]) +
+                                e[p].DS[b] * (half * e[q].S0[c] + third * e[q].DS[c]));
                 const int base = jo[p][b] + jo[q][c];
 #pragma unroll
-                for (int a = 0; a < NW; ++a)
+                for (int a = 0; a < NW; ++a) {
+                    if (a == NW - 1 && !xm)
+                        continue;
                     add(m, base + jo[m][a], P[a] * C);
+                }
             }
         }
     }

@@ -101,6 +101,9 @@ hipError_t launch_curl(bool forward, const CurlArgs<T> &a, hipStream_t st);
 template <typename T>
 hipError_t launch_fill(T *p, int64_t n, T v, hipStream_t st);
 template <typename T>
+hipError_t launch_scale(T *out, const T *in, int64_t n, T a, hipStream_t st);
+hipError_t launch_sum2(const double *in, double *out, hipStream_t st);
+template <typename T>
 hipError_t launch_bin_count(const PArr<T> &sp, const TileGeo &tg, int *counts, int *key, int *rank, int *err,
                             hipStream_t st);
 template <typename T>

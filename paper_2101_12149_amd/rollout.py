@@ -1,0 +1,106 @@
+"""Differentiable PIC rollout: a torch.autograd.Function over pic_step with a
+hand-written reverse sweep (pic_step_adjoint) and checkpointing every k steps.
+
+Forward: nsteps PIC steps from the initial momenta u0 with the source map
+`amp` on the plane k_plane; the state is stored every k steps.  The loss is
+the field energy U_E + U_B after the last step (pic_energy_loss).
+Backward: for each checkpoint segment, last first, the segment is replayed
+from its checkpoint keeping every step's input state, then the steps are
+reversed with pic_step_adjoint.  Returns dL/du0 and dL/damp.
+
+Particles are not re-sorted inside the rollout, so the particle order of the
+adjoint arrays is the order of u0.  All arithmetic runs in the library's
+kernels; this module only orders the calls and holds device buffers.
+"""
+import torch
+
+from . import _lib
+from . import workloads as wl
+
+
+class Problem:
+    """Static inputs of a rollout: grid, the particles' positions/weights,
+    initial fields, the source time series, step count and checkpoint
+    interval.  Tensors live on the device in the working precision."""
+
+    def __init__(self, grid, species, fields, source, nsteps, checkpoint_every, dtype):
+        self.grid = grid
+        self.species = species
+        self.fields = fields
+        self.source = source
+        self.nsteps = int(nsteps)
+        self.k = max(1, int(checkpoint_every or nsteps))
+        self.dtype = dtype
+        self.ws = _lib.workspace(grid, dtype, species.n)
+
+    def source_with(self, amp):
+        if self.source is None:
+            return None
+        return wl.Source(self.source.k_plane, amp.detach().contiguous(), self.source.g)
+
+
+class _Adjoint:
+    def __init__(self, n, fields):
+        self.lx = torch.zeros((3, n), dtype=fields.E.dtype, device=fields.E.device)
+        self.lu = torch.zeros((3, n), dtype=fields.E.dtype, device=fields.E.device)
+        self.lE = torch.zeros_like(fields.E)
+        self.lB = torch.zeros_like(fields.B)
+
+
+def _advance(pb, sp, f, src, step0, nsteps):
+    if nsteps > 0:
+        _lib.pic_step(pb.grid, sp, f, src, step0, nsteps, 0, None, pb.ws)
+
+
+class PICRollout(torch.autograd.Function):
+    @staticmethod
+    def forward(ctx, u0, amp, pb):
+        sp = pb.species.clone()
+        sp.u = u0.detach().clone().contiguous()
+        f = pb.fields.clone()
+        src = pb.source_with(amp) if amp is not None else None
+        checkpoints = []
+        s = 0
+        while s < pb.nsteps:
+            checkpoints.append((s, sp.clone(), f.clone()))
+            n = min(pb.k, pb.nsteps - s)
+            _advance(pb, sp, f, src, s, n)
+            s += n
+        lam = _Adjoint(sp.n, f)
+        loss = _lib.pic_energy_loss(pb.grid, f, lam, pb.ws)
+        ctx.pb = pb
+        ctx.src = src
+        ctx.checkpoints = checkpoints
+        ctx.final_fields = f
+        ctx.has_amp = amp is not None
+        return loss[0].clone()
+
+    @staticmethod
+    def backward(ctx, grad_loss):
+        pb, src = ctx.pb, ctx.src
+        seed = float(grad_loss.detach().cpu())
+        lam = _Adjoint(pb.species.n, ctx.final_fields)
+        _lib.pic_energy_loss(pb.grid, ctx.final_fields, lam, pb.ws, seed=seed)
+        dA = None
+        if ctx.has_amp and src is not None:
+            dA = torch.zeros(src.amp.shape, dtype=torch.float64, device=src.amp.device)
+        for (s0, sp0, f0) in reversed(ctx.checkpoints):
+            n = min(pb.k, pb.nsteps - s0)
+            # replay the segment, keeping the input state of every step
+            states = []
+            sp, f = sp0.clone(), f0.clone()
+            for i in range(n):
+                states.append((sp.clone(), f.clone()))
+                _advance(pb, sp, f, src, s0 + i, 1)
+            for i in reversed(range(n)):
+                sp_n, f_n = states[i]
+                _lib.pic_step_adjoint(pb.grid, sp_n, f_n, src, s0 + i, lam, dA, pb.ws)
+        ctx.checkpoints = None
+        du0 = lam.lu.clone()
+        damp = dA.to(src.amp.dtype) if dA is not None else None
+        return du0, damp, None
+
+
+def rollout_loss(u0, amp, pb):
+    """Field energy after pb.nsteps steps, differentiable in u0 and amp."""
+    return PICRollout.apply(u0, amp, pb)

@@ -1,0 +1,158 @@
+"""Parity of the hand-written adjoint on the GPU (through the C ABI) with the
+FP64 oracle's adjoint, and of the differentiable rollout with the oracle's
+reverse sweep and with central finite differences (eps = 1e-6, rel <= 1e-6
+in FP64, plus the rounding noise of the difference)."""
+import numpy as np
+import pytest
+import torch
+
+import oracle
+from paper_2101_12149_amd import _lib
+from paper_2101_12149_amd import rollout as ro
+from paper_2101_12149_amd import workloads as wl
+from pic_cases import NS, dev, max_rel, random_fields, random_species, rel_l2, tdtype
+
+pytestmark = pytest.mark.gpu
+
+
+def _cpu(t):
+    return t.detach().cpu().to(torch.float64).numpy()
+
+
+def _random_lambda(g, n, seed, dtype):
+    gen = torch.Generator().manual_seed(seed)
+    shape = (3, int(g.n[2]), int(g.n[1]), int(g.n[0]))
+    t = tdtype(dtype)
+    return NS(lx=torch.randn((3, n), generator=gen, dtype=torch.float64).to(t),
+              lu=torch.randn((3, n), generator=gen, dtype=torch.float64).to(t),
+              lE=torch.randn(shape, generator=gen, dtype=torch.float64).to(t),
+              lB=torch.randn(shape, generator=gen, dtype=torch.float64).to(t))
+
+
+def _oracle_lambda(lam):
+    a = oracle.Adjoint(NS(n=(lam.lE.shape[3], lam.lE.shape[2], lam.lE.shape[1])), lam.lx.shape[1])
+    a.lx[:] = _cpu(lam.lx)
+    a.lu[:] = _cpu(lam.lu)
+    a.lE[:] = _cpu(lam.lE)
+    a.lB[:] = _cpu(lam.lB)
+    return a
+
+
+@pytest.mark.parametrize("order", [1, 3])
+@pytest.mark.parametrize("dtype", ["f64", "f32"])
+def test_adjoint_step_matches_oracle(order, dtype):
+    g = wl.plasma_grid((12, 16, 20), order)
+    n = 3000
+    sp = random_species(g, n, 101, u_th=0.2, dtype=dtype)
+    f = random_fields(g, 102, scale=0.3, dtype=dtype)
+    amp = torch.randn((16, 12), dtype=torch.float64, generator=torch.Generator().manual_seed(103))
+    src = wl.Source(4, amp.to(tdtype(dtype)), np.array([0.2, -0.7, 1.1, 0.4]))
+    lam = _random_lambda(g, n, 104, dtype)
+    olam = _oracle_lambda(lam)
+    dlam = NS(lx=dev(lam.lx), lu=dev(lam.lu), lE=dev(lam.lE), lB=dev(lam.lB))
+    dA = torch.zeros((16, 12), dtype=torch.float64, device="cuda")
+    ws = _lib.workspace(g, dtype, n)
+    _lib.pic_step_adjoint(g, dev(sp), dev(f), src.to(device="cuda"), 2, dlam, dA, ws)
+    torch.cuda.synchronize()
+    odA = np.zeros((16, 12))
+    oracle.step_adjoint(g, sp.numpy(), f.numpy(), src.numpy(), 2, olam, odA)
+    tol = 1e-12 if dtype == "f64" else 1e-4
+    for name in ("lx", "lu", "lE", "lB"):
+        r = rel_l2(_cpu(getattr(dlam, name)), getattr(olam, name))
+        assert r < tol, (name, r)
+    assert rel_l2(dA.cpu().numpy(), odA) < tol
+
+
+def test_energy_loss_and_seed():
+    g = wl.plasma_grid((8, 12, 16), 3)
+    f = random_fields(g, 111, scale=0.4)
+    lam = NS(lx=torch.full((3, 5), 9.0, dtype=torch.float64, device="cuda"),
+             lu=torch.full((3, 5), 9.0, dtype=torch.float64, device="cuda"),
+             lE=torch.zeros((3, 16, 12, 8), dtype=torch.float64, device="cuda"),
+             lB=torch.zeros((3, 16, 12, 8), dtype=torch.float64, device="cuda"))
+    ws = _lib.workspace(g, "f64", 5)
+    df = dev(f)
+    out = _lib.pic_energy_loss(g, df, lam, ws, seed=2.5)
+    torch.cuda.synchronize()
+    L, olam = oracle.loss(g, f.numpy(), 5)
+    assert abs(out.item() - L) <= 1e-13 * abs(L)
+    assert rel_l2(_cpu(lam.lE), 2.5 * olam.lE) < 1e-14
+    assert rel_l2(_cpu(lam.lB), 2.5 * olam.lB) < 1e-14
+    assert torch.count_nonzero(lam.lx) == 0 and torch.count_nonzero(lam.lu) == 0
+
+
+def _problem(w):
+    g = w.grid
+    sp, f = dev(w.species), dev(w.fields)
+    src = w.source.to(device="cuda") if w.source is not None else None
+    return ro.Problem(g, sp, f, src, w.nsteps, w.checkpoint_every, w.dtype)
+
+
+def _gpu_loss(pb, u0, amp):
+    with torch.no_grad():
+        return ro.rollout_loss(u0, amp, pb).item()
+
+
+def test_rollout_gradient_matches_oracle_reverse_sweep():
+    """Reduced differentiable workload (16^3, 2 ppc, order 3, FP64, 8 steps,
+    checkpoint every 3): torch autograd through the GPU rollout against the
+    oracle's own forward + reverse sweep."""
+    w = wl.differentiable((16, 16, 16), 2, 0.05, 3, 8, "f64", 1234, checkpoint_every=3, amp0=5e-3, period=6)
+    pb = _problem(w)
+    u0 = pb.species.u.clone().requires_grad_(True)
+    amp = pb.source.amp.clone().requires_grad_(True)
+    L = ro.rollout_loss(u0, amp, pb)
+    L.backward()
+    oL, ogu, ogA, _, _ = oracle.rollout_grad(w.grid, w.species.numpy(), w.fields.numpy(), w.source.numpy(), 0,
+                                             w.nsteps)
+    assert abs(L.item() - oL) <= 1e-12 * abs(oL)
+    assert rel_l2(_cpu(u0.grad), ogu) < 1e-10
+    assert rel_l2(_cpu(amp.grad), ogA) < 1e-10
+
+
+@pytest.mark.parametrize("shape,ppc,nsteps,k", [((16, 16, 16), 2, 8, 3), ((64, 64, 64), 4, 20, 5)])
+def test_rollout_gradient_matches_central_differences(shape, ppc, nsteps, k):
+    """Central differences with eps = 1e-6 along the gradient direction, a
+    seeded mix of it with a random unit direction, and the largest single
+    coordinates, for the momenta and the source map.  The directions are
+    chosen so that each derivative is well above the difference's rounding
+    noise (a few ulps of L over eps), which the test checks as well.  The
+    second case is the full 64^3, 4 ppc, 20-step, checkpoint-every-5
+    differentiable workload."""
+    w = wl.differentiable(shape, ppc, 0.05, 3, nsteps, "f64", 1004, checkpoint_every=k)
+    pb = _problem(w)
+    u0 = pb.species.u.clone().requires_grad_(True)
+    amp = pb.source.amp.clone().requires_grad_(True)
+    L = ro.rollout_loss(u0, amp, pb)
+    L.backward()
+    gu, gA = u0.grad.detach(), amp.grad.detach()
+    eps = 1e-6
+    gen = torch.Generator(device="cuda").manual_seed(7)
+    base_u, base_a = u0.detach(), amp.detach()
+
+    def dirs(gr):
+        out = [gr / gr.norm()]
+        r = torch.randn(gr.shape, generator=gen, device="cuda", dtype=torch.float64)
+        v = gr / gr.norm() + r / r.norm()
+        out.append(v / v.norm())
+        return out
+
+    checks = []
+    for v in dirs(gu):
+        fd = (_gpu_loss(pb, base_u + eps * v, base_a) - _gpu_loss(pb, base_u - eps * v, base_a)) / (2 * eps)
+        checks.append(("u-dir", fd, torch.sum(gu * v).item()))
+    for v in dirs(gA):
+        fd = (_gpu_loss(pb, base_u, base_a + eps * v) - _gpu_loss(pb, base_u, base_a - eps * v)) / (2 * eps)
+        checks.append(("A-dir", fd, torch.sum(gA * v).item()))
+    flat = gu.abs().flatten()
+    for idx in torch.topk(flat, 3).indices.tolist():
+        v = torch.zeros_like(base_u).flatten()
+        v[idx] = 1.0
+        v = v.view_as(base_u)
+        fd = (_gpu_loss(pb, base_u + eps * v, base_a) - _gpu_loss(pb, base_u - eps * v, base_a)) / (2 * eps)
+        checks.append(("u-coord", fd, gu.flatten()[idx].item()))
+    Lv = L.item()
+    noise = 10 * np.finfo(float).eps * abs(Lv) / eps
+    for kind, fd, an in checks:
+        assert noise < 0.5e-6 * abs(an), (kind, an, noise)
+        assert abs(fd - an) <= 1e-6 * abs(an) + noise, (kind, fd, an, noise)

@@ -309,8 +309,8 @@ def test_laser_plasma_reduced_with_empty_tiles_and_source():
 def test_zero_particles_and_edge_offsets():
     g = wl.plasma_grid((8, 8, 8), 3)
     # no particles: the step is a pure field solve
-    empty = wl.Species(torch.zeros((3, 0), dtype=torch.int32), torch.zeros((3, 0)), torch.zeros((3, 0)), None,
-                       1.0)
+    empty = wl.Species(torch.zeros((3, 0), dtype=torch.int32), torch.zeros((3, 0), dtype=torch.float64),
+                       torch.zeros((3, 0), dtype=torch.float64), None, 1.0)
     f = random_fields(g, 92)
     w = wl.Workload("empty", g, empty, f, None, 2, 1, "f64", 0)
     _, gf, _ = _run_gpu_steps(w, 2, 1)
