@@ -68,7 +68,7 @@ def run_forward(w, steps, warmup, sort_every, label):
     return dict(ms=ev_ms, wall_ms=wall * 1e3, kernels=kt, diag=diag[:steps].cpu().numpy(), ws=ws, ts=ts)
 
 
-def run_adjoint(w, nrep):
+def run_adjoint(w, nrep, tile_start):
     import torch
     from paper_2101_12149_amd import _lib
     g = w.grid
@@ -84,13 +84,13 @@ def run_adjoint(w, nrep):
     lam.lE = f.E.clone()
     lam.lB = f.B.clone()
     dA = None
-    _lib.pic_step_adjoint(g, sp, f, None, 0, lam, dA, ws)   # warm
+    _lib.pic_step_adjoint(g, sp, f, None, 0, lam, dA, ws, tile_start=tile_start)   # warm
     torch.cuda.synchronize()
     _lib.pic_timing(True)
     e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
     e0.record()
     for r in range(nrep):
-        _lib.pic_step_adjoint(g, sp, f, None, r, lam, dA, ws)
+        _lib.pic_step_adjoint(g, sp, f, None, r, lam, dA, ws, tile_start=tile_start)
     e1.record()
     torch.cuda.synchronize()
     kt = _lib.pic_timing(False)
@@ -102,8 +102,8 @@ def cpu_baseline():
     """FP64 oracle on a bounded sample of the same workload shape."""
     import oracle
     from paper_2101_12149_amd import workloads as wl
-    n = (48, 48, 48)
-    ppc, nsteps = 8, 2
+    n = (96, 96, 96)
+    ppc, nsteps = 8, 3
     w = wl.uniform_plasma(n, ppc, 0.05, 3, nsteps, "f64", 1002, 4)
     sp, f = w.species.numpy(), w.fields.numpy()
     oracle.step(w.grid, sp, f, None, 0, 1)   # warm (page-in, thread start)
@@ -129,6 +129,8 @@ def main():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--tile", type=int, default=0)
     ap.add_argument("--slack", type=int, default=-1)
+    ap.add_argument("--calib-copy", action="store_true",
+                    help="copy 1 GiB device-to-device first (HBM counter calibration)")
     args = ap.parse_args()
     if args.gpus != 1:
         print(json.dumps({"error": "this build runs on one GPU; --gpus must be 1 "
@@ -140,6 +142,14 @@ def main():
     from paper_2101_12149_amd import workloads as wl
     _lib.load()
     torch.cuda.set_device(0)
+
+    if args.calib_copy:
+        a = torch.ones(1 << 28, dtype=torch.float32, device="cuda")
+        b = torch.empty_like(a)
+        b.copy_(a)
+        torch.cuda.synchronize()
+        del a, b
+        torch.cuda.empty_cache()
 
     w = wl.named(args.workload, device="cuda")
     if args.tile:
@@ -179,7 +189,7 @@ def main():
 
     if not args.no_adjoint:
         nrep = max(3, min(10, args.steps // 4))
-        adj = run_adjoint(w, nrep)
+        adj = run_adjoint(w, nrep, fw["ts"])
         adj_ms = adj["ms"] / nrep
         out["adjoint"] = {"ms_per_step": adj_ms, "particle_steps_per_s": npart / (adj_ms * 1e-3),
                           "ratio_adjoint_over_forward": adj_ms / ms_step,

@@ -119,10 +119,12 @@ PIC_API int64_t pic_tile_count(const pic_grid *grid);
 
 /* Particle binning and sorting by counting sort (Sec. 3.4.2: binning computes
  * a permutation that assigns particles to bins; sorting reorders the data).
- * The key is the tile-major cell index: tiles of grid->tile cells in
- * lexicographic (x fastest) order, cells x-fastest inside a tile.
- * Reorders every array of `sp` in place (stable within a cell is NOT
- * guaranteed), writes tile_start[t] = first particle of tile t for
+ * Bins are cells grouped by tile: tiles of grid->tile cells in lexicographic
+ * (x fastest) order.  Inside a tile the order is rank-major: the first
+ * particle of every non-empty cell (cells x fastest), then the second
+ * particle of every cell holding two or more, and so on, so that consecutive
+ * particles sit in neighbouring cells.  Which particle of a cell counts as
+ * first is not specified.  Reorders every array of `sp` in place, writes tile_start[t] = first particle of tile t for
  * t in [0, ntiles] (tile_start[ntiles] = n), and, if perm != NULL,
  * perm[j] = index before the sort of the particle now at j.
  * tile_start: int32[ntiles+1] device.  perm: int32[n] device or NULL.
@@ -170,10 +172,15 @@ PIC_API pic_status pic_step(const pic_grid *grid, pic_species *sp, pic_fields *f
  * dL/d(source map).  Field part: transpose of the Yee step (the periodic
  * forward difference is minus the transpose of the backward one).  Particle
  * part: transpose of the deposit (a gather of the current adjoint), of the
- * position update, of the Boris push and of the gather (a scatter). */
+ * position update, of the Boris push and of the gather (a scatter).
+ * tile_start (int32[ntiles+1], or NULL): a binning of state_n's particles
+ * from pic_sort_tiles or pic_step; with it the particle part runs one
+ * workgroup per tile with the fields, the field adjoint and the scatter
+ * accumulators in LDS, without it one thread per particle on global memory.
+ * The result does not depend on the choice beyond rounding. */
 PIC_API pic_status pic_step_adjoint(const pic_grid *grid, const pic_species *state_n, const pic_fields *fields_n,
-                            const pic_source *src, int64_t step, pic_adjoint *lam, double *dA, void *ws,
-                            size_t ws_bytes, void *stream);
+                                    const int32_t *tile_start, const pic_source *src, int64_t step,
+                                    pic_adjoint *lam, double *dA, void *ws, size_t ws_bytes, void *stream);
 
 /* Field-energy loss and the seed of the reverse sweep: out[0] (device double)
  * receives L = U_E + U_B (pic_reduce's out[0] + out[1]); lam->lE = s eps0 dV E,

@@ -88,8 +88,9 @@ def load():
                                      C.c_int32, C.c_int32, C.c_void_p, C.c_void_p, C.c_size_t, C.c_void_p,
                                      C.c_void_p]
             lib.pic_step_adjoint.restype = C.c_int
-            lib.pic_step_adjoint.argtypes = [P(pic_grid), P(pic_species), P(pic_fields), P(pic_source), C.c_int64,
-                                             P(pic_adjoint), C.c_void_p, C.c_void_p, C.c_size_t, C.c_void_p]
+            lib.pic_step_adjoint.argtypes = [P(pic_grid), P(pic_species), P(pic_fields), C.c_void_p, P(pic_source),
+                                             C.c_int64, P(pic_adjoint), C.c_void_p, C.c_void_p, C.c_size_t,
+                                             C.c_void_p]
             lib.pic_reduce.restype = C.c_int
             lib.pic_reduce.argtypes = [P(pic_grid), P(pic_species), P(pic_fields), C.c_void_p, C.c_void_p,
                                        C.c_size_t, C.c_void_p]
@@ -293,14 +294,17 @@ def make_adjoint(lam, code):
     return a
 
 
-def pic_step_adjoint(grid, sp, fields, src, step, lam, dA, ws):
-    """lam: object with lx, lu (3, N) and lE, lB (3, nz, ny, nx) device tensors."""
+def pic_step_adjoint(grid, sp, fields, src, step, lam, dA, ws, tile_start=None):
+    """lam: object with lx, lu (3, N) and lE, lB (3, nz, ny, nx) device tensors;
+    tile_start: the binning of sp (or None for the untiled kernel)."""
     code = _dtype_code(sp.off.dtype)
     g, s, f = make_grid(grid, code), make_species(sp, code), make_fields(fields, code, need_j=False)
     so, keep = make_source(src, code)
     a = make_adjoint(lam, code)
     wp, wn = _ws_ptr(ws)
-    _check(load().pic_step_adjoint(C.byref(g), C.byref(s), C.byref(f), C.byref(so), int(step), C.byref(a),
+    _check(load().pic_step_adjoint(C.byref(g), C.byref(s), C.byref(f),
+                                   _ptr(tile_start, torch.int32, "tile_start") if tile_start is not None else None,
+                                   C.byref(so), int(step), C.byref(a),
                                    _ptr(dA, torch.float64, "dA") if dA is not None else None, wp, wn, _stream()))
     del keep
 

@@ -163,6 +163,24 @@ void region_extents(int order, TileGeo &tg)
     tg.lo_j = s + gl;
 }
 
+// LDS of the tiled adjoint: same tiles, no slack; FP64 accumulators of the
+// gather transpose, E and B with the gather halo, hatE with the deposit halo
+TileGeo adjoint_geo(const GridInfo &gi)
+{
+    TileGeo a = gi.tg;
+    a.slack = 0;
+    region_extents(gi.order, a);
+    return a;
+}
+
+size_t adj_lds_bytes(const GridInfo &gi)
+{
+    const TileGeo a = adjoint_geo(gi);
+    const size_t rf = (size_t)a.rf[0] * a.rf[1] * a.rf[2];
+    const size_t rj = (size_t)a.rj[0] * a.rj[1] * a.rj[2];
+    return 6 * rf * sizeof(double) + 6 * rf * gi.tsize + 3 * rj * gi.tsize;
+}
+
 size_t lds_bytes(const GridInfo &gi)
 {
     const size_t rf = (size_t)gi.tg.rf[0] * gi.tg.rf[1] * gi.tg.rf[2];
@@ -224,17 +242,26 @@ pic_status check_grid(const pic_grid *g, GridInfo &gi)
         gi.tg.slack = 0;
         region_extents(gi.order, gi.tg);
     }
-    // an automatic tile shrinks until its LDS regions fit one workgroup
-    while (lds_bytes(gi) > limit) {
+    // an automatic tile shrinks until the forward regions (with the chosen
+    // slack) and the adjoint regions (without slack) fit one workgroup
+    while (lds_bytes(gi) > limit || adj_lds_bytes(gi) > limit) {
         int dmax = -1;
         for (int d = 0; d < 3; ++d)
             if (auto_tile[d] && gi.tg.t[d] >= 4 && gi.tg.t[d] % 2 == 0 &&
-                (dmax < 0 || gi.tg.t[d] > gi.tg.t[dmax]))
+                (dmax < 0 || gi.tg.t[d] > gi.tg.t[dmax] || (gi.tg.t[d] == gi.tg.t[dmax] && d > dmax)))
                 dmax = d;
         if (dmax < 0)
             break;
         gi.tg.t[dmax] /= 2;
         region_extents(gi.order, gi.tg);
+        if (g->slack < 0 && gi.tg.slack == 0) {
+            gi.tg.slack = 1;
+            region_extents(gi.order, gi.tg);
+            if (lds_bytes(gi) > limit) {
+                gi.tg.slack = 0;
+                region_extents(gi.order, gi.tg);
+            }
+        }
     }
     if (lds_bytes(gi) > limit)
         return fail(PIC_E_UNSUPPORTED, "tile plus halo does not fit in LDS; use a smaller tile or slack");
@@ -276,7 +303,7 @@ pic_status check_fields(const pic_fields *f, bool need_j)
 
 // workspace layout
 struct WsLayout {
-    size_t err, counts, bsum, key, rank, scell, soff, su, sw, hatE, partials, red5, total;
+    size_t err, counts, bsum, key, rank, slot, scell, soff, su, sw, hatE, partials, red5, total;
 };
 
 size_t al(size_t x)
@@ -298,6 +325,8 @@ WsLayout layout(const GridInfo &gi, int64_t np)
     L.key = o;
     o += al(sizeof(int) * n);
     L.rank = o;
+    o += al(sizeof(int) * n);
+    L.slot = o;
     o += al(sizeof(int) * n);
     L.scell = o;
     o += 3 * al(sizeof(int) * n);
@@ -465,7 +494,9 @@ pic_status do_sort(const GridInfo &gi, const pic_species *sp, char *ws, const Ws
     PIC_HIP(launch_bin_count<T>(in, gi.tg, counts, key, rank, err, st));
     PIC_HIP(launch_scan(counts, gi.ncell, bsum, st));
     PIC_HIP(launch_tile_start(counts, gi.tile_cells, gi.ntiles, sp->n, tile_start, st));
-    PIC_HIP(launch_scatter<T>(in, sorted, key, rank, counts, perm, st));
+    int *slot = reinterpret_cast<int *>(ws + L.slot);
+    PIC_HIP(launch_interleave(counts, tile_start, gi.tile_cells, gi.ntiles, slot, st));
+    PIC_HIP(launch_scatter<T>(in, sorted, key, rank, counts, slot, tile_start, gi.tile_cells, perm, st));
     return PIC_OK;
 }
 
@@ -584,8 +615,8 @@ pic_status step_t(const pic_grid *g, const GridInfo &gi, pic_species *sp, pic_fi
 
 template <typename T>
 pic_status adjoint_t(const pic_grid *g, const GridInfo &gi, const pic_species *sp, const pic_fields *f,
-                     const pic_source *src, int64_t step, pic_adjoint *lam, double *dA, void *ws, const WsLayout &L,
-                     hipStream_t st)
+                     const int32_t *tile_start, const pic_source *src, int64_t step, pic_adjoint *lam, double *dA,
+                     void *ws, const WsLayout &L, hipStream_t st)
 {
     char *w = static_cast<char *>(ws);
     int *err = reinterpret_cast<int *>(w + L.err);
@@ -649,7 +680,12 @@ pic_status adjoint_t(const pic_grid *g, const GridInfo &gi, const pic_species *s
     if (sp->n > 0) {
         TimedScope tp(5, st);
         const PConst<T> pc = make_const<T>(g, sp);
-        PIC_HIP(launch_adjoint_particles<T>(gi.order, pc, parr<T>(sp), fptrs<T>(f), hat, lx, lu, lE, lB, err, st));
+        if (tile_start)
+            PIC_HIP(launch_adjoint_tile<T>(gi.order, pc, adjoint_geo(gi), parr<T>(sp), fptrs<T>(f), hat, lx, lu, lE,
+                                           lB, tile_start, err, st));
+        else
+            PIC_HIP(launch_adjoint_particles<T>(gi.order, pc, parr<T>(sp), fptrs<T>(f), hat, lx, lu, lE, lB, err,
+                                                st));
     }
     return PIC_OK;
 }
@@ -865,8 +901,8 @@ pic_status pic_step(const pic_grid *grid, pic_species *sp, pic_fields *f, const 
 }
 
 pic_status pic_step_adjoint(const pic_grid *grid, const pic_species *state_n, const pic_fields *fields_n,
-                            const pic_source *src, int64_t step, pic_adjoint *lam, double *dA, void *ws,
-                            size_t ws_bytes, void *stream)
+                            const int32_t *tile_start, const pic_source *src, int64_t step, pic_adjoint *lam,
+                            double *dA, void *ws, size_t ws_bytes, void *stream)
 {
     try {
         GridInfo gi;
@@ -883,8 +919,8 @@ pic_status pic_step_adjoint(const pic_grid *grid, const pic_species *state_n, co
         PIC_TRY(check_ws(gi, state_n->n, ws, ws_bytes, L));
         hipStream_t st = static_cast<hipStream_t>(stream);
         if (gi.dtype == PIC_F64)
-            return adjoint_t<double>(grid, gi, state_n, fields_n, src, step, lam, dA, ws, L, st);
-        return adjoint_t<float>(grid, gi, state_n, fields_n, src, step, lam, dA, ws, L, st);
+            return adjoint_t<double>(grid, gi, state_n, fields_n, tile_start, src, step, lam, dA, ws, L, st);
+        return adjoint_t<float>(grid, gi, state_n, fields_n, tile_start, src, step, lam, dA, ws, L, st);
     } catch (...) {
         return fail(PIC_E_DEVICE, "unexpected host exception");
     }

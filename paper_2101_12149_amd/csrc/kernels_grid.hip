@@ -180,14 +180,108 @@ hipError_t launch_bin_count(const PArr<T> &sp, const TileGeo &tg, int *counts, i
     return hipGetLastError();
 }
 
+// Order inside a tile: rank-major ("interleaved"), i.e. the first particle of
+// every non-empty cell in cell order, then the second particle of every cell
+// holding at least two, and so on.  Consecutive particles then sit in
+// consecutive cells, so a wave that reads them with coalesced loads has its
+// lanes in distinct neighbouring cells (distinct LDS addresses for the same
+// stencil offset).  One workgroup per tile computes the in-tile slot of
+// every (cell, rank) pair from the cell offsets of the counting sort:
+//   slot(c, r) = sum_{r' < r} #{cells with count > r'} + #{c' < c : count(c') > r}
+// written to slot_of[offset(c) + r].
+static constexpr int IL_T = 512;
+
+__device__ inline int block_excl_scan_512(int v, int *sh, int &total)
+{
+    // inclusive scan inside each wave, then over the eight wave totals
+    const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
+    int x = v;
+    for (int o = 1; o < 64; o <<= 1) {
+        const int y = __shfl_up(x, o, 64);
+        if (lane >= o)
+            x += y;
+    }
+    if (lane == 63)
+        sh[wv] = x;
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        int run = 0;
+        for (int w = 0; w < IL_T / 64; ++w) {
+            const int t = sh[w];
+            sh[w] = run;
+            run += t;
+        }
+        sh[IL_T / 64] = run;
+    }
+    __syncthreads();
+    const int res = sh[wv] + x - v;
+    total = sh[IL_T / 64];
+    __syncthreads();
+    return res;
+}
+
+__global__ void __launch_bounds__(IL_T) k_interleave(const int *offsets, const int *tile_start, int tile_cells,
+                                                     int *slot_of)
+{
+    __shared__ int sh[IL_T / 64 + 1];
+    __shared__ int smax;
+    const int t = blockIdx.x;
+    const int64_t c0 = (int64_t)t * tile_cells;
+    const int per = (tile_cells + IL_T - 1) / IL_T;   // cells per thread, contiguous
+    const int tend = tile_start[t + 1];
+    int cnt[8], off[8];
+    int mymax = 0;
+    for (int i = 0; i < per && i < 8; ++i) {
+        const int lc = threadIdx.x * per + i;
+        cnt[i] = 0;
+        off[i] = 0;
+        if (lc < tile_cells) {
+            off[i] = offsets[c0 + lc];
+            const int nxt = (lc + 1 < tile_cells) ? offsets[c0 + lc + 1] : tend;
+            cnt[i] = nxt - off[i];
+            mymax = cnt[i] > mymax ? cnt[i] : mymax;
+        }
+    }
+    if (threadIdx.x == 0)
+        smax = 0;
+    __syncthreads();
+    atomicMax(&smax, mymax);
+    __syncthreads();
+    const int levels = smax;
+    int base = 0;
+    for (int r = 0; r < levels; ++r) {
+        int mine = 0;
+        for (int i = 0; i < per && i < 8; ++i)
+            mine += cnt[i] > r ? 1 : 0;
+        int total = 0;
+        int pos = block_excl_scan_512(mine, sh, total) + base;
+        for (int i = 0; i < per && i < 8; ++i)
+            if (cnt[i] > r)
+                slot_of[off[i] + r] = pos++;
+        base += total;
+    }
+}
+
+hipError_t launch_interleave(const int *offsets, const int *tile_start, int tile_cells, int ntiles, int *slot_of,
+                             hipStream_t st)
+{
+    if (tile_cells > 8 * IL_T)
+        return hipErrorInvalidValue;
+    hipLaunchKernelGGL(k_interleave, dim3((unsigned)ntiles), dim3(IL_T), 0, st, offsets, tile_start, tile_cells,
+                       slot_of);
+    return hipGetLastError();
+}
+
 template <typename T>
 __global__ void __launch_bounds__(256) k_scatter(PArr<T> in, PArr<T> out, const int *key, const int *rank,
-                                                 const int *offsets, int *perm)
+                                                 const int *offsets, const int *slot_of, const int *tile_start,
+                                                 int tile_cells, int *perm)
 {
     const int64_t p = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (p >= in.n)
         return;
-    const int64_t q = (int64_t)offsets[key[p]] + rank[p];
+    const int k = key[p];
+    const int64_t q = (int64_t)tile_start[k / tile_cells] + slot_of[(int64_t)offsets[k] + rank[p]];
 #pragma unroll
     for (int d = 0; d < 3; ++d) {
         out.cell[d][q] = in.cell[d][p];
@@ -202,12 +296,13 @@ __global__ void __launch_bounds__(256) k_scatter(PArr<T> in, PArr<T> out, const 
 
 template <typename T>
 hipError_t launch_scatter(const PArr<T> &in, const PArr<T> &out, const int *key, const int *rank,
-                          const int *offsets, int *perm, hipStream_t st)
+                          const int *offsets, const int *slot_of, const int *tile_start, int tile_cells, int *perm,
+                          hipStream_t st)
 {
     if (in.n == 0)
         return hipSuccess;
     hipLaunchKernelGGL((k_scatter<T>), dim3((unsigned)((in.n + 255) / 256)), dim3(256), 0, st, in, out, key, rank,
-                       offsets, perm);
+                       offsets, slot_of, tile_start, tile_cells, perm);
     return hipGetLastError();
 }
 
@@ -449,7 +544,7 @@ hipError_t launch_reduce(const PArr<T> *sp, const FieldPtrs<T> &f, int64_t ncell
     template hipError_t launch_bin_count<T>(const PArr<T> &, const TileGeo &, int *, int *, int *, int *,         \
                                             hipStream_t);                                                         \
     template hipError_t launch_scatter<T>(const PArr<T> &, const PArr<T> &, const int *, const int *, const int *, \
-                                          int *, hipStream_t);                                                    \
+                                          const int *, const int *, int, int *, hipStream_t);                     \
     template hipError_t launch_reduce<T>(const PArr<T> *, const FieldPtrs<T> &, int64_t, double *, int,           \
                                          const double[7], double *, hipStream_t);
 

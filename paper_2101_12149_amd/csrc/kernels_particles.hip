@@ -216,12 +216,11 @@ __global__ void __launch_bounds__(TILE_THREADS) k_particles_tile(PConst<T> pc, T
     const int sf[3] = {1, rfx, rfx * rfy};
     const int sj[3] = {1, rjx, rjx * rjy};
     const int np = (int)(pe - ps);
-    const int per = (np + nth - 1) / nth;
-    // each thread takes a contiguous run of the tile's particles, so the
-    // lanes of a wave sit in different cells and their LDS atomics rarely
-    // hit the same address
-    for (int it = 0; it < per; ++it) {
-        const int j = tid * per + it;
+    // coalesced: the tile's particles are stored rank-major (one particle
+    // per cell, cell after cell, then the next rank), so consecutive lanes
+    // read consecutive memory and sit in distinct neighbouring cells
+    for (int j0 = 0; j0 < np; j0 += nth) {
+        const int j = j0 + tid;
         if (j < np) {
             const int64_t p = ps + j;
             int c[3];
@@ -413,37 +412,38 @@ __global__ void __launch_bounds__(256) k_deposit(PConst<T> pc, PArr<T> b, PArr<T
 // Transpose of the particle part of one step.  The forward quantities are
 // recomputed from the state at step n with the same device functions as the
 // forward kernels, so the reverse sweep follows exactly the forward rounding.
-template <typename T, int O>
-__global__ void __launch_bounds__(256)
-    k_adjoint_particles(PConst<T> pc, PArr<T> sp, FieldPtrs<T> fp, const T *hE0, const T *hE1, const T *hE2,
-                        T *lx0, T *lx1, T *lx2, T *lu0, T *lu1, T *lu2, T *lE0, T *lE1, T *lE2, T *lB0, T *lB1,
-                        T *lB2, int *err)
+// With LOCAL the particle lies inside the tile's LDS regions: fields and the
+// field adjoint hatE are read from LDS and the gather transpose accumulates
+// into the FP64 LDS tiles sLE/sLB; otherwise everything is global.
+template <typename T>
+struct AdjPtrs {
+    const T *hat[3];   // hatE: lE - dt/2 curl_b(lB), the current adjoint is lj * hatE
+    T *lx[3], *lu[3], *lE[3], *lB[3];
+};
+
+template <typename T, int O, bool LOCAL>
+__device__ inline void adjoint_particle(const PConst<T> &pc, const PArr<T> &sp, const AdjPtrs<T> &ap,
+                                        const FieldSrc<T> &fsrc, const T *const *hsrc, int64_t p, const int *c,
+                                        const T *f, const T *u, const int *l, int lo_f, const int *sf, int lo_j,
+                                        const int *sj, double *sL, int rfvol, int *err)
 {
     constexpr int NW = Shape<O, T>::NW;
-    const int64_t p = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    if (p >= sp.n)
-        return;
-    int c[3];
-    T f[3], u[3];
-    if (!load_particle(sp, p, pc.n, c, f, u, err))
-        return;
     const int gs[3] = {1, pc.n[0], pc.n[0] * pc.n[1]};
     AxisW<O, T> aw[3];
     int on[3][NW], os[3][NW];
 #pragma unroll
     for (int d = 0; d < 3; ++d) {
         axis_weights<O>(f[d], aw[d]);
-        axis_offsets_global<NW>(c[d], aw[d].bn, pc.n[d], gs[d], on[d]);
-        axis_offsets_global<NW>(c[d], aw[d].bs, pc.n[d], gs[d], os[d]);
-    }
-    FieldSrc<T> gf;
-#pragma unroll
-    for (int m = 0; m < 3; ++m) {
-        gf.c[m] = fp.E[m];
-        gf.c[3 + m] = fp.B[m];
+        if (LOCAL) {
+            axis_offsets_local<NW>(l[d] + lo_f, aw[d].bn, sf[d], on[d]);
+            axis_offsets_local<NW>(l[d] + lo_f, aw[d].bs, sf[d], os[d]);
+        } else {
+            axis_offsets_global<NW>(c[d], aw[d].bn, pc.n[d], gs[d], on[d]);
+            axis_offsets_global<NW>(c[d], aw[d].bs, pc.n[d], gs[d], os[d]);
+        }
     }
     T E[3], B[3];
-    gather_eb<O>(gf, aw, on, os, E, B);
+    gather_eb<O>(fsrc, aw, on, os, E, B);
     BorisTape<T> tp;
     T u1[3];
     boris(pc.h, pc.inv_c2, u, E, B, u1, tp);
@@ -472,17 +472,18 @@ __global__ void __launch_bounds__(256)
         esk_axis<O>(f[d], f1[d], kap[d], e[d]);
         esk_axis_deriv<O>(f[d], f1[d], kap[d], dS0[d], dDS1[d]);
         K[d] = pc.jk[d] * w * pc.lj;
-        axis_offsets_global<NW + 1>(c[d], e[d].lo, pc.n[d], gs[d], jo[d]);
+        if (LOCAL)
+            axis_offsets_local<NW + 1>(l[d] + lo_j, e[d].lo, sj[d], jo[d]);
+        else
+            axis_offsets_global<NW + 1>(c[d], e[d].lo, pc.n[d], gs[d], jo[d]);
     }
-    const T *hE[3] = {hE0, hE1, hE2};
     T g0[3], g1[3];
-    esk_gather_adjoint<O>(e, dS0, dDS1, jo, K, [&](int m, int idx) { return hE[m][idx]; }, g0, g1);
-    T *LX[3] = {lx0, lx1, lx2}, *LU[3] = {lu0, lu1, lu2};
+    esk_gather_adjoint<O>(e, dS0, dDS1, jo, K, [&](int m, int idx) { return hsrc[m][idx]; }, g0, g1);
     T lxa[3], lxb[3], v[3];
     T uv = T(0);
 #pragma unroll
     for (int d = 0; d < 3; ++d) {
-        lxb[d] = LX[d][p] + g1[d];                 // dL/dx^{n+1} incl. the deposit
+        lxb[d] = ap.lx[d][p] + g1[d];              // dL/dx^{n+1} incl. the deposit
         lxa[d] = g0[d] + lxb[d];                   // x^{n+1} = x^n + disp
         v[d] = pc.dtd[d] * lxb[d];
         uv += u1[d] * v[d];
@@ -492,7 +493,7 @@ __global__ void __launch_bounds__(256)
     const T ig3 = ig * ig * ig * pc.inv_c2 * uv;
 #pragma unroll
     for (int d = 0; d < 3; ++d)
-        ub[d] = LU[d][p] + v[d] * ig - u1[d] * ig3;
+        ub[d] = ap.lu[d][p] + v[d] * ig - u1[d] * ig3;
     T u0b[3], Eb[3], Bb[3];
     boris_adjoint(pc.h, pc.inv_c2, B, tp, ub, u0b, Eb, Bb);
     // gather transpose: scatter S * (Eb, Bb) and add the shape gradient
@@ -500,14 +501,12 @@ __global__ void __launch_bounds__(256)
 #pragma unroll
     for (int d = 0; d < 3; ++d)
         axis_dweights<O>(f[d], dn[d], ds[d]);
-    T *LE[3] = {lE0, lE1, lE2}, *LB[3] = {lB0, lB1, lB2};
     // component staggering: E_x(s,n,n) E_y(n,s,n) E_z(n,n,s) B_x(n,s,s) B_y(s,n,s) B_z(s,s,n)
     const bool stag[6][3] = {{1, 0, 0}, {0, 1, 0}, {0, 0, 1}, {0, 1, 1}, {1, 0, 1}, {1, 1, 0}};
 #pragma unroll
     for (int comp = 0; comp < 6; ++comp) {
         const T vb = comp < 3 ? Eb[comp] : Bb[comp - 3];
-        const T *F = gf.c[comp];
-        T *L = comp < 3 ? LE[comp] : LB[comp - 3];
+        const T *F = fsrc.c[comp];
         const T *wx = stag[comp][0] ? aw[0].ws : aw[0].wn;
         const T *wy = stag[comp][1] ? aw[1].ws : aw[1].wn;
         const T *wz = stag[comp][2] ? aw[2].ws : aw[2].wn;
@@ -523,13 +522,17 @@ __global__ void __launch_bounds__(256)
 #pragma unroll
             for (int j = 0; j < NW; ++j) {
                 const int rowo = yo[j] + zo[k];
+                const T wyz = wy[j] * wz[k] * vb;
                 T ax = T(0), adx = T(0);
 #pragma unroll
                 for (int i = 0; i < NW; ++i) {
                     const T val = F[rowo + xo[i]];
                     ax += wx[i] * val;
                     adx += dx[i] * val;
-                    gatomic_add(L + rowo + xo[i], wx[i] * wy[j] * wz[k] * vb);
+                    if (LOCAL)
+                        latomic_add(sL + comp * rfvol + rowo + xo[i], (double)(wx[i] * wyz));
+                    else
+                        gatomic_add((comp < 3 ? ap.lE[comp] : ap.lB[comp - 3]) + rowo + xo[i], wx[i] * wyz);
                 }
                 gx += adx * wy[j] * wz[k];
                 gy += ax * dy[j] * wz[k];
@@ -541,8 +544,144 @@ __global__ void __launch_bounds__(256)
     }
 #pragma unroll
     for (int d = 0; d < 3; ++d) {
-        LX[d][p] = lxa[d];
-        LU[d][p] = u0b[d];
+        ap.lx[d][p] = lxa[d];
+        ap.lu[d][p] = u0b[d];
+    }
+}
+
+template <typename T, int O>
+__global__ void __launch_bounds__(256) k_adjoint_particles(PConst<T> pc, PArr<T> sp, FieldPtrs<T> fp, AdjPtrs<T> ap,
+                                                           int *err)
+{
+    const int64_t p = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (p >= sp.n)
+        return;
+    int c[3];
+    T f[3], u[3];
+    if (!load_particle(sp, p, pc.n, c, f, u, err))
+        return;
+    FieldSrc<T> gf;
+#pragma unroll
+    for (int m = 0; m < 3; ++m) {
+        gf.c[m] = fp.E[m];
+        gf.c[3 + m] = fp.B[m];
+    }
+    const int z3[3] = {0, 0, 0};
+    adjoint_particle<T, O, false>(pc, sp, ap, gf, ap.hat, p, c, f, u, z3, 0, z3, 0, z3, nullptr, 0, err);
+}
+
+// Tiled transpose: one workgroup per tile of the binning the forward sort
+// produced.  LDS holds E, B with the gather halo, hatE with the deposit
+// halo, and FP64 accumulators of the gather transpose (flushed with one
+// global atomic per non-zero value).  No slack: particles outside the tile
+// take the global path.
+template <typename T, int O>
+__global__ void __launch_bounds__(TILE_THREADS) k_adjoint_tile(PConst<T> pc, TileGeo tg, PArr<T> sp, FieldPtrs<T> fp,
+                                                               AdjPtrs<T> ap, const int *__restrict__ tile_start,
+                                                               int *err)
+{
+    extern __shared__ __align__(16) unsigned char smem_raw[];
+    const int rfx = tg.rf[0], rfy = tg.rf[1];
+    const int rfvol = rfx * rfy * tg.rf[2];
+    const int rjx = tg.rj[0], rjy = tg.rj[1];
+    const int rjvol = rjx * rjy * tg.rj[2];
+    double *sL = reinterpret_cast<double *>(smem_raw);                  // 6 * rfvol doubles
+    T *sF = reinterpret_cast<T *>(smem_raw + 6 * rfvol * sizeof(double));
+    T *sH = sF + 6 * rfvol;                                              // 3 * rjvol
+
+    const int ntiles = tg.nt[0] * tg.nt[1] * tg.nt[2];
+    int t = blockIdx.x;
+    if (tg.xcd_map)
+        t = (t & 7) * (ntiles >> 3) + (t >> 3);
+    const int tx = t % tg.nt[0], ty = (t / tg.nt[0]) % tg.nt[1], tz = t / (tg.nt[0] * tg.nt[1]);
+    const int t0[3] = {tx * tg.t[0], ty * tg.t[1], tz * tg.t[2]};
+    const int64_t N = sp.n;
+    int64_t ps = tile_start[t], pe = tile_start[t + 1];
+    ps = ps < 0 ? 0 : (ps > N ? N : ps);
+    pe = pe < ps ? ps : (pe > N ? N : pe);
+    if (pe <= ps)
+        return;   // uniform across the workgroup
+
+    const int tid = threadIdx.x, nth = blockDim.x;
+    for (int r = tid; r < rfvol; r += nth) {
+        const int rx = r % rfx, ry = (r / rfx) % rfy, rz = r / (rfx * rfy);
+        const int gx = wrap_any(t0[0] - tg.lo_f + rx, pc.n[0]);
+        const int gy = wrap_any(t0[1] - tg.lo_f + ry, pc.n[1]);
+        const int gz = wrap_any(t0[2] - tg.lo_f + rz, pc.n[2]);
+        const int gi = gx + pc.n[0] * (gy + pc.n[1] * gz);
+#pragma unroll
+        for (int m = 0; m < 3; ++m) {
+            sF[m * rfvol + r] = fp.E[m][gi];
+            sF[(3 + m) * rfvol + r] = fp.B[m][gi];
+        }
+#pragma unroll
+        for (int m = 0; m < 6; ++m)
+            sL[m * rfvol + r] = 0.0;
+    }
+    for (int r = tid; r < rjvol; r += nth) {
+        const int rx = r % rjx, ry = (r / rjx) % rjy, rz = r / (rjx * rjy);
+        const int gx = wrap_any(t0[0] - tg.lo_j + rx, pc.n[0]);
+        const int gy = wrap_any(t0[1] - tg.lo_j + ry, pc.n[1]);
+        const int gz = wrap_any(t0[2] - tg.lo_j + rz, pc.n[2]);
+        const int gi = gx + pc.n[0] * (gy + pc.n[1] * gz);
+#pragma unroll
+        for (int m = 0; m < 3; ++m)
+            sH[m * rjvol + r] = ap.hat[m][gi];
+    }
+    __syncthreads();
+
+    FieldSrc<T> lf, gf;
+#pragma unroll
+    for (int m = 0; m < 3; ++m) {
+        lf.c[m] = sF + m * rfvol;
+        lf.c[3 + m] = sF + (3 + m) * rfvol;
+        gf.c[m] = fp.E[m];
+        gf.c[3 + m] = fp.B[m];
+    }
+    const T *lh[3] = {sH, sH + rjvol, sH + 2 * rjvol};
+    const int sf[3] = {1, rfx, rfx * rfy};
+    const int sj[3] = {1, rjx, rjx * rjy};
+    const int np = (int)(pe - ps);
+    for (int j0 = 0; j0 < np; j0 += nth) {
+        const int j = j0 + tid;
+        if (j < np) {
+            const int64_t p = ps + j;
+            int c[3];
+            T f[3], u[3];
+            if (load_particle(sp, p, pc.n, c, f, u, err)) {
+                int l[3];
+                bool inside = true;
+#pragma unroll
+                for (int d = 0; d < 3; ++d) {
+                    int v = c[d] - t0[d];
+                    if (v < -tg.slack)
+                        v += pc.n[d];
+                    else if (v >= tg.t[d] + tg.slack)
+                        v -= pc.n[d];
+                    l[d] = v;
+                    inside = inside && v >= -tg.slack && v < tg.t[d] + tg.slack;
+                }
+                if (inside)
+                    adjoint_particle<T, O, true>(pc, sp, ap, lf, lh, p, c, f, u, l, tg.lo_f, sf, tg.lo_j, sj, sL,
+                                                 rfvol, err);
+                else
+                    adjoint_particle<T, O, false>(pc, sp, ap, gf, ap.hat, p, c, f, u, l, tg.lo_f, sf, tg.lo_j, sj,
+                                                  nullptr, rfvol, err);
+            }
+        }
+    }
+    __syncthreads();
+    for (int r = tid; r < 6 * rfvol; r += nth) {
+        const T v = (T)sL[r];
+        if (v != T(0)) {
+            const int m = r / rfvol, rr = r - m * rfvol;
+            const int rx = rr % rfx, ry = (rr / rfx) % rfy, rz = rr / (rfx * rfy);
+            const int gx = wrap_any(t0[0] - tg.lo_f + rx, pc.n[0]);
+            const int gy = wrap_any(t0[1] - tg.lo_f + ry, pc.n[1]);
+            const int gz = wrap_any(t0[2] - tg.lo_f + rz, pc.n[2]);
+            T *dst = m < 3 ? ap.lE[m] : ap.lB[m - 3];
+            gatomic_add(dst + gx + pc.n[0] * (gy + pc.n[1] * gz), v);
+        }
     }
 }
 
@@ -644,21 +783,69 @@ hipError_t launch_deposit(int order, const PConst<T> &pc, const PArr<T> &before,
 }
 
 template <typename T>
+static AdjPtrs<T> adj_ptrs(T *const hatE[3], T *const lx[3], T *const lu[3], T *const lE[3], T *const lB[3])
+{
+    AdjPtrs<T> a{};
+    for (int d = 0; d < 3; ++d) {
+        a.hat[d] = hatE[d];
+        a.lx[d] = lx[d];
+        a.lu[d] = lu[d];
+        a.lE[d] = lE[d];
+        a.lB[d] = lB[d];
+    }
+    return a;
+}
+
+template <typename T>
 hipError_t launch_adjoint_particles(int order, const PConst<T> &pc, const PArr<T> &sp, const FieldPtrs<T> &f,
                                     T *const hatE[3], T *const lx[3], T *const lu[3], T *const lE[3],
                                     T *const lB[3], int *err, hipStream_t st)
 {
     if (sp.n == 0)
         return hipSuccess;
+    const AdjPtrs<T> ap = adj_ptrs<T>(hatE, lx, lu, lE, lB);
     if (order == 1)
-        hipLaunchKernelGGL((k_adjoint_particles<T, 1>), dim3(nblk(sp.n, 256)), dim3(256), 0, st, pc, sp, f,
-                           hatE[0], hatE[1], hatE[2], lx[0], lx[1], lx[2], lu[0], lu[1], lu[2], lE[0], lE[1],
-                           lE[2], lB[0], lB[1], lB[2], err);
+        hipLaunchKernelGGL((k_adjoint_particles<T, 1>), dim3(nblk(sp.n, 256)), dim3(256), 0, st, pc, sp, f, ap, err);
     else
-        hipLaunchKernelGGL((k_adjoint_particles<T, 3>), dim3(nblk(sp.n, 256)), dim3(256), 0, st, pc, sp, f,
-                           hatE[0], hatE[1], hatE[2], lx[0], lx[1], lx[2], lu[0], lu[1], lu[2], lE[0], lE[1],
-                           lE[2], lB[0], lB[1], lB[2], err);
+        hipLaunchKernelGGL((k_adjoint_particles<T, 3>), dim3(nblk(sp.n, 256)), dim3(256), 0, st, pc, sp, f, ap, err);
     return hipGetLastError();
+}
+
+template <typename T>
+size_t adjoint_lds_bytes(int, const TileGeo &tg)
+{
+    const size_t rf = (size_t)tg.rf[0] * tg.rf[1] * tg.rf[2];
+    const size_t rj = (size_t)tg.rj[0] * tg.rj[1] * tg.rj[2];
+    return 6 * rf * sizeof(double) + 6 * rf * sizeof(T) + 3 * rj * sizeof(T);
+}
+
+template <typename T, int O>
+static hipError_t launch_adj_tile_o(const PConst<T> &pc, const TileGeo &tg, const PArr<T> &sp, const FieldPtrs<T> &f,
+                                    const AdjPtrs<T> &ap, const int *tile_start, int *err, hipStream_t st)
+{
+    const size_t lds = adjoint_lds_bytes<T>(O, tg);
+    static bool attr_set = false;
+    if (!attr_set) {
+        hipFuncSetAttribute(reinterpret_cast<const void *>(&k_adjoint_tile<T, O>),
+                            hipFuncAttributeMaxDynamicSharedMemorySize, 160 * 1024);
+        attr_set = true;
+    }
+    const unsigned ntiles = (unsigned)(tg.nt[0] * tg.nt[1] * tg.nt[2]);
+    hipLaunchKernelGGL((k_adjoint_tile<T, O>), dim3(ntiles), dim3(TILE_THREADS), lds, st, pc, tg, sp, f, ap,
+                       tile_start, err);
+    return hipGetLastError();
+}
+
+template <typename T>
+hipError_t launch_adjoint_tile(int order, const PConst<T> &pc, const TileGeo &tg, const PArr<T> &sp,
+                               const FieldPtrs<T> &f, T *const hatE[3], T *const lx[3], T *const lu[3],
+                               T *const lE[3], T *const lB[3], const int *tile_start, int *err, hipStream_t st)
+{
+    if (sp.n == 0)
+        return hipSuccess;
+    const AdjPtrs<T> ap = adj_ptrs<T>(hatE, lx, lu, lE, lB);
+    return order == 1 ? launch_adj_tile_o<T, 1>(pc, tg, sp, f, ap, tile_start, err, st)
+                      : launch_adj_tile_o<T, 3>(pc, tg, sp, f, ap, tile_start, err, st);
 }
 
 #define PIC_INST(T)                                                                                               \
@@ -676,7 +863,11 @@ hipError_t launch_adjoint_particles(int order, const PConst<T> &pc, const PArr<T
                                           const FieldPtrs<T> &, int *, hipStream_t);                               \
     template hipError_t launch_adjoint_particles<T>(int, const PConst<T> &, const PArr<T> &, const FieldPtrs<T> &, \
                                                     T *const[3], T *const[3], T *const[3], T *const[3],            \
-                                                    T *const[3], int *, hipStream_t);
+                                                    T *const[3], int *, hipStream_t);                              \
+    template size_t adjoint_lds_bytes<T>(int, const TileGeo &);                                                    \
+    template hipError_t launch_adjoint_tile<T>(int, const PConst<T> &, const TileGeo &, const PArr<T> &,           \
+                                               const FieldPtrs<T> &, T *const[3], T *const[3], T *const[3],        \
+                                               T *const[3], T *const[3], const int *, int *, hipStream_t);
 
 PIC_INST(float)
 PIC_INST(double)

@@ -95,6 +95,12 @@ hipError_t launch_adjoint_particles(int order, const PConst<T> &pc, const PArr<T
                                     T *const lB[3], int *err, hipStream_t st);
 template <typename T>
 size_t tile_lds_bytes(int order, const TileGeo &tg);
+template <typename T>
+size_t adjoint_lds_bytes(int order, const TileGeo &tg);
+template <typename T>
+hipError_t launch_adjoint_tile(int order, const PConst<T> &pc, const TileGeo &tg, const PArr<T> &sp,
+                               const FieldPtrs<T> &f, T *const hatE[3], T *const lx[3], T *const lu[3],
+                               T *const lE[3], T *const lB[3], const int *tile_start, int *err, hipStream_t st);
 
 template <typename T>
 hipError_t launch_curl(bool forward, const CurlArgs<T> &a, hipStream_t st);
@@ -108,7 +114,10 @@ hipError_t launch_bin_count(const PArr<T> &sp, const TileGeo &tg, int *counts, i
                             hipStream_t st);
 template <typename T>
 hipError_t launch_scatter(const PArr<T> &in, const PArr<T> &out, const int *key, const int *rank,
-                          const int *offsets, int *perm, hipStream_t st);
+                          const int *offsets, const int *slot_of, const int *tile_start, int tile_cells, int *perm,
+                          hipStream_t st);
+hipError_t launch_interleave(const int *offsets, const int *tile_start, int tile_cells, int ntiles, int *slot_of,
+                             hipStream_t st);
 hipError_t launch_scan(int *data, int64_t n, int *block_sums, hipStream_t st);
 hipError_t launch_tile_start(const int *offsets, int tile_cells, int ntiles, int64_t nparticles, int *tile_start,
                              hipStream_t st);

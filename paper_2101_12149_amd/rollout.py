@@ -8,9 +8,13 @@ Backward: for each checkpoint segment, last first, the segment is replayed
 from its checkpoint keeping every step's input state, then the steps are
 reversed with pic_step_adjoint.  Returns dL/du0 and dL/damp.
 
-Particles are not re-sorted inside the rollout, so the particle order of the
-adjoint arrays is the order of u0.  All arithmetic runs in the library's
-kernels; this module only orders the calls and holds device buffers.
+With `tiled` (the default) the particles are binned by tile once, before the
+first step (pic_sort_tiles, keeping the permutation); every forward step and
+every adjoint step then runs the tile kernels on that binning, and dL/du0 is
+scattered back to the order of u0.  Particles are not re-sorted inside the
+rollout, so one binning serves the whole reverse sweep.  All arithmetic runs
+in the library's kernels; this module only orders the calls and holds device
+buffers.
 """
 import torch
 
@@ -23,7 +27,7 @@ class Problem:
     initial fields, the source time series, step count and checkpoint
     interval.  Tensors live on the device in the working precision."""
 
-    def __init__(self, grid, species, fields, source, nsteps, checkpoint_every, dtype):
+    def __init__(self, grid, species, fields, source, nsteps, checkpoint_every, dtype, tiled=True):
         self.grid = grid
         self.species = species
         self.fields = fields
@@ -32,6 +36,11 @@ class Problem:
         self.k = max(1, int(checkpoint_every or nsteps))
         self.dtype = dtype
         self.ws = _lib.workspace(grid, dtype, species.n)
+        self.tiled = bool(tiled) and species.n > 0
+        self.tile_start = None
+        if self.tiled:
+            self.tile_start = torch.zeros(_lib.pic_tile_count(grid, dtype) + 1, dtype=torch.int32,
+                                          device=species.off.device)
 
     def source_with(self, amp):
         if self.source is None:
@@ -49,7 +58,7 @@ class _Adjoint:
 
 def _advance(pb, sp, f, src, step0, nsteps):
     if nsteps > 0:
-        _lib.pic_step(pb.grid, sp, f, src, step0, nsteps, 0, None, pb.ws)
+        _lib.pic_step(pb.grid, sp, f, src, step0, nsteps, 0, pb.tile_start, pb.ws)
 
 
 class PICRollout(torch.autograd.Function):
@@ -57,6 +66,10 @@ class PICRollout(torch.autograd.Function):
     def forward(ctx, u0, amp, pb):
         sp = pb.species.clone()
         sp.u = u0.detach().clone().contiguous()
+        perm = None
+        if pb.tiled:
+            perm = torch.empty(sp.n, dtype=torch.int32, device=sp.off.device)
+            _lib.pic_sort_tiles(pb.grid, sp, pb.tile_start, pb.ws, perm=perm)
         f = pb.fields.clone()
         src = pb.source_with(amp) if amp is not None else None
         checkpoints = []
@@ -73,6 +86,7 @@ class PICRollout(torch.autograd.Function):
         ctx.checkpoints = checkpoints
         ctx.final_fields = f
         ctx.has_amp = amp is not None
+        ctx.perm = perm
         return loss[0].clone()
 
     @staticmethod
@@ -94,9 +108,13 @@ class PICRollout(torch.autograd.Function):
                 _advance(pb, sp, f, src, s0 + i, 1)
             for i in reversed(range(n)):
                 sp_n, f_n = states[i]
-                _lib.pic_step_adjoint(pb.grid, sp_n, f_n, src, s0 + i, lam, dA, pb.ws)
+                _lib.pic_step_adjoint(pb.grid, sp_n, f_n, src, s0 + i, lam, dA, pb.ws, tile_start=pb.tile_start)
         ctx.checkpoints = None
-        du0 = lam.lu.clone()
+        if ctx.perm is not None:
+            du0 = torch.empty_like(lam.lu)
+            du0[:, ctx.perm.long()] = lam.lu      # back to the order of u0
+        else:
+            du0 = lam.lu.clone()
         damp = dA.to(src.amp.dtype) if dA is not None else None
         return du0, damp, None
 

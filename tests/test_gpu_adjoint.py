@@ -38,9 +38,13 @@ def _oracle_lambda(lam):
     return a
 
 
+@pytest.mark.parametrize("tiled", [False, True])
 @pytest.mark.parametrize("order", [1, 3])
 @pytest.mark.parametrize("dtype", ["f64", "f32"])
-def test_adjoint_step_matches_oracle(order, dtype):
+def test_adjoint_step_matches_oracle(order, dtype, tiled):
+    """One reverse step with random adjoint inputs; the tiled variant bins the
+    particles first (most particles in their tile's LDS region, some thrown
+    outside it by the high thermal speed) and permutes the results back."""
     g = wl.plasma_grid((12, 16, 20), order)
     n = 3000
     sp = random_species(g, n, 101, u_th=0.2, dtype=dtype)
@@ -49,11 +53,25 @@ def test_adjoint_step_matches_oracle(order, dtype):
     src = wl.Source(4, amp.to(tdtype(dtype)), np.array([0.2, -0.7, 1.1, 0.4]))
     lam = _random_lambda(g, n, 104, dtype)
     olam = _oracle_lambda(lam)
+    dsp = dev(sp)
     dlam = NS(lx=dev(lam.lx), lu=dev(lam.lu), lE=dev(lam.lE), lB=dev(lam.lB))
     dA = torch.zeros((16, 12), dtype=torch.float64, device="cuda")
     ws = _lib.workspace(g, dtype, n)
-    _lib.pic_step_adjoint(g, dev(sp), dev(f), src.to(device="cuda"), 2, dlam, dA, ws)
+    ts = None
+    if tiled:
+        ts = torch.zeros(_lib.pic_tile_count(g, dtype) + 1, dtype=torch.int32, device="cuda")
+        perm = torch.empty(n, dtype=torch.int32, device="cuda")
+        _lib.pic_sort_tiles(g, dsp, ts, ws, perm=perm)
+        pl = perm.long()
+        dlam.lx = dlam.lx[:, pl].contiguous()
+        dlam.lu = dlam.lu[:, pl].contiguous()
+    _lib.pic_step_adjoint(g, dsp, dev(f), src.to(device="cuda"), 2, dlam, dA, ws, tile_start=ts)
     torch.cuda.synchronize()
+    if tiled:
+        for name in ("lx", "lu"):
+            back = torch.empty_like(getattr(dlam, name))
+            back[:, pl] = getattr(dlam, name)
+            setattr(dlam, name, back)
     odA = np.zeros((16, 12))
     oracle.step_adjoint(g, sp.numpy(), f.numpy(), src.numpy(), 2, olam, odA)
     tol = 1e-12 if dtype == "f64" else 1e-4
@@ -81,11 +99,11 @@ def test_energy_loss_and_seed():
     assert torch.count_nonzero(lam.lx) == 0 and torch.count_nonzero(lam.lu) == 0
 
 
-def _problem(w):
+def _problem(w, tiled=True):
     g = w.grid
     sp, f = dev(w.species), dev(w.fields)
     src = w.source.to(device="cuda") if w.source is not None else None
-    return ro.Problem(g, sp, f, src, w.nsteps, w.checkpoint_every, w.dtype)
+    return ro.Problem(g, sp, f, src, w.nsteps, w.checkpoint_every, w.dtype, tiled=tiled)
 
 
 def _gpu_loss(pb, u0, amp):
@@ -93,12 +111,13 @@ def _gpu_loss(pb, u0, amp):
         return ro.rollout_loss(u0, amp, pb).item()
 
 
-def test_rollout_gradient_matches_oracle_reverse_sweep():
+@pytest.mark.parametrize("tiled", [False, True])
+def test_rollout_gradient_matches_oracle_reverse_sweep(tiled):
     """Reduced differentiable workload (16^3, 2 ppc, order 3, FP64, 8 steps,
     checkpoint every 3): torch autograd through the GPU rollout against the
     oracle's own forward + reverse sweep."""
     w = wl.differentiable((16, 16, 16), 2, 0.05, 3, 8, "f64", 1234, checkpoint_every=3, amp0=5e-3, period=6)
-    pb = _problem(w)
+    pb = _problem(w, tiled)
     u0 = pb.species.u.clone().requires_grad_(True)
     amp = pb.source.amp.clone().requires_grad_(True)
     L = ro.rollout_loss(u0, amp, pb)

@@ -156,13 +156,21 @@ def test_sort_tiles_is_a_binning_permutation():
     assert torch.equal(d.off.cpu(), sp.off[:, p])
     assert torch.equal(d.u.cpu(), sp.u[:, p])
     assert torch.equal(d.w.cpu(), sp.w[p])
-    # tile-major cell keys are non-decreasing; tile_start is the histogram prefix
+    # tiles are contiguous and in order; inside a tile the order is rank-major:
+    # (occurrence of the particle's cell so far, local cell) strictly increases
     tx, ty, tz = 8, 8, 8
     c = d.cell.cpu().numpy().astype(np.int64)
     tile = (c[0] // tx) + (g.n[0] // tx) * ((c[1] // ty) + (g.n[1] // ty) * (c[2] // tz))
     local = (c[0] % tx) + tx * ((c[1] % ty) + ty * (c[2] % tz))
-    key = tile * (tx * ty * tz) + local
-    assert np.all(np.diff(key) >= 0)
+    assert np.all(np.diff(tile) >= 0)
+    seen = {}
+    occ = np.empty(sp.n, dtype=np.int64)
+    for j in range(sp.n):
+        k = (tile[j], local[j])
+        occ[j] = seen.get(k, 0)
+        seen[k] = occ[j] + 1
+    key2 = tile * (1 << 40) + occ * (1 << 20) + local
+    assert np.all(np.diff(key2) > 0)
     hist = np.bincount(tile, minlength=nt)
     assert nt == (g.n[0] // tx) * (g.n[1] // ty) * (g.n[2] // tz)
     want = np.concatenate([[0], np.cumsum(hist)])
