@@ -680,7 +680,11 @@ pic_status adjoint_t(const pic_grid *g, const GridInfo &gi, const pic_species *s
     if (sp->n > 0) {
         TimedScope tp(5, st);
         const PConst<T> pc = make_const<T>(g, sp);
-        if (tile_start)
+        // The tiled FP64 order-3 transpose is switched off: that instantiation
+        // spills over a thousand registers and returned wrong position
+        // adjoints on the device, so it takes the per-particle kernel.
+        const bool tiled_ok = !(gi.dtype == PIC_F64 && gi.order == 3);
+        if (tile_start && tiled_ok)
             PIC_HIP(launch_adjoint_tile<T>(gi.order, pc, adjoint_geo(gi), parr<T>(sp), fptrs<T>(f), hat, lx, lu, lE,
                                            lB, tile_start, err, st));
         else

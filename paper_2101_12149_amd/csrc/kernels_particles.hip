@@ -21,6 +21,9 @@ namespace pic {
 // thread takes about one cell's particles, so neighbouring lanes touch
 // neighbouring LDS words
 constexpr int TILE_THREADS = 512;
+// the adjoint keeps far more values live per particle; one wave per SIMD
+// gives it the full register file
+constexpr int ADJ_THREADS = 256;
 
 template <typename T>
 __device__ inline void gatomic_add(T *p, T v)
@@ -90,7 +93,7 @@ __device__ inline void copy_particle(const PArr<T> &in, const PArr<T> &out, int6
 // particle lies in the LDS regions (positions l[] relative to the tile);
 // otherwise everything is read and scattered in global memory.
 template <typename T, int O, bool LOCAL>
-__device__ inline void particle_step(const PConst<T> &pc, const PArr<T> &in, const PArr<T> &out,
+__device__ __attribute__((always_inline)) inline void particle_step(const PConst<T> &pc, const PArr<T> &in, const PArr<T> &out,
                                      const FieldPtrs<T> &fp, const FieldSrc<T> &fsrc, int64_t p, const int *c,
                                      const T *f, const T *u, const int *l, int lo_f, const int *sf, int lo_j,
                                      const int *sj, double *sJ, int rjvol, int *err)
@@ -421,16 +424,58 @@ struct AdjPtrs {
     T *lx[3], *lu[3], *lE[3], *lB[3];
 };
 
+// Gather transpose of one field component with staggering (SX, SY, SZ):
+// scatter S * vb into the component's adjoint (FP64 LDS accumulators or
+// global atomics) and add vb * grad(gathered value) to the position adjoint.
+template <int O, typename T, bool LOCAL, int SX, int SY, int SZ>
+__device__ __attribute__((always_inline)) inline void gather_transpose(const T *F, T *Lglob, double *sL, int lbase, T vb, const AxisW<O, T> *aw,
+                                        const T (*dn)[Shape<O, T>::NW], const T (*ds)[Shape<O, T>::NW],
+                                        const int (*on)[Shape<O, T>::NW], const int (*os)[Shape<O, T>::NW], T *lxa)
+{
+    constexpr int NW = Shape<O, T>::NW;
+    const T *wx = SX ? aw[0].ws : aw[0].wn;
+    const T *wy = SY ? aw[1].ws : aw[1].wn;
+    const T *wz = SZ ? aw[2].ws : aw[2].wn;
+    const T *dx = SX ? ds[0] : dn[0];
+    const T *dy = SY ? ds[1] : dn[1];
+    const T *dz = SZ ? ds[2] : dn[2];
+    const int *xo = SX ? os[0] : on[0];
+    const int *yo = SY ? os[1] : on[1];
+    const int *zo = SZ ? os[2] : on[2];
+    T gx = T(0), gy = T(0), gz = T(0);
+#pragma unroll
+    for (int k = 0; k < NW; ++k)
+#pragma unroll
+        for (int j = 0; j < NW; ++j) {
+            const int rowo = yo[j] + zo[k];
+            const T wyz = wy[j] * wz[k] * vb;
+            T ax = T(0), adx = T(0);
+#pragma unroll
+            for (int i = 0; i < NW; ++i) {
+                const T val = F[rowo + xo[i]];
+                ax += wx[i] * val;
+                adx += dx[i] * val;
+                if (LOCAL)
+                    latomic_add(sL + lbase + rowo + xo[i], (double)(wx[i] * wyz));
+                else
+                    gatomic_add(Lglob + rowo + xo[i], wx[i] * wyz);
+            }
+            gx += adx * wy[j] * wz[k];
+            gy += ax * dy[j] * wz[k];
+            gz += ax * wy[j] * dz[k];
+        }
+    lxa[0] += vb * gx;
+    lxa[1] += vb * gy;
+    lxa[2] += vb * gz;
+}
+
 template <typename T, int O, bool LOCAL>
-__device__ inline void adjoint_particle(const PConst<T> &pc, const PArr<T> &sp, const AdjPtrs<T> &ap,
-                                        const FieldSrc<T> &fsrc, const T *const *hsrc, int64_t p, const int *c,
-                                        const T *f, const T *u, const int *l, int lo_f, const int *sf, int lo_j,
-                                        const int *sj, double *sL, int rfvol, int *err)
+__device__ __attribute__((always_inline)) inline void adjoint_offsets(const PConst<T> &pc, const int *c, const T *f, const int *l, int lo_f,
+                                       const int *sf, AxisW<O, T> *aw, int (*on)[Shape<O, T>::NW],
+                                       int (*os)[Shape<O, T>::NW])
 {
     constexpr int NW = Shape<O, T>::NW;
     const int gs[3] = {1, pc.n[0], pc.n[0] * pc.n[1]};
-    AxisW<O, T> aw[3];
-    int on[3][NW], os[3][NW];
 #pragma unroll
     for (int d = 0; d < 3; ++d) {
         axis_weights<O>(f[d], aw[d]);
@@ -442,8 +487,24 @@ __device__ inline void adjoint_particle(const PConst<T> &pc, const PArr<T> &sp, 
             axis_offsets_global<NW>(c[d], aw[d].bs, pc.n[d], gs[d], os[d]);
         }
     }
+}
+
+template <typename T, int O, bool LOCAL>
+__device__ __attribute__((always_inline)) inline void adjoint_particle(const PConst<T> &pc, const PArr<T> &sp, const AdjPtrs<T> &ap,
+                                        const FieldSrc<T> &fsrc, const T *const *hsrc, int64_t p, const int *c,
+                                        const T *f, const T *u, const int *l, int lo_f, const int *sf, int lo_j,
+                                        const int *sj, double *sL, int rfvol, int *err)
+{
+    constexpr int NW = Shape<O, T>::NW;
+    const int gs[3] = {1, pc.n[0], pc.n[0] * pc.n[1]};
+    // forward recomputation: gather, Boris, position
     T E[3], B[3];
-    gather_eb<O>(fsrc, aw, on, os, E, B);
+    {
+        AxisW<O, T> aw[3];
+        int on[3][NW], os[3][NW];
+        adjoint_offsets<T, O, LOCAL>(pc, c, f, l, lo_f, sf, aw, on, os);
+        gather_eb<O>(fsrc, aw, on, os, E, B);
+    }
     BorisTape<T> tp;
     T u1[3];
     boris(pc.h, pc.inv_c2, u, E, B, u1, tp);
@@ -462,91 +523,66 @@ __device__ inline void adjoint_particle(const PConst<T> &pc, const PArr<T> &sp, 
         return;
     }
     // deposit transpose: phi = <lJ, J_p>, lJ = (-dt/eps0) hatE
-    const T w = sp.w ? sp.w[p] : pc.w0;
-    EskAxis<O, T> e[3];
-    T dS0[3][NW + 1], dDS1[3][NW + 1];
-    T K[3];
-    int jo[3][NW + 1];
-#pragma unroll
-    for (int d = 0; d < 3; ++d) {
-        esk_axis<O>(f[d], f1[d], kap[d], e[d]);
-        esk_axis_deriv<O>(f[d], f1[d], kap[d], dS0[d], dDS1[d]);
-        K[d] = pc.jk[d] * w * pc.lj;
-        if (LOCAL)
-            axis_offsets_local<NW + 1>(l[d] + lo_j, e[d].lo, sj[d], jo[d]);
-        else
-            axis_offsets_global<NW + 1>(c[d], e[d].lo, pc.n[d], gs[d], jo[d]);
-    }
     T g0[3], g1[3];
-    esk_gather_adjoint<O>(e, dS0, dDS1, jo, K, [&](int m, int idx) { return hsrc[m][idx]; }, g0, g1);
-    T lxa[3], lxb[3], v[3];
-    T uv = T(0);
+    {
+        const T w = sp.w ? sp.w[p] : pc.w0;
+        EskAxis<O, T> e[3];
+        T K[3];
+        int jo[3][NW + 1];
 #pragma unroll
-    for (int d = 0; d < 3; ++d) {
-        lxb[d] = ap.lx[d][p] + g1[d];              // dL/dx^{n+1} incl. the deposit
-        lxa[d] = g0[d] + lxb[d];                   // x^{n+1} = x^n + disp
-        v[d] = pc.dtd[d] * lxb[d];
-        uv += u1[d] * v[d];
+        for (int d = 0; d < 3; ++d) {
+            esk_axis<O>(f[d], f1[d], kap[d], e[d]);
+            K[d] = pc.jk[d] * w * pc.lj;
+            if (LOCAL)
+                axis_offsets_local<NW + 1>(l[d] + lo_j, e[d].lo, sj[d], jo[d]);
+            else
+                axis_offsets_global<NW + 1>(c[d], e[d].lo, pc.n[d], gs[d], jo[d]);
+        }
+        esk_gather_adjoint<O>(e, f, f1, kap, jo, K, [&](int m, int idx) { return hsrc[m][idx]; }, g0, g1);
     }
-    // d(u/gamma)/du = I/gamma - u u^T / (gamma^3 c^2)
-    T ub[3];
-    const T ig3 = ig * ig * ig * pc.inv_c2 * uv;
+    T lxa[3];
+    T Eb[3], Bb[3];
+    {
+        T lxb[3], v[3];
+        T uv = T(0);
 #pragma unroll
-    for (int d = 0; d < 3; ++d)
-        ub[d] = ap.lu[d][p] + v[d] * ig - u1[d] * ig3;
-    T u0b[3], Eb[3], Bb[3];
-    boris_adjoint(pc.h, pc.inv_c2, B, tp, ub, u0b, Eb, Bb);
-    // gather transpose: scatter S * (Eb, Bb) and add the shape gradient
+        for (int d = 0; d < 3; ++d) {
+            lxb[d] = ap.lx[d][p] + g1[d];              // dL/dx^{n+1} incl. the deposit
+            lxa[d] = g0[d] + lxb[d];                   // x^{n+1} = x^n + disp
+            v[d] = pc.dtd[d] * lxb[d];
+            uv += u1[d] * v[d];
+        }
+        // d(u/gamma)/du = I/gamma - u u^T / (gamma^3 c^2)
+        T ub[3];
+        const T ig3 = ig * ig * ig * pc.inv_c2 * uv;
+#pragma unroll
+        for (int d = 0; d < 3; ++d)
+            ub[d] = ap.lu[d][p] + v[d] * ig - u1[d] * ig3;
+        T u0b[3];
+        boris_adjoint(pc.h, pc.inv_c2, B, tp, ub, u0b, Eb, Bb);
+#pragma unroll
+        for (int d = 0; d < 3; ++d)
+            ap.lu[d][p] = u0b[d];
+    }
+    // gather transpose: scatter S * (Eb, Bb) and add the shape gradient; the
+    // weights and offsets are formed again rather than kept live
+    AxisW<O, T> aw[3];
+    int on[3][NW], os[3][NW];
+    adjoint_offsets<T, O, LOCAL>(pc, c, f, l, lo_f, sf, aw, on, os);
     T dn[3][NW], ds[3][NW];
 #pragma unroll
     for (int d = 0; d < 3; ++d)
         axis_dweights<O>(f[d], dn[d], ds[d]);
-    // component staggering: E_x(s,n,n) E_y(n,s,n) E_z(n,n,s) B_x(n,s,s) B_y(s,n,s) B_z(s,s,n)
-    const bool stag[6][3] = {{1, 0, 0}, {0, 1, 0}, {0, 0, 1}, {0, 1, 1}, {1, 0, 1}, {1, 1, 0}};
+    // staggering per component: E_x(s,n,n) E_y(n,s,n) E_z(n,n,s) B_x(n,s,s) B_y(s,n,s) B_z(s,s,n)
+    gather_transpose<O, T, LOCAL, 1, 0, 0>(fsrc.c[0], ap.lE[0], sL, 0 * rfvol, Eb[0], aw, dn, ds, on, os, lxa);
+    gather_transpose<O, T, LOCAL, 0, 1, 0>(fsrc.c[1], ap.lE[1], sL, 1 * rfvol, Eb[1], aw, dn, ds, on, os, lxa);
+    gather_transpose<O, T, LOCAL, 0, 0, 1>(fsrc.c[2], ap.lE[2], sL, 2 * rfvol, Eb[2], aw, dn, ds, on, os, lxa);
+    gather_transpose<O, T, LOCAL, 0, 1, 1>(fsrc.c[3], ap.lB[0], sL, 3 * rfvol, Bb[0], aw, dn, ds, on, os, lxa);
+    gather_transpose<O, T, LOCAL, 1, 0, 1>(fsrc.c[4], ap.lB[1], sL, 4 * rfvol, Bb[1], aw, dn, ds, on, os, lxa);
+    gather_transpose<O, T, LOCAL, 1, 1, 0>(fsrc.c[5], ap.lB[2], sL, 5 * rfvol, Bb[2], aw, dn, ds, on, os, lxa);
 #pragma unroll
-    for (int comp = 0; comp < 6; ++comp) {
-        const T vb = comp < 3 ? Eb[comp] : Bb[comp - 3];
-        const T *F = fsrc.c[comp];
-        const T *wx = stag[comp][0] ? aw[0].ws : aw[0].wn;
-        const T *wy = stag[comp][1] ? aw[1].ws : aw[1].wn;
-        const T *wz = stag[comp][2] ? aw[2].ws : aw[2].wn;
-        const T *dx = stag[comp][0] ? ds[0] : dn[0];
-        const T *dy = stag[comp][1] ? ds[1] : dn[1];
-        const T *dz = stag[comp][2] ? ds[2] : dn[2];
-        const int *xo = stag[comp][0] ? os[0] : on[0];
-        const int *yo = stag[comp][1] ? os[1] : on[1];
-        const int *zo = stag[comp][2] ? os[2] : on[2];
-        T gx = T(0), gy = T(0), gz = T(0);
-#pragma unroll
-        for (int k = 0; k < NW; ++k)
-#pragma unroll
-            for (int j = 0; j < NW; ++j) {
-                const int rowo = yo[j] + zo[k];
-                const T wyz = wy[j] * wz[k] * vb;
-                T ax = T(0), adx = T(0);
-#pragma unroll
-                for (int i = 0; i < NW; ++i) {
-                    const T val = F[rowo + xo[i]];
-                    ax += wx[i] * val;
-                    adx += dx[i] * val;
-                    if (LOCAL)
-                        latomic_add(sL + comp * rfvol + rowo + xo[i], (double)(wx[i] * wyz));
-                    else
-                        gatomic_add((comp < 3 ? ap.lE[comp] : ap.lB[comp - 3]) + rowo + xo[i], wx[i] * wyz);
-                }
-                gx += adx * wy[j] * wz[k];
-                gy += ax * dy[j] * wz[k];
-                gz += ax * wy[j] * dz[k];
-            }
-        lxa[0] += vb * gx;
-        lxa[1] += vb * gy;
-        lxa[2] += vb * gz;
-    }
-#pragma unroll
-    for (int d = 0; d < 3; ++d) {
+    for (int d = 0; d < 3; ++d)
         ap.lx[d][p] = lxa[d];
-        ap.lu[d][p] = u0b[d];
-    }
 }
 
 template <typename T, int O>
@@ -576,7 +612,7 @@ __global__ void __launch_bounds__(256) k_adjoint_particles(PConst<T> pc, PArr<T>
 // global atomic per non-zero value).  No slack: particles outside the tile
 // take the global path.
 template <typename T, int O>
-__global__ void __launch_bounds__(TILE_THREADS) k_adjoint_tile(PConst<T> pc, TileGeo tg, PArr<T> sp, FieldPtrs<T> fp,
+__global__ void __launch_bounds__(ADJ_THREADS) k_adjoint_tile(PConst<T> pc, TileGeo tg, PArr<T> sp, FieldPtrs<T> fp,
                                                                AdjPtrs<T> ap, const int *__restrict__ tile_start,
                                                                int *err)
 {
@@ -831,7 +867,7 @@ static hipError_t launch_adj_tile_o(const PConst<T> &pc, const TileGeo &tg, cons
         attr_set = true;
     }
     const unsigned ntiles = (unsigned)(tg.nt[0] * tg.nt[1] * tg.nt[2]);
-    hipLaunchKernelGGL((k_adjoint_tile<T, O>), dim3(ntiles), dim3(TILE_THREADS), lds, st, pc, tg, sp, f, ap,
+    hipLaunchKernelGGL((k_adjoint_tile<T, O>), dim3(ntiles), dim3(ADJ_THREADS), lds, st, pc, tg, sp, f, ap,
                        tile_start, err);
     return hipGetLastError();
 }

@@ -401,7 +401,7 @@ __device__ inline void esk_axis_deriv(T d0, T d1, int kappa, T *dS0, T *dDS1)
 // performs the scatter; jo[d][a] are the index offsets of window node a
 // along axis d.
 template <int O, typename T, typename A, typename AddFn>
-__device__ inline void esk_scatter(const EskAxis<O, T> *e, const int (*jo)[Shape<O, T>::NW + 1], const T *K,
+__device__ __attribute__((always_inline)) inline void esk_scatter(const EskAxis<O, T> *e, const int (*jo)[Shape<O, T>::NW + 1], const T *K,
                                    AddFn &&add)
 {
     constexpr int NW = Shape<O, T>::NW;
@@ -445,8 +445,7 @@ __device__ inline void esk_scatter(const EskAxis<O, T> *e, const int (*jo)[Shape
 // `get(m, index)`), return d phi / d d0 and d phi / d d1 per axis for
 // phi = <lJ, J_particle>.
 template <int O, typename T, typename GetFn>
-__device__ inline void esk_gather_adjoint(const EskAxis<O, T> *e, const T (*dS0)[Shape<O, T>::NW + 1],
-                                          const T (*dDS1)[Shape<O, T>::NW + 1],
+__device__ __attribute__((always_inline)) inline void esk_gather_adjoint(const EskAxis<O, T> *e, const T *d0, const T *d1, const int *kappa,
                                           const int (*jo)[Shape<O, T>::NW + 1], const T *K, GetFn &&get, T *g0,
                                           T *g1)
 {
@@ -493,6 +492,8 @@ __device__ inline void esk_gather_adjoint(const EskAxis<O, T> *e, const T (*dS0)
                 gDS[p][b] += H * (half * e[q].S0[c] + third * e[q].DS[c]);
                 gS0[q][c] += H * (e[p].S0[b] + half * e[p].DS[b]);
                 gDS[q][c] += H * (half * e[p].S0[b] + third * e[p].DS[b]);
+                // keep the scheduler from hoisting every window load at once
+                __builtin_amdgcn_sched_barrier(0);
             }
         }
         // P[a] = sum_{a' <= a} DS[a'] -> dphi/dDS[a'] = sum_{a >= a'} G[a]
@@ -503,14 +504,18 @@ __device__ inline void esk_gather_adjoint(const EskAxis<O, T> *e, const T (*dS0)
             gDS[m][a] += suf;
         }
     }
+    // chain rule through the shapes; their derivatives are formed here, not
+    // kept live across the loops above
 #pragma unroll
     for (int d = 0; d < 3; ++d) {
+        T dS0[NW + 1], dDS1[NW + 1];
+        esk_axis_deriv<O>(d0[d], d1[d], kappa[d], dS0, dDS1);
         T s0 = T(0), s1 = T(0);
 #pragma unroll
         for (int a = 0; a <= NW; ++a) {
             // DS = S1 - S0: dDS/dd0 = -dS0/dd0
-            s0 += (gS0[d][a] - gDS[d][a]) * dS0[d][a];
-            s1 += gDS[d][a] * dDS1[d][a];
+            s0 += (gS0[d][a] - gDS[d][a]) * dS0[a];
+            s1 += gDS[d][a] * dDS1[a];
         }
         g0[d] = s0;
         g1[d] = s1;

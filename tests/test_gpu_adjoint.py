@@ -45,6 +45,9 @@ def test_adjoint_step_matches_oracle(order, dtype, tiled):
     """One reverse step with random adjoint inputs; the tiled variant bins the
     particles first (most particles in their tile's LDS region, some thrown
     outside it by the high thermal speed) and permutes the results back."""
+    if tiled and dtype == "f64" and order == 3:
+        pytest.skip("tiled FP64 order-3 adjoint is switched off in the library (it returned wrong position "
+                    "adjoints on the device; the request runs the per-particle kernel, covered by the untiled case)")
     g = wl.plasma_grid((12, 16, 20), order)
     n = 3000
     sp = random_species(g, n, 101, u_th=0.2, dtype=dtype)
@@ -163,8 +166,10 @@ def test_rollout_gradient_matches_central_differences(shape, ppc, nsteps, k):
     for v in dirs(gA):
         fd = (_gpu_loss(pb, base_u, base_a + eps * v) - _gpu_loss(pb, base_u, base_a - eps * v)) / (2 * eps)
         checks.append(("A-dir", fd, torch.sum(gA * v).item()))
+    # single momenta: at 64^3 one particle moves L by less than the rounding
+    # noise of a difference with eps = 1e-6, so they are checked on 16^3 only
     flat = gu.abs().flatten()
-    for idx in torch.topk(flat, 3).indices.tolist():
+    for idx in (torch.topk(flat, 3).indices.tolist() if shape[0] <= 16 else []):
         v = torch.zeros_like(base_u).flatten()
         v[idx] = 1.0
         v = v.view_as(base_u)
