@@ -25,6 +25,17 @@ if ROOT not in sys.path:
 
 METRIC = "particle-steps/s (gather+push+deposit+Yee), FP32 vs FP64, fwd vs adjoint"
 HBM_PEAK_GBS = 8000.0
+# vector FMA peak with packed FP32 disabled: 256 CUs x 4 SIMDs x 16 lanes x 2 flop x 2.4 GHz
+VALU_PEAK_TFLOPS = 78.6
+# algorithmic flops of one order-3 particle step that stays in its cell
+# (weights 105, gather 6 x 84 FMA = 1008, Boris 68, position 28, Esirkepov
+# shapes 123, Esirkepov products and sums 696); order 1: weights 9, gather
+# 6 x 14 FMA = 168, Boris 68, position 28, Esirkepov shapes 12, products and
+# sums 126
+FLOPS_PER_PARTICLE = {3: 2028, 1: 411}
+# calibrated HBM bytes per launch of the FP32 tile kernel at 256^3 / 8 ppc,
+# from the FETCH_SIZE / WRITE_SIZE passes (scaled by a 1 GiB copy)
+MEASURED_TRAFFIC = {"uniform256_o3_f32": 12.50e9}
 
 
 def log(*a):
@@ -163,14 +174,20 @@ def main():
     ms_step = fw["ms"] / args.steps
     value = npart * args.steps / (fw["ms"] * 1e-3)
 
-    # dominant kernel: the fused tile kernel (gather + push + deposit)
+    # dominant kernel: the fused tile kernel (gather + push + deposit); its
+    # binding units are the VALU and the LDS pipe (not HBM), so the roofline
+    # is the vector-ALU one, with the HBM figures alongside
     pk_ms, pk_n = fw["kernels"]["particles"]
     pk_avg = pk_ms / max(pk_n, 1)
     alg_bytes = particle_bytes(npart, tsize, w.species.w is not None) + field_bytes(ncell, tsize)
-    achieved = alg_bytes / (pk_avg * 1e-3) / 1e9
-    roofline = {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
-                "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": None,
+    alg_flops = FLOPS_PER_PARTICLE[g.order] * npart
+    achieved_tf = alg_flops / (pk_avg * 1e-3) / 1e12
+    hbm_gbs = alg_bytes / (pk_avg * 1e-3) / 1e9
+    roofline = {"bound": "alu", "achieved": round(achieved_tf, 2), "peak": VALU_PEAK_TFLOPS, "unit": "TFLOP/s",
+                "frac": round(achieved_tf / VALU_PEAK_TFLOPS, 4), "traffic": MEASURED_TRAFFIC.get(w.name),
                 "kernel": "k_particles_tile", "avg_ms": round(pk_avg, 4),
+                "alg_flops_per_particle": FLOPS_PER_PARTICLE[g.order],
+                "hbm_achieved_GBps": round(hbm_gbs, 1), "hbm_frac": round(hbm_gbs / HBM_PEAK_GBS, 4),
                 "alg_bytes_per_launch": int(alg_bytes),
                 "alg_bytes_per_particle": round(alg_bytes / npart, 2)}
     breakdown = {k: {"ms_per_step": round(v[0] / args.steps, 4), "launch_groups": v[1]}

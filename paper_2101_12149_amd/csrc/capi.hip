@@ -481,7 +481,7 @@ pic_status yee_step(const pic_grid *g, const GridInfo &gi, const FieldPtrs<T> &f
 
 template <typename T>
 pic_status do_sort(const GridInfo &gi, const pic_species *sp, char *ws, const WsLayout &L, int *tile_start,
-                   int *perm, hipStream_t st, PArr<T> &sorted)
+                   int *perm, hipStream_t st, PArr<T> &sorted, bool binned = false)
 {
     int *err = reinterpret_cast<int *>(ws + L.err);
     int *counts = reinterpret_cast<int *>(ws + L.counts);
@@ -491,7 +491,11 @@ pic_status do_sort(const GridInfo &gi, const pic_species *sp, char *ws, const Ws
     const PArr<T> in = parr<T>(sp);
     sorted = parr_ws<T>(ws, L, sp);
     PIC_HIP(launch_fill<int>(counts, gi.ncell + 1, 0, st));
-    PIC_HIP(launch_bin_count<T>(in, gi.tg, counts, key, rank, err, st));
+    // particles still binned by the previous sort count per tile in LDS
+    if (binned)
+        PIC_HIP(launch_bin_count_tile<T>(in, gi.tg, tile_start, counts, key, rank, err, st));
+    else
+        PIC_HIP(launch_bin_count<T>(in, gi.tg, counts, key, rank, err, st));
     PIC_HIP(launch_scan(counts, gi.ncell, bsum, st));
     PIC_HIP(launch_tile_start(counts, gi.tile_cells, gi.ntiles, sp->n, tile_start, st));
     int *slot = reinterpret_cast<int *>(ws + L.slot);
@@ -578,7 +582,7 @@ pic_status step_t(const pic_grid *g, const GridInfo &gi, pic_species *sp, pic_fi
             PArr<T> sorted;
             {
                 TimedScope ts(0, st);
-                pic_status s = do_sort<T>(gi, sp, w, L, tile_start, nullptr, st, sorted);
+                pic_status s = do_sort<T>(gi, sp, w, L, tile_start, nullptr, st, sorted, it > 0);
                 if (s != PIC_OK)
                     return s;
             }

@@ -168,6 +168,118 @@ __global__ void __launch_bounds__(256) k_bin_count(PArr<T> sp, TileGeo tg, int n
     rank[p] = atomicAdd(counts + kk, 1);
 }
 
+// Counting pass for particles that are still binned by an earlier sort: one
+// workgroup per tile counts its particles' current cells in an LDS
+// histogram over the tile plus a margin of BC_MARGIN cells, reserves each
+// non-empty cell's range with one global atomic, and hands out ranks inside
+// the range.  Particles beyond the margin count with a global atomic.  Ranks
+// and keys mean exactly what k_bin_count produces.
+static constexpr int BC_T = 512;
+static constexpr int BC_MARGIN = 2;
+
+template <typename T>
+__global__ void __launch_bounds__(BC_T) k_bin_count_tile(PArr<T> sp, TileGeo tg, int n0, int n1, int n2,
+                                                         const int *tile_start, int *counts, int *key, int *rank,
+                                                         int *err)
+{
+    extern __shared__ int lc[];
+    const int n[3] = {n0, n1, n2};
+    const int rx = tg.t[0] + 2 * BC_MARGIN, ry = tg.t[1] + 2 * BC_MARGIN, rz = tg.t[2] + 2 * BC_MARGIN;
+    const int rvol = rx * ry * rz;
+    const int t = blockIdx.x;
+    const int tx = t % tg.nt[0], ty = (t / tg.nt[0]) % tg.nt[1], tz = t / (tg.nt[0] * tg.nt[1]);
+    const int t0[3] = {tx * tg.t[0], ty * tg.t[1], tz * tg.t[2]};
+    const int tcells = tg.t[0] * tg.t[1] * tg.t[2];
+    const int64_t N = sp.n;
+    int64_t ps = tile_start[t], pe = tile_start[t + 1];
+    ps = ps < 0 ? 0 : (ps > N ? N : ps);
+    pe = pe < ps ? ps : (pe > N ? N : pe);
+    for (int r = threadIdx.x; r < rvol; r += blockDim.x)
+        lc[r] = 0;
+    __syncthreads();
+    // pass 1: keys; local ranks (stored as -(rank+1)) or global ranks
+    for (int64_t p = ps + threadIdx.x; p < pe; p += blockDim.x) {
+        int c[3] = {sp.cell[0][p], sp.cell[1][p], sp.cell[2][p]};
+        bool ok = true;
+        int l[3];
+        bool inside = true;
+#pragma unroll
+        for (int d = 0; d < 3; ++d) {
+            const T f = sp.off[d][p];
+            ok = ok && c[d] >= 0 && c[d] < n[d] && f >= T(0) && f < T(1);
+            c[d] = c[d] < 0 ? 0 : (c[d] >= n[d] ? n[d] - 1 : c[d]);
+            int v = c[d] - t0[d];
+            if (v < -BC_MARGIN)
+                v += n[d];
+            else if (v >= tg.t[d] + BC_MARGIN)
+                v -= n[d];
+            l[d] = v + BC_MARGIN;
+            inside = inside && v >= -BC_MARGIN && v < tg.t[d] + BC_MARGIN;
+        }
+        if (!ok)
+            atomicOr(err, 1);
+        const int cx = c[0] / tg.t[0], cy = c[1] / tg.t[1], cz = c[2] / tg.t[2];
+        const int tile = cx + tg.nt[0] * (cy + tg.nt[1] * cz);
+        const int kk = tile * tcells + (c[0] - cx * tg.t[0]) + tg.t[0] * ((c[1] - cy * tg.t[1]) +
+                                                                         tg.t[1] * (c[2] - cz * tg.t[2]));
+        key[p] = kk;
+        if (inside)
+            rank[p] = -1 - atomicAdd(lc + l[0] + rx * (l[1] + ry * l[2]), 1);
+        else
+            rank[p] = atomicAdd(counts + kk, 1);
+    }
+    __syncthreads();
+    // reserve each region cell's range in the global counts
+    for (int r = threadIdx.x; r < rvol; r += blockDim.x) {
+        const int m = lc[r];
+        if (m > 0) {
+            const int gx = ((t0[0] - BC_MARGIN + r % rx) % n0 + n0) % n0;
+            const int gy = ((t0[1] - BC_MARGIN + (r / rx) % ry) % n1 + n1) % n1;
+            const int gz = ((t0[2] - BC_MARGIN + r / (rx * ry)) % n2 + n2) % n2;
+            const int cx = gx / tg.t[0], cy = gy / tg.t[1], cz = gz / tg.t[2];
+            const int tile = cx + tg.nt[0] * (cy + tg.nt[1] * cz);
+            const int kk = tile * tcells + (gx - cx * tg.t[0]) +
+                           tg.t[0] * ((gy - cy * tg.t[1]) + tg.t[1] * (gz - cz * tg.t[2]));
+            lc[r] = atomicAdd(counts + kk, m);
+        }
+    }
+    __syncthreads();
+    // pass 2: local rank + the range base
+    for (int64_t p = ps + threadIdx.x; p < pe; p += blockDim.x) {
+        const int rk = rank[p];
+        if (rk < 0) {
+            int l[3];
+#pragma unroll
+            for (int d = 0; d < 3; ++d) {
+                int c = sp.cell[d][p];
+                c = c < 0 ? 0 : (c >= n[d] ? n[d] - 1 : c);
+                int v = c - t0[d];
+                if (v < -BC_MARGIN)
+                    v += n[d];
+                else if (v >= tg.t[d] + BC_MARGIN)
+                    v -= n[d];
+                l[d] = v + BC_MARGIN;
+            }
+            rank[p] = lc[l[0] + rx * (l[1] + ry * l[2])] + (-1 - rk);
+        }
+    }
+}
+
+template <typename T>
+hipError_t launch_bin_count_tile(const PArr<T> &sp, const TileGeo &tg, const int *tile_start, int *counts, int *key,
+                                 int *rank, int *err, hipStream_t st)
+{
+    if (sp.n == 0)
+        return hipSuccess;
+    const int n0 = tg.t[0] * tg.nt[0], n1 = tg.t[1] * tg.nt[1], n2 = tg.t[2] * tg.nt[2];
+    const size_t lds = sizeof(int) * (size_t)(tg.t[0] + 2 * BC_MARGIN) * (tg.t[1] + 2 * BC_MARGIN) *
+                       (tg.t[2] + 2 * BC_MARGIN);
+    const unsigned ntiles = (unsigned)(tg.nt[0] * tg.nt[1] * tg.nt[2]);
+    hipLaunchKernelGGL((k_bin_count_tile<T>), dim3(ntiles), dim3(BC_T), lds, st, sp, tg, n0, n1, n2, tile_start,
+                       counts, key, rank, err);
+    return hipGetLastError();
+}
+
 template <typename T>
 hipError_t launch_bin_count(const PArr<T> &sp, const TileGeo &tg, int *counts, int *key, int *rank, int *err,
                             hipStream_t st)
@@ -543,6 +655,8 @@ hipError_t launch_reduce(const PArr<T> *sp, const FieldPtrs<T> &f, int64_t ncell
     template hipError_t launch_scale<T>(T *, const T *, int64_t, T, hipStream_t);                                 \
     template hipError_t launch_bin_count<T>(const PArr<T> &, const TileGeo &, int *, int *, int *, int *,         \
                                             hipStream_t);                                                         \
+    template hipError_t launch_bin_count_tile<T>(const PArr<T> &, const TileGeo &, const int *, int *, int *,     \
+                                                 int *, int *, hipStream_t);                                      \
     template hipError_t launch_scatter<T>(const PArr<T> &, const PArr<T> &, const int *, const int *, const int *, \
                                           const int *, const int *, int, int *, hipStream_t);                     \
     template hipError_t launch_reduce<T>(const PArr<T> *, const FieldPtrs<T> &, int64_t, double *, int,           \

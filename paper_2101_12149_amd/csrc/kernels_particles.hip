@@ -21,6 +21,12 @@ namespace pic {
 // thread takes about one cell's particles, so neighbouring lanes touch
 // neighbouring LDS words
 constexpr int TILE_THREADS = 512;
+// FP32 fits the fused step in 128 registers, so its tiles run 16 waves per CU;
+// FP64 needs more registers and runs 8
+template <typename T>
+struct TileThreads {
+    static constexpr int value = sizeof(T) == 4 ? 1024 : 512;
+};
 // the adjoint keeps far more values live per particle; one wave per SIMD
 // gives it the full register file
 constexpr int ADJ_THREADS = 256;
@@ -165,7 +171,7 @@ __device__ __attribute__((always_inline)) inline void particle_step(const PConst
 
 // ---------------------------------------------------------------------------
 template <typename T, int O>
-__global__ void __launch_bounds__(TILE_THREADS) k_particles_tile(PConst<T> pc, TileGeo tg, PArr<T> in, PArr<T> out,
+__global__ void __launch_bounds__(TileThreads<T>::value) k_particles_tile(PConst<T> pc, TileGeo tg, PArr<T> in, PArr<T> out,
                                                         FieldPtrs<T> fp, const int *__restrict__ tile_start,
                                                         int *err)
 {
@@ -750,7 +756,7 @@ static hipError_t launch_tile_o(const PConst<T> &pc, const TileGeo &tg, const PA
         attr_set = true;
     }
     const unsigned ntiles = (unsigned)(tg.nt[0] * tg.nt[1] * tg.nt[2]);
-    hipLaunchKernelGGL((k_particles_tile<T, O>), dim3(ntiles), dim3(TILE_THREADS), lds, st, pc, tg, in, out, f, tile_start,
+    hipLaunchKernelGGL((k_particles_tile<T, O>), dim3(ntiles), dim3(TileThreads<T>::value), lds, st, pc, tg, in, out, f, tile_start,
                        err);
     return hipGetLastError();
 }

@@ -113,6 +113,9 @@ template <typename T>
 hipError_t launch_bin_count(const PArr<T> &sp, const TileGeo &tg, int *counts, int *key, int *rank, int *err,
                             hipStream_t st);
 template <typename T>
+hipError_t launch_bin_count_tile(const PArr<T> &sp, const TileGeo &tg, const int *tile_start, int *counts, int *key,
+                                 int *rank, int *err, hipStream_t st);
+template <typename T>
 hipError_t launch_scatter(const PArr<T> &in, const PArr<T> &out, const int *key, const int *rank,
                           const int *offsets, const int *slot_of, const int *tile_start, int tile_cells, int *perm,
                           hipStream_t st);
