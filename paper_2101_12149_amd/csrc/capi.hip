@@ -163,8 +163,9 @@ void region_extents(int order, TileGeo &tg)
     tg.lo_j = s + gl;
 }
 
-// LDS of the tiled adjoint: same tiles, no slack; FP64 accumulators of the
-// gather transpose, E and B with the gather halo, hatE with the deposit halo
+// regions of the tiled adjoint: same tiles, no slack.  Its first pass holds
+// E, B with the gather halo and hatE with the deposit halo, its second the
+// FP64 accumulators and fields of one group of three components.
 TileGeo adjoint_geo(const GridInfo &gi)
 {
     TileGeo a = gi.tg;
@@ -178,7 +179,9 @@ size_t adj_lds_bytes(const GridInfo &gi)
     const TileGeo a = adjoint_geo(gi);
     const size_t rf = (size_t)a.rf[0] * a.rf[1] * a.rf[2];
     const size_t rj = (size_t)a.rj[0] * a.rj[1] * a.rj[2];
-    return 6 * rf * sizeof(double) + 6 * rf * gi.tsize + 3 * rj * gi.tsize;
+    const size_t push = 6 * rf * gi.tsize + 3 * rj * gi.tsize;
+    const size_t scatter = 3 * rf * (sizeof(double) + gi.tsize);
+    return push > scatter ? push : scatter;
 }
 
 size_t lds_bytes(const GridInfo &gi)
@@ -624,10 +627,15 @@ pic_status adjoint_t(const pic_grid *g, const GridInfo &gi, const pic_species *s
 {
     char *w = static_cast<char *>(ws);
     int *err = reinterpret_cast<int *>(w + L.err);
-    T *hat[3];
+    T *hat[3], *vb[6];
     T *lE[3], *lB[3], *lx[3], *lu[3];
+    const size_t np = (size_t)sp->n;
     for (int d = 0; d < 3; ++d) {
         hat[d] = reinterpret_cast<T *>(w + L.hatE + d * al(sizeof(T) * (size_t)gi.ncell));
+        // the adjoints of the gathered fields pass between the two particle
+        // passes in the sort's staging buffers, which the adjoint does not use
+        vb[d] = reinterpret_cast<T *>(w + L.soff + d * al(sizeof(T) * np));
+        vb[3 + d] = reinterpret_cast<T *>(w + L.su + d * al(sizeof(T) * np));
         lE[d] = static_cast<T *>(lam->lE[d]);
         lB[d] = static_cast<T *>(lam->lB[d]);
         lx[d] = static_cast<T *>(lam->lx[d]);
@@ -674,6 +682,7 @@ pic_status adjoint_t(const pic_grid *g, const GridInfo &gi, const pic_species *s
     e.cy = a.cy;
     e.cz = a.cz;
     e.kplane = -1;
+    PIC_HIP(launch_fill<int>(err, 1, 0, st));
     {
         TimedScope tf(4, st);
         PIC_HIP(launch_curl<T>(false, a, st));   // hatE
@@ -684,17 +693,23 @@ pic_status adjoint_t(const pic_grid *g, const GridInfo &gi, const pic_species *s
     if (sp->n > 0) {
         TimedScope tp(5, st);
         const PConst<T> pc = make_const<T>(g, sp);
-        // The tiled FP64 order-3 transpose is switched off: that instantiation
-        // spills over a thousand registers and returned wrong position
-        // adjoints on the device, so it takes the per-particle kernel.
+        // The tiled FP64 order-3 transpose stays switched off: an earlier
+        // fused form of it returned wrong position adjoints on the device
+        // without a cause found in its code, so that request takes the
+        // per-particle kernels.
         const bool tiled_ok = !(gi.dtype == PIC_F64 && gi.order == 3);
         if (tile_start && tiled_ok)
             PIC_HIP(launch_adjoint_tile<T>(gi.order, pc, adjoint_geo(gi), parr<T>(sp), fptrs<T>(f), hat, lx, lu, lE,
-                                           lB, tile_start, err, st));
+                                           lB, vb, tile_start, err, st));
         else
-            PIC_HIP(launch_adjoint_particles<T>(gi.order, pc, parr<T>(sp), fptrs<T>(f), hat, lx, lu, lE, lB, err,
-                                                st));
+            PIC_HIP(launch_adjoint_particles<T>(gi.order, pc, parr<T>(sp), fptrs<T>(f), hat, lx, lu, lE, lB, vb,
+                                                err, st));
     }
+    int herr = 0;
+    PIC_HIP(hipMemcpyAsync(&herr, err, sizeof(int), hipMemcpyDeviceToHost, st));
+    PIC_HIP(hipStreamSynchronize(st));
+    if (herr)
+        return fail(PIC_E_STATE, "corrupt particle state (cell, offset, momentum or a displacement >= 1 cell)");
     return PIC_OK;
 }
 

@@ -11,7 +11,8 @@
 //  k_particles_global the same fused step without tiles (global memory and
 //                     global atomics, the paper's GPU deposition, Sec. 3.4.1)
 //  k_gather / k_push / k_deposit   the separate operations
-//  k_adjoint_particles             transpose of the particle part of a step
+//  k_adjoint_push / k_adjoint_scatter (and their tiled forms)
+//                     transpose of the particle part of a step, two passes
 #include "pic_device.hpp"
 #include "pic_types.hpp"
 
@@ -27,9 +28,6 @@ template <typename T>
 struct TileThreads {
     static constexpr int value = sizeof(T) == 4 ? 1024 : 512;
 };
-// the adjoint keeps far more values live per particle; one wave per SIMD
-// gives it the full register file
-constexpr int ADJ_THREADS = 256;
 
 template <typename T>
 __device__ inline void gatomic_add(T *p, T v)
@@ -418,23 +416,33 @@ __global__ void __launch_bounds__(256) k_deposit(PConst<T> pc, PArr<T> b, PArr<T
 }
 
 // ---------------------------------------------------------------------------
-// Transpose of the particle part of one step.  The forward quantities are
-// recomputed from the state at step n with the same device functions as the
-// forward kernels, so the reverse sweep follows exactly the forward rounding.
-// With LOCAL the particle lies inside the tile's LDS regions: fields and the
-// field adjoint hatE are read from LDS and the gather transpose accumulates
-// into the FP64 LDS tiles sLE/sLB; otherwise everything is global.
+// Transpose of the particle part of one step, in two passes so that neither
+// keeps the whole reverse chain live in registers.
+//  pass 1 (push): the forward quantities are recomputed from the state at
+//     step n with the forward device functions (gather, Boris, move), so the
+//     reverse sweep follows the forward rounding; then the deposit transpose
+//     (a gather of the current adjoint lj * hatE over the Esirkepov window)
+//     and the position and Boris transposes.  Writes lu <- dL/du^n,
+//     lx <- dL/dx^n without the gather term, and the adjoints of the
+//     gathered fields (Eb, Bb) per particle.
+//  pass 2 (scatter): the gather transpose of a group of three field
+//     components (E or B): scatters S * vb into the component's adjoint and
+//     adds vb * grad(S) . F to lx.
+// With LOCAL the particle lies inside the tile's LDS regions: fields and
+// hatE come from LDS and the scatter accumulates into FP64 LDS tiles;
+// otherwise everything is global.
 template <typename T>
 struct AdjPtrs {
     const T *hat[3];   // hatE: lE - dt/2 curl_b(lB), the current adjoint is lj * hatE
     T *lx[3], *lu[3], *lE[3], *lB[3];
+    T *vb[6];          // per-particle adjoints of the gathered E and B
 };
 
 // Gather transpose of one field component with staggering (SX, SY, SZ):
 // scatter S * vb into the component's adjoint (FP64 LDS accumulators or
 // global atomics) and add vb * grad(gathered value) to the position adjoint.
 template <int O, typename T, bool LOCAL, int SX, int SY, int SZ>
-__device__ __attribute__((always_inline)) inline void gather_transpose(const T *F, T *Lglob, double *sL, int lbase, T vb, const AxisW<O, T> *aw,
+__device__ __attribute__((always_inline)) inline void gather_transpose(const T *F, T *Lglob, double *sL, T vb, const AxisW<O, T> *aw,
                                         const T (*dn)[Shape<O, T>::NW], const T (*ds)[Shape<O, T>::NW],
                                         const int (*on)[Shape<O, T>::NW], const int (*os)[Shape<O, T>::NW], T *lxa)
 {
@@ -462,7 +470,7 @@ __device__ __attribute__((always_inline)) inline void gather_transpose(const T *
                 ax += wx[i] * val;
                 adx += dx[i] * val;
                 if (LOCAL)
-                    latomic_add(sL + lbase + rowo + xo[i], (double)(wx[i] * wyz));
+                    latomic_add(sL + rowo + xo[i], (double)(wx[i] * wyz));
                 else
                     gatomic_add(Lglob + rowo + xo[i], wx[i] * wyz);
             }
@@ -495,11 +503,20 @@ __device__ __attribute__((always_inline)) inline void adjoint_offsets(const PCon
     }
 }
 
+template <typename T>
+__device__ inline void clear_vb(const AdjPtrs<T> &ap, int64_t p)
+{
+#pragma unroll
+    for (int m = 0; m < 6; ++m)
+        ap.vb[m][p] = T(0);
+}
+
+// pass 1 for one particle
 template <typename T, int O, bool LOCAL>
-__device__ __attribute__((always_inline)) inline void adjoint_particle(const PConst<T> &pc, const PArr<T> &sp, const AdjPtrs<T> &ap,
-                                        const FieldSrc<T> &fsrc, const T *const *hsrc, int64_t p, const int *c,
-                                        const T *f, const T *u, const int *l, int lo_f, const int *sf, int lo_j,
-                                        const int *sj, double *sL, int rfvol, int *err)
+__device__ __attribute__((always_inline)) inline void adjoint_push_particle(const PConst<T> &pc, const PArr<T> &sp, const AdjPtrs<T> &ap,
+                                             const FieldSrc<T> &fsrc, const T *const *hsrc, int64_t p, const int *c,
+                                             const T *f, const T *u, const int *l, int lo_f, const int *sf, int lo_j,
+                                             const int *sj, int *err)
 {
     constexpr int NW = Shape<O, T>::NW;
     const int gs[3] = {1, pc.n[0], pc.n[0] * pc.n[1]};
@@ -511,21 +528,24 @@ __device__ __attribute__((always_inline)) inline void adjoint_particle(const PCo
         adjoint_offsets<T, O, LOCAL>(pc, c, f, l, lo_f, sf, aw, on, os);
         gather_eb<O>(fsrc, aw, on, os, E, B);
     }
-    BorisTape<T> tp;
-    T u1[3];
-    boris(pc.h, pc.inv_c2, u, E, B, u1, tp);
-    const T ig = T(1) / sqrt(T(1) + (u1[0] * u1[0] + u1[1] * u1[1] + u1[2] * u1[2]) * pc.inv_c2);
     T f1[3];
     int kap[3];
     bool ok = true;
+    {
+        BorisTape<T> tp;
+        T u1[3];
+        boris(pc.h, pc.inv_c2, u, E, B, u1, tp);
+        const T ig = T(1) / sqrt(T(1) + (u1[0] * u1[0] + u1[1] * u1[1] + u1[2] * u1[2]) * pc.inv_c2);
 #pragma unroll
-    for (int d = 0; d < 3; ++d) {
-        const T disp = pc.dtd[d] * u1[d] * ig;
-        ok = ok && fabs(disp) < T(1);
-        move_axis(f[d], disp, f1[d], kap[d]);
+        for (int d = 0; d < 3; ++d) {
+            const T disp = pc.dtd[d] * u1[d] * ig;
+            ok = ok && fabs(disp) < T(1);
+            move_axis(f[d], disp, f1[d], kap[d]);
+        }
     }
     if (!ok) {
         atomicOr(err, 2);
+        clear_vb(ap, p);
         return;
     }
     // deposit transpose: phi = <lJ, J_p>, lJ = (-dt/eps0) hatE
@@ -546,32 +566,48 @@ __device__ __attribute__((always_inline)) inline void adjoint_particle(const PCo
         }
         esk_gather_adjoint<O>(e, f, f1, kap, jo, K, [&](int m, int idx) { return hsrc[m][idx]; }, g0, g1);
     }
-    T lxa[3];
-    T Eb[3], Bb[3];
-    {
-        T lxb[3], v[3];
-        T uv = T(0);
+    // The Boris step again, for its tape: only E and B stay live across the
+    // deposit transpose.  The register operands keep the compiler from
+    // reusing the first evaluation; the inputs and so the values are the same.
+    asm volatile("" : "+v"(E[0]), "+v"(E[1]), "+v"(E[2]), "+v"(B[0]), "+v"(B[1]), "+v"(B[2]));
+    BorisTape<T> tp;
+    T u1[3];
+    boris(pc.h, pc.inv_c2, u, E, B, u1, tp);
+    const T ig = T(1) / sqrt(T(1) + (u1[0] * u1[0] + u1[1] * u1[1] + u1[2] * u1[2]) * pc.inv_c2);
+    T lxb[3], v[3];
+    T uv = T(0);
 #pragma unroll
-        for (int d = 0; d < 3; ++d) {
-            lxb[d] = ap.lx[d][p] + g1[d];              // dL/dx^{n+1} incl. the deposit
-            lxa[d] = g0[d] + lxb[d];                   // x^{n+1} = x^n + disp
-            v[d] = pc.dtd[d] * lxb[d];
-            uv += u1[d] * v[d];
-        }
-        // d(u/gamma)/du = I/gamma - u u^T / (gamma^3 c^2)
-        T ub[3];
-        const T ig3 = ig * ig * ig * pc.inv_c2 * uv;
-#pragma unroll
-        for (int d = 0; d < 3; ++d)
-            ub[d] = ap.lu[d][p] + v[d] * ig - u1[d] * ig3;
-        T u0b[3];
-        boris_adjoint(pc.h, pc.inv_c2, B, tp, ub, u0b, Eb, Bb);
-#pragma unroll
-        for (int d = 0; d < 3; ++d)
-            ap.lu[d][p] = u0b[d];
+    for (int d = 0; d < 3; ++d) {
+        lxb[d] = ap.lx[d][p] + g1[d];   // dL/dx^{n+1} incl. the deposit
+        v[d] = pc.dtd[d] * lxb[d];
+        uv += u1[d] * v[d];
+        ap.lx[d][p] = g0[d] + lxb[d];   // x^{n+1} = x^n + disp; the gather term follows in pass 2
     }
-    // gather transpose: scatter S * (Eb, Bb) and add the shape gradient; the
-    // weights and offsets are formed again rather than kept live
+    // d(u/gamma)/du = I/gamma - u u^T / (gamma^3 c^2)
+    T ub[3];
+    const T ig3 = ig * ig * ig * pc.inv_c2 * uv;
+#pragma unroll
+    for (int d = 0; d < 3; ++d)
+        ub[d] = ap.lu[d][p] + v[d] * ig - u1[d] * ig3;
+    T u0b[3], Eb[3], Bb[3];
+    boris_adjoint(pc.h, pc.inv_c2, B, tp, ub, u0b, Eb, Bb);
+#pragma unroll
+    for (int d = 0; d < 3; ++d) {
+        ap.lu[d][p] = u0b[d];
+        ap.vb[d][p] = Eb[d];
+        ap.vb[3 + d][p] = Bb[d];
+    }
+}
+
+// pass 2 for one particle: components of group G (0: E, 1: B, 2: both).
+// fsrc.c[m] is component m (E_x..E_z, B_x..B_z); the LDS accumulators hold
+// the group's components at sL + (m - 3 G) * rfvol.
+template <typename T, int O, bool LOCAL, int G>
+__device__ __attribute__((always_inline)) inline void adjoint_scatter_particle(const PConst<T> &pc, const AdjPtrs<T> &ap,
+                                                const FieldSrc<T> &fsrc, int64_t p, const int *c, const T *f,
+                                                const int *l, int lo_f, const int *sf, double *sL, int rfvol)
+{
+    constexpr int NW = Shape<O, T>::NW;
     AxisW<O, T> aw[3];
     int on[3][NW], os[3][NW];
     adjoint_offsets<T, O, LOCAL>(pc, c, f, l, lo_f, sf, aw, on, os);
@@ -579,150 +615,294 @@ __device__ __attribute__((always_inline)) inline void adjoint_particle(const PCo
 #pragma unroll
     for (int d = 0; d < 3; ++d)
         axis_dweights<O>(f[d], dn[d], ds[d]);
+    T lxa[3] = {ap.lx[0][p], ap.lx[1][p], ap.lx[2][p]};
+    constexpr int b = G == 1 ? 3 : 0;
     // staggering per component: E_x(s,n,n) E_y(n,s,n) E_z(n,n,s) B_x(n,s,s) B_y(s,n,s) B_z(s,s,n)
-    gather_transpose<O, T, LOCAL, 1, 0, 0>(fsrc.c[0], ap.lE[0], sL, 0 * rfvol, Eb[0], aw, dn, ds, on, os, lxa);
-    gather_transpose<O, T, LOCAL, 0, 1, 0>(fsrc.c[1], ap.lE[1], sL, 1 * rfvol, Eb[1], aw, dn, ds, on, os, lxa);
-    gather_transpose<O, T, LOCAL, 0, 0, 1>(fsrc.c[2], ap.lE[2], sL, 2 * rfvol, Eb[2], aw, dn, ds, on, os, lxa);
-    gather_transpose<O, T, LOCAL, 0, 1, 1>(fsrc.c[3], ap.lB[0], sL, 3 * rfvol, Bb[0], aw, dn, ds, on, os, lxa);
-    gather_transpose<O, T, LOCAL, 1, 0, 1>(fsrc.c[4], ap.lB[1], sL, 4 * rfvol, Bb[1], aw, dn, ds, on, os, lxa);
-    gather_transpose<O, T, LOCAL, 1, 1, 0>(fsrc.c[5], ap.lB[2], sL, 5 * rfvol, Bb[2], aw, dn, ds, on, os, lxa);
+    if (G != 1) {
+        gather_transpose<O, T, LOCAL, 1, 0, 0>(fsrc.c[0], ap.lE[0], sL + (0 - b) * rfvol, ap.vb[0][p], aw, dn, ds, on,
+                                               os, lxa);
+        gather_transpose<O, T, LOCAL, 0, 1, 0>(fsrc.c[1], ap.lE[1], sL + (1 - b) * rfvol, ap.vb[1][p], aw, dn, ds, on,
+                                               os, lxa);
+        gather_transpose<O, T, LOCAL, 0, 0, 1>(fsrc.c[2], ap.lE[2], sL + (2 - b) * rfvol, ap.vb[2][p], aw, dn, ds, on,
+                                               os, lxa);
+    }
+    if (G != 0) {
+        gather_transpose<O, T, LOCAL, 0, 1, 1>(fsrc.c[3], ap.lB[0], sL + (3 - b) * rfvol, ap.vb[3][p], aw, dn, ds, on,
+                                               os, lxa);
+        gather_transpose<O, T, LOCAL, 1, 0, 1>(fsrc.c[4], ap.lB[1], sL + (4 - b) * rfvol, ap.vb[4][p], aw, dn, ds, on,
+                                               os, lxa);
+        gather_transpose<O, T, LOCAL, 1, 1, 0>(fsrc.c[5], ap.lB[2], sL + (5 - b) * rfvol, ap.vb[5][p], aw, dn, ds, on,
+                                               os, lxa);
+    }
 #pragma unroll
     for (int d = 0; d < 3; ++d)
         ap.lx[d][p] = lxa[d];
 }
 
-template <typename T, int O>
-__global__ void __launch_bounds__(256) k_adjoint_particles(PConst<T> pc, PArr<T> sp, FieldPtrs<T> fp, AdjPtrs<T> ap,
-                                                           int *err)
+// positions only (pass 2): a particle that fails the check was flagged by
+// pass 1 and is skipped
+template <typename T>
+__device__ inline bool load_position(const PArr<T> &in, int64_t p, const int *n, int *c, T *f)
 {
-    const int64_t p = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    if (p >= sp.n)
-        return;
-    int c[3];
-    T f[3], u[3];
-    if (!load_particle(sp, p, pc.n, c, f, u, err))
-        return;
+    bool ok = true;
+#pragma unroll
+    for (int d = 0; d < 3; ++d) {
+        c[d] = in.cell[d][p];
+        f[d] = in.off[d][p];
+        ok = ok && c[d] >= 0 && c[d] < n[d] && f[d] >= T(0) && f[d] < T(1);
+    }
+    return ok;
+}
+
+template <typename T>
+__device__ inline FieldSrc<T> global_fields(const FieldPtrs<T> &fp)
+{
     FieldSrc<T> gf;
 #pragma unroll
     for (int m = 0; m < 3; ++m) {
         gf.c[m] = fp.E[m];
         gf.c[3 + m] = fp.B[m];
     }
-    const int z3[3] = {0, 0, 0};
-    adjoint_particle<T, O, false>(pc, sp, ap, gf, ap.hat, p, c, f, u, z3, 0, z3, 0, z3, nullptr, 0, err);
+    return gf;
 }
 
-// Tiled transpose: one workgroup per tile of the binning the forward sort
-// produced.  LDS holds E, B with the gather halo, hatE with the deposit
-// halo, and FP64 accumulators of the gather transpose (flushed with one
-// global atomic per non-zero value).  No slack: particles outside the tile
-// take the global path.
 template <typename T, int O>
-__global__ void __launch_bounds__(ADJ_THREADS) k_adjoint_tile(PConst<T> pc, TileGeo tg, PArr<T> sp, FieldPtrs<T> fp,
-                                                               AdjPtrs<T> ap, const int *__restrict__ tile_start,
-                                                               int *err)
+__global__ void __launch_bounds__(256) k_adjoint_push(PConst<T> pc, PArr<T> sp, FieldPtrs<T> fp, AdjPtrs<T> ap,
+                                                      int *err)
+{
+    const int64_t p = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (p >= sp.n)
+        return;
+    int c[3];
+    T f[3], u[3];
+    if (!load_particle(sp, p, pc.n, c, f, u, err)) {
+        clear_vb(ap, p);
+        return;
+    }
+    const int z3[3] = {0, 0, 0};
+    adjoint_push_particle<T, O, false>(pc, sp, ap, global_fields(fp), ap.hat, p, c, f, u, z3, 0, z3, 0, z3, err);
+}
+
+template <typename T, int O>
+__global__ void __launch_bounds__(256) k_adjoint_scatter(PConst<T> pc, PArr<T> sp, FieldPtrs<T> fp, AdjPtrs<T> ap)
+{
+    const int64_t p = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (p >= sp.n)
+        return;
+    int c[3];
+    T f[3];
+    if (!load_position(sp, p, pc.n, c, f))
+        return;
+    const int z3[3] = {0, 0, 0};
+    adjoint_scatter_particle<T, O, false, 2>(pc, ap, global_fields(fp), p, c, f, z3, 0, z3, nullptr, 0);
+}
+
+// ---------------------------------------------------------------------------
+// Tiled transpose: one workgroup per tile of the binning the forward sort
+// produced; no slack, particles outside the tile take the global path.
+template <typename T>
+struct AdjThreads {
+    static constexpr int value = sizeof(T) == 4 ? 1024 : 512;
+};
+
+struct TileSpan {
+    int t0[3];
+    int64_t ps, pe;
+};
+
+__device__ inline TileSpan tile_span(const TileGeo &tg, const int *tile_start, int64_t N)
+{
+    const int ntiles = tg.nt[0] * tg.nt[1] * tg.nt[2];
+    int t = blockIdx.x;
+    if (tg.xcd_map)
+        t = (t & 7) * (ntiles >> 3) + (t >> 3);
+    TileSpan s;
+    s.t0[0] = (t % tg.nt[0]) * tg.t[0];
+    s.t0[1] = ((t / tg.nt[0]) % tg.nt[1]) * tg.t[1];
+    s.t0[2] = (t / (tg.nt[0] * tg.nt[1])) * tg.t[2];
+    int64_t ps = tile_start[t], pe = tile_start[t + 1];
+    ps = ps < 0 ? 0 : (ps > N ? N : ps);
+    pe = pe < ps ? ps : (pe > N ? N : pe);
+    s.ps = ps;
+    s.pe = pe;
+    return s;
+}
+
+// cell position relative to the tile origin, periodic; true when inside
+__device__ inline bool tile_local(const TileGeo &tg, const int *n, const int *t0, const int *c, int *l)
+{
+    bool inside = true;
+#pragma unroll
+    for (int d = 0; d < 3; ++d) {
+        int v = c[d] - t0[d];
+        if (v < -tg.slack)
+            v += n[d];
+        else if (v >= tg.t[d] + tg.slack)
+            v -= n[d];
+        l[d] = v;
+        inside = inside && v >= -tg.slack && v < tg.t[d] + tg.slack;
+    }
+    return inside;
+}
+
+__device__ inline int region_global(const int *n, const int *t0, int lo, int rx, int ry, int rz)
+{
+    const int gx = wrap_any(t0[0] - lo + rx, n[0]);
+    const int gy = wrap_any(t0[1] - lo + ry, n[1]);
+    const int gz = wrap_any(t0[2] - lo + rz, n[2]);
+    return gx + n[0] * (gy + n[1] * gz);
+}
+
+// pass 1, tiled: LDS holds E, B with the gather halo and hatE with the
+// deposit halo.  Particles that drifted out of their tile are left to
+// k_adjoint_push_strays, so this kernel carries only the LDS path.
+template <typename T, int O>
+__global__ void __launch_bounds__(AdjThreads<T>::value) k_adjoint_push_tile(PConst<T> pc, TileGeo tg, PArr<T> sp,
+                                                                           FieldPtrs<T> fp, AdjPtrs<T> ap,
+                                                                           const int *__restrict__ tile_start,
+                                                                           int *err)
 {
     extern __shared__ __align__(16) unsigned char smem_raw[];
     const int rfx = tg.rf[0], rfy = tg.rf[1];
     const int rfvol = rfx * rfy * tg.rf[2];
     const int rjx = tg.rj[0], rjy = tg.rj[1];
     const int rjvol = rjx * rjy * tg.rj[2];
-    double *sL = reinterpret_cast<double *>(smem_raw);                  // 6 * rfvol doubles
-    T *sF = reinterpret_cast<T *>(smem_raw + 6 * rfvol * sizeof(double));
-    T *sH = sF + 6 * rfvol;                                              // 3 * rjvol
-
-    const int ntiles = tg.nt[0] * tg.nt[1] * tg.nt[2];
-    int t = blockIdx.x;
-    if (tg.xcd_map)
-        t = (t & 7) * (ntiles >> 3) + (t >> 3);
-    const int tx = t % tg.nt[0], ty = (t / tg.nt[0]) % tg.nt[1], tz = t / (tg.nt[0] * tg.nt[1]);
-    const int t0[3] = {tx * tg.t[0], ty * tg.t[1], tz * tg.t[2]};
-    const int64_t N = sp.n;
-    int64_t ps = tile_start[t], pe = tile_start[t + 1];
-    ps = ps < 0 ? 0 : (ps > N ? N : ps);
-    pe = pe < ps ? ps : (pe > N ? N : pe);
-    if (pe <= ps)
+    T *sF = reinterpret_cast<T *>(smem_raw);   // 6 * rfvol
+    T *sH = sF + 6 * rfvol;                    // 3 * rjvol
+    const TileSpan ts = tile_span(tg, tile_start, sp.n);
+    if (ts.pe <= ts.ps)
         return;   // uniform across the workgroup
-
     const int tid = threadIdx.x, nth = blockDim.x;
     for (int r = tid; r < rfvol; r += nth) {
-        const int rx = r % rfx, ry = (r / rfx) % rfy, rz = r / (rfx * rfy);
-        const int gx = wrap_any(t0[0] - tg.lo_f + rx, pc.n[0]);
-        const int gy = wrap_any(t0[1] - tg.lo_f + ry, pc.n[1]);
-        const int gz = wrap_any(t0[2] - tg.lo_f + rz, pc.n[2]);
-        const int gi = gx + pc.n[0] * (gy + pc.n[1] * gz);
+        const int gi = region_global(pc.n, ts.t0, tg.lo_f, r % rfx, (r / rfx) % rfy, r / (rfx * rfy));
 #pragma unroll
         for (int m = 0; m < 3; ++m) {
             sF[m * rfvol + r] = fp.E[m][gi];
             sF[(3 + m) * rfvol + r] = fp.B[m][gi];
         }
-#pragma unroll
-        for (int m = 0; m < 6; ++m)
-            sL[m * rfvol + r] = 0.0;
     }
     for (int r = tid; r < rjvol; r += nth) {
-        const int rx = r % rjx, ry = (r / rjx) % rjy, rz = r / (rjx * rjy);
-        const int gx = wrap_any(t0[0] - tg.lo_j + rx, pc.n[0]);
-        const int gy = wrap_any(t0[1] - tg.lo_j + ry, pc.n[1]);
-        const int gz = wrap_any(t0[2] - tg.lo_j + rz, pc.n[2]);
-        const int gi = gx + pc.n[0] * (gy + pc.n[1] * gz);
+        const int gi = region_global(pc.n, ts.t0, tg.lo_j, r % rjx, (r / rjx) % rjy, r / (rjx * rjy));
 #pragma unroll
         for (int m = 0; m < 3; ++m)
             sH[m * rjvol + r] = ap.hat[m][gi];
     }
     __syncthreads();
-
-    FieldSrc<T> lf, gf;
+    FieldSrc<T> lf;
 #pragma unroll
-    for (int m = 0; m < 3; ++m) {
+    for (int m = 0; m < 6; ++m)
         lf.c[m] = sF + m * rfvol;
-        lf.c[3 + m] = sF + (3 + m) * rfvol;
-        gf.c[m] = fp.E[m];
-        gf.c[3 + m] = fp.B[m];
-    }
     const T *lh[3] = {sH, sH + rjvol, sH + 2 * rjvol};
     const int sf[3] = {1, rfx, rfx * rfy};
     const int sj[3] = {1, rjx, rjx * rjy};
-    const int np = (int)(pe - ps);
+    const int np = (int)(ts.pe - ts.ps);
     for (int j0 = 0; j0 < np; j0 += nth) {
         const int j = j0 + tid;
         if (j < np) {
-            const int64_t p = ps + j;
+            const int64_t p = ts.ps + j;
             int c[3];
             T f[3], u[3];
-            if (load_particle(sp, p, pc.n, c, f, u, err)) {
+            if (!load_particle(sp, p, pc.n, c, f, u, err)) {
+                clear_vb(ap, p);
+            } else {
                 int l[3];
-                bool inside = true;
+                if (tile_local(tg, pc.n, ts.t0, c, l))
+                    adjoint_push_particle<T, O, true>(pc, sp, ap, lf, lh, p, c, f, u, l, tg.lo_f, sf, tg.lo_j, sj,
+                                                      err);
+            }
+        }
+    }
+}
+
+// pass 1 for the particles of each tile that lie outside it, on global
+// memory; the others only have their cell read
+template <typename T, int O>
+__global__ void __launch_bounds__(256) k_adjoint_push_strays(PConst<T> pc, TileGeo tg, PArr<T> sp, FieldPtrs<T> fp,
+                                                             AdjPtrs<T> ap, const int *__restrict__ tile_start,
+                                                             int *err)
+{
+    const TileSpan ts = tile_span(tg, tile_start, sp.n);
+    const int np = (int)(ts.pe - ts.ps);
+    for (int j = threadIdx.x; j < np; j += blockDim.x) {
+        const int64_t p = ts.ps + j;
+        int c[3], l[3];
+        bool ok = true;
 #pragma unroll
-                for (int d = 0; d < 3; ++d) {
-                    int v = c[d] - t0[d];
-                    if (v < -tg.slack)
-                        v += pc.n[d];
-                    else if (v >= tg.t[d] + tg.slack)
-                        v -= pc.n[d];
-                    l[d] = v;
-                    inside = inside && v >= -tg.slack && v < tg.t[d] + tg.slack;
-                }
-                if (inside)
-                    adjoint_particle<T, O, true>(pc, sp, ap, lf, lh, p, c, f, u, l, tg.lo_f, sf, tg.lo_j, sj, sL,
-                                                 rfvol, err);
+        for (int d = 0; d < 3; ++d) {
+            c[d] = sp.cell[d][p];
+            ok = ok && c[d] >= 0 && c[d] < pc.n[d];
+        }
+        if (!ok || tile_local(tg, pc.n, ts.t0, c, l))
+            continue;   // bad cells are flagged by the tile kernel
+        T f[3], u[3];
+        if (!load_particle(sp, p, pc.n, c, f, u, err)) {
+            clear_vb(ap, p);
+            continue;
+        }
+        const int z3[3] = {0, 0, 0};
+        adjoint_push_particle<T, O, false>(pc, sp, ap, global_fields(fp), ap.hat, p, c, f, u, z3, 0, z3, 0, z3, err);
+    }
+}
+
+// pass 2, tiled, for group G (0: E, 1: B): LDS holds FP64 accumulators of
+// the group's three adjoints and the group's fields with the gather halo;
+// the accumulators are flushed with one global atomic per non-zero value
+template <typename T, int O, int G>
+__global__ void __launch_bounds__(AdjThreads<T>::value) k_adjoint_scatter_tile(PConst<T> pc, TileGeo tg, PArr<T> sp,
+                                                                              FieldPtrs<T> fp, AdjPtrs<T> ap,
+                                                                              const int *__restrict__ tile_start)
+{
+    extern __shared__ __align__(16) unsigned char smem_raw[];
+    const int rfx = tg.rf[0], rfy = tg.rf[1];
+    const int rfvol = rfx * rfy * tg.rf[2];
+    double *sL = reinterpret_cast<double *>(smem_raw);               // 3 * rfvol
+    T *sF = reinterpret_cast<T *>(smem_raw + 3 * rfvol * sizeof(double));   // 3 * rfvol
+    const TileSpan ts = tile_span(tg, tile_start, sp.n);
+    if (ts.pe <= ts.ps)
+        return;
+    T *const *gsrc = G == 0 ? fp.E : fp.B;
+    T *const *gdst = G == 0 ? ap.lE : ap.lB;
+    const int tid = threadIdx.x, nth = blockDim.x;
+    for (int r = tid; r < rfvol; r += nth) {
+        const int gi = region_global(pc.n, ts.t0, tg.lo_f, r % rfx, (r / rfx) % rfy, r / (rfx * rfy));
+#pragma unroll
+        for (int m = 0; m < 3; ++m) {
+            sF[m * rfvol + r] = gsrc[m][gi];
+            sL[m * rfvol + r] = 0.0;
+        }
+    }
+    __syncthreads();
+    FieldSrc<T> lf;
+#pragma unroll
+    for (int m = 0; m < 3; ++m) {
+        lf.c[3 * G + m] = sF + m * rfvol;
+        lf.c[3 * (1 - G) + m] = nullptr;
+    }
+    const FieldSrc<T> gf = global_fields(fp);
+    const int sf[3] = {1, rfx, rfx * rfy};
+    const int np = (int)(ts.pe - ts.ps);
+    for (int j0 = 0; j0 < np; j0 += nth) {
+        const int j = j0 + tid;
+        if (j < np) {
+            const int64_t p = ts.ps + j;
+            int c[3];
+            T f[3];
+            if (load_position(sp, p, pc.n, c, f)) {
+                int l[3];
+                if (tile_local(tg, pc.n, ts.t0, c, l))
+                    adjoint_scatter_particle<T, O, true, G>(pc, ap, lf, p, c, f, l, tg.lo_f, sf, sL, rfvol);
                 else
-                    adjoint_particle<T, O, false>(pc, sp, ap, gf, ap.hat, p, c, f, u, l, tg.lo_f, sf, tg.lo_j, sj,
-                                                  nullptr, rfvol, err);
+                    adjoint_scatter_particle<T, O, false, G>(pc, ap, gf, p, c, f, l, tg.lo_f, sf, nullptr, rfvol);
             }
         }
     }
     __syncthreads();
-    for (int r = tid; r < 6 * rfvol; r += nth) {
+    for (int r = tid; r < 3 * rfvol; r += nth) {
         const T v = (T)sL[r];
         if (v != T(0)) {
             const int m = r / rfvol, rr = r - m * rfvol;
-            const int rx = rr % rfx, ry = (rr / rfx) % rfy, rz = rr / (rfx * rfy);
-            const int gx = wrap_any(t0[0] - tg.lo_f + rx, pc.n[0]);
-            const int gy = wrap_any(t0[1] - tg.lo_f + ry, pc.n[1]);
-            const int gz = wrap_any(t0[2] - tg.lo_f + rz, pc.n[2]);
-            T *dst = m < 3 ? ap.lE[m] : ap.lB[m - 3];
-            gatomic_add(dst + gx + pc.n[0] * (gy + pc.n[1] * gz), v);
+            const int gi = region_global(pc.n, ts.t0, tg.lo_f, rr % rfx, (rr / rfx) % rfy, rr / (rfx * rfy));
+            gatomic_add(gdst[m] + gi, v);
         }
     }
 }
@@ -825,7 +1005,8 @@ hipError_t launch_deposit(int order, const PConst<T> &pc, const PArr<T> &before,
 }
 
 template <typename T>
-static AdjPtrs<T> adj_ptrs(T *const hatE[3], T *const lx[3], T *const lu[3], T *const lE[3], T *const lB[3])
+static AdjPtrs<T> adj_ptrs(T *const hatE[3], T *const lx[3], T *const lu[3], T *const lE[3], T *const lB[3],
+                           T *const vb[6])
 {
     AdjPtrs<T> a{};
     for (int d = 0; d < 3; ++d) {
@@ -835,57 +1016,97 @@ static AdjPtrs<T> adj_ptrs(T *const hatE[3], T *const lx[3], T *const lu[3], T *
         a.lE[d] = lE[d];
         a.lB[d] = lB[d];
     }
+    for (int m = 0; m < 6; ++m)
+        a.vb[m] = vb[m];
     return a;
 }
 
 template <typename T>
 hipError_t launch_adjoint_particles(int order, const PConst<T> &pc, const PArr<T> &sp, const FieldPtrs<T> &f,
                                     T *const hatE[3], T *const lx[3], T *const lu[3], T *const lE[3],
-                                    T *const lB[3], int *err, hipStream_t st)
+                                    T *const lB[3], T *const vb[6], int *err, hipStream_t st)
 {
     if (sp.n == 0)
         return hipSuccess;
-    const AdjPtrs<T> ap = adj_ptrs<T>(hatE, lx, lu, lE, lB);
-    if (order == 1)
-        hipLaunchKernelGGL((k_adjoint_particles<T, 1>), dim3(nblk(sp.n, 256)), dim3(256), 0, st, pc, sp, f, ap, err);
-    else
-        hipLaunchKernelGGL((k_adjoint_particles<T, 3>), dim3(nblk(sp.n, 256)), dim3(256), 0, st, pc, sp, f, ap, err);
+    const AdjPtrs<T> ap = adj_ptrs<T>(hatE, lx, lu, lE, lB, vb);
+    const unsigned nb = nblk(sp.n, 256);
+    if (order == 1) {
+        hipLaunchKernelGGL((k_adjoint_push<T, 1>), dim3(nb), dim3(256), 0, st, pc, sp, f, ap, err);
+        hipLaunchKernelGGL((k_adjoint_scatter<T, 1>), dim3(nb), dim3(256), 0, st, pc, sp, f, ap);
+    } else {
+        hipLaunchKernelGGL((k_adjoint_push<T, 3>), dim3(nb), dim3(256), 0, st, pc, sp, f, ap, err);
+        hipLaunchKernelGGL((k_adjoint_scatter<T, 3>), dim3(nb), dim3(256), 0, st, pc, sp, f, ap);
+    }
     return hipGetLastError();
+}
+
+// LDS of the two tiled passes: pass 1 E, B (gather halo) and hatE (deposit
+// halo) in the working precision; pass 2 FP64 accumulators and fields of one
+// group of three components
+template <typename T>
+size_t adjoint_push_lds(const TileGeo &tg)
+{
+    const size_t rf = (size_t)tg.rf[0] * tg.rf[1] * tg.rf[2];
+    const size_t rj = (size_t)tg.rj[0] * tg.rj[1] * tg.rj[2];
+    return 6 * rf * sizeof(T) + 3 * rj * sizeof(T);
+}
+
+template <typename T>
+size_t adjoint_scatter_lds(const TileGeo &tg)
+{
+    const size_t rf = (size_t)tg.rf[0] * tg.rf[1] * tg.rf[2];
+    return 3 * rf * (sizeof(double) + sizeof(T));
 }
 
 template <typename T>
 size_t adjoint_lds_bytes(int, const TileGeo &tg)
 {
-    const size_t rf = (size_t)tg.rf[0] * tg.rf[1] * tg.rf[2];
-    const size_t rj = (size_t)tg.rj[0] * tg.rj[1] * tg.rj[2];
-    return 6 * rf * sizeof(double) + 6 * rf * sizeof(T) + 3 * rj * sizeof(T);
+    const size_t a = adjoint_push_lds<T>(tg), b = adjoint_scatter_lds<T>(tg);
+    return a > b ? a : b;
+}
+
+template <typename K>
+static void allow_big_lds(K *kernel, bool &done)
+{
+    if (!done) {
+        // allow more than the default dynamic LDS per workgroup
+        hipFuncSetAttribute(reinterpret_cast<const void *>(kernel), hipFuncAttributeMaxDynamicSharedMemorySize,
+                            160 * 1024);
+        done = true;
+    }
 }
 
 template <typename T, int O>
 static hipError_t launch_adj_tile_o(const PConst<T> &pc, const TileGeo &tg, const PArr<T> &sp, const FieldPtrs<T> &f,
                                     const AdjPtrs<T> &ap, const int *tile_start, int *err, hipStream_t st)
 {
-    const size_t lds = adjoint_lds_bytes<T>(O, tg);
-    static bool attr_set = false;
-    if (!attr_set) {
-        hipFuncSetAttribute(reinterpret_cast<const void *>(&k_adjoint_tile<T, O>),
-                            hipFuncAttributeMaxDynamicSharedMemorySize, 160 * 1024);
-        attr_set = true;
-    }
+    static bool a1 = false, a2 = false, a3 = false;
+    allow_big_lds(&k_adjoint_push_tile<T, O>, a1);
+    allow_big_lds(&k_adjoint_scatter_tile<T, O, 0>, a2);
+    allow_big_lds(&k_adjoint_scatter_tile<T, O, 1>, a3);
     const unsigned ntiles = (unsigned)(tg.nt[0] * tg.nt[1] * tg.nt[2]);
-    hipLaunchKernelGGL((k_adjoint_tile<T, O>), dim3(ntiles), dim3(ADJ_THREADS), lds, st, pc, tg, sp, f, ap,
-                       tile_start, err);
+    const unsigned nth = AdjThreads<T>::value;
+    const size_t l1 = adjoint_push_lds<T>(tg), l2 = adjoint_scatter_lds<T>(tg);
+    hipLaunchKernelGGL((k_adjoint_push_tile<T, O>), dim3(ntiles), dim3(nth), l1, st, pc, tg, sp, f, ap, tile_start,
+                       err);
+    hipLaunchKernelGGL((k_adjoint_push_strays<T, O>), dim3(ntiles), dim3(256), 0, st, pc, tg, sp, f, ap, tile_start,
+                       err);
+    hipLaunchKernelGGL((k_adjoint_scatter_tile<T, O, 0>), dim3(ntiles), dim3(nth), l2, st, pc, tg, sp, f, ap,
+                       tile_start);
+    hipLaunchKernelGGL((k_adjoint_scatter_tile<T, O, 1>), dim3(ntiles), dim3(nth), l2, st, pc, tg, sp, f, ap,
+                       tile_start);
     return hipGetLastError();
 }
 
 template <typename T>
 hipError_t launch_adjoint_tile(int order, const PConst<T> &pc, const TileGeo &tg, const PArr<T> &sp,
                                const FieldPtrs<T> &f, T *const hatE[3], T *const lx[3], T *const lu[3],
-                               T *const lE[3], T *const lB[3], const int *tile_start, int *err, hipStream_t st)
+                               T *const lE[3], T *const lB[3], T *const vb[6], const int *tile_start, int *err,
+                               hipStream_t st)
 {
     if (sp.n == 0)
         return hipSuccess;
-    const AdjPtrs<T> ap = adj_ptrs<T>(hatE, lx, lu, lE, lB);
+    const AdjPtrs<T> ap = adj_ptrs<T>(hatE, lx, lu, lE, lB, vb);
     return order == 1 ? launch_adj_tile_o<T, 1>(pc, tg, sp, f, ap, tile_start, err, st)
                       : launch_adj_tile_o<T, 3>(pc, tg, sp, f, ap, tile_start, err, st);
 }
@@ -905,11 +1126,12 @@ hipError_t launch_adjoint_tile(int order, const PConst<T> &pc, const TileGeo &tg
                                           const FieldPtrs<T> &, int *, hipStream_t);                               \
     template hipError_t launch_adjoint_particles<T>(int, const PConst<T> &, const PArr<T> &, const FieldPtrs<T> &, \
                                                     T *const[3], T *const[3], T *const[3], T *const[3],            \
-                                                    T *const[3], int *, hipStream_t);                              \
+                                                    T *const[3], T *const[6], int *, hipStream_t);                 \
     template size_t adjoint_lds_bytes<T>(int, const TileGeo &);                                                    \
     template hipError_t launch_adjoint_tile<T>(int, const PConst<T> &, const TileGeo &, const PArr<T> &,           \
                                                const FieldPtrs<T> &, T *const[3], T *const[3], T *const[3],        \
-                                               T *const[3], T *const[3], const int *, int *, hipStream_t);
+                                               T *const[3], T *const[3], T *const[6], const int *, int *,          \
+                                               hipStream_t);
 
 PIC_INST(float)
 PIC_INST(double)

@@ -492,7 +492,13 @@ __device__ __attribute__((always_inline)) inline void esk_gather_adjoint(const E
                 gDS[p][b] += H * (half * e[q].S0[c] + third * e[q].DS[c]);
                 gS0[q][c] += H * (e[p].S0[b] + half * e[p].DS[b]);
                 gDS[q][c] += H * (half * e[p].S0[b] + third * e[p].DS[b]);
-                // keep the scheduler from hoisting every window load at once
+                // Finish this window entry's arithmetic here: without the
+                // register operands below the compiler issues every window
+                // load first and parks the values in scratch memory.
+#pragma unroll
+                for (int a = 0; a < NW; ++a)
+                    asm volatile("" : "+v"(G[a]));
+                asm volatile("" : "+v"(gS0[p][b]), "+v"(gDS[p][b]), "+v"(gS0[q][c]), "+v"(gDS[q][c]));
                 __builtin_amdgcn_sched_barrier(0);
             }
         }

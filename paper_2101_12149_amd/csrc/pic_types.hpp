@@ -89,10 +89,12 @@ hipError_t launch_push(const PConst<T> &pc, const PArr<T> &sp, T *const Ep[3], T
 template <typename T>
 hipError_t launch_deposit(int order, const PConst<T> &pc, const PArr<T> &before, const PArr<T> &after,
                           const FieldPtrs<T> &f, int *err, hipStream_t st);
+// adjoint launchers: vb[6] is per-particle scratch (T[n] each) that carries
+// the adjoints of the gathered E and B from the first pass to the second
 template <typename T>
 hipError_t launch_adjoint_particles(int order, const PConst<T> &pc, const PArr<T> &sp, const FieldPtrs<T> &f,
                                     T *const hatE[3], T *const lx[3], T *const lu[3], T *const lE[3],
-                                    T *const lB[3], int *err, hipStream_t st);
+                                    T *const lB[3], T *const vb[6], int *err, hipStream_t st);
 template <typename T>
 size_t tile_lds_bytes(int order, const TileGeo &tg);
 template <typename T>
@@ -100,7 +102,8 @@ size_t adjoint_lds_bytes(int order, const TileGeo &tg);
 template <typename T>
 hipError_t launch_adjoint_tile(int order, const PConst<T> &pc, const TileGeo &tg, const PArr<T> &sp,
                                const FieldPtrs<T> &f, T *const hatE[3], T *const lx[3], T *const lu[3],
-                               T *const lE[3], T *const lB[3], const int *tile_start, int *err, hipStream_t st);
+                               T *const lE[3], T *const lB[3], T *const vb[6], const int *tile_start, int *err,
+                               hipStream_t st);
 
 template <typename T>
 hipError_t launch_curl(bool forward, const CurlArgs<T> &a, hipStream_t st);
