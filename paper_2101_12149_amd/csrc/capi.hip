@@ -163,25 +163,34 @@ void region_extents(int order, TileGeo &tg)
     tg.lo_j = s + gl;
 }
 
-// regions of the tiled adjoint: same tiles, no slack.  Its first pass holds
-// E, B with the gather halo and hatE with the deposit halo, its second the
-// FP64 accumulators and fields of one group of three components.
-TileGeo adjoint_geo(const GridInfo &gi)
+// LDS of the tiled adjoint: its first pass holds E, B with the gather halo
+// and hatE with the deposit halo, its second the FP64 accumulators and the
+// fields of one group of three components
+size_t adj_lds_for(const GridInfo &gi, const TileGeo &a)
 {
-    TileGeo a = gi.tg;
-    a.slack = 0;
-    region_extents(gi.order, a);
-    return a;
-}
-
-size_t adj_lds_bytes(const GridInfo &gi)
-{
-    const TileGeo a = adjoint_geo(gi);
     const size_t rf = (size_t)a.rf[0] * a.rf[1] * a.rf[2];
     const size_t rj = (size_t)a.rj[0] * a.rj[1] * a.rj[2];
     const size_t push = 6 * rf * gi.tsize + 3 * rj * gi.tsize;
     const size_t scatter = 3 * rf * (sizeof(double) + gi.tsize);
     return push > scatter ? push : scatter;
+}
+
+// regions of the tiled adjoint: the forward's tiles, with its slack when
+// the adjoint regions fit the LDS and without otherwise
+TileGeo adjoint_geo(const GridInfo &gi)
+{
+    TileGeo a = gi.tg;
+    region_extents(gi.order, a);
+    if (a.slack > 0 && adj_lds_for(gi, a) > (size_t)lds_limit()) {
+        a.slack = 0;
+        region_extents(gi.order, a);
+    }
+    return a;
+}
+
+size_t adj_lds_bytes(const GridInfo &gi)
+{
+    return adj_lds_for(gi, adjoint_geo(gi));
 }
 
 size_t lds_bytes(const GridInfo &gi)
@@ -238,33 +247,28 @@ pic_status check_grid(const pic_grid *g, GridInfo &gi)
     if (g->slack < -1 || g->slack > 2)
         return fail(PIC_E_INVALID, "slack must be -1 (automatic) or in [0,2]");
     const size_t limit = (size_t)lds_limit();
-    // automatic slack: one cell when the regions still fit one workgroup
-    gi.tg.slack = g->slack < 0 ? 1 : g->slack;
+    // Automatic slack is one cell.  While the forward regions (with slack)
+    // or the adjoint regions (without) do not fit one workgroup, an automatic
+    // tile halves its largest dimension; only when no dimension can shrink
+    // does an automatic slack drop to zero.  A smaller tile with slack beats
+    // a larger one without: particles that drift out of a slack-free tile
+    // between sorts take the global path.
+    const bool auto_slack = g->slack < 0;
+    gi.tg.slack = auto_slack ? 1 : g->slack;
     region_extents(gi.order, gi.tg);
-    if (g->slack < 0 && lds_bytes(gi) > limit) {
-        gi.tg.slack = 0;
-        region_extents(gi.order, gi.tg);
-    }
-    // an automatic tile shrinks until the forward regions (with the chosen
-    // slack) and the adjoint regions (without slack) fit one workgroup
     while (lds_bytes(gi) > limit || adj_lds_bytes(gi) > limit) {
         int dmax = -1;
         for (int d = 0; d < 3; ++d)
             if (auto_tile[d] && gi.tg.t[d] >= 4 && gi.tg.t[d] % 2 == 0 &&
                 (dmax < 0 || gi.tg.t[d] > gi.tg.t[dmax] || (gi.tg.t[d] == gi.tg.t[dmax] && d > dmax)))
                 dmax = d;
-        if (dmax < 0)
+        if (dmax >= 0)
+            gi.tg.t[dmax] /= 2;
+        else if (auto_slack && gi.tg.slack > 0)
+            gi.tg.slack = 0;
+        else
             break;
-        gi.tg.t[dmax] /= 2;
         region_extents(gi.order, gi.tg);
-        if (g->slack < 0 && gi.tg.slack == 0) {
-            gi.tg.slack = 1;
-            region_extents(gi.order, gi.tg);
-            if (lds_bytes(gi) > limit) {
-                gi.tg.slack = 0;
-                region_extents(gi.order, gi.tg);
-            }
-        }
     }
     if (lds_bytes(gi) > limit)
         return fail(PIC_E_UNSUPPORTED, "tile plus halo does not fit in LDS; use a smaller tile or slack");
@@ -575,6 +579,9 @@ pic_status step_t(const pic_grid *g, const GridInfo &gi, pic_species *sp, pic_fi
     const PConst<T> pc = make_const<T>(g, sp);
     const FieldPtrs<T> fp = fptrs<T>(f);
     const PArr<T> user = parr<T>(sp);
+    // per-particle stray marks of the tile kernels, in the sort's key buffer
+    // (free once the sort of the step is done)
+    unsigned char *stray = reinterpret_cast<unsigned char *>(w + L.key);
     PIC_HIP(launch_fill<int>(err, 1, 0, st));
     for (int d = 0; d < 3; ++d)
         PIC_HIP(launch_fill<T>(fp.J[d], gi.ncell, T(0), st));
@@ -590,10 +597,10 @@ pic_status step_t(const pic_grid *g, const GridInfo &gi, pic_species *sp, pic_fi
                     return s;
             }
             TimedScope ts(1, st);
-            PIC_HIP(launch_particles_tile<T>(gi.order, pc, gi.tg, sorted, user, fp, tile_start, err, st));
+            PIC_HIP(launch_particles_tile<T>(gi.order, pc, gi.tg, sorted, user, fp, tile_start, stray, err, st));
         } else if (tile_start && sp->n > 0) {
             TimedScope ts(1, st);
-            PIC_HIP(launch_particles_tile<T>(gi.order, pc, gi.tg, user, user, fp, tile_start, err, st));
+            PIC_HIP(launch_particles_tile<T>(gi.order, pc, gi.tg, user, user, fp, tile_start, stray, err, st));
         } else {
             TimedScope ts(1, st);
             PIC_HIP(launch_particles_global<T>(gi.order, pc, user, fp, err, st));
@@ -696,8 +703,8 @@ pic_status adjoint_t(const pic_grid *g, const GridInfo &gi, const pic_species *s
         // The tiled FP64 order-3 transpose stays switched off: an earlier
         // fused form of it returned wrong position adjoints on the device
         // without a cause found in its code, so that request takes the
-        // per-particle kernels.
-        const bool tiled_ok = !(gi.dtype == PIC_F64 && gi.order == 3);
+        // per-particle kernels, as does a tile whose regions exceed the LDS.
+        const bool tiled_ok = !(gi.dtype == PIC_F64 && gi.order == 3) && adj_lds_bytes(gi) <= (size_t)lds_limit();
         if (tile_start && tiled_ok)
             PIC_HIP(launch_adjoint_tile<T>(gi.order, pc, adjoint_geo(gi), parr<T>(sp), fptrs<T>(f), hat, lx, lu, lE,
                                            lB, vb, tile_start, err, st));

@@ -93,6 +93,117 @@ __device__ inline void copy_particle(const PArr<T> &in, const PArr<T> &out, int6
 }
 
 // ---------------------------------------------------------------------------
+// tiles
+
+template <typename T>
+__device__ inline FieldSrc<T> global_fields(const FieldPtrs<T> &fp)
+{
+    FieldSrc<T> gf;
+#pragma unroll
+    for (int m = 0; m < 3; ++m) {
+        gf.c[m] = fp.E[m];
+        gf.c[3 + m] = fp.B[m];
+    }
+    return gf;
+}
+
+struct TileSpan {
+    int t0[3];
+    int64_t ps, pe;
+};
+
+__device__ inline TileSpan tile_span(const TileGeo &tg, const int *tile_start, int64_t N)
+{
+    const int ntiles = tg.nt[0] * tg.nt[1] * tg.nt[2];
+    int t = blockIdx.x;
+    if (tg.xcd_map)
+        t = (t & 7) * (ntiles >> 3) + (t >> 3);
+    TileSpan s;
+    s.t0[0] = (t % tg.nt[0]) * tg.t[0];
+    s.t0[1] = ((t / tg.nt[0]) % tg.nt[1]) * tg.t[1];
+    s.t0[2] = (t / (tg.nt[0] * tg.nt[1])) * tg.t[2];
+    int64_t ps = tile_start[t], pe = tile_start[t + 1];
+    ps = ps < 0 ? 0 : (ps > N ? N : ps);
+    pe = pe < ps ? ps : (pe > N ? N : pe);
+    s.ps = ps;
+    s.pe = pe;
+    return s;
+}
+
+// cell position relative to the tile origin, periodic; true when inside
+__device__ inline bool tile_local(const TileGeo &tg, const int *n, const int *t0, const int *c, int *l)
+{
+    bool inside = true;
+#pragma unroll
+    for (int d = 0; d < 3; ++d) {
+        int v = c[d] - t0[d];
+        if (v < -tg.slack)
+            v += n[d];
+        else if (v >= tg.t[d] + tg.slack)
+            v -= n[d];
+        l[d] = v;
+        inside = inside && v >= -tg.slack && v < tg.t[d] + tg.slack;
+    }
+    return inside;
+}
+
+__device__ inline int region_global(const int *n, const int *t0, int lo, int rx, int ry, int rz)
+{
+    const int gx = wrap_any(t0[0] - lo + rx, n[0]);
+    const int gy = wrap_any(t0[1] - lo + ry, n[1]);
+    const int gz = wrap_any(t0[2] - lo + rz, n[2]);
+    return gx + n[0] * (gy + n[1] * gz);
+}
+
+// Particles of a tile whose cell lies outside the tile's regions (they
+// drifted since the binning) are left out by the tile kernels and taken by
+// the stray kernels below, which first gather a chunk's strays into an LDS
+// list so that they run in full waves rather than as a few divergent lanes
+// of every wave.
+constexpr int STRAY_THREADS = 256;
+constexpr int STRAY_CHUNK = 4096;
+
+// Collect the in-tile indices j in [j0, j0 + STRAY_CHUNK) for which
+// is_stray(p) holds into the LDS list; returns the count.
+template <typename Pred>
+__device__ inline int collect_strays(const TileSpan &ts, int j0, int *list, int *cnt, Pred &&is_stray)
+{
+    if (threadIdx.x == 0)
+        *cnt = 0;
+    __syncthreads();
+    const int np = (int)(ts.pe - ts.ps);
+    const int je = np < j0 + STRAY_CHUNK ? np : j0 + STRAY_CHUNK;
+    for (int j = j0 + (int)threadIdx.x; j < je; j += blockDim.x)
+        if (is_stray(ts.ps + j))
+            list[atomicAdd(cnt, 1)] = j;
+    __syncthreads();
+    const int k = *cnt;
+    __syncthreads();   // every thread has the count before the next reset
+    return k;
+}
+
+// stray test from the cell (for kernels that do not move particles); an
+// invalid cell is not a stray, the tile kernel flags it
+template <typename T>
+struct CellStray {
+    const TileGeo &tg;
+    const int *n;
+    const TileSpan &ts;
+    const PArr<T> &sp;
+    __device__ bool operator()(int64_t p) const
+    {
+        int c[3], l[3];
+        bool ok = true;
+#pragma unroll
+        for (int d = 0; d < 3; ++d) {
+            c[d] = sp.cell[d][p];
+            ok = ok && c[d] >= 0 && c[d] < n[d];
+        }
+        return ok && !tile_local(tg, n, ts.t0, c, l);
+    }
+};
+
+// ---------------------------------------------------------------------------
 // One particle through gather -> Boris -> move -> Esirkepov.  With LOCAL the
 // particle lies in the LDS regions (positions l[] relative to the tile);
 // otherwise everything is read and scattered in global memory.
@@ -168,10 +279,13 @@ __device__ __attribute__((always_inline)) inline void particle_step(const PConst
 }
 
 // ---------------------------------------------------------------------------
+// stray[p] records whether particle p was left to k_particles_strays: when
+// the step runs in place the cells are overwritten, so the stray kernel
+// cannot tell the strays from the cells any more.
 template <typename T, int O>
 __global__ void __launch_bounds__(TileThreads<T>::value) k_particles_tile(PConst<T> pc, TileGeo tg, PArr<T> in, PArr<T> out,
                                                         FieldPtrs<T> fp, const int *__restrict__ tile_start,
-                                                        int *err)
+                                                        unsigned char *__restrict__ stray, int *err)
 {
     extern __shared__ __align__(16) unsigned char smem_raw[];
     T *sF = reinterpret_cast<T *>(smem_raw);
@@ -181,27 +295,13 @@ __global__ void __launch_bounds__(TileThreads<T>::value) k_particles_tile(PConst
     const int rjvol = rjx * rjy * tg.rj[2];
     // the current tile accumulates in FP64 (fast LDS atomics), after the fields
     double *sJ = reinterpret_cast<double *>(smem_raw + ((6 * rfvol * sizeof(T) + 15) & ~size_t(15)));
-
-    const int ntiles = tg.nt[0] * tg.nt[1] * tg.nt[2];
-    int t = blockIdx.x;
-    if (tg.xcd_map)
-        t = (t & 7) * (ntiles >> 3) + (t >> 3);
-    const int tx = t % tg.nt[0], ty = (t / tg.nt[0]) % tg.nt[1], tz = t / (tg.nt[0] * tg.nt[1]);
-    const int t0[3] = {tx * tg.t[0], ty * tg.t[1], tz * tg.t[2]};
-    const int64_t N = in.n;
-    int64_t ps = tile_start[t], pe = tile_start[t + 1];
-    ps = ps < 0 ? 0 : (ps > N ? N : ps);
-    pe = pe < ps ? ps : (pe > N ? N : pe);
-    if (pe <= ps)
+    const TileSpan ts = tile_span(tg, tile_start, in.n);
+    if (ts.pe <= ts.ps)
         return;   // uniform across the workgroup
 
     const int tid = threadIdx.x, nth = blockDim.x;
     for (int r = tid; r < rfvol; r += nth) {
-        const int rx = r % rfx, ry = (r / rfx) % rfy, rz = r / (rfx * rfy);
-        const int gx = wrap_any(t0[0] - tg.lo_f + rx, pc.n[0]);
-        const int gy = wrap_any(t0[1] - tg.lo_f + ry, pc.n[1]);
-        const int gz = wrap_any(t0[2] - tg.lo_f + rz, pc.n[2]);
-        const int gi = gx + pc.n[0] * (gy + pc.n[1] * gz);
+        const int gi = region_global(pc.n, ts.t0, tg.lo_f, r % rfx, (r / rfx) % rfy, r / (rfx * rfy));
 #pragma unroll
         for (int m = 0; m < 3; ++m) {
             sF[m * rfvol + r] = fp.E[m][gi];
@@ -212,48 +312,34 @@ __global__ void __launch_bounds__(TileThreads<T>::value) k_particles_tile(PConst
         sJ[r] = 0.0;
     __syncthreads();
 
-    FieldSrc<T> lf, gf;
+    FieldSrc<T> lf;
 #pragma unroll
-    for (int m = 0; m < 3; ++m) {
+    for (int m = 0; m < 6; ++m)
         lf.c[m] = sF + m * rfvol;
-        lf.c[3 + m] = sF + (3 + m) * rfvol;
-        gf.c[m] = fp.E[m];
-        gf.c[3 + m] = fp.B[m];
-    }
     const int sf[3] = {1, rfx, rfx * rfy};
     const int sj[3] = {1, rjx, rjx * rjy};
-    const int np = (int)(pe - ps);
+    const int np = (int)(ts.pe - ts.ps);
     // coalesced: the tile's particles are stored rank-major (one particle
     // per cell, cell after cell, then the next rank), so consecutive lanes
     // read consecutive memory and sit in distinct neighbouring cells
     for (int j0 = 0; j0 < np; j0 += nth) {
         const int j = j0 + tid;
         if (j < np) {
-            const int64_t p = ps + j;
+            const int64_t p = ts.ps + j;
             int c[3];
             T f[3], u[3];
+            unsigned char st = 0;
             if (!load_particle(in, p, pc.n, c, f, u, err)) {
                 copy_particle(in, out, p);
             } else {
                 int l[3];
-                bool inside = true;
-#pragma unroll
-                for (int d = 0; d < 3; ++d) {
-                    int v = c[d] - t0[d];
-                    if (v < -tg.slack)
-                        v += pc.n[d];
-                    else if (v >= tg.t[d] + tg.slack)
-                        v -= pc.n[d];
-                    l[d] = v;
-                    inside = inside && v >= -tg.slack && v < tg.t[d] + tg.slack;
-                }
-                if (inside)
+                if (tile_local(tg, pc.n, ts.t0, c, l))
                     particle_step<T, O, true>(pc, in, out, fp, lf, p, c, f, u, l, tg.lo_f, sf, tg.lo_j, sj, sJ,
                                               rjvol, err);
                 else
-                    particle_step<T, O, false>(pc, in, out, fp, gf, p, c, f, u, l, tg.lo_f, sf, tg.lo_j, sj, sJ,
-                                               rjvol, err);
+                    st = 1;
             }
+            stray[p] = st;
         }
     }
     __syncthreads();
@@ -261,12 +347,36 @@ __global__ void __launch_bounds__(TileThreads<T>::value) k_particles_tile(PConst
         const T v = (T)sJ[r];
         if (v != T(0)) {
             const int m = r / rjvol, rr = r - m * rjvol;
-            const int rx = rr % rjx, ry = (rr / rjx) % rjy, rz = rr / (rjx * rjy);
-            const int gx = wrap_any(t0[0] - tg.lo_j + rx, pc.n[0]);
-            const int gy = wrap_any(t0[1] - tg.lo_j + ry, pc.n[1]);
-            const int gz = wrap_any(t0[2] - tg.lo_j + rz, pc.n[2]);
-            gatomic_add(fp.J[m] + gx + pc.n[0] * (gy + pc.n[1] * gz), v);
+            const int gi = region_global(pc.n, ts.t0, tg.lo_j, rr % rjx, (rr / rjx) % rjy, rr / (rjx * rjy));
+            gatomic_add(fp.J[m] + gi, v);
         }
+    }
+}
+
+// the fused step for the strays of each tile, on global memory
+template <typename T, int O>
+__global__ void __launch_bounds__(STRAY_THREADS) k_particles_strays(PConst<T> pc, TileGeo tg, PArr<T> in, PArr<T> out,
+                                                                    FieldPtrs<T> fp, const int *__restrict__ tile_start,
+                                                                    const unsigned char *__restrict__ stray, int *err)
+{
+    __shared__ int list[STRAY_CHUNK];
+    __shared__ int cnt;
+    const TileSpan ts = tile_span(tg, tile_start, in.n);
+    const int np = (int)(ts.pe - ts.ps);
+    FieldSrc<T> gf = global_fields(fp);
+    const int z3[3] = {0, 0, 0};
+    for (int j0 = 0; j0 < np; j0 += STRAY_CHUNK) {
+        const int k = collect_strays(ts, j0, list, &cnt, [&](int64_t p) { return stray[p] != 0; });
+        for (int i = threadIdx.x; i < k; i += blockDim.x) {
+            const int64_t p = ts.ps + list[i];
+            int c[3];
+            T f[3], u[3];
+            if (!load_particle(in, p, pc.n, c, f, u, err))
+                copy_particle(in, out, p);
+            else
+                particle_step<T, O, false>(pc, in, out, fp, gf, p, c, f, u, z3, 0, z3, 0, z3, nullptr, 0, err);
+        }
+        __syncthreads();   // the list is rewritten by the next chunk
     }
 }
 
@@ -654,18 +764,6 @@ __device__ inline bool load_position(const PArr<T> &in, int64_t p, const int *n,
     return ok;
 }
 
-template <typename T>
-__device__ inline FieldSrc<T> global_fields(const FieldPtrs<T> &fp)
-{
-    FieldSrc<T> gf;
-#pragma unroll
-    for (int m = 0; m < 3; ++m) {
-        gf.c[m] = fp.E[m];
-        gf.c[3 + m] = fp.B[m];
-    }
-    return gf;
-}
-
 template <typename T, int O>
 __global__ void __launch_bounds__(256) k_adjoint_push(PConst<T> pc, PArr<T> sp, FieldPtrs<T> fp, AdjPtrs<T> ap,
                                                       int *err)
@@ -705,57 +803,8 @@ struct AdjThreads {
     static constexpr int value = sizeof(T) == 4 ? 1024 : 512;
 };
 
-struct TileSpan {
-    int t0[3];
-    int64_t ps, pe;
-};
-
-__device__ inline TileSpan tile_span(const TileGeo &tg, const int *tile_start, int64_t N)
-{
-    const int ntiles = tg.nt[0] * tg.nt[1] * tg.nt[2];
-    int t = blockIdx.x;
-    if (tg.xcd_map)
-        t = (t & 7) * (ntiles >> 3) + (t >> 3);
-    TileSpan s;
-    s.t0[0] = (t % tg.nt[0]) * tg.t[0];
-    s.t0[1] = ((t / tg.nt[0]) % tg.nt[1]) * tg.t[1];
-    s.t0[2] = (t / (tg.nt[0] * tg.nt[1])) * tg.t[2];
-    int64_t ps = tile_start[t], pe = tile_start[t + 1];
-    ps = ps < 0 ? 0 : (ps > N ? N : ps);
-    pe = pe < ps ? ps : (pe > N ? N : pe);
-    s.ps = ps;
-    s.pe = pe;
-    return s;
-}
-
-// cell position relative to the tile origin, periodic; true when inside
-__device__ inline bool tile_local(const TileGeo &tg, const int *n, const int *t0, const int *c, int *l)
-{
-    bool inside = true;
-#pragma unroll
-    for (int d = 0; d < 3; ++d) {
-        int v = c[d] - t0[d];
-        if (v < -tg.slack)
-            v += n[d];
-        else if (v >= tg.t[d] + tg.slack)
-            v -= n[d];
-        l[d] = v;
-        inside = inside && v >= -tg.slack && v < tg.t[d] + tg.slack;
-    }
-    return inside;
-}
-
-__device__ inline int region_global(const int *n, const int *t0, int lo, int rx, int ry, int rz)
-{
-    const int gx = wrap_any(t0[0] - lo + rx, n[0]);
-    const int gy = wrap_any(t0[1] - lo + ry, n[1]);
-    const int gz = wrap_any(t0[2] - lo + rz, n[2]);
-    return gx + n[0] * (gy + n[1] * gz);
-}
-
 // pass 1, tiled: LDS holds E, B with the gather halo and hatE with the
-// deposit halo.  Particles that drifted out of their tile are left to
-// k_adjoint_push_strays, so this kernel carries only the LDS path.
+// deposit halo; strays are left to k_adjoint_push_strays
 template <typename T, int O>
 __global__ void __launch_bounds__(AdjThreads<T>::value) k_adjoint_push_tile(PConst<T> pc, TileGeo tg, PArr<T> sp,
                                                                            FieldPtrs<T> fp, AdjPtrs<T> ap,
@@ -814,39 +863,62 @@ __global__ void __launch_bounds__(AdjThreads<T>::value) k_adjoint_push_tile(PCon
     }
 }
 
-// pass 1 for the particles of each tile that lie outside it, on global
-// memory; the others only have their cell read
+// pass 1 for the strays of each tile, on global memory
 template <typename T, int O>
-__global__ void __launch_bounds__(256) k_adjoint_push_strays(PConst<T> pc, TileGeo tg, PArr<T> sp, FieldPtrs<T> fp,
-                                                             AdjPtrs<T> ap, const int *__restrict__ tile_start,
-                                                             int *err)
+__global__ void __launch_bounds__(STRAY_THREADS) k_adjoint_push_strays(PConst<T> pc, TileGeo tg, PArr<T> sp,
+                                                                       FieldPtrs<T> fp, AdjPtrs<T> ap,
+                                                                       const int *__restrict__ tile_start, int *err)
 {
+    __shared__ int list[STRAY_CHUNK];
+    __shared__ int cnt;
     const TileSpan ts = tile_span(tg, tile_start, sp.n);
     const int np = (int)(ts.pe - ts.ps);
-    for (int j = threadIdx.x; j < np; j += blockDim.x) {
-        const int64_t p = ts.ps + j;
-        int c[3], l[3];
-        bool ok = true;
-#pragma unroll
-        for (int d = 0; d < 3; ++d) {
-            c[d] = sp.cell[d][p];
-            ok = ok && c[d] >= 0 && c[d] < pc.n[d];
+    const FieldSrc<T> gf = global_fields(fp);
+    const int z3[3] = {0, 0, 0};
+    for (int j0 = 0; j0 < np; j0 += STRAY_CHUNK) {
+        const int k = collect_strays(ts, j0, list, &cnt, CellStray<T>{tg, pc.n, ts, sp});
+        for (int i = threadIdx.x; i < k; i += blockDim.x) {
+            const int64_t p = ts.ps + list[i];
+            int c[3];
+            T f[3], u[3];
+            if (!load_particle(sp, p, pc.n, c, f, u, err))
+                clear_vb(ap, p);
+            else
+                adjoint_push_particle<T, O, false>(pc, sp, ap, gf, ap.hat, p, c, f, u, z3, 0, z3, 0, z3, err);
         }
-        if (!ok || tile_local(tg, pc.n, ts.t0, c, l))
-            continue;   // bad cells are flagged by the tile kernel
-        T f[3], u[3];
-        if (!load_particle(sp, p, pc.n, c, f, u, err)) {
-            clear_vb(ap, p);
-            continue;
+        __syncthreads();
+    }
+}
+
+// pass 2 for the strays of each tile, both groups, on global memory
+template <typename T, int O>
+__global__ void __launch_bounds__(STRAY_THREADS) k_adjoint_scatter_strays(PConst<T> pc, TileGeo tg, PArr<T> sp,
+                                                                          FieldPtrs<T> fp, AdjPtrs<T> ap,
+                                                                          const int *__restrict__ tile_start)
+{
+    __shared__ int list[STRAY_CHUNK];
+    __shared__ int cnt;
+    const TileSpan ts = tile_span(tg, tile_start, sp.n);
+    const int np = (int)(ts.pe - ts.ps);
+    const FieldSrc<T> gf = global_fields(fp);
+    const int z3[3] = {0, 0, 0};
+    for (int j0 = 0; j0 < np; j0 += STRAY_CHUNK) {
+        const int k = collect_strays(ts, j0, list, &cnt, CellStray<T>{tg, pc.n, ts, sp});
+        for (int i = threadIdx.x; i < k; i += blockDim.x) {
+            const int64_t p = ts.ps + list[i];
+            int c[3];
+            T f[3];
+            if (load_position(sp, p, pc.n, c, f))
+                adjoint_scatter_particle<T, O, false, 2>(pc, ap, gf, p, c, f, z3, 0, z3, nullptr, 0);
         }
-        const int z3[3] = {0, 0, 0};
-        adjoint_push_particle<T, O, false>(pc, sp, ap, global_fields(fp), ap.hat, p, c, f, u, z3, 0, z3, 0, z3, err);
+        __syncthreads();
     }
 }
 
 // pass 2, tiled, for group G (0: E, 1: B): LDS holds FP64 accumulators of
 // the group's three adjoints and the group's fields with the gather halo;
-// the accumulators are flushed with one global atomic per non-zero value
+// the accumulators are flushed with one global atomic per non-zero value.
+// Strays are left to k_adjoint_scatter_strays.
 template <typename T, int O, int G>
 __global__ void __launch_bounds__(AdjThreads<T>::value) k_adjoint_scatter_tile(PConst<T> pc, TileGeo tg, PArr<T> sp,
                                                                               FieldPtrs<T> fp, AdjPtrs<T> ap,
@@ -878,7 +950,6 @@ __global__ void __launch_bounds__(AdjThreads<T>::value) k_adjoint_scatter_tile(P
         lf.c[3 * G + m] = sF + m * rfvol;
         lf.c[3 * (1 - G) + m] = nullptr;
     }
-    const FieldSrc<T> gf = global_fields(fp);
     const int sf[3] = {1, rfx, rfx * rfy};
     const int np = (int)(ts.pe - ts.ps);
     for (int j0 = 0; j0 < np; j0 += nth) {
@@ -887,13 +958,9 @@ __global__ void __launch_bounds__(AdjThreads<T>::value) k_adjoint_scatter_tile(P
             const int64_t p = ts.ps + j;
             int c[3];
             T f[3];
-            if (load_position(sp, p, pc.n, c, f)) {
-                int l[3];
-                if (tile_local(tg, pc.n, ts.t0, c, l))
-                    adjoint_scatter_particle<T, O, true, G>(pc, ap, lf, p, c, f, l, tg.lo_f, sf, sL, rfvol);
-                else
-                    adjoint_scatter_particle<T, O, false, G>(pc, ap, gf, p, c, f, l, tg.lo_f, sf, nullptr, rfvol);
-            }
+            int l[3];
+            if (load_position(sp, p, pc.n, c, f) && tile_local(tg, pc.n, ts.t0, c, l))
+                adjoint_scatter_particle<T, O, true, G>(pc, ap, lf, p, c, f, l, tg.lo_f, sf, sL, rfvol);
         }
     }
     __syncthreads();
@@ -923,31 +990,40 @@ size_t tile_lds_bytes(int, const TileGeo &tg)
     return ((6 * rf * sizeof(T) + 15) & ~size_t(15)) + 3 * rj * sizeof(double);
 }
 
+template <typename K>
+static void allow_big_lds(K *kernel, bool &done)
+{
+    if (!done) {
+        // allow more than the default dynamic LDS per workgroup
+        hipFuncSetAttribute(reinterpret_cast<const void *>(kernel), hipFuncAttributeMaxDynamicSharedMemorySize,
+                            160 * 1024);
+        done = true;
+    }
+}
+
 template <typename T, int O>
 static hipError_t launch_tile_o(const PConst<T> &pc, const TileGeo &tg, const PArr<T> &in, const PArr<T> &out,
-                                const FieldPtrs<T> &f, const int *tile_start, int *err, hipStream_t st)
+                                const FieldPtrs<T> &f, const int *tile_start, unsigned char *stray, int *err,
+                                hipStream_t st)
 {
-    const size_t lds = tile_lds_bytes<T>(O, tg);
     static bool attr_set = false;
-    if (!attr_set) {
-        // allow more than the default dynamic LDS per workgroup
-        hipFuncSetAttribute(reinterpret_cast<const void *>(&k_particles_tile<T, O>),
-                            hipFuncAttributeMaxDynamicSharedMemorySize, 160 * 1024);
-        attr_set = true;
-    }
+    allow_big_lds(&k_particles_tile<T, O>, attr_set);
+    const size_t lds = tile_lds_bytes<T>(O, tg);
     const unsigned ntiles = (unsigned)(tg.nt[0] * tg.nt[1] * tg.nt[2]);
-    hipLaunchKernelGGL((k_particles_tile<T, O>), dim3(ntiles), dim3(TileThreads<T>::value), lds, st, pc, tg, in, out, f, tile_start,
-                       err);
+    hipLaunchKernelGGL((k_particles_tile<T, O>), dim3(ntiles), dim3(TileThreads<T>::value), lds, st, pc, tg, in, out,
+                       f, tile_start, stray, err);
+    hipLaunchKernelGGL((k_particles_strays<T, O>), dim3(ntiles), dim3(STRAY_THREADS), 0, st, pc, tg, in, out, f,
+                       tile_start, stray, err);
     return hipGetLastError();
 }
 
 template <typename T>
 hipError_t launch_particles_tile(int order, const PConst<T> &pc, const TileGeo &tg, const PArr<T> &in,
-                                 const PArr<T> &out, const FieldPtrs<T> &f, const int *tile_start, int *err,
-                                 hipStream_t st)
+                                 const PArr<T> &out, const FieldPtrs<T> &f, const int *tile_start,
+                                 unsigned char *stray, int *err, hipStream_t st)
 {
-    return order == 1 ? launch_tile_o<T, 1>(pc, tg, in, out, f, tile_start, err, st)
-                      : launch_tile_o<T, 3>(pc, tg, in, out, f, tile_start, err, st);
+    return order == 1 ? launch_tile_o<T, 1>(pc, tg, in, out, f, tile_start, stray, err, st)
+                      : launch_tile_o<T, 3>(pc, tg, in, out, f, tile_start, stray, err, st);
 }
 
 template <typename T>
@@ -1065,17 +1141,6 @@ size_t adjoint_lds_bytes(int, const TileGeo &tg)
     return a > b ? a : b;
 }
 
-template <typename K>
-static void allow_big_lds(K *kernel, bool &done)
-{
-    if (!done) {
-        // allow more than the default dynamic LDS per workgroup
-        hipFuncSetAttribute(reinterpret_cast<const void *>(kernel), hipFuncAttributeMaxDynamicSharedMemorySize,
-                            160 * 1024);
-        done = true;
-    }
-}
-
 template <typename T, int O>
 static hipError_t launch_adj_tile_o(const PConst<T> &pc, const TileGeo &tg, const PArr<T> &sp, const FieldPtrs<T> &f,
                                     const AdjPtrs<T> &ap, const int *tile_start, int *err, hipStream_t st)
@@ -1089,11 +1154,13 @@ static hipError_t launch_adj_tile_o(const PConst<T> &pc, const TileGeo &tg, cons
     const size_t l1 = adjoint_push_lds<T>(tg), l2 = adjoint_scatter_lds<T>(tg);
     hipLaunchKernelGGL((k_adjoint_push_tile<T, O>), dim3(ntiles), dim3(nth), l1, st, pc, tg, sp, f, ap, tile_start,
                        err);
-    hipLaunchKernelGGL((k_adjoint_push_strays<T, O>), dim3(ntiles), dim3(256), 0, st, pc, tg, sp, f, ap, tile_start,
-                       err);
+    hipLaunchKernelGGL((k_adjoint_push_strays<T, O>), dim3(ntiles), dim3(STRAY_THREADS), 0, st, pc, tg, sp, f, ap,
+                       tile_start, err);
     hipLaunchKernelGGL((k_adjoint_scatter_tile<T, O, 0>), dim3(ntiles), dim3(nth), l2, st, pc, tg, sp, f, ap,
                        tile_start);
     hipLaunchKernelGGL((k_adjoint_scatter_tile<T, O, 1>), dim3(ntiles), dim3(nth), l2, st, pc, tg, sp, f, ap,
+                       tile_start);
+    hipLaunchKernelGGL((k_adjoint_scatter_strays<T, O>), dim3(ntiles), dim3(STRAY_THREADS), 0, st, pc, tg, sp, f, ap,
                        tile_start);
     return hipGetLastError();
 }
@@ -1114,8 +1181,8 @@ hipError_t launch_adjoint_tile(int order, const PConst<T> &pc, const TileGeo &tg
 #define PIC_INST(T)                                                                                               \
     template size_t tile_lds_bytes<T>(int, const TileGeo &);                                                       \
     template hipError_t launch_particles_tile<T>(int, const PConst<T> &, const TileGeo &, const PArr<T> &,         \
-                                                 const PArr<T> &, const FieldPtrs<T> &, const int *, int *,        \
-                                                 hipStream_t);                                                     \
+                                                 const PArr<T> &, const FieldPtrs<T> &, const int *,               \
+                                                 unsigned char *, int *, hipStream_t);                             \
     template hipError_t launch_particles_global<T>(int, const PConst<T> &, const PArr<T> &, const FieldPtrs<T> &,  \
                                                    int *, hipStream_t);                                            \
     template hipError_t launch_gather<T>(int, const PConst<T> &, const PArr<T> &, const FieldPtrs<T> &,            \

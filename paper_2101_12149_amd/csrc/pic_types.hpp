@@ -73,10 +73,12 @@ struct CurlArgs {
 // ---------------------------------------------------------------------------
 // launchers (return hipSuccess or the launch error)
 
+// stray: per-particle scratch (uint8[n]) marking the particles that the tile
+// kernel leaves to the stray kernel
 template <typename T>
 hipError_t launch_particles_tile(int order, const PConst<T> &pc, const TileGeo &tg, const PArr<T> &in,
-                                 const PArr<T> &out, const FieldPtrs<T> &f, const int *tile_start, int *err,
-                                 hipStream_t st);
+                                 const PArr<T> &out, const FieldPtrs<T> &f, const int *tile_start,
+                                 unsigned char *stray, int *err, hipStream_t st);
 template <typename T>
 hipError_t launch_particles_global(int order, const PConst<T> &pc, const PArr<T> &sp, const FieldPtrs<T> &f,
                                    int *err, hipStream_t st);
