@@ -272,6 +272,14 @@ pic_status check_grid(const pic_grid *g, GridInfo &gi)
     }
     if (lds_bytes(gi) > limit)
         return fail(PIC_E_UNSUPPORTED, "tile plus halo does not fit in LDS; use a smaller tile or slack");
+    // the LDS left over holds the forward tile kernel's queue of
+    // cell-crossing particles (up to 1024 entries)
+    {
+        const size_t used = lds_bytes(gi) + sizeof(int);
+        const size_t entry = 6 * gi.tsize + 2 * sizeof(int);
+        const size_t room = limit > used ? (limit - used) / entry : 0;
+        gi.tg.qcap = (int)(room < 1024 ? room : 1024);
+    }
     int nt = 1;
     for (int d = 0; d < 3; ++d) {
         gi.tg.nt[d] = gi.n[d] / gi.tg.t[d];

@@ -204,14 +204,85 @@ struct CellStray {
 };
 
 // ---------------------------------------------------------------------------
+// LDS queue of the cell-crossing particles of a tile.  Nearly every wave
+// holds a few particles that cross a cell face, and the rim of their wider
+// Esirkepov window would make every wave issue the rim's LDS atomics with
+// only those lanes active.  The tile kernel deposits the particles that stay
+// in their cells with the narrow window and queues the others (their
+// in-tile index, local cell, cell change and old / new offsets), then
+// deposits the queue in full waves.  A particle that finds the queue full
+// is deposited at once.
+template <typename T>
+struct CrossQueue {
+    int *cnt;
+    int cap;
+    int *j, *pk;
+    T *f0, *f1;   // [3][cap]
+
+    __device__ bool push(int jj, const int *l, const int *kap, const T *a, const T *b) const
+    {
+        const int i = atomicAdd(cnt, 1);
+        if (i >= cap)
+            return false;
+        j[i] = jj;
+        pk[i] = pack(l, kap);
+#pragma unroll
+        for (int d = 0; d < 3; ++d) {
+            f0[d * cap + i] = a[d];
+            f1[d * cap + i] = b[d];
+        }
+        return true;
+    }
+    // local cell + 8 in 5 bits and the cell change + 1 in 2 bits per axis
+    __device__ static int pack(const int *l, const int *kap)
+    {
+        int v = 0;
+#pragma unroll
+        for (int d = 0; d < 3; ++d)
+            v |= ((l[d] + 8) | ((kap[d] + 1) << 5)) << (7 * d);
+        return v;
+    }
+    __device__ static void unpack(int v, int *l, int *kap)
+    {
+#pragma unroll
+        for (int d = 0; d < 3; ++d) {
+            const int x = (v >> (7 * d)) & 127;
+            l[d] = (x & 31) - 8;
+            kap[d] = (x >> 5) - 1;
+        }
+    }
+};
+
+// Esirkepov deposit with the full window into the LDS current tile; with
+// MSEL in 0..2 only that component
+template <typename T, int O, int MSEL = -1>
+__device__ __attribute__((always_inline)) inline void deposit_local_full(const PConst<T> &pc, const T *f0, const T *f1, const int *kap,
+                                          const int *l, int lo_j, const int *sj, T w, double *sJ, int rjvol)
+{
+    constexpr int NW = Shape<O, T>::NW;
+    EskAxis<O, T> e[3];
+    T K[3];
+    int jo[3][NW + 1];
+#pragma unroll
+    for (int d = 0; d < 3; ++d) {
+        esk_axis<O>(f0[d], f1[d], kap[d], e[d]);
+        K[d] = pc.jk[d] * w;
+        axis_offsets_local<NW + 1>(l[d] + lo_j, e[d].lo, sj[d], jo[d]);
+    }
+    esk_scatter<O, T, double, MSEL>(e, jo, K,
+                                    [&](int m, int idx, double v) { latomic_add(sJ + m * rjvol + idx, v); });
+}
+
 // One particle through gather -> Boris -> move -> Esirkepov.  With LOCAL the
-// particle lies in the LDS regions (positions l[] relative to the tile);
+// particle lies in the LDS regions (positions l[] relative to the tile) and,
+// when cq is given, a cell-crossing particle's deposit goes to the queue;
 // otherwise everything is read and scattered in global memory.
 template <typename T, int O, bool LOCAL>
 __device__ __attribute__((always_inline)) inline void particle_step(const PConst<T> &pc, const PArr<T> &in, const PArr<T> &out,
                                      const FieldPtrs<T> &fp, const FieldSrc<T> &fsrc, int64_t p, const int *c,
                                      const T *f, const T *u, const int *l, int lo_f, const int *sf, int lo_j,
-                                     const int *sj, double *sJ, int rjvol, int *err)
+                                     const int *sj, double *sJ, int rjvol, int *err,
+                                     const CrossQueue<T> *cq = nullptr, int jj = 0)
 {
     constexpr int NW = Shape<O, T>::NW;
     const int gs[3] = {1, pc.n[0], pc.n[0] * pc.n[1]};
@@ -250,24 +321,6 @@ __device__ __attribute__((always_inline)) inline void particle_step(const PConst
         return;
     }
     const T w = in.w ? in.w[p] : pc.w0;
-    EskAxis<O, T> e[3];
-    T K[3];
-    int jo[3][NW + 1];
-#pragma unroll
-    for (int d = 0; d < 3; ++d) {
-        esk_axis<O>(f[d], f1[d], kap[d], e[d]);
-        K[d] = pc.jk[d] * w;
-        if (LOCAL)
-            axis_offsets_local<NW + 1>(l[d] + lo_j, e[d].lo, sj[d], jo[d]);
-        else
-            axis_offsets_global<NW + 1>(c[d], e[d].lo, pc.n[d], gs[d], jo[d]);
-    }
-    if (LOCAL) {
-        esk_scatter<O, T, double>(e, jo, K,
-                                  [&](int m, int idx, double v) { latomic_add(sJ + m * rjvol + idx, v); });
-    } else {
-        esk_scatter<O, T, T>(e, jo, K, [&](int m, int idx, T v) { gatomic_add(fp.J[m] + idx, v); });
-    }
 #pragma unroll
     for (int d = 0; d < 3; ++d) {
         out.cell[d][p] = wrap_once(c[d] + kap[d], pc.n[d]);
@@ -276,6 +329,33 @@ __device__ __attribute__((always_inline)) inline void particle_step(const PConst
     }
     if (out.w && out.w != in.w)
         out.w[p] = in.w[p];
+    if (LOCAL) {
+        if ((kap[0] | kap[1] | kap[2]) == 0) {
+            T S0[3][NW], DS[3][NW], K[3];
+            int jo[3][NW];
+#pragma unroll
+            for (int d = 0; d < 3; ++d) {
+                esk_axis_still<O>(f[d], f1[d], S0[d], DS[d]);
+                K[d] = pc.jk[d] * w;
+                axis_offsets_local<NW>(l[d] + lo_j, Shape<O, T>::NB, sj[d], jo[d]);
+            }
+            esk_scatter_still<O, T, double>(S0, DS, jo, K,
+                                            [&](int m, int idx, double v) { latomic_add(sJ + m * rjvol + idx, v); });
+        } else if (!(cq && cq->push(jj, l, kap, f, f1))) {
+            deposit_local_full<T, O>(pc, f, f1, kap, l, lo_j, sj, w, sJ, rjvol);
+        }
+    } else {
+        EskAxis<O, T> e[3];
+        T K[3];
+        int jo[3][NW + 1];
+#pragma unroll
+        for (int d = 0; d < 3; ++d) {
+            esk_axis<O>(f[d], f1[d], kap[d], e[d]);
+            K[d] = pc.jk[d] * w;
+            axis_offsets_global<NW + 1>(c[d], e[d].lo, pc.n[d], gs[d], jo[d]);
+        }
+        esk_scatter<O, T, T>(e, jo, K, [&](int m, int idx, T v) { gatomic_add(fp.J[m] + idx, v); });
+    }
 }
 
 // ---------------------------------------------------------------------------
@@ -295,6 +375,14 @@ __global__ void __launch_bounds__(TileThreads<T>::value) k_particles_tile(PConst
     const int rjvol = rjx * rjy * tg.rj[2];
     // the current tile accumulates in FP64 (fast LDS atomics), after the fields
     double *sJ = reinterpret_cast<double *>(smem_raw + ((6 * rfvol * sizeof(T) + 15) & ~size_t(15)));
+    // then the queue of cell-crossing particles: offsets, indices, count
+    CrossQueue<T> cq;
+    cq.cap = tg.qcap;
+    cq.f0 = reinterpret_cast<T *>(sJ + 3 * rjvol);
+    cq.f1 = cq.f0 + 3 * cq.cap;
+    cq.j = reinterpret_cast<int *>(cq.f1 + 3 * cq.cap);
+    cq.pk = cq.j + cq.cap;
+    cq.cnt = cq.pk + cq.cap;
     const TileSpan ts = tile_span(tg, tile_start, in.n);
     if (ts.pe <= ts.ps)
         return;   // uniform across the workgroup
@@ -310,6 +398,8 @@ __global__ void __launch_bounds__(TileThreads<T>::value) k_particles_tile(PConst
     }
     for (int r = tid; r < 3 * rjvol; r += nth)
         sJ[r] = 0.0;
+    if (tid == 0)
+        *cq.cnt = 0;
     __syncthreads();
 
     FieldSrc<T> lf;
@@ -335,12 +425,36 @@ __global__ void __launch_bounds__(TileThreads<T>::value) k_particles_tile(PConst
                 int l[3];
                 if (tile_local(tg, pc.n, ts.t0, c, l))
                     particle_step<T, O, true>(pc, in, out, fp, lf, p, c, f, u, l, tg.lo_f, sf, tg.lo_j, sj, sJ,
-                                              rjvol, err);
+                                              rjvol, err, &cq, j);
                 else
                     st = 1;
             }
             stray[p] = st;
         }
+    }
+    __syncthreads();
+    // deposit the queued cell-crossing particles in full waves, one lane per
+    // particle and current component (component-major, so that a wave
+    // mostly takes one component)
+    const int nq = *cq.cnt < cq.cap ? *cq.cnt : cq.cap;
+    for (int i = tid; i < 3 * nq; i += nth) {
+        const int m = i / nq, k = i - m * nq;
+        const int64_t p = ts.ps + cq.j[k];
+        int l[3], kap[3];
+        CrossQueue<T>::unpack(cq.pk[k], l, kap);
+        T f0[3], f1[3];
+#pragma unroll
+        for (int d = 0; d < 3; ++d) {
+            f0[d] = cq.f0[d * cq.cap + k];
+            f1[d] = cq.f1[d * cq.cap + k];
+        }
+        const T w = in.w ? in.w[p] : pc.w0;
+        if (m == 0)
+            deposit_local_full<T, O, 0>(pc, f0, f1, kap, l, tg.lo_j, sj, w, sJ, rjvol);
+        else if (m == 1)
+            deposit_local_full<T, O, 1>(pc, f0, f1, kap, l, tg.lo_j, sj, w, sJ, rjvol);
+        else
+            deposit_local_full<T, O, 2>(pc, f0, f1, kap, l, tg.lo_j, sj, w, sJ, rjvol);
     }
     __syncthreads();
     for (int r = tid; r < 3 * rjvol; r += nth) {
@@ -987,7 +1101,8 @@ size_t tile_lds_bytes(int, const TileGeo &tg)
 {
     const size_t rf = (size_t)tg.rf[0] * tg.rf[1] * tg.rf[2];
     const size_t rj = (size_t)tg.rj[0] * tg.rj[1] * tg.rj[2];
-    return ((6 * rf * sizeof(T) + 15) & ~size_t(15)) + 3 * rj * sizeof(double);
+    return ((6 * rf * sizeof(T) + 15) & ~size_t(15)) + 3 * rj * sizeof(double) +
+           (size_t)tg.qcap * (6 * sizeof(T) + 2 * sizeof(int)) + sizeof(int);
 }
 
 template <typename K>

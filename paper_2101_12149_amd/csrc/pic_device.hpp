@@ -400,7 +400,8 @@ __device__ inline void esk_axis_deriv(T d0, T d1, int kappa, T *dS0, T *dDS1)
 // are far faster than FP32 ones on gfx950).  `add(m, index, value)`
 // performs the scatter; jo[d][a] are the index offsets of window node a
 // along axis d.
-template <int O, typename T, typename A, typename AddFn>
+// With MSEL in 0..2 only that component is scattered.
+template <int O, typename T, typename A, int MSEL = -1, typename AddFn>
 __device__ __attribute__((always_inline)) inline void esk_scatter(const EskAxis<O, T> *e, const int (*jo)[Shape<O, T>::NW + 1], const T *K,
                                    AddFn &&add)
 {
@@ -408,6 +409,8 @@ __device__ __attribute__((always_inline)) inline void esk_scatter(const EskAxis<
     const T half = T(0.5), third = T(1) / T(3);
 #pragma unroll
     for (int m = 0; m < 3; ++m) {
+        if (MSEL >= 0 && m != MSEL)
+            continue;
         const int p = (m + 1) % 3, q = (m + 2) % 3;
         A P[NW];
         T run = T(0);
@@ -436,6 +439,56 @@ __device__ __attribute__((always_inline)) inline void esk_scatter(const EskAxis<
                         continue;
                     add(m, base + jo[m][a], P[a] * C);
                 }
+            }
+        }
+    }
+}
+
+// The window of a particle that stays in its cell along every axis: the
+// kappa = 0 case of esk_axis without the rim node (same arithmetic).
+template <int O, typename T>
+__device__ inline void esk_axis_still(T d0, T d1, T *S0, T *DS)
+{
+    using S = Shape<O, T>;
+    constexpr int NW = S::NW;
+    T qa[NW];
+    S::w(d0, S0);
+    S::q(d0, d1, qa);
+    const T dd = d1 - d0;
+#pragma unroll
+    for (int a = 0; a < NW; ++a)
+        DS[a] = dd * qa[a];
+}
+
+// esk_scatter for a particle that stays in its cell along every axis: the
+// NW x NW cross-section and the NW - 1 nodes along m that carry current (the
+// same sums as esk_scatter, without its rim branches).  jo[d][a] are the
+// index offsets of the window nodes starting at the first gather node.
+template <int O, typename T, typename A, typename AddFn>
+__device__ __attribute__((always_inline)) inline void esk_scatter_still(const T (*S0)[Shape<O, T>::NW], const T (*DS)[Shape<O, T>::NW],
+                                         const int (*jo)[Shape<O, T>::NW], const T *K, AddFn &&add)
+{
+    constexpr int NW = Shape<O, T>::NW;
+    const T half = T(0.5), third = T(1) / T(3);
+#pragma unroll
+    for (int m = 0; m < 3; ++m) {
+        const int p = (m + 1) % 3, q = (m + 2) % 3;
+        A P[NW - 1];
+        T run = T(0);
+#pragma unroll
+        for (int a = 0; a < NW - 1; ++a) {
+            run += DS[m][a];
+            P[a] = (A)(K[m] * run);
+        }
+#pragma unroll
+        for (int c = 0; c < NW; ++c) {
+#pragma unroll
+            for (int b = 0; b < NW; ++b) {
+                const A C = (A)(S0[p][b] * (S0[q][c] + half * DS[q][c]) + DS[p][b] * (half * S0[q][c] + third * DS[q][c]));
+                const int base = jo[p][b] + jo[q][c];
+#pragma unroll
+                for (int a = 0; a < NW - 1; ++a)
+                    add(m, base + jo[m][a], P[a] * C);
             }
         }
     }

@@ -46,6 +46,7 @@ struct TileGeo {
     int lo_f, rf[3];
     int lo_j, rj[3];
     int xcd_map;   // spread consecutive tiles so each XCD gets a contiguous block
+    int qcap;      // entries of the tile kernel's LDS queue of cell-crossing particles
 };
 
 // Arguments of the curl-update kernel:
