@@ -34,8 +34,9 @@ VALU_PEAK_TFLOPS = 78.6
 # sums 126
 FLOPS_PER_PARTICLE = {3: 2028, 1: 411}
 # calibrated HBM bytes per launch of the FP32 tile kernel at 256^3 / 8 ppc,
-# from the FETCH_SIZE / WRITE_SIZE passes (scaled by a 1 GiB copy)
-MEASURED_TRAFFIC = {"uniform256_o3_f32": 12.50e9}
+# from the FETCH_SIZE / WRITE_SIZE passes (scaled by a 1 GiB copy); only
+# figures taken on the current kernel are listed
+MEASURED_TRAFFIC = {}
 
 
 def log(*a):
