@@ -161,6 +161,7 @@ void region_extents(int order, TileGeo &tg)
     }
     tg.lo_f = s + gl;
     tg.lo_j = s + gl;
+    tg.jp = tg.rj[0];
 }
 
 // LDS of the tiled adjoint: its first pass holds E, B with the gather halo
@@ -196,7 +197,7 @@ size_t adj_lds_bytes(const GridInfo &gi)
 size_t lds_bytes(const GridInfo &gi)
 {
     const size_t rf = (size_t)gi.tg.rf[0] * gi.tg.rf[1] * gi.tg.rf[2];
-    const size_t rj = (size_t)gi.tg.rj[0] * gi.tg.rj[1] * gi.tg.rj[2];
+    const size_t rj = (size_t)gi.tg.jp * gi.tg.rj[1] * gi.tg.rj[2];
     // fields in the working precision, the current tile in FP64
     return ((6 * rf * gi.tsize + 15) & ~size_t(15)) + 3 * rj * sizeof(double);
 }

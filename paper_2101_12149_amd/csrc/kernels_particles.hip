@@ -273,16 +273,16 @@ __device__ __attribute__((always_inline)) inline void deposit_local_full(const P
                                     [&](int m, int idx, double v) { latomic_add(sJ + m * rjvol + idx, v); });
 }
 
-// One particle through gather -> Boris -> move -> Esirkepov.  With LOCAL the
-// particle lies in the LDS regions (positions l[] relative to the tile) and,
-// when cq is given, a cell-crossing particle's deposit goes to the queue;
-// otherwise everything is read and scattered in global memory.
+// One particle through gather -> Boris -> move; writes the new state to
+// `out` and returns the new offsets f1, the cell change kap and the weight
+// w, or flags the error word and returns false for a displacement of a cell
+// or more.  With LOCAL the fields come from the LDS tile (positions l[]
+// relative to the tile), otherwise from global memory.
 template <typename T, int O, bool LOCAL>
-__device__ __attribute__((always_inline)) inline void particle_step(const PConst<T> &pc, const PArr<T> &in, const PArr<T> &out,
-                                     const FieldPtrs<T> &fp, const FieldSrc<T> &fsrc, int64_t p, const int *c,
-                                     const T *f, const T *u, const int *l, int lo_f, const int *sf, int lo_j,
-                                     const int *sj, double *sJ, int rjvol, int *err,
-                                     const CrossQueue<T> *cq = nullptr, int jj = 0)
+__device__ __attribute__((always_inline)) inline bool particle_advance(const PConst<T> &pc, const PArr<T> &in, const PArr<T> &out,
+                                        const FieldSrc<T> &fsrc, int64_t p, const int *c, const T *f,
+                                        const T *u, const int *l, int lo_f, const int *sf, T *f1, int *kap,
+                                        T &w, int *err)
 {
     constexpr int NW = Shape<O, T>::NW;
     const int gs[3] = {1, pc.n[0], pc.n[0] * pc.n[1]};
@@ -306,8 +306,6 @@ __device__ __attribute__((always_inline)) inline void particle_step(const PConst
     T u1[3];
     boris(pc.h, pc.inv_c2, u, E, B, u1, tp);
     const T ig = T(1) / sqrt(T(1) + (u1[0] * u1[0] + u1[1] * u1[1] + u1[2] * u1[2]) * pc.inv_c2);
-    T f1[3];
-    int kap[3];
     bool ok = true;
 #pragma unroll
     for (int d = 0; d < 3; ++d) {
@@ -318,9 +316,9 @@ __device__ __attribute__((always_inline)) inline void particle_step(const PConst
     if (!ok) {
         atomicOr(err, 2);
         copy_particle(in, out, p);
-        return;
+        return false;
     }
-    const T w = in.w ? in.w[p] : pc.w0;
+    w = in.w ? in.w[p] : pc.w0;
 #pragma unroll
     for (int d = 0; d < 3; ++d) {
         out.cell[d][p] = wrap_once(c[d] + kap[d], pc.n[d]);
@@ -329,33 +327,192 @@ __device__ __attribute__((always_inline)) inline void particle_step(const PConst
     }
     if (out.w && out.w != in.w)
         out.w[p] = in.w[p];
-    if (LOCAL) {
-        if ((kap[0] | kap[1] | kap[2]) == 0) {
-            T S0[3][NW], DS[3][NW], K[3];
-            int jo[3][NW];
+    return true;
+}
+
+// The fused step on global memory (global atomics for the current).
+template <typename T, int O>
+__device__ __attribute__((always_inline)) inline void particle_step_global(const PConst<T> &pc, const PArr<T> &in, const PArr<T> &out,
+                                            const FieldPtrs<T> &fp, int64_t p, const int *c, const T *f,
+                                            const T *u, int *err)
+{
+    constexpr int NW = Shape<O, T>::NW;
+    const int gs[3] = {1, pc.n[0], pc.n[0] * pc.n[1]};
+    const int z3[3] = {0, 0, 0};
+    T f1[3], w;
+    int kap[3];
+    if (!particle_advance<T, O, false>(pc, in, out, global_fields(fp), p, c, f, u, z3, 0, z3, f1, kap, w, err))
+        return;
+    EskAxis<O, T> e[3];
+    T K[3];
+    int jo[3][NW + 1];
 #pragma unroll
-            for (int d = 0; d < 3; ++d) {
-                esk_axis_still<O>(f[d], f1[d], S0[d], DS[d]);
-                K[d] = pc.jk[d] * w;
-                axis_offsets_local<NW>(l[d] + lo_j, Shape<O, T>::NB, sj[d], jo[d]);
-            }
-            esk_scatter_still<O, T, double>(S0, DS, jo, K,
-                                            [&](int m, int idx, double v) { latomic_add(sJ + m * rjvol + idx, v); });
-        } else if (!(cq && cq->push(jj, l, kap, f, f1))) {
-            deposit_local_full<T, O>(pc, f, f1, kap, l, lo_j, sj, w, sJ, rjvol);
-        }
-    } else {
-        EskAxis<O, T> e[3];
-        T K[3];
-        int jo[3][NW + 1];
-#pragma unroll
-        for (int d = 0; d < 3; ++d) {
-            esk_axis<O>(f[d], f1[d], kap[d], e[d]);
-            K[d] = pc.jk[d] * w;
-            axis_offsets_global<NW + 1>(c[d], e[d].lo, pc.n[d], gs[d], jo[d]);
-        }
-        esk_scatter<O, T, T>(e, jo, K, [&](int m, int idx, T v) { gatomic_add(fp.J[m] + idx, v); });
+    for (int d = 0; d < 3; ++d) {
+        esk_axis<O>(f[d], f1[d], kap[d], e[d]);
+        K[d] = pc.jk[d] * w;
+        axis_offsets_global<NW + 1>(c[d], e[d].lo, pc.n[d], gs[d], jo[d]);
     }
+    esk_scatter<O, T, T>(e, jo, K, [&](int m, int idx, T v) { gatomic_add(fp.J[m] + idx, v); });
+}
+
+// ---------------------------------------------------------------------------
+// Lane-shared current rows.  In the rank-major order the lanes of a wave sit
+// in neighbouring cells, so a lane's window row along x overlaps the rows of
+// the lanes to its left shifted by one node per lane.  A run is a maximal
+// group of consecutive lanes (within one 16-lane DPP row) whose particles
+// stay in their cells and lie in consecutive cells along x of one (y, z)
+// row.  Each lane adds the taps of up to three lanes to its left that land
+// on its first node (row shifts across lanes) and writes that node with one
+// LDS atomic; the last lane of a run also writes the remaining nodes.  The
+// values added are those of the per-lane scatter; only the summation order
+// changes, and a wave issues far fewer lane atomics, spread over more banks.
+
+// Row shift of a 64-bit value: lane L receives lane L-K's value within its
+// 16-lane row (lanes with no source receive 0), or lane L+1's for K = -1.
+template <int K>
+__device__ inline double dpp_shift(double v)
+{
+    constexpr int CTRL = K > 0 ? 0x110 + K : 0x101;   // row_shr:K / row_shl:1
+    const long long b = __double_as_longlong(v);
+    const int lo = __builtin_amdgcn_update_dpp(0, (int)(b & 0xffffffffLL), CTRL, 0xf, 0xf, false);
+    const int hi = __builtin_amdgcn_update_dpp(0, (int)(b >> 32), CTRL, 0xf, 0xf, false);
+    return __longlong_as_double(((long long)hi << 32) | (long long)(unsigned)lo);
+}
+
+template <int K>
+__device__ inline int dpp_shift_int(int v)
+{
+    constexpr int CTRL = K > 0 ? 0x110 + K : 0x101;
+    return __builtin_amdgcn_update_dpp(0, v, CTRL, 0xf, 0xf, false);
+}
+
+struct XRun {
+    bool a1, a2, a3;   // lanes L-1, L-2, L-3 belong to this lane's run
+    bool last;         // the run ends at this lane
+};
+
+// key: 0 for a lane outside the shared deposit, else a positive code of the
+// local cell with x in the low bits (x - 1 is key - 1).  Call with the whole
+// wave converged.
+__device__ inline int xrun_key(const int *l)
+{
+    return (1 << 20) | (l[0] + 8) | ((l[1] + 8) << 6) | ((l[2] + 8) << 12);
+}
+
+__device__ inline XRun xrun(int key)
+{
+    const int k1 = dpp_shift_int<1>(key);
+    const bool a1 = key != 0 && k1 == key - 1;
+    const int a1i = a1 ? 1 : 0;
+    const int p1 = dpp_shift_int<1>(a1i), p2 = dpp_shift_int<2>(a1i), n1 = dpp_shift_int<-1>(a1i);
+    XRun r;
+    r.a1 = a1;
+    r.a2 = a1 && p1 != 0;
+    r.a3 = r.a2 && p2 != 0;
+    r.last = key != 0 && n1 == 0;
+    return r;
+}
+
+// one window row of NT taps along x, starting at `row` (this lane's first node)
+template <int NT>
+__device__ __attribute__((always_inline)) inline void xrow_add(double *row, const double *r, const XRun &xr)
+{
+    double s = r[0];
+    double e[NT > 1 ? NT : 2];
+    if constexpr (NT >= 2) {
+        const double t = dpp_shift<1>(r[1]);
+        s += xr.a1 ? t : 0.0;
+        e[1] = r[1];
+    }
+    if constexpr (NT >= 3) {
+        const double t2 = dpp_shift<2>(r[2]);
+        s += xr.a2 ? t2 : 0.0;
+        const double t1 = dpp_shift<1>(r[2]);
+        e[1] += xr.a1 ? t1 : 0.0;
+        e[2] = r[2];
+    }
+    if constexpr (NT >= 4) {
+        const double t3 = dpp_shift<3>(r[3]);
+        s += xr.a3 ? t3 : 0.0;
+        const double t2 = dpp_shift<2>(r[3]);
+        e[1] += xr.a2 ? t2 : 0.0;
+        const double t1 = dpp_shift<1>(r[3]);
+        e[2] += xr.a1 ? t1 : 0.0;
+        e[3] = r[3];
+    }
+    latomic_add(row, s);
+    if (xr.last) {
+#pragma unroll
+        for (int k = 1; k < NT; ++k)
+            latomic_add(row + k, e[k]);
+    }
+}
+
+// Esirkepov deposit of a particle that stays in its cell, into the LDS
+// current tile with lane-shared rows along x (esk_scatter_still's values).
+template <typename T, int O>
+__device__ __attribute__((always_inline)) inline void deposit_still_shared(const PConst<T> &pc, const T *f0, const T *f1, const int *l,
+                                            int lo_j, const int *sj, T w, double *sJ, int rjvol, const XRun &xr)
+{
+    constexpr int NW = Shape<O, T>::NW;
+    const T half = T(0.5), third = T(1) / T(3);
+    T S0[3][NW], DS[3][NW], K[3];
+    int jo[3][NW];
+#pragma unroll
+    for (int d = 0; d < 3; ++d) {
+        esk_axis_still<O>(f0[d], f1[d], S0[d], DS[d]);
+        K[d] = pc.jk[d] * w;
+        axis_offsets_local<NW>(l[d] + lo_j, Shape<O, T>::NB, sj[d], jo[d]);
+    }
+    // P_m[a] = K_m * (running sum of DS_m), a < NW - 1
+    double P[3][NW - 1];
+#pragma unroll
+    for (int m = 0; m < 3; ++m) {
+        T run = T(0);
+#pragma unroll
+        for (int a = 0; a < NW - 1; ++a) {
+            run += DS[m][a];
+            P[m][a] = (double)(K[m] * run);
+        }
+    }
+    // C for (p, q) at (b, c), as in esk_scatter_still
+    auto cw = [&](int p, int q, int b, int c) -> double {
+        return (double)(S0[p][b] * (S0[q][c] + half * DS[q][c]) + DS[p][b] * (half * S0[q][c] + third * DS[q][c]));
+    };
+    // J_x (p = y, q = z): rows along x are the taps a
+#pragma unroll
+    for (int c = 0; c < NW; ++c)
+#pragma unroll
+        for (int b = 0; b < NW; ++b) {
+            const double C = cw(1, 2, b, c);
+            double r[NW - 1];
+#pragma unroll
+            for (int a = 0; a < NW - 1; ++a)
+                r[a] = P[0][a] * C;
+            xrow_add<NW - 1>(sJ + jo[1][b] + jo[2][c] + jo[0][0], r, xr);
+        }
+    // J_y (p = z, q = x): rows along x are the taps c
+#pragma unroll
+    for (int a = 0; a < NW - 1; ++a)
+#pragma unroll
+        for (int b = 0; b < NW; ++b) {
+            double r[NW];
+#pragma unroll
+            for (int c = 0; c < NW; ++c)
+                r[c] = P[1][a] * cw(2, 0, b, c);
+            xrow_add<NW>(sJ + rjvol + jo[2][b] + jo[1][a] + jo[0][0], r, xr);
+        }
+    // J_z (p = x, q = y): rows along x are the taps b
+#pragma unroll
+    for (int a = 0; a < NW - 1; ++a)
+#pragma unroll
+        for (int c = 0; c < NW; ++c) {
+            double r[NW];
+#pragma unroll
+            for (int b = 0; b < NW; ++b)
+                r[b] = P[2][a] * cw(0, 1, b, c);
+            xrow_add<NW>(sJ + 2 * rjvol + jo[1][c] + jo[2][a] + jo[0][0], r, xr);
+        }
 }
 
 // ---------------------------------------------------------------------------
@@ -371,8 +528,8 @@ __global__ void __launch_bounds__(TileThreads<T>::value) k_particles_tile(PConst
     T *sF = reinterpret_cast<T *>(smem_raw);
     const int rfx = tg.rf[0], rfy = tg.rf[1];
     const int rfvol = rfx * rfy * tg.rf[2];
-    const int rjx = tg.rj[0], rjy = tg.rj[1];
-    const int rjvol = rjx * rjy * tg.rj[2];
+    const int rjx = tg.rj[0], rjy = tg.rj[1], jpx = tg.jp;
+    const int rjvol = jpx * rjy * tg.rj[2];   // rows padded to jp values
     // the current tile accumulates in FP64 (fast LDS atomics), after the fields
     double *sJ = reinterpret_cast<double *>(smem_raw + ((6 * rfvol * sizeof(T) + 15) & ~size_t(15)));
     // then the queue of cell-crossing particles: offsets, indices, count
@@ -407,30 +564,40 @@ __global__ void __launch_bounds__(TileThreads<T>::value) k_particles_tile(PConst
     for (int m = 0; m < 6; ++m)
         lf.c[m] = sF + m * rfvol;
     const int sf[3] = {1, rfx, rfx * rfy};
-    const int sj[3] = {1, rjx, rjx * rjy};
+    const int sj[3] = {1, jpx, jpx * rjy};
     const int np = (int)(ts.pe - ts.ps);
     // coalesced: the tile's particles are stored rank-major (one particle
     // per cell, cell after cell, then the next rank), so consecutive lanes
     // read consecutive memory and sit in distinct neighbouring cells
     for (int j0 = 0; j0 < np; j0 += nth) {
         const int j = j0 + tid;
+        int key = 0;   // non-zero: a particle that stays in its cell, deposited below
+        int l[3] = {0, 0, 0};
+        T f[3] = {T(0), T(0), T(0)}, f1[3] = {T(0), T(0), T(0)}, w = T(0);
         if (j < np) {
             const int64_t p = ts.ps + j;
             int c[3];
-            T f[3], u[3];
+            T u[3];
             unsigned char st = 0;
             if (!load_particle(in, p, pc.n, c, f, u, err)) {
                 copy_particle(in, out, p);
+            } else if (!tile_local(tg, pc.n, ts.t0, c, l)) {
+                st = 1;
             } else {
-                int l[3];
-                if (tile_local(tg, pc.n, ts.t0, c, l))
-                    particle_step<T, O, true>(pc, in, out, fp, lf, p, c, f, u, l, tg.lo_f, sf, tg.lo_j, sj, sJ,
-                                              rjvol, err, &cq, j);
-                else
-                    st = 1;
+                int kap[3];
+                if (particle_advance<T, O, true>(pc, in, out, lf, p, c, f, u, l, tg.lo_f, sf, f1, kap, w, err)) {
+                    if ((kap[0] | kap[1] | kap[2]) == 0)
+                        key = xrun_key(l);
+                    else if (!cq.push(j, l, kap, f, f1))
+                        deposit_local_full<T, O>(pc, f, f1, kap, l, tg.lo_j, sj, w, sJ, rjvol);
+                }
             }
             stray[p] = st;
         }
+        // the wave is converged here: find the runs, then deposit
+        const XRun xr = xrun(key);
+        if (key != 0)
+            deposit_still_shared<T, O>(pc, f, f1, l, tg.lo_j, sj, w, sJ, rjvol, xr);
     }
     __syncthreads();
     // deposit the queued cell-crossing particles in full waves, one lane per
@@ -459,9 +626,10 @@ __global__ void __launch_bounds__(TileThreads<T>::value) k_particles_tile(PConst
     __syncthreads();
     for (int r = tid; r < 3 * rjvol; r += nth) {
         const T v = (T)sJ[r];
-        if (v != T(0)) {
-            const int m = r / rjvol, rr = r - m * rjvol;
-            const int gi = region_global(pc.n, ts.t0, tg.lo_j, rr % rjx, (rr / rjx) % rjy, rr / (rjx * rjy));
+        const int m = r / rjvol, rr = r - m * rjvol;
+        const int rx = rr % jpx;
+        if (v != T(0) && rx < rjx) {
+            const int gi = region_global(pc.n, ts.t0, tg.lo_j, rx, (rr / jpx) % rjy, rr / (jpx * rjy));
             gatomic_add(fp.J[m] + gi, v);
         }
     }
@@ -488,7 +656,7 @@ __global__ void __launch_bounds__(STRAY_THREADS) k_particles_strays(PConst<T> pc
             if (!load_particle(in, p, pc.n, c, f, u, err))
                 copy_particle(in, out, p);
             else
-                particle_step<T, O, false>(pc, in, out, fp, gf, p, c, f, u, z3, 0, z3, 0, z3, nullptr, 0, err);
+                particle_step_global<T, O>(pc, in, out, fp, p, c, f, u, err);
         }
         __syncthreads();   // the list is rewritten by the next chunk
     }
@@ -504,14 +672,7 @@ __global__ void __launch_bounds__(256) k_particles_global(PConst<T> pc, PArr<T> 
     T f[3], u[3];
     if (!load_particle(sp, p, pc.n, c, f, u, err))
         return;
-    FieldSrc<T> gf;
-#pragma unroll
-    for (int m = 0; m < 3; ++m) {
-        gf.c[m] = fp.E[m];
-        gf.c[3 + m] = fp.B[m];
-    }
-    const int z3[3] = {0, 0, 0};
-    particle_step<T, O, false>(pc, sp, sp, fp, gf, p, c, f, u, z3, 0, z3, 0, z3, nullptr, 0, err);
+    particle_step_global<T, O>(pc, sp, sp, fp, p, c, f, u, err);
 }
 
 template <typename T, int O>
@@ -1100,7 +1261,7 @@ template <typename T>
 size_t tile_lds_bytes(int, const TileGeo &tg)
 {
     const size_t rf = (size_t)tg.rf[0] * tg.rf[1] * tg.rf[2];
-    const size_t rj = (size_t)tg.rj[0] * tg.rj[1] * tg.rj[2];
+    const size_t rj = (size_t)tg.jp * tg.rj[1] * tg.rj[2];
     return ((6 * rf * sizeof(T) + 15) & ~size_t(15)) + 3 * rj * sizeof(double) +
            (size_t)tg.qcap * (6 * sizeof(T) + 2 * sizeof(int)) + sizeof(int);
 }

@@ -45,6 +45,7 @@ struct TileGeo {
     int slack;
     int lo_f, rf[3];
     int lo_j, rj[3];
+    int jp;        // row pitch of the forward kernel's LDS current tile (>= rj[0])
     int xcd_map;   // spread consecutive tiles so each XCD gets a contiguous block
     int qcap;      // entries of the tile kernel's LDS queue of cell-crossing particles
 };
