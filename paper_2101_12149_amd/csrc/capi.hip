@@ -319,7 +319,7 @@ pic_status check_fields(const pic_fields *f, bool need_j)
 
 // workspace layout
 struct WsLayout {
-    size_t err, counts, bsum, key, rank, slot, scell, soff, su, sw, hatE, partials, red5, total;
+    size_t err, counts, bsum, key, rank, slot, scell, soff, su, sw, hatE, partials, red5, old_ts, total;
 };
 
 size_t al(size_t x)
@@ -358,6 +358,8 @@ WsLayout layout(const GridInfo &gi, int64_t np)
     o += al(sizeof(double) * 5 * (size_t)reduce_max_blocks());
     L.red5 = o;
     o += 256;
+    L.old_ts = o;
+    o += al(sizeof(int) * ((size_t)gi.ntiles + 1));
     L.total = o;
     return L;
 }
@@ -513,10 +515,18 @@ pic_status do_sort(const GridInfo &gi, const pic_species *sp, char *ws, const Ws
     else
         PIC_HIP(launch_bin_count<T>(in, gi.tg, counts, key, rank, err, st));
     PIC_HIP(launch_scan(counts, gi.ncell, bsum, st));
+    // a re-sort keeps the previous binning: the scatter is staged per old tile
+    int *old_start = nullptr;
+    if (binned) {
+        old_start = reinterpret_cast<int *>(ws + L.old_ts);
+        PIC_HIP(hipMemcpyAsync(old_start, tile_start, sizeof(int) * ((size_t)gi.ntiles + 1), hipMemcpyDeviceToDevice,
+                               st));
+    }
     PIC_HIP(launch_tile_start(counts, gi.tile_cells, gi.ntiles, sp->n, tile_start, st));
     int *slot = reinterpret_cast<int *>(ws + L.slot);
     PIC_HIP(launch_interleave(counts, tile_start, gi.tile_cells, gi.ntiles, slot, st));
-    PIC_HIP(launch_scatter<T>(in, sorted, key, rank, counts, slot, tile_start, gi.tile_cells, perm, st));
+    PIC_HIP(launch_scatter<T>(in, sorted, key, rank, counts, slot, tile_start, old_start, gi.ntiles, gi.tile_cells,
+                              perm, st));
     return PIC_OK;
 }
 

@@ -197,38 +197,44 @@ __global__ void __launch_bounds__(BC_T) k_bin_count_tile(PArr<T> sp, TileGeo tg,
     for (int r = threadIdx.x; r < rvol; r += blockDim.x)
         lc[r] = 0;
     __syncthreads();
-    // pass 1: keys; local ranks (stored as -(rank+1)) or global ranks
-    for (int64_t p = ps + threadIdx.x; p < pe; p += blockDim.x) {
-        int c[3] = {sp.cell[0][p], sp.cell[1][p], sp.cell[2][p]};
-        bool ok = true;
-        int l[3];
-        bool inside = true;
+    // pass 1: keys; local ranks (stored as -(rank+1)) or global ranks.  The
+    // chunks of blockDim.x particles are ranked one after the other (a
+    // barrier between them), so particles that kept their cell keep their
+    // order and the scatter below writes long runs of consecutive slots.
+    for (int64_t p0 = ps; p0 < pe; p0 += blockDim.x) {
+        const int64_t p = p0 + threadIdx.x;
+        if (p < pe) {
+            int c[3] = {sp.cell[0][p], sp.cell[1][p], sp.cell[2][p]};
+            bool ok = true;
+            int l[3];
+            bool inside = true;
 #pragma unroll
-        for (int d = 0; d < 3; ++d) {
-            const T f = sp.off[d][p];
-            ok = ok && c[d] >= 0 && c[d] < n[d] && f >= T(0) && f < T(1);
-            c[d] = c[d] < 0 ? 0 : (c[d] >= n[d] ? n[d] - 1 : c[d]);
-            int v = c[d] - t0[d];
-            if (v < -BC_MARGIN)
-                v += n[d];
-            else if (v >= tg.t[d] + BC_MARGIN)
-                v -= n[d];
-            l[d] = v + BC_MARGIN;
-            inside = inside && v >= -BC_MARGIN && v < tg.t[d] + BC_MARGIN;
+            for (int d = 0; d < 3; ++d) {
+                const T f = sp.off[d][p];
+                ok = ok && c[d] >= 0 && c[d] < n[d] && f >= T(0) && f < T(1);
+                c[d] = c[d] < 0 ? 0 : (c[d] >= n[d] ? n[d] - 1 : c[d]);
+                int v = c[d] - t0[d];
+                if (v < -BC_MARGIN)
+                    v += n[d];
+                else if (v >= tg.t[d] + BC_MARGIN)
+                    v -= n[d];
+                l[d] = v + BC_MARGIN;
+                inside = inside && v >= -BC_MARGIN && v < tg.t[d] + BC_MARGIN;
+            }
+            if (!ok)
+                atomicOr(err, 1);
+            const int cx = c[0] / tg.t[0], cy = c[1] / tg.t[1], cz = c[2] / tg.t[2];
+            const int tile = cx + tg.nt[0] * (cy + tg.nt[1] * cz);
+            const int kk = tile * tcells + (c[0] - cx * tg.t[0]) + tg.t[0] * ((c[1] - cy * tg.t[1]) +
+                                                                             tg.t[1] * (c[2] - cz * tg.t[2]));
+            key[p] = kk;
+            if (inside)
+                rank[p] = -1 - atomicAdd(lc + l[0] + rx * (l[1] + ry * l[2]), 1);
+            else
+                rank[p] = atomicAdd(counts + kk, 1);
         }
-        if (!ok)
-            atomicOr(err, 1);
-        const int cx = c[0] / tg.t[0], cy = c[1] / tg.t[1], cz = c[2] / tg.t[2];
-        const int tile = cx + tg.nt[0] * (cy + tg.nt[1] * cz);
-        const int kk = tile * tcells + (c[0] - cx * tg.t[0]) + tg.t[0] * ((c[1] - cy * tg.t[1]) +
-                                                                         tg.t[1] * (c[2] - cz * tg.t[2]));
-        key[p] = kk;
-        if (inside)
-            rank[p] = -1 - atomicAdd(lc + l[0] + rx * (l[1] + ry * l[2]), 1);
-        else
-            rank[p] = atomicAdd(counts + kk, 1);
+        __syncthreads();   // uniform: every thread runs every chunk
     }
-    __syncthreads();
     // reserve each region cell's range in the global counts
     for (int r = threadIdx.x; r < rvol; r += blockDim.x) {
         const int m = lc[r];
@@ -406,13 +412,163 @@ __global__ void __launch_bounds__(256) k_scatter(PArr<T> in, PArr<T> out, const 
         perm[q] = (int)p;
 }
 
+// Tile-staged scatter for a re-sort.  One workgroup per old tile moves that
+// tile's particles.  Between sorts particles enter and leave cells, which
+// shifts the ranks inside most cells, so even the particles that stay in the
+// tile land at slots scattered over its new segment.  The workgroup places
+// them into an LDS image of the segment, one array at a time, and writes the
+// image out with coalesced stores of only the slots it filled; particles
+// bound for another tile are stored directly.  A tile whose old or new
+// segment exceeds SCT_CAP particles stores every particle directly.
+static constexpr int SCT_T = 1024;
+static constexpr int SCT_CAP = 8192;   // a multiple of SCT_T
+
+static constexpr int SCT_PER = SCT_CAP / SCT_T;
+
+template <typename V>
+__device__ inline void sct_array(const V *src, V *dst, int64_t ps, int np, int ws, int wn, const int *qb,
+                                 V *img, const unsigned char *mark)
+{
+    // all of a thread's loads are issued before its stores
+    V v[SCT_PER];
+#pragma unroll
+    for (int k = 0; k < SCT_PER; ++k) {
+        const int j = threadIdx.x + k * SCT_T;
+        if (j < np)
+            v[k] = src[ps + j];
+    }
+#pragma unroll
+    for (int k = 0; k < SCT_PER; ++k) {
+        const int j = threadIdx.x + k * SCT_T;
+        if (j < np) {
+            const int q = qb[j];
+            const int rel = q - ws;
+            if (rel >= 0 && rel < wn)
+                img[rel] = v[k];
+            else
+                dst[q] = v[k];
+        }
+    }
+    __syncthreads();
+    for (int i = threadIdx.x; i < wn; i += blockDim.x)
+        if (mark[i])
+            dst[ws + i] = img[i];
+    __syncthreads();
+}
+
+template <typename T>
+__global__ void __launch_bounds__(SCT_T) k_scatter_tile(PArr<T> in, PArr<T> out, const int *key, const int *rank,
+                                                        const int *offsets, const int *slot_of,
+                                                        const int *tile_start, const int *old_start, int tile_cells,
+                                                        int *perm)
+{
+    extern __shared__ __align__(16) unsigned char sct_raw[];
+    void *img = sct_raw;                                                  // SCT_CAP values of T (or int)
+    int *qb = reinterpret_cast<int *>(sct_raw + SCT_CAP * sizeof(T));    // destination of each particle
+    unsigned char *mark = sct_raw + SCT_CAP * (sizeof(T) + 4);           // image slots this workgroup fills
+    const int t = blockIdx.x;
+    const int64_t N = in.n;
+    int64_t ps = old_start[t], pe = old_start[t + 1];
+    ps = ps < 0 ? 0 : (ps > N ? N : ps);
+    pe = pe < ps ? ps : (pe > N ? N : pe);
+    const int np = (int)(pe - ps);
+    const int ws = tile_start[t], wn = tile_start[t + 1] - ws;
+    if (np == 0)
+        return;
+    auto dest = [&](int64_t p) {
+        const int k = key[p];
+        return tile_start[k / tile_cells] + slot_of[(int64_t)offsets[k] + rank[p]];
+    };
+    if (np > SCT_CAP || wn > SCT_CAP || wn < 0) {   // uniform across the workgroup
+        for (int j = threadIdx.x; j < np; j += blockDim.x) {
+            const int64_t p = ps + j;
+            const int q = dest(p);
+#pragma unroll
+            for (int d = 0; d < 3; ++d) {
+                out.cell[d][q] = in.cell[d][p];
+                out.off[d][q] = in.off[d][p];
+                out.u[d][q] = in.u[d][p];
+            }
+            if (in.w)
+                out.w[q] = in.w[p];
+            if (perm)
+                perm[q] = (int)p;
+        }
+        return;
+    }
+    for (int i = threadIdx.x; i < wn; i += blockDim.x)
+        mark[i] = 0;
+    {
+        // the dependent loads of a thread's particles proceed side by side
+        int k[SCT_PER], o[SCT_PER];
+#pragma unroll
+        for (int e = 0; e < SCT_PER; ++e) {
+            const int j = threadIdx.x + e * SCT_T;
+            k[e] = j < np ? key[ps + j] : 0;
+        }
+#pragma unroll
+        for (int e = 0; e < SCT_PER; ++e) {
+            const int j = threadIdx.x + e * SCT_T;
+            o[e] = j < np ? offsets[k[e]] + rank[ps + j] : 0;
+        }
+#pragma unroll
+        for (int e = 0; e < SCT_PER; ++e) {
+            const int j = threadIdx.x + e * SCT_T;
+            if (j < np)
+                qb[j] = tile_start[k[e] / tile_cells] + slot_of[o[e]];
+        }
+    }
+    __syncthreads();
+    for (int j = threadIdx.x; j < np; j += blockDim.x) {
+        const int rel = qb[j] - ws;
+        if (rel >= 0 && rel < wn)
+            mark[rel] = 1;
+    }
+    __syncthreads();
+    int *ii = static_cast<int *>(img);
+    T *ti = static_cast<T *>(img);
+#pragma unroll
+    for (int d = 0; d < 3; ++d) {
+        sct_array<int>(in.cell[d], out.cell[d], ps, np, ws, wn, qb, ii, mark);
+        sct_array<T>(in.off[d], out.off[d], ps, np, ws, wn, qb, ti, mark);
+        sct_array<T>(in.u[d], out.u[d], ps, np, ws, wn, qb, ti, mark);
+    }
+    if (in.w)
+        sct_array<T>(in.w, out.w, ps, np, ws, wn, qb, ti, mark);
+    if (perm) {
+        for (int j = threadIdx.x; j < np; j += blockDim.x) {
+            const int rel = qb[j] - ws;
+            if (rel >= 0 && rel < wn)
+                ii[rel] = (int)(ps + j);
+            else
+                perm[qb[j]] = (int)(ps + j);
+        }
+        __syncthreads();
+        for (int i = threadIdx.x; i < wn; i += blockDim.x)
+            if (mark[i])
+                perm[ws + i] = ii[i];
+    }
+}
+
 template <typename T>
 hipError_t launch_scatter(const PArr<T> &in, const PArr<T> &out, const int *key, const int *rank,
-                          const int *offsets, const int *slot_of, const int *tile_start, int tile_cells, int *perm,
-                          hipStream_t st)
+                          const int *offsets, const int *slot_of, const int *tile_start, const int *old_start,
+                          int ntiles, int tile_cells, int *perm, hipStream_t st)
 {
     if (in.n == 0)
         return hipSuccess;
+    if (old_start) {
+        static bool attr = false;
+        const size_t lds = (size_t)SCT_CAP * (sizeof(T) + 5);
+        if (!attr) {
+            hipFuncSetAttribute(reinterpret_cast<const void *>(&k_scatter_tile<T>),
+                                hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
+            attr = true;
+        }
+        hipLaunchKernelGGL((k_scatter_tile<T>), dim3((unsigned)ntiles), dim3(SCT_T), lds, st, in, out, key, rank,
+                           offsets, slot_of, tile_start, old_start, tile_cells, perm);
+        return hipGetLastError();
+    }
     hipLaunchKernelGGL((k_scatter<T>), dim3((unsigned)((in.n + 255) / 256)), dim3(256), 0, st, in, out, key, rank,
                        offsets, slot_of, tile_start, tile_cells, perm);
     return hipGetLastError();
@@ -658,7 +814,7 @@ hipError_t launch_reduce(const PArr<T> *sp, const FieldPtrs<T> &f, int64_t ncell
     template hipError_t launch_bin_count_tile<T>(const PArr<T> &, const TileGeo &, const int *, int *, int *,     \
                                                  int *, int *, hipStream_t);                                      \
     template hipError_t launch_scatter<T>(const PArr<T> &, const PArr<T> &, const int *, const int *, const int *, \
-                                          const int *, const int *, int, int *, hipStream_t);                     \
+                                          const int *, const int *, const int *, int, int, int *, hipStream_t);   \
     template hipError_t launch_reduce<T>(const PArr<T> *, const FieldPtrs<T> &, int64_t, double *, int,           \
                                          const double[7], double *, hipStream_t);
 

@@ -122,10 +122,12 @@ hipError_t launch_bin_count(const PArr<T> &sp, const TileGeo &tg, int *counts, i
 template <typename T>
 hipError_t launch_bin_count_tile(const PArr<T> &sp, const TileGeo &tg, const int *tile_start, int *counts, int *key,
                                  int *rank, int *err, hipStream_t st);
+// old_start (the binning before this sort, or null): with it the scatter is
+// staged per old tile in LDS
 template <typename T>
 hipError_t launch_scatter(const PArr<T> &in, const PArr<T> &out, const int *key, const int *rank,
-                          const int *offsets, const int *slot_of, const int *tile_start, int tile_cells, int *perm,
-                          hipStream_t st);
+                          const int *offsets, const int *slot_of, const int *tile_start, const int *old_start,
+                          int ntiles, int tile_cells, int *perm, hipStream_t st);
 hipError_t launch_interleave(const int *offsets, const int *tile_start, int tile_cells, int ntiles, int *slot_of,
                              hipStream_t st);
 hipError_t launch_scan(int *data, int64_t n, int *block_sums, hipStream_t st);
