@@ -824,12 +824,14 @@ struct AdjPtrs {
 };
 
 // Gather transpose of one field component with staggering (SX, SY, SZ):
-// scatter S * vb into the component's adjoint (FP64 LDS accumulators or
-// global atomics) and add vb * grad(gathered value) to the position adjoint.
+// scatter S * vb into the component's adjoint (FP64 LDS accumulators, rows
+// along x shared between lanes as in the forward deposit, or global atomics)
+// and add vb * grad(gathered value) to the position adjoint.
 template <int O, typename T, bool LOCAL, int SX, int SY, int SZ>
 __device__ __attribute__((always_inline)) inline void gather_transpose(const T *F, T *Lglob, double *sL, T vb, const AxisW<O, T> *aw,
                                         const T (*dn)[Shape<O, T>::NW], const T (*ds)[Shape<O, T>::NW],
-                                        const int (*on)[Shape<O, T>::NW], const int (*os)[Shape<O, T>::NW], T *lxa)
+                                        const int (*on)[Shape<O, T>::NW], const int (*os)[Shape<O, T>::NW], T *lxa,
+                                        const XRun &xr)
 {
     constexpr int NW = Shape<O, T>::NW;
     const T *wx = SX ? aw[0].ws : aw[0].wn;
@@ -849,19 +851,28 @@ __device__ __attribute__((always_inline)) inline void gather_transpose(const T *
             const int rowo = yo[j] + zo[k];
             const T wyz = wy[j] * wz[k] * vb;
             T ax = T(0), adx = T(0);
+            double r[NW];
 #pragma unroll
             for (int i = 0; i < NW; ++i) {
                 const T val = F[rowo + xo[i]];
                 ax += wx[i] * val;
                 adx += dx[i] * val;
                 if (LOCAL)
-                    latomic_add(sL + rowo + xo[i], (double)(wx[i] * wyz));
+                    r[i] = (double)(wx[i] * wyz);
                 else
                     gatomic_add(Lglob + rowo + xo[i], wx[i] * wyz);
             }
+            if (LOCAL)
+                xrow_add<NW>(sL + rowo + xo[0], r, xr);   // LDS x offsets are consecutive
             gx += adx * wy[j] * wz[k];
             gy += ax * dy[j] * wz[k];
             gz += ax * wy[j] * dz[k];
+            if (LOCAL) {
+                // finish the row here (the compiler would otherwise issue
+                // every row's loads first and park them in scratch memory)
+                asm volatile("" : "+v"(gx), "+v"(gy), "+v"(gz));
+                __builtin_amdgcn_sched_barrier(0);
+            }
         }
     lxa[0] += vb * gx;
     lxa[1] += vb * gy;
@@ -987,11 +998,14 @@ __device__ __attribute__((always_inline)) inline void adjoint_push_particle(cons
 // pass 2 for one particle: components of group G (0: E, 1: B, 2: both).
 // fsrc.c[m] is component m (E_x..E_z, B_x..B_z); the LDS accumulators hold
 // the group's components at sL + (m - 3 G) * rfvol.
+// xr[k]: the lane runs of the group's k-th component (LOCAL only)
 template <typename T, int O, bool LOCAL, int G>
 __device__ __attribute__((always_inline)) inline void adjoint_scatter_particle(const PConst<T> &pc, const AdjPtrs<T> &ap,
                                                 const FieldSrc<T> &fsrc, int64_t p, const int *c, const T *f,
-                                                const int *l, int lo_f, const int *sf, double *sL, int rfvol)
+                                                const int *l, int lo_f, const int *sf, double *sL, int rfvol,
+                                                const XRun *xr = nullptr)
 {
+    const XRun none{false, false, false, true};
     constexpr int NW = Shape<O, T>::NW;
     AxisW<O, T> aw[3];
     int on[3][NW], os[3][NW];
@@ -1005,19 +1019,19 @@ __device__ __attribute__((always_inline)) inline void adjoint_scatter_particle(c
     // staggering per component: E_x(s,n,n) E_y(n,s,n) E_z(n,n,s) B_x(n,s,s) B_y(s,n,s) B_z(s,s,n)
     if (G != 1) {
         gather_transpose<O, T, LOCAL, 1, 0, 0>(fsrc.c[0], ap.lE[0], sL + (0 - b) * rfvol, ap.vb[0][p], aw, dn, ds, on,
-                                               os, lxa);
+                                               os, lxa, LOCAL ? xr[0] : none);
         gather_transpose<O, T, LOCAL, 0, 1, 0>(fsrc.c[1], ap.lE[1], sL + (1 - b) * rfvol, ap.vb[1][p], aw, dn, ds, on,
-                                               os, lxa);
+                                               os, lxa, LOCAL ? xr[1] : none);
         gather_transpose<O, T, LOCAL, 0, 0, 1>(fsrc.c[2], ap.lE[2], sL + (2 - b) * rfvol, ap.vb[2][p], aw, dn, ds, on,
-                                               os, lxa);
+                                               os, lxa, LOCAL ? xr[2] : none);
     }
     if (G != 0) {
         gather_transpose<O, T, LOCAL, 0, 1, 1>(fsrc.c[3], ap.lB[0], sL + (3 - b) * rfvol, ap.vb[3][p], aw, dn, ds, on,
-                                               os, lxa);
+                                               os, lxa, LOCAL ? xr[0] : none);
         gather_transpose<O, T, LOCAL, 1, 0, 1>(fsrc.c[4], ap.lB[1], sL + (4 - b) * rfvol, ap.vb[4][p], aw, dn, ds, on,
-                                               os, lxa);
+                                               os, lxa, LOCAL ? xr[1] : none);
         gather_transpose<O, T, LOCAL, 1, 1, 0>(fsrc.c[5], ap.lB[2], sL + (5 - b) * rfvol, ap.vb[5][p], aw, dn, ds, on,
-                                               os, lxa);
+                                               os, lxa, LOCAL ? xr[2] : none);
     }
 #pragma unroll
     for (int d = 0; d < 3; ++d)
@@ -1227,16 +1241,33 @@ __global__ void __launch_bounds__(AdjThreads<T>::value) k_adjoint_scatter_tile(P
     }
     const int sf[3] = {1, rfx, rfx * rfy};
     const int np = (int)(ts.pe - ts.ps);
+    // staggering of the group's components along x, y, z
+    constexpr int SX[6] = {1, 0, 0, 0, 1, 1}, SY[6] = {0, 1, 0, 1, 0, 1}, SZ[6] = {0, 0, 1, 1, 1, 0};
     for (int j0 = 0; j0 < np; j0 += nth) {
         const int j = j0 + tid;
-        if (j < np) {
-            const int64_t p = ts.ps + j;
-            int c[3];
-            T f[3];
-            int l[3];
-            if (load_position(sp, p, pc.n, c, f) && tile_local(tg, pc.n, ts.t0, c, l))
-                adjoint_scatter_particle<T, O, true, G>(pc, ap, lf, p, c, f, l, tg.lo_f, sf, sL, rfvol);
+        int c[3] = {0, 0, 0}, l[3] = {0, 0, 0};
+        T f[3] = {T(0), T(0), T(0)};
+        int key[3] = {0, 0, 0};
+        const bool act = j < np && load_position(sp, ts.ps + j, pc.n, c, f) && tile_local(tg, pc.n, ts.t0, c, l);
+        if (act) {
+            // a lane's window of component k starts at its cell plus the
+            // component's first-node offset; lanes share rows when these
+            // starts are consecutive along x
+            int bs[3];
+#pragma unroll
+            for (int d = 0; d < 3; ++d)
+                bs[d] = f[d] >= T(0.5) ? Shape<O, T>::NB : Shape<O, T>::NB - 1;
+#pragma unroll
+            for (int k = 0; k < 3; ++k) {
+                const int m = 3 * G + k;
+                const int st[3] = {l[0] + (SX[m] ? bs[0] : Shape<O, T>::NB), l[1] + (SY[m] ? bs[1] : Shape<O, T>::NB),
+                                   l[2] + (SZ[m] ? bs[2] : Shape<O, T>::NB)};
+                key[k] = xrun_key(st);
+            }
         }
+        const XRun xr[3] = {xrun(key[0]), xrun(key[1]), xrun(key[2])};   // converged
+        if (act)
+            adjoint_scatter_particle<T, O, true, G>(pc, ap, lf, ts.ps + j, c, f, l, tg.lo_f, sf, sL, rfvol, xr);
     }
     __syncthreads();
     for (int r = tid; r < 3 * rfvol; r += nth) {
