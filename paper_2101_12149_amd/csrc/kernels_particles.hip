@@ -367,33 +367,36 @@ __device__ __attribute__((always_inline)) inline void particle_step_global(const
 // values added are those of the per-lane scatter; only the summation order
 // changes, and a wave issues far fewer lane atomics, spread over more banks.
 
-// Row shift of a 64-bit value: lane L receives lane L-K's value within its
-// 16-lane row (lanes with no source receive 0), or lane L+1's for K = -1.
-template <int K>
-__device__ inline double dpp_shift(double v)
-{
-    constexpr int CTRL = K > 0 ? 0x110 + K : 0x101;   // row_shr:K / row_shl:1
-    const long long b = __double_as_longlong(v);
-    const int lo = __builtin_amdgcn_update_dpp(0, (int)(b & 0xffffffffLL), CTRL, 0xf, 0xf, false);
-    const int hi = __builtin_amdgcn_update_dpp(0, (int)(b >> 32), CTRL, 0xf, 0xf, false);
-    return __longlong_as_double(((long long)hi << 32) | (long long)(unsigned)lo);
-}
-
+// Row shift by one lane: lane L receives lane L-1's value within its 16-lane
+// row (lane 0 of a row receives 0); K = -1 shifts the other way.
 template <int K>
 __device__ inline int dpp_shift_int(int v)
 {
-    constexpr int CTRL = K > 0 ? 0x110 + K : 0x101;
+    constexpr int CTRL = K > 0 ? 0x110 + K : 0x101;   // row_shr:K / row_shl:1
     return __builtin_amdgcn_update_dpp(0, v, CTRL, 0xf, 0xf, false);
 }
 
+__device__ inline float dpp_shift1(float v)
+{
+    return __int_as_float(dpp_shift_int<1>(__float_as_int(v)));
+}
+
+__device__ inline double dpp_shift1(double v)
+{
+    const long long b = __double_as_longlong(v);
+    const int lo = dpp_shift_int<1>((int)(b & 0xffffffffLL));
+    const int hi = dpp_shift_int<1>((int)(b >> 32));
+    return __longlong_as_double(((long long)hi << 32) | (long long)(unsigned)lo);
+}
+
 struct XRun {
-    bool a1, a2, a3;   // lanes L-1, L-2, L-3 belong to this lane's run
-    bool last;         // the run ends at this lane
+    bool a1;     // lane L-1 belongs to this lane's run
+    bool last;   // the run ends at this lane
 };
 
 // key: 0 for a lane outside the shared deposit, else a positive code of the
-// local cell with x in the low bits (x - 1 is key - 1).  Call with the whole
-// wave converged.
+// first window node with x in the low bits (x - 1 is key - 1).  Call with the
+// whole wave converged.
 __device__ inline int xrun_key(const int *l)
 {
     return (1 << 20) | (l[0] + 8) | ((l[1] + 8) << 6) | ((l[2] + 8) << 12);
@@ -403,48 +406,34 @@ __device__ inline XRun xrun(int key)
 {
     const int k1 = dpp_shift_int<1>(key);
     const bool a1 = key != 0 && k1 == key - 1;
-    const int a1i = a1 ? 1 : 0;
-    const int p1 = dpp_shift_int<1>(a1i), p2 = dpp_shift_int<2>(a1i), n1 = dpp_shift_int<-1>(a1i);
+    const int n1 = dpp_shift_int<-1>(a1 ? 1 : 0);
     XRun r;
     r.a1 = a1;
-    r.a2 = a1 && p1 != 0;
-    r.a3 = r.a2 && p2 != 0;
     r.last = key != 0 && n1 == 0;
     return r;
 }
 
-// one window row of NT taps along x, starting at `row` (this lane's first node)
-template <int NT>
-__device__ __attribute__((always_inline)) inline void xrow_add(double *row, const double *r, const XRun &xr)
+// One window row of NT taps along x, starting at `row` (this lane's first
+// node).  Node k of this lane collects its own tap k and, through the run,
+// tap k+1 of the lane to its left, tap k+2 of the next one and so on:
+// e[k] = r[k] + e_left[k+1], built from the last tap down.  The lane writes
+// e[0]; the last lane of a run also writes e[1..NT-1].  V is the type the
+// row is summed in; the LDS accumulators are FP64.
+template <int NT, typename V>
+__device__ __attribute__((always_inline)) inline void xrow_add(double *row, const V *r, const XRun &xr)
 {
-    double s = r[0];
-    double e[NT > 1 ? NT : 2];
-    if constexpr (NT >= 2) {
-        const double t = dpp_shift<1>(r[1]);
-        s += xr.a1 ? t : 0.0;
-        e[1] = r[1];
+    V e[NT];
+    e[NT - 1] = r[NT - 1];
+#pragma unroll
+    for (int k = NT - 2; k >= 0; --k) {
+        const V t = dpp_shift1(e[k + 1]);
+        e[k] = r[k] + (xr.a1 ? t : V(0));
     }
-    if constexpr (NT >= 3) {
-        const double t2 = dpp_shift<2>(r[2]);
-        s += xr.a2 ? t2 : 0.0;
-        const double t1 = dpp_shift<1>(r[2]);
-        e[1] += xr.a1 ? t1 : 0.0;
-        e[2] = r[2];
-    }
-    if constexpr (NT >= 4) {
-        const double t3 = dpp_shift<3>(r[3]);
-        s += xr.a3 ? t3 : 0.0;
-        const double t2 = dpp_shift<2>(r[3]);
-        e[1] += xr.a2 ? t2 : 0.0;
-        const double t1 = dpp_shift<1>(r[3]);
-        e[2] += xr.a1 ? t1 : 0.0;
-        e[3] = r[3];
-    }
-    latomic_add(row, s);
+    latomic_add(row, (double)e[0]);
     if (xr.last) {
 #pragma unroll
         for (int k = 1; k < NT; ++k)
-            latomic_add(row + k, e[k]);
+            latomic_add(row + k, (double)e[k]);
     }
 }
 
@@ -851,14 +840,14 @@ __device__ __attribute__((always_inline)) inline void gather_transpose(const T *
             const int rowo = yo[j] + zo[k];
             const T wyz = wy[j] * wz[k] * vb;
             T ax = T(0), adx = T(0);
-            double r[NW];
+            T r[NW];
 #pragma unroll
             for (int i = 0; i < NW; ++i) {
                 const T val = F[rowo + xo[i]];
                 ax += wx[i] * val;
                 adx += dx[i] * val;
                 if (LOCAL)
-                    r[i] = (double)(wx[i] * wyz);
+                    r[i] = wx[i] * wyz;
                 else
                     gatomic_add(Lglob + rowo + xo[i], wx[i] * wyz);
             }
@@ -1005,7 +994,7 @@ __device__ __attribute__((always_inline)) inline void adjoint_scatter_particle(c
                                                 const int *l, int lo_f, const int *sf, double *sL, int rfvol,
                                                 const XRun *xr = nullptr)
 {
-    const XRun none{false, false, false, true};
+    const XRun none{false, true};
     constexpr int NW = Shape<O, T>::NW;
     AxisW<O, T> aw[3];
     int on[3][NW], os[3][NW];
