@@ -367,31 +367,36 @@ __device__ __attribute__((always_inline)) inline void particle_step_global(const
 // values added are those of the per-lane scatter; only the summation order
 // changes, and a wave issues far fewer lane atomics, spread over more banks.
 
-// Row shift by one lane: lane L receives lane L-1's value within its 16-lane
-// row (lane 0 of a row receives 0); K = -1 shifts the other way.
+// Row shifts within 16-lane DPP rows: K > 0 gives lane L the value of lane
+// L-K, K < 0 that of lane L+|K| (0 where the source is outside the row).
 template <int K>
 __device__ inline int dpp_shift_int(int v)
 {
-    constexpr int CTRL = K > 0 ? 0x110 + K : 0x101;   // row_shr:K / row_shl:1
-    return __builtin_amdgcn_update_dpp(0, v, CTRL, 0xf, 0xf, false);
+    constexpr int CTRL = K > 0 ? 0x110 + K : 0x100 - K;   // row_shr:K / row_shl:-K
+    return __builtin_amdgcn_update_dpp(0, v, CTRL, 0xf, 0xf, true);
 }
 
-__device__ inline float dpp_shift1(float v)
+template <int K>
+__device__ inline float dpp_shift(float v)
 {
-    return __int_as_float(dpp_shift_int<1>(__float_as_int(v)));
+    return __int_as_float(dpp_shift_int<K>(__float_as_int(v)));
 }
 
-__device__ inline double dpp_shift1(double v)
+template <int K>
+__device__ inline double dpp_shift(double v, int = 0)
 {
     const long long b = __double_as_longlong(v);
-    const int lo = dpp_shift_int<1>((int)(b & 0xffffffffLL));
-    const int hi = dpp_shift_int<1>((int)(b >> 32));
+    const int lo = dpp_shift_int<K>((int)(b & 0xffffffffLL));
+    const int hi = dpp_shift_int<K>((int)(b >> 32));
     return __longlong_as_double(((long long)hi << 32) | (long long)(unsigned)lo);
 }
 
 struct XRun {
     bool a1;     // lane L-1 belongs to this lane's run
     bool last;   // the run ends at this lane
+    bool send;   // lane L+1 belongs to this lane's run
+    int d;       // lanes between this one and its run's last lane (4: more, or no run)
+    int len;     // at the last lane: the run's length, counted up to 4
 };
 
 // key: 0 for a lane outside the shared deposit, else a positive code of the
@@ -406,19 +411,33 @@ __device__ inline XRun xrun(int key)
 {
     const int k1 = dpp_shift_int<1>(key);
     const bool a1 = key != 0 && k1 == key - 1;
-    const int n1 = dpp_shift_int<-1>(a1 ? 1 : 0);
+    const int a1i = a1 ? 1 : 0;
+    const bool send = dpp_shift_int<-1>(a1i) != 0;
+    const bool last = key != 0 && !send;
+    // flags of the lanes to the right: bit 0 "aligned to its left", bit 1 "last"
+    const int f = a1i | (last ? 2 : 0);
+    const int f1 = dpp_shift_int<-1>(f), f2 = dpp_shift_int<-2>(f), f3 = dpp_shift_int<-3>(f);
     XRun r;
     r.a1 = a1;
-    r.last = key != 0 && n1 == 0;
+    r.last = last;
+    r.send = send;
+    r.d = last ? 0
+               : ((f1 & 3) == 3) ? 1
+                                 : ((f1 & 1) && (f2 & 3) == 3) ? 2 : ((f1 & 1) && (f2 & 1) && (f3 & 3) == 3) ? 3 : 4;
+    const int b1 = dpp_shift_int<1>(a1i), b2 = dpp_shift_int<2>(a1i);
+    r.len = 1 + (a1 ? 1 + (b1 ? 1 + (b2 ? 1 : 0) : 0) : 0);
     return r;
 }
 
 // One window row of NT taps along x, starting at `row` (this lane's first
 // node).  Node k of this lane collects its own tap k and, through the run,
 // tap k+1 of the lane to its left, tap k+2 of the next one and so on:
-// e[k] = r[k] + e_left[k+1], built from the last tap down.  The lane writes
-// e[0]; the last lane of a run also writes e[1..NT-1].  V is the type the
-// row is summed in; the LDS accumulators are FP64.
+// e[k] = r[k] + e_left[k+1], built from the last tap down.  Every lane writes
+// e[0]; the run's last lane R holds e[1..NT-1] for the nodes past the run,
+// and lane R-d writes e_R[d+1] (node X_R + d + 1) in a second instruction,
+// so a row costs two LDS instructions; a run shorter than NT - 1 lanes
+// leaves the rest to its last lane.  V is the type the row is summed in; the
+// LDS accumulators are FP64.
 template <int NT, typename V>
 __device__ __attribute__((always_inline)) inline void xrow_add(double *row, const V *r, const XRun &xr)
 {
@@ -426,19 +445,50 @@ __device__ __attribute__((always_inline)) inline void xrow_add(double *row, cons
     e[NT - 1] = r[NT - 1];
 #pragma unroll
     for (int k = NT - 2; k >= 0; --k) {
-        const V t = dpp_shift1(e[k + 1]);
-        e[k] = r[k] + (xr.a1 ? t : V(0));
+        // the sender masks, so the shift can fold into the add
+        const V snd = xr.send ? e[k + 1] : V(0);
+        e[k] = r[k] + dpp_shift<1>(snd);
     }
     latomic_add(row, (double)e[0]);
-    if (xr.last) {
+    if constexpr (NT >= 2) {
+        V x = e[1];
+        int off = xr.d == 0 ? 1 : -1;
+        if constexpr (NT >= 3) {
+            const V t = dpp_shift<-1>(e[2]);
+            if (xr.d == 1) {
+                x = t;
+                off = 3;
+            }
+        }
+        if constexpr (NT >= 4) {
+            const V t = dpp_shift<-2>(e[3]);
+            if (xr.d == 2) {
+                x = t;
+                off = 5;
+            }
+        }
+        if constexpr (NT >= 5) {
+            const V t = dpp_shift<-3>(e[4]);
+            if (xr.d == 3) {
+                x = t;
+                off = 7;
+            }
+        }
+        if (off > 0)
+            latomic_add(row + off, (double)x);
+        if (xr.last && xr.len < NT - 1) {
 #pragma unroll
-        for (int k = 1; k < NT; ++k)
-            latomic_add(row + k, (double)e[k]);
+            for (int k = 2; k < NT; ++k)
+                if (k > xr.len)
+                    latomic_add(row + k, (double)e[k]);
+        }
     }
 }
 
 // Esirkepov deposit of a particle that stays in its cell, into the LDS
-// current tile with lane-shared rows along x (esk_scatter_still's values).
+// current tile with lane-shared rows along x: esk_scatter_still's values,
+// formed and summed along the run in the working precision and added to the
+// FP64 accumulators.
 template <typename T, int O>
 __device__ __attribute__((always_inline)) inline void deposit_still_shared(const PConst<T> &pc, const T *f0, const T *f1, const int *l,
                                             int lo_j, const int *sj, T w, double *sJ, int rjvol, const XRun &xr)
@@ -454,27 +504,27 @@ __device__ __attribute__((always_inline)) inline void deposit_still_shared(const
         axis_offsets_local<NW>(l[d] + lo_j, Shape<O, T>::NB, sj[d], jo[d]);
     }
     // P_m[a] = K_m * (running sum of DS_m), a < NW - 1
-    double P[3][NW - 1];
+    T P[3][NW - 1];
 #pragma unroll
     for (int m = 0; m < 3; ++m) {
         T run = T(0);
 #pragma unroll
         for (int a = 0; a < NW - 1; ++a) {
             run += DS[m][a];
-            P[m][a] = (double)(K[m] * run);
+            P[m][a] = K[m] * run;
         }
     }
     // C for (p, q) at (b, c), as in esk_scatter_still
-    auto cw = [&](int p, int q, int b, int c) -> double {
-        return (double)(S0[p][b] * (S0[q][c] + half * DS[q][c]) + DS[p][b] * (half * S0[q][c] + third * DS[q][c]));
+    auto cw = [&](int p, int q, int b, int c) -> T {
+        return S0[p][b] * (S0[q][c] + half * DS[q][c]) + DS[p][b] * (half * S0[q][c] + third * DS[q][c]);
     };
     // J_x (p = y, q = z): rows along x are the taps a
 #pragma unroll
     for (int c = 0; c < NW; ++c)
 #pragma unroll
         for (int b = 0; b < NW; ++b) {
-            const double C = cw(1, 2, b, c);
-            double r[NW - 1];
+            const T C = cw(1, 2, b, c);
+            T r[NW - 1];
 #pragma unroll
             for (int a = 0; a < NW - 1; ++a)
                 r[a] = P[0][a] * C;
@@ -485,7 +535,7 @@ __device__ __attribute__((always_inline)) inline void deposit_still_shared(const
     for (int a = 0; a < NW - 1; ++a)
 #pragma unroll
         for (int b = 0; b < NW; ++b) {
-            double r[NW];
+            T r[NW];
 #pragma unroll
             for (int c = 0; c < NW; ++c)
                 r[c] = P[1][a] * cw(2, 0, b, c);
@@ -496,7 +546,7 @@ __device__ __attribute__((always_inline)) inline void deposit_still_shared(const
     for (int a = 0; a < NW - 1; ++a)
 #pragma unroll
         for (int c = 0; c < NW; ++c) {
-            double r[NW];
+            T r[NW];
 #pragma unroll
             for (int b = 0; b < NW; ++b)
                 r[b] = P[2][a] * cw(0, 1, b, c);
@@ -994,7 +1044,7 @@ __device__ __attribute__((always_inline)) inline void adjoint_scatter_particle(c
                                                 const int *l, int lo_f, const int *sf, double *sL, int rfvol,
                                                 const XRun *xr = nullptr)
 {
-    const XRun none{false, true};
+    const XRun none{false, true, false, 0, 1};
     constexpr int NW = Shape<O, T>::NW;
     AxisW<O, T> aw[3];
     int on[3][NW], os[3][NW];
