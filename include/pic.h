@@ -199,9 +199,10 @@ PIC_API pic_status pic_reduce(const pic_grid *grid, const pic_species *sp, const
 
 /* Kernel timing with HIP events recorded on the caller's stream around the
  * launches of pic_step and pic_step_adjoint, by category:
- *   0 sort (binning + scan + scatter)   1 fused particle kernel
+ *   0 sort (binning + scan + scatter)   1 fused particle (tile) kernel
  *   2 Yee field update                  3 FP64 reductions
- *   4 adjoint field transposes          5 adjoint particle kernel
+ *   4 adjoint field transposes          5 adjoint particle kernels
+ *   6 particles outside their tile's region (stray kernel)
  * Completes the pending measurements (synchronising on their events),
  * writes the accumulated milliseconds and launch counts of the first n
  * categories to ms / count (either may be NULL), resets the accumulators and

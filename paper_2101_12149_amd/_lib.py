@@ -51,7 +51,7 @@ class pic_adjoint(C.Structure):
 
 EXPORTS = ("pic_workspace_bytes", "pic_tile_count", "pic_sort_tiles", "pic_gather", "pic_push", "pic_deposit",
            "pic_yee", "pic_step", "pic_step_adjoint", "pic_reduce", "pic_energy_loss", "pic_timing", "pic_last_error")
-TIMING_CATEGORIES = ("sort", "particles", "yee", "reduce", "adjoint_fields", "adjoint_particles")
+TIMING_CATEGORIES = ("sort", "particles", "yee", "reduce", "adjoint_fields", "adjoint_particles", "strays")
 
 _lock = threading.Lock()
 _lib = None

@@ -49,7 +49,7 @@ pic_status hip_fail(hipError_t e, const char *where)
 
 // ---------------------------------------------------------------------------
 // optional kernel timing (pic_timing): event pairs recorded around launches
-constexpr int NCAT = 6;
+constexpr int NCAT = 7;
 struct Timer {
     bool on = false;
     struct Pending {
@@ -615,11 +615,19 @@ pic_status step_t(const pic_grid *g, const GridInfo &gi, pic_species *sp, pic_fi
                 if (s != PIC_OK)
                     return s;
             }
-            TimedScope ts(1, st);
-            PIC_HIP(launch_particles_tile<T>(gi.order, pc, gi.tg, sorted, user, fp, tile_start, stray, err, st));
+            {
+                TimedScope ts(1, st);
+                PIC_HIP(launch_particles_tile<T>(gi.order, pc, gi.tg, sorted, user, fp, tile_start, stray, err, st));
+            }
+            TimedScope ts(6, st);
+            PIC_HIP(launch_particles_strays<T>(gi.order, pc, gi.tg, sorted, user, fp, tile_start, stray, err, st));
         } else if (tile_start && sp->n > 0) {
-            TimedScope ts(1, st);
-            PIC_HIP(launch_particles_tile<T>(gi.order, pc, gi.tg, user, user, fp, tile_start, stray, err, st));
+            {
+                TimedScope ts(1, st);
+                PIC_HIP(launch_particles_tile<T>(gi.order, pc, gi.tg, user, user, fp, tile_start, stray, err, st));
+            }
+            TimedScope ts(6, st);
+            PIC_HIP(launch_particles_strays<T>(gi.order, pc, gi.tg, user, user, fp, tile_start, stray, err, st));
         } else {
             TimedScope ts(1, st);
             PIC_HIP(launch_particles_global<T>(gi.order, pc, user, fp, err, st));

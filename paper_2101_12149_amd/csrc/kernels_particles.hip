@@ -1358,8 +1358,6 @@ static hipError_t launch_tile_o(const PConst<T> &pc, const TileGeo &tg, const PA
     const unsigned ntiles = (unsigned)(tg.nt[0] * tg.nt[1] * tg.nt[2]);
     hipLaunchKernelGGL((k_particles_tile<T, O>), dim3(ntiles), dim3(TileThreads<T>::value), lds, st, pc, tg, in, out,
                        f, tile_start, stray, err);
-    hipLaunchKernelGGL((k_particles_strays<T, O>), dim3(ntiles), dim3(STRAY_THREADS), 0, st, pc, tg, in, out, f,
-                       tile_start, stray, err);
     return hipGetLastError();
 }
 
@@ -1370,6 +1368,21 @@ hipError_t launch_particles_tile(int order, const PConst<T> &pc, const TileGeo &
 {
     return order == 1 ? launch_tile_o<T, 1>(pc, tg, in, out, f, tile_start, stray, err, st)
                       : launch_tile_o<T, 3>(pc, tg, in, out, f, tile_start, stray, err, st);
+}
+
+template <typename T>
+hipError_t launch_particles_strays(int order, const PConst<T> &pc, const TileGeo &tg, const PArr<T> &in,
+                                   const PArr<T> &out, const FieldPtrs<T> &f, const int *tile_start,
+                                   const unsigned char *stray, int *err, hipStream_t st)
+{
+    const unsigned ntiles = (unsigned)(tg.nt[0] * tg.nt[1] * tg.nt[2]);
+    if (order == 1)
+        hipLaunchKernelGGL((k_particles_strays<T, 1>), dim3(ntiles), dim3(STRAY_THREADS), 0, st, pc, tg, in, out, f,
+                           tile_start, stray, err);
+    else
+        hipLaunchKernelGGL((k_particles_strays<T, 3>), dim3(ntiles), dim3(STRAY_THREADS), 0, st, pc, tg, in, out, f,
+                           tile_start, stray, err);
+    return hipGetLastError();
 }
 
 template <typename T>
@@ -1529,6 +1542,9 @@ hipError_t launch_adjoint_tile(int order, const PConst<T> &pc, const TileGeo &tg
     template hipError_t launch_particles_tile<T>(int, const PConst<T> &, const TileGeo &, const PArr<T> &,         \
                                                  const PArr<T> &, const FieldPtrs<T> &, const int *,               \
                                                  unsigned char *, int *, hipStream_t);                             \
+    template hipError_t launch_particles_strays<T>(int, const PConst<T> &, const TileGeo &, const PArr<T> &,       \
+                                                   const PArr<T> &, const FieldPtrs<T> &, const int *,             \
+                                                   const unsigned char *, int *, hipStream_t);                     \
     template hipError_t launch_particles_global<T>(int, const PConst<T> &, const PArr<T> &, const FieldPtrs<T> &,  \
                                                    int *, hipStream_t);                                            \
     template hipError_t launch_gather<T>(int, const PConst<T> &, const PArr<T> &, const FieldPtrs<T> &,            \

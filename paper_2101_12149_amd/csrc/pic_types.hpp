@@ -81,6 +81,11 @@ template <typename T>
 hipError_t launch_particles_tile(int order, const PConst<T> &pc, const TileGeo &tg, const PArr<T> &in,
                                  const PArr<T> &out, const FieldPtrs<T> &f, const int *tile_start,
                                  unsigned char *stray, int *err, hipStream_t st);
+// the particles the tile kernel marked in `stray`, on global memory
+template <typename T>
+hipError_t launch_particles_strays(int order, const PConst<T> &pc, const TileGeo &tg, const PArr<T> &in,
+                                   const PArr<T> &out, const FieldPtrs<T> &f, const int *tile_start,
+                                   const unsigned char *stray, int *err, hipStream_t st);
 template <typename T>
 hipError_t launch_particles_global(int order, const PConst<T> &pc, const PArr<T> &sp, const FieldPtrs<T> &f,
                                    int *err, hipStream_t st);
