@@ -157,8 +157,10 @@ PIC_API pic_status pic_yee(const pic_grid *grid, pic_fields *f, const pic_source
  * + position update + Esirkepov deposit (one fused tile kernel, Sec. 3.1) ->
  * Yee update.  Sorting happens before the first step of the call and before
  * every step whose index is a multiple of sort_every when sort_every > 0;
- * with sort_every == 0 the binning already in tile_start is used, and with
- * tile_start == NULL as well the particles are processed without tiles.
+ * with sort_every == 0 the binning already in tile_start is used (it must
+ * run from 0 to n, else PIC_E_INVALID; particles that left their tile since
+ * take the stray path), and with tile_start == NULL as well the particles are
+ * processed without tiles.
  * On return J holds the current of the last step.  diag (optional, device
  * double[nsteps][5]) receives pic_reduce's five values after every step.
  * Synchronises the stream at the end to read the device error word. */
@@ -174,7 +176,8 @@ PIC_API pic_status pic_step(const pic_grid *grid, pic_species *sp, pic_fields *f
  * part: transpose of the deposit (a gather of the current adjoint), of the
  * position update, of the Boris push and of the gather (a scatter).
  * tile_start (int32[ntiles+1], or NULL): a binning of state_n's particles
- * from pic_sort_tiles or pic_step; with it the particle part runs one
+ * from pic_sort_tiles or pic_step (running from 0 to n, else
+ * PIC_E_INVALID); with it the particle part runs one
  * workgroup per tile with the fields, the field adjoint and the scatter
  * accumulators in LDS, without it one thread per particle on global memory.
  * The result does not depend on the choice beyond rounding. */

@@ -930,6 +930,21 @@ pic_status pic_yee(const pic_grid *grid, pic_fields *f, const pic_source *src, i
     return yee_step<float>(grid, gi, fptrs<float>(f), src, step, false, st);
 }
 
+// A binning handed in by the caller must at least span the particles: its
+// first entry 0 and its last n (a binning of other particles, or an array
+// never filled, would leave particles unprocessed).  Reads two ints.
+pic_status check_binning(const GridInfo &gi, const int32_t *tile_start, int64_t n, hipStream_t st)
+{
+    int32_t ends[2] = {-1, -1};
+    PIC_HIP(hipMemcpyAsync(&ends[0], tile_start, sizeof(int32_t), hipMemcpyDeviceToHost, st));
+    PIC_HIP(hipMemcpyAsync(&ends[1], tile_start + gi.ntiles, sizeof(int32_t), hipMemcpyDeviceToHost, st));
+    PIC_HIP(hipStreamSynchronize(st));
+    if (ends[0] != 0 || ends[1] != n)
+        return fail(PIC_E_INVALID, "tile_start is not a binning of these particles (it must run from 0 to n); "
+                                   "sort them first");
+    return PIC_OK;
+}
+
 pic_status pic_step(const pic_grid *grid, pic_species *sp, pic_fields *f, const pic_source *src, int64_t step0,
                     int32_t nsteps, int32_t sort_every, int32_t *tile_start, void *ws, size_t ws_bytes,
                     double *diag, void *stream)
@@ -949,6 +964,8 @@ pic_status pic_step(const pic_grid *grid, pic_species *sp, pic_fields *f, const 
             return fail(PIC_E_INVALID, "sorting needs a tile_start array");
         PIC_TRY(check_ws(gi, sp->n, ws, ws_bytes, L));
         hipStream_t st = static_cast<hipStream_t>(stream);
+        if (sort_every == 0 && tile_start && sp->n > 0 && nsteps > 0)
+            PIC_TRY(check_binning(gi, tile_start, sp->n, st));
         if (gi.dtype == PIC_F64)
             return step_t<double>(grid, gi, sp, f, src, step0, nsteps, sort_every, tile_start, ws, L, diag, st);
         return step_t<float>(grid, gi, sp, f, src, step0, nsteps, sort_every, tile_start, ws, L, diag, st);
@@ -975,6 +992,8 @@ pic_status pic_step_adjoint(const pic_grid *grid, const pic_species *state_n, co
                 return fail(PIC_E_INVALID, "NULL adjoint array");
         PIC_TRY(check_ws(gi, state_n->n, ws, ws_bytes, L));
         hipStream_t st = static_cast<hipStream_t>(stream);
+        if (tile_start && state_n->n > 0)
+            PIC_TRY(check_binning(gi, tile_start, state_n->n, st));
         if (gi.dtype == PIC_F64)
             return adjoint_t<double>(grid, gi, state_n, fields_n, tile_start, src, step, lam, dA, ws, L, st);
         return adjoint_t<float>(grid, gi, state_n, fields_n, tile_start, src, step, lam, dA, ws, L, st);

@@ -278,6 +278,20 @@ def test_stale_binning_uses_the_fallback_path_correctly():
         assert rel_l2(_cpu(getattr(gf, name)), getattr(of, name)) < F64_TOL, name
 
 
+def test_step_rejects_a_binning_that_does_not_span_the_particles():
+    """sort_every = 0 with a tile_start that was never filled (all zeros)
+    would leave every tile empty: the call fails before any launch."""
+    g = _grid()
+    sp, f = dev(random_species(g, 1000, 91)), dev(random_fields(g, 92))
+    E0 = f.E.clone()
+    ts = torch.zeros(_lib.pic_tile_count(g, "f64") + 1, dtype=torch.int32, device="cuda")
+    ws = _lib.workspace(g, "f64", sp.n)
+    with pytest.raises(_lib.PicError) as ei:
+        _lib.pic_step(g, sp, f, None, 0, 1, 0, ts, ws)
+    assert ei.value.name == "PIC_E_INVALID"
+    assert torch.equal(f.E, E0)
+
+
 def test_f32_split_precision_one_step_bounds():
     """FP32 fields/momenta with int32 cell + FP32 offset: rel-L2 of E, B, J
     <= 1e-5 after one step against the oracle started from the same FP32
