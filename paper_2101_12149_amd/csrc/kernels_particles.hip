@@ -485,6 +485,36 @@ __device__ __attribute__((always_inline)) inline void xrow_add(double *row, cons
     }
 }
 
+// The same row on global memory: add(k, v) adds v to node k of this lane's
+// window (the lane's own, wrapped, node indices); the run's last lane writes
+// the nodes past the run itself.
+template <int NT, typename V, typename AddFn>
+__device__ __attribute__((always_inline)) inline void xrow_apply(const V *r, const XRun &xr, AddFn &&add)
+{
+    V e[NT];
+    e[NT - 1] = r[NT - 1];
+#pragma unroll
+    for (int k = NT - 2; k >= 0; --k) {
+        const V snd = xr.send ? e[k + 1] : V(0);
+        e[k] = r[k] + dpp_shift<1>(snd);
+    }
+    add(0, e[0]);
+    if (xr.last) {
+#pragma unroll
+        for (int k = 1; k < NT; ++k)
+            add(k, e[k]);
+    }
+}
+
+// run key of a window starting at the unwrapped global node st (0 where the
+// grid is too large to encode, which turns the sharing off)
+__device__ inline int xrun_key_global(const int *st, const int *n)
+{
+    const long long k = 1 + (long long)(st[0] + 8) +
+                        (long long)(n[0] + 16) * ((st[1] + 8) + (long long)(n[1] + 16) * (st[2] + 8));
+    return k < (1LL << 31) ? (int)k : 0;
+}
+
 // Esirkepov deposit of a particle that stays in its cell, into the LDS
 // current tile with lane-shared rows along x: esk_scatter_still's values,
 // formed and summed along the run in the working precision and added to the
@@ -896,22 +926,19 @@ __device__ __attribute__((always_inline)) inline void gather_transpose(const T *
                 const T val = F[rowo + xo[i]];
                 ax += wx[i] * val;
                 adx += dx[i] * val;
-                if (LOCAL)
-                    r[i] = wx[i] * wyz;
-                else
-                    gatomic_add(Lglob + rowo + xo[i], wx[i] * wyz);
+                r[i] = wx[i] * wyz;
             }
             if (LOCAL)
                 xrow_add<NW>(sL + rowo + xo[0], r, xr);   // LDS x offsets are consecutive
+            else
+                xrow_apply<NW>(r, xr, [&](int i, T v) { gatomic_add(Lglob + rowo + xo[i], v); });
             gx += adx * wy[j] * wz[k];
             gy += ax * dy[j] * wz[k];
             gz += ax * wy[j] * dz[k];
-            if (LOCAL) {
-                // finish the row here (the compiler would otherwise issue
-                // every row's loads first and park them in scratch memory)
-                asm volatile("" : "+v"(gx), "+v"(gy), "+v"(gz));
-                __builtin_amdgcn_sched_barrier(0);
-            }
+            // finish the row here (the compiler would otherwise issue every
+            // row's loads first and park them in scratch memory)
+            asm volatile("" : "+v"(gx), "+v"(gy), "+v"(gz));
+            __builtin_amdgcn_sched_barrier(0);
         }
     lxa[0] += vb * gx;
     lxa[1] += vb * gy;
@@ -1037,14 +1064,16 @@ __device__ __attribute__((always_inline)) inline void adjoint_push_particle(cons
 // pass 2 for one particle: components of group G (0: E, 1: B, 2: both).
 // fsrc.c[m] is component m (E_x..E_z, B_x..B_z); the LDS accumulators hold
 // the group's components at sL + (m - 3 G) * rfvol.
-// xr[k]: the lane runs of the group's k-th component (LOCAL only)
+// x0..x2: the lane runs of the group's three components (the default: a
+// lane on its own)
 template <typename T, int O, bool LOCAL, int G>
 __device__ __attribute__((always_inline)) inline void adjoint_scatter_particle(const PConst<T> &pc, const AdjPtrs<T> &ap,
                                                 const FieldSrc<T> &fsrc, int64_t p, const int *c, const T *f,
                                                 const int *l, int lo_f, const int *sf, double *sL, int rfvol,
-                                                const XRun *xr = nullptr)
+                                                const XRun x0 = XRun{false, true, false, 0, 1},
+                                                const XRun x1 = XRun{false, true, false, 0, 1},
+                                                const XRun x2 = XRun{false, true, false, 0, 1})
 {
-    const XRun none{false, true, false, 0, 1};
     constexpr int NW = Shape<O, T>::NW;
     AxisW<O, T> aw[3];
     int on[3][NW], os[3][NW];
@@ -1058,19 +1087,19 @@ __device__ __attribute__((always_inline)) inline void adjoint_scatter_particle(c
     // staggering per component: E_x(s,n,n) E_y(n,s,n) E_z(n,n,s) B_x(n,s,s) B_y(s,n,s) B_z(s,s,n)
     if (G != 1) {
         gather_transpose<O, T, LOCAL, 1, 0, 0>(fsrc.c[0], ap.lE[0], sL + (0 - b) * rfvol, ap.vb[0][p], aw, dn, ds, on,
-                                               os, lxa, LOCAL ? xr[0] : none);
+                                               os, lxa, x0);
         gather_transpose<O, T, LOCAL, 0, 1, 0>(fsrc.c[1], ap.lE[1], sL + (1 - b) * rfvol, ap.vb[1][p], aw, dn, ds, on,
-                                               os, lxa, LOCAL ? xr[1] : none);
+                                               os, lxa, x1);
         gather_transpose<O, T, LOCAL, 0, 0, 1>(fsrc.c[2], ap.lE[2], sL + (2 - b) * rfvol, ap.vb[2][p], aw, dn, ds, on,
-                                               os, lxa, LOCAL ? xr[2] : none);
+                                               os, lxa, x2);
     }
     if (G != 0) {
         gather_transpose<O, T, LOCAL, 0, 1, 1>(fsrc.c[3], ap.lB[0], sL + (3 - b) * rfvol, ap.vb[3][p], aw, dn, ds, on,
-                                               os, lxa, LOCAL ? xr[0] : none);
+                                               os, lxa, x0);
         gather_transpose<O, T, LOCAL, 1, 0, 1>(fsrc.c[4], ap.lB[1], sL + (4 - b) * rfvol, ap.vb[4][p], aw, dn, ds, on,
-                                               os, lxa, LOCAL ? xr[1] : none);
+                                               os, lxa, x1);
         gather_transpose<O, T, LOCAL, 1, 1, 0>(fsrc.c[5], ap.lB[2], sL + (5 - b) * rfvol, ap.vb[5][p], aw, dn, ds, on,
-                                               os, lxa, LOCAL ? xr[2] : none);
+                                               os, lxa, x2);
     }
 #pragma unroll
     for (int d = 0; d < 3; ++d)
@@ -1109,18 +1138,36 @@ __global__ void __launch_bounds__(256) k_adjoint_push(PConst<T> pc, PArr<T> sp, 
     adjoint_push_particle<T, O, false>(pc, sp, ap, global_fields(fp), ap.hat, p, c, f, u, z3, 0, z3, 0, z3, err);
 }
 
-template <typename T, int O>
+template <typename T, int O, int G>
 __global__ void __launch_bounds__(256) k_adjoint_scatter(PConst<T> pc, PArr<T> sp, FieldPtrs<T> fp, AdjPtrs<T> ap)
 {
+    // group G of components; consecutive particles of a binned order sit in
+    // neighbouring cells, so their rows are shared as in the tiled pass
     const int64_t p = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    if (p >= sp.n)
-        return;
-    int c[3];
-    T f[3];
-    if (!load_position(sp, p, pc.n, c, f))
-        return;
-    const int z3[3] = {0, 0, 0};
-    adjoint_scatter_particle<T, O, false, 2>(pc, ap, global_fields(fp), p, c, f, z3, 0, z3, nullptr, 0);
+    int c[3] = {0, 0, 0};
+    T f[3] = {T(0), T(0), T(0)};
+    int key[3] = {0, 0, 0};
+    const bool act = p < sp.n && load_position(sp, p, pc.n, c, f);
+    if (act) {
+        constexpr int SX[6] = {1, 0, 0, 0, 1, 1}, SY[6] = {0, 1, 0, 1, 0, 1}, SZ[6] = {0, 0, 1, 1, 1, 0};
+        int bs[3];
+#pragma unroll
+        for (int d = 0; d < 3; ++d)
+            bs[d] = f[d] >= T(0.5) ? Shape<O, T>::NB : Shape<O, T>::NB - 1;
+#pragma unroll
+        for (int k = 0; k < 3; ++k) {
+            const int m = 3 * G + k;
+            const int st[3] = {c[0] + (SX[m] ? bs[0] : Shape<O, T>::NB), c[1] + (SY[m] ? bs[1] : Shape<O, T>::NB),
+                               c[2] + (SZ[m] ? bs[2] : Shape<O, T>::NB)};
+            key[k] = xrun_key_global(st, pc.n);
+        }
+    }
+    const XRun xr[3] = {xrun(key[0]), xrun(key[1]), xrun(key[2])};   // converged
+    if (act) {
+        const int z3[3] = {0, 0, 0};
+        adjoint_scatter_particle<T, O, false, G>(pc, ap, global_fields(fp), p, c, f, z3, 0, z3, nullptr, 0, xr[0],
+                                                 xr[1], xr[2]);
+    }
 }
 
 // ---------------------------------------------------------------------------
@@ -1306,7 +1353,8 @@ __global__ void __launch_bounds__(AdjThreads<T>::value) k_adjoint_scatter_tile(P
         }
         const XRun xr[3] = {xrun(key[0]), xrun(key[1]), xrun(key[2])};   // converged
         if (act)
-            adjoint_scatter_particle<T, O, true, G>(pc, ap, lf, ts.ps + j, c, f, l, tg.lo_f, sf, sL, rfvol, xr);
+            adjoint_scatter_particle<T, O, true, G>(pc, ap, lf, ts.ps + j, c, f, l, tg.lo_f, sf, sL, rfvol, xr[0],
+                                                    xr[1], xr[2]);
     }
     __syncthreads();
     for (int r = tid; r < 3 * rfvol; r += nth) {
@@ -1467,10 +1515,12 @@ hipError_t launch_adjoint_particles(int order, const PConst<T> &pc, const PArr<T
     const unsigned nb = nblk(sp.n, 256);
     if (order == 1) {
         hipLaunchKernelGGL((k_adjoint_push<T, 1>), dim3(nb), dim3(256), 0, st, pc, sp, f, ap, err);
-        hipLaunchKernelGGL((k_adjoint_scatter<T, 1>), dim3(nb), dim3(256), 0, st, pc, sp, f, ap);
+        hipLaunchKernelGGL((k_adjoint_scatter<T, 1, 0>), dim3(nb), dim3(256), 0, st, pc, sp, f, ap);
+        hipLaunchKernelGGL((k_adjoint_scatter<T, 1, 1>), dim3(nb), dim3(256), 0, st, pc, sp, f, ap);
     } else {
         hipLaunchKernelGGL((k_adjoint_push<T, 3>), dim3(nb), dim3(256), 0, st, pc, sp, f, ap, err);
-        hipLaunchKernelGGL((k_adjoint_scatter<T, 3>), dim3(nb), dim3(256), 0, st, pc, sp, f, ap);
+        hipLaunchKernelGGL((k_adjoint_scatter<T, 3, 0>), dim3(nb), dim3(256), 0, st, pc, sp, f, ap);
+        hipLaunchKernelGGL((k_adjoint_scatter<T, 3, 1>), dim3(nb), dim3(256), 0, st, pc, sp, f, ap);
     }
     return hipGetLastError();
 }
