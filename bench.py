@@ -131,6 +131,59 @@ def cpu_baseline():
                       f"after 1 warm-up step ({dt:.1f} s)"}
 
 
+def stray_fraction(w, ts):
+    """Fraction of the particles whose cell lies outside their tile's LDS
+    region (tile + slack) under the binning ts: the particles the stray
+    kernel takes."""
+    import torch
+    from paper_2101_12149_amd import _lib
+    g = w.grid
+    info = _lib.tile_geometry(g, w.dtype)
+    t, nt, slack = info["tile"], info["ntiles_xyz"], info["slack"]
+    n = w.species.n
+    idx = torch.arange(n, device=ts.device, dtype=torch.int32)
+    tile = torch.searchsorted(ts[1:].contiguous(), idx, right=True)
+    origin = [(tile % nt[0]) * t[0], ((tile // nt[0]) % nt[1]) * t[1], (tile // (nt[0] * nt[1])) * t[2]]
+    outside = torch.zeros(n, dtype=torch.bool, device=ts.device)
+    for d in range(3):
+        v = w.species.cell[d].long() - origin[d]
+        v = torch.where(v < -slack, v + g.n[d], torch.where(v >= t[d] + slack, v - g.n[d], v))
+        outside |= (v < -slack) | (v >= t[d] + slack)
+    return float(outside.float().mean())
+
+
+def sort_sweep(args):
+    """Sort interval x tile size on one workload: throughput, the sort, tile
+    and stray kernel times per step, and the fraction of stray particles in
+    the last step of a sort cycle."""
+    import torch
+    from paper_2101_12149_amd import workloads as wl
+    rows = []
+    for tile in [tuple(int(x) for x in t.split(",")) for t in args.sweep_tiles.split(";")]:
+        for se in [int(x) for x in args.sweep_intervals.split(",")]:
+            w = wl.named(args.workload, device="cuda")
+            w.grid.tile = tile
+            fw = run_forward(w, args.steps, args.warmup, se, f"tile {tile} sort every {se}")
+            k = fw["kernels"]
+            per = {c: round(k[c][0] / args.steps, 3) for c in ("sort", "particles", "strays", "yee", "reduce")}
+            # strays at the end of a sort cycle: sort, then se - 1 steps on that binning
+            from paper_2101_12149_amd import _lib
+            ts = fw["ts"]
+            _lib.pic_sort_tiles(w.grid, w.species, ts, fw["ws"])
+            if se > 1:
+                _lib.pic_step(w.grid, w.species, w.fields, None, args.warmup + args.steps, se - 1, 0, ts, fw["ws"])
+            torch.cuda.synchronize()
+            rows.append({"tile": list(tile), "sort_every": se,
+                         "particle_steps_per_s": w.species.n * args.steps / (fw["ms"] * 1e-3),
+                         "ms_per_step": round(fw["ms"] / args.steps, 3), "kernels_ms_per_step": per,
+                         "stray_fraction_cycle_end": round(stray_fraction(w, ts), 6)})
+            log(json.dumps(rows[-1]))
+            del w, fw
+            torch.cuda.empty_cache()
+    print(json.dumps({"sweep": "sort interval x tile", "workload": args.workload, "steps": args.steps,
+                      "warmup": args.warmup, "rows": rows}))
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -145,10 +198,14 @@ def main():
     ap.add_argument("--slack", type=int, default=-1)
     ap.add_argument("--calib-copy", action="store_true",
                     help="copy 1 GiB device-to-device first (HBM counter calibration)")
+    ap.add_argument("--sort-sweep", action="store_true",
+                    help="sweep the sort interval and the tile size instead of the benchmark line")
+    ap.add_argument("--sweep-intervals", default="1,2,4,8,16")
+    ap.add_argument("--sweep-tiles", default="8,8,8;8,8,4;4,4,4")
     args = ap.parse_args()
     if args.gpus != 1:
-        print(json.dumps({"error": "this build runs on one GPU; --gpus must be 1 "
-                                   "(multi-GPU sharding is described in DESIGN.md, not built)"}))
+        print(json.dumps({"error": "this library runs on one GPU; --gpus must be 1 "
+                                   "(the multi-GPU sharding is a design, not built)"}))
         sys.exit(2)
 
     import torch
@@ -156,6 +213,10 @@ def main():
     from paper_2101_12149_amd import workloads as wl
     _lib.load()
     torch.cuda.set_device(0)
+
+    if args.sort_sweep:
+        sort_sweep(args)
+        return
 
     if args.calib_copy:
         a = torch.ones(1 << 28, dtype=torch.float32, device="cuda")

@@ -117,6 +117,13 @@ PIC_API size_t pic_workspace_bytes(const pic_grid *grid, int64_t n_particles);
  * edge starts at 8 and is halved until the LDS regions fit one workgroup. */
 PIC_API int64_t pic_tile_count(const pic_grid *grid);
 
+/* The tile edge in cells per direction (tile[3]) and the slack in cells
+ * (*slack) that the library uses for this grid, resolving the automatic
+ * choices of pic_grid.tile and pic_grid.slack.  Tile t of tile_start covers
+ * the cells tile[d] * (t_x, t_y, t_z) onwards, t = t_x + nx (t_y + ny t_z)
+ * with n[d] / tile[d] tiles per direction.  Host-only. */
+PIC_API pic_status pic_tile_shape(const pic_grid *grid, int32_t *tile, int32_t *slack);
+
 /* Particle binning and sorting by counting sort (Sec. 3.4.2: binning computes
  * a permutation that assigns particles to bins; sorting reorders the data).
  * Bins are cells grouped by tile: tiles of grid->tile cells in lexicographic

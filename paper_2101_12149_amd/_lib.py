@@ -49,7 +49,7 @@ class pic_adjoint(C.Structure):
     _fields_ = [("lx", C.c_void_p * 3), ("lu", C.c_void_p * 3), ("lE", C.c_void_p * 3), ("lB", C.c_void_p * 3)]
 
 
-EXPORTS = ("pic_workspace_bytes", "pic_tile_count", "pic_sort_tiles", "pic_gather", "pic_push", "pic_deposit",
+EXPORTS = ("pic_workspace_bytes", "pic_tile_count", "pic_tile_shape", "pic_sort_tiles", "pic_gather", "pic_push", "pic_deposit",
            "pic_yee", "pic_step", "pic_step_adjoint", "pic_reduce", "pic_energy_loss", "pic_timing", "pic_last_error")
 TIMING_CATEGORIES = ("sort", "particles", "yee", "reduce", "adjoint_fields", "adjoint_particles", "strays")
 
@@ -72,6 +72,8 @@ def load():
             lib.pic_workspace_bytes.argtypes = [P(pic_grid), C.c_int64]
             lib.pic_tile_count.restype = C.c_int64
             lib.pic_tile_count.argtypes = [P(pic_grid)]
+            lib.pic_tile_shape.restype = C.c_int
+            lib.pic_tile_shape.argtypes = [P(pic_grid), C.c_void_p, C.c_void_p]
             lib.pic_sort_tiles.restype = C.c_int
             lib.pic_sort_tiles.argtypes = [P(pic_grid), P(pic_species), C.c_void_p, C.c_void_p, C.c_void_p,
                                            C.c_size_t, C.c_void_p]
@@ -213,6 +215,21 @@ def pic_workspace_bytes(grid, dtype, n_particles):
 def pic_tile_count(grid, dtype):
     g = make_grid(grid, dtype)
     return int(load().pic_tile_count(C.byref(g)))
+
+
+def pic_tile_shape(grid, dtype):
+    """(tile edge per direction, slack) the library uses for this grid."""
+    g = make_grid(grid, dtype)
+    t = (C.c_int32 * 3)()
+    sl = C.c_int32()
+    _check(load().pic_tile_shape(C.byref(g), C.cast(t, C.c_void_p), C.cast(C.pointer(sl), C.c_void_p)))
+    return tuple(t), sl.value
+
+
+def tile_geometry(grid, dtype):
+    """Tile edges, tiles per direction and slack as a dict."""
+    t, sl = pic_tile_shape(grid, dtype)
+    return {"tile": t, "ntiles_xyz": tuple(int(grid.n[d]) // t[d] for d in range(3)), "slack": sl}
 
 
 def workspace(grid, dtype, n_particles, device="cuda"):

@@ -809,6 +809,18 @@ int64_t pic_tile_count(const pic_grid *grid)
     return gi.ntiles;
 }
 
+pic_status pic_tile_shape(const pic_grid *grid, int32_t *tile, int32_t *slack)
+{
+    GridInfo gi;
+    PIC_TRY(check_grid(grid, gi));
+    if (!tile || !slack)
+        return fail(PIC_E_INVALID, "tile and slack must not be NULL");
+    for (int d = 0; d < 3; ++d)
+        tile[d] = gi.tg.t[d];
+    *slack = gi.tg.slack;
+    return PIC_OK;
+}
+
 pic_status pic_sort_tiles(const pic_grid *grid, pic_species *sp, int32_t *tile_start, int32_t *perm, void *ws,
                           size_t ws_bytes, void *stream)
 {

@@ -50,6 +50,25 @@ def test_workspace_bytes_grows_with_particles_and_rejects_bad_grids():
     assert _lib.pic_tile_count(_grid(tile=(8, 8, 8)), "f64") in (8, 16, 32, 64)
 
 
+def test_tile_shape_resolves_the_automatic_choices():
+    """The automatic tile is the largest divisor of n not above 8 with one
+    cell of slack; while the LDS regions do not fit, the largest tile edge
+    halves before the slack is dropped; a fixed tile that cannot hold the
+    slack keeps the tile and drops the slack."""
+    big = wl.plasma_grid((256, 256, 256), 3)
+    assert _lib.pic_tile_shape(big, "f32") == ((8, 8, 8), 1)
+    assert _lib.pic_tile_shape(big, "f64") == ((8, 8, 4), 1)
+    assert _lib.pic_tile_shape(wl.plasma_grid((12, 16, 20), 3), "f32") == ((6, 8, 5), 1)
+    fixed = wl.plasma_grid((16, 16, 16), 3)
+    fixed.tile = (8, 8, 8)
+    assert _lib.pic_tile_shape(fixed, "f64") == ((8, 8, 8), 0)
+    for g, dt in ((big, "f32"), (big, "f64"), (fixed, "f64")):
+        t, _ = _lib.pic_tile_shape(g, dt)
+        assert _lib.pic_tile_count(g, dt) == (g.n[0] // t[0]) * (g.n[1] // t[1]) * (g.n[2] // t[2])
+    with pytest.raises(_lib.PicError):
+        _lib.pic_tile_shape(_grid(order=2), "f64")
+
+
 def _raw_call_step(grid, dtype="f64"):
     lib = _lib.load()
     g = _lib.make_grid(grid, dtype)
