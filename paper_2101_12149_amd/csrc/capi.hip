@@ -165,14 +165,14 @@ void region_extents(int order, TileGeo &tg)
 }
 
 // LDS of the tiled adjoint: its first pass holds E, B with the gather halo
-// and hatE with the deposit halo, its second the FP64 accumulators and the
-// fields of one group of three components
+// and hatE with the deposit halo, its second the FP64 accumulators of the
+// six field adjoints
 size_t adj_lds_for(const GridInfo &gi, const TileGeo &a)
 {
     const size_t rf = (size_t)a.rf[0] * a.rf[1] * a.rf[2];
     const size_t rj = (size_t)a.rj[0] * a.rj[1] * a.rj[2];
     const size_t push = 6 * rf * gi.tsize + 3 * rj * gi.tsize;
-    const size_t scatter = 3 * rf * (sizeof(double) + gi.tsize);
+    const size_t scatter = 6 * rf * sizeof(double);
     return push > scatter ? push : scatter;
 }
 

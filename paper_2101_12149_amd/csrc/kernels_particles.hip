@@ -892,15 +892,15 @@ struct AdjPtrs {
     T *vb[6];          // per-particle adjoints of the gathered E and B
 };
 
-// Gather transpose of one field component with staggering (SX, SY, SZ):
-// scatter S * vb into the component's adjoint (FP64 LDS accumulators, rows
-// along x shared between lanes as in the forward deposit, or global atomics)
-// and add vb * grad(gathered value) to the position adjoint.
-template <int O, typename T, bool LOCAL, int SX, int SY, int SZ>
-__device__ __attribute__((always_inline)) inline void gather_transpose(const T *F, T *Lglob, double *sL, T vb, const AxisW<O, T> *aw,
-                                        const T (*dn)[Shape<O, T>::NW], const T (*ds)[Shape<O, T>::NW],
-                                        const int (*on)[Shape<O, T>::NW], const int (*os)[Shape<O, T>::NW], T *lxa,
-                                        const XRun &xr)
+// Gather transpose of one field component with staggering (SX, SY, SZ), in
+// two parts.  gather_grad adds vb * grad(gathered value) to the position
+// adjoint (it reads the field window); scatter_component scatters S * vb
+// into the component's adjoint (FP64 LDS accumulators, rows along x shared
+// between lanes as in the forward deposit, or global atomics).
+template <int O, typename T, int SX, int SY, int SZ>
+__device__ __attribute__((always_inline)) inline void gather_grad(const T *F, T vb, const AxisW<O, T> *aw,
+                                   const T (*dn)[Shape<O, T>::NW], const T (*ds)[Shape<O, T>::NW],
+                                   const int (*on)[Shape<O, T>::NW], const int (*os)[Shape<O, T>::NW], T *lxa)
 {
     constexpr int NW = Shape<O, T>::NW;
     const T *wx = SX ? aw[0].ws : aw[0].wn;
@@ -918,20 +918,13 @@ __device__ __attribute__((always_inline)) inline void gather_transpose(const T *
 #pragma unroll
         for (int j = 0; j < NW; ++j) {
             const int rowo = yo[j] + zo[k];
-            const T wyz = wy[j] * wz[k] * vb;
             T ax = T(0), adx = T(0);
-            T r[NW];
 #pragma unroll
             for (int i = 0; i < NW; ++i) {
                 const T val = F[rowo + xo[i]];
                 ax += wx[i] * val;
                 adx += dx[i] * val;
-                r[i] = wx[i] * wyz;
             }
-            if (LOCAL)
-                xrow_add<NW>(sL + rowo + xo[0], r, xr);   // LDS x offsets are consecutive
-            else
-                xrow_apply<NW>(r, xr, [&](int i, T v) { gatomic_add(Lglob + rowo + xo[i], v); });
             gx += adx * wy[j] * wz[k];
             gy += ax * dy[j] * wz[k];
             gz += ax * wy[j] * dz[k];
@@ -944,6 +937,55 @@ __device__ __attribute__((always_inline)) inline void gather_transpose(const T *
     lxa[1] += vb * gy;
     lxa[2] += vb * gz;
 }
+
+template <int O, typename T, bool LOCAL, int SX, int SY, int SZ>
+__device__ __attribute__((always_inline)) inline void scatter_component(T *Lglob, double *sL, T vb, const AxisW<O, T> *aw,
+                                         const int (*on)[Shape<O, T>::NW], const int (*os)[Shape<O, T>::NW],
+                                         const XRun &xr)
+{
+    constexpr int NW = Shape<O, T>::NW;
+    const T *wx = SX ? aw[0].ws : aw[0].wn;
+    const T *wy = SY ? aw[1].ws : aw[1].wn;
+    const T *wz = SZ ? aw[2].ws : aw[2].wn;
+    const int *xo = SX ? os[0] : on[0];
+    const int *yo = SY ? os[1] : on[1];
+    const int *zo = SZ ? os[2] : on[2];
+#pragma unroll
+    for (int k = 0; k < NW; ++k)
+#pragma unroll
+        for (int j = 0; j < NW; ++j) {
+            const int rowo = yo[j] + zo[k];
+            const T wyz = wy[j] * wz[k] * vb;
+            T r[NW];
+#pragma unroll
+            for (int i = 0; i < NW; ++i)
+                r[i] = wx[i] * wyz;
+            if (LOCAL)
+                xrow_add<NW>(sL + rowo + xo[0], r, xr);   // LDS x offsets are consecutive
+            else
+                xrow_apply<NW>(r, xr, [&](int i, T v) { gatomic_add(Lglob + rowo + xo[i], v); });
+        }
+}
+
+// lane runs packed in an int: a1 | last << 1 | send << 2 | d << 3 | len << 6
+__device__ inline int xrun_pack(const XRun &r)
+{
+    return (r.a1 ? 1 : 0) | (r.last ? 2 : 0) | (r.send ? 4 : 0) | (r.d << 3) | (r.len << 6);
+}
+
+__device__ inline XRun xrun_unpack(int v)
+{
+    XRun r;
+    r.a1 = (v & 1) != 0;
+    r.last = (v & 2) != 0;
+    r.send = (v & 4) != 0;
+    r.d = (v >> 3) & 7;
+    r.len = (v >> 6) & 7;
+    return r;
+}
+
+// a lane on its own: no neighbour, the last of its run
+constexpr int XRUN_ALONE = 2 | (1 << 6);
 
 template <typename T, int O, bool LOCAL>
 __device__ __attribute__((always_inline)) inline void adjoint_offsets(const PConst<T> &pc, const int *c, const T *f, const int *l, int lo_f,
@@ -1036,14 +1078,14 @@ __device__ __attribute__((always_inline)) inline void adjoint_push_particle(cons
     T u1[3];
     boris(pc.h, pc.inv_c2, u, E, B, u1, tp);
     const T ig = T(1) / sqrt(T(1) + (u1[0] * u1[0] + u1[1] * u1[1] + u1[2] * u1[2]) * pc.inv_c2);
-    T lxb[3], v[3];
+    T lxb[3], v[3], lxa[3];
     T uv = T(0);
 #pragma unroll
     for (int d = 0; d < 3; ++d) {
         lxb[d] = ap.lx[d][p] + g1[d];   // dL/dx^{n+1} incl. the deposit
         v[d] = pc.dtd[d] * lxb[d];
         uv += u1[d] * v[d];
-        ap.lx[d][p] = g0[d] + lxb[d];   // x^{n+1} = x^n + disp; the gather term follows in pass 2
+        lxa[d] = g0[d] + lxb[d];   // x^{n+1} = x^n + disp
     }
     // d(u/gamma)/du = I/gamma - u u^T / (gamma^3 c^2)
     T ub[3];
@@ -1059,51 +1101,88 @@ __device__ __attribute__((always_inline)) inline void adjoint_push_particle(cons
         ap.vb[d][p] = Eb[d];
         ap.vb[3 + d][p] = Bb[d];
     }
+    // the position part of the gather transpose: vb . grad(gathered fields).
+    // The weights and offsets are evaluated again; the register operands keep
+    // the compiler from carrying those of the first gather across the
+    // deposit transpose.
+    {
+        T fr[3] = {f[0], f[1], f[2]};
+        int cr[3] = {c[0], c[1], c[2]}, lr[3] = {l[0], l[1], l[2]};
+        asm volatile("" : "+v"(fr[0]), "+v"(fr[1]), "+v"(fr[2]));
+        asm volatile("" : "+v"(cr[0]), "+v"(cr[1]), "+v"(cr[2]), "+v"(lr[0]), "+v"(lr[1]), "+v"(lr[2]));
+        AxisW<O, T> aw[3];
+        int on[3][NW], os[3][NW];
+        adjoint_offsets<T, O, LOCAL>(pc, cr, fr, lr, lo_f, sf, aw, on, os);
+        T dn[3][NW], ds[3][NW];
+#pragma unroll
+        for (int d = 0; d < 3; ++d)
+            axis_dweights<O>(fr[d], dn[d], ds[d]);
+        // staggering: E_x(s,n,n) E_y(n,s,n) E_z(n,n,s) B_x(n,s,s) B_y(s,n,s) B_z(s,s,n)
+        gather_grad<O, T, 1, 0, 0>(fsrc.c[0], Eb[0], aw, dn, ds, on, os, lxa);
+        gather_grad<O, T, 0, 1, 0>(fsrc.c[1], Eb[1], aw, dn, ds, on, os, lxa);
+        gather_grad<O, T, 0, 0, 1>(fsrc.c[2], Eb[2], aw, dn, ds, on, os, lxa);
+        gather_grad<O, T, 0, 1, 1>(fsrc.c[3], Bb[0], aw, dn, ds, on, os, lxa);
+        gather_grad<O, T, 1, 0, 1>(fsrc.c[4], Bb[1], aw, dn, ds, on, os, lxa);
+        gather_grad<O, T, 1, 1, 0>(fsrc.c[5], Bb[2], aw, dn, ds, on, os, lxa);
+    }
+#pragma unroll
+    for (int d = 0; d < 3; ++d)
+        ap.lx[d][p] = lxa[d];
 }
 
-// pass 2 for one particle: components of group G (0: E, 1: B, 2: both).
-// fsrc.c[m] is component m (E_x..E_z, B_x..B_z); the LDS accumulators hold
-// the group's components at sL + (m - 3 G) * rfvol.
-// x0..x2: the lane runs of the group's three components (the default: a
-// lane on its own)
+// pass 2 for one particle: the scatter of the gather transpose for the
+// components of group G (0: E, 1: B, 2: both).  The LDS accumulators hold the
+// group's components at sL + (m - 3 G0) * rfvol (G0 = 1 for group B alone);
+// runs[k] are the packed lane runs of the group's k-th component (null: none).
 template <typename T, int O, bool LOCAL, int G>
-__device__ __attribute__((always_inline)) inline void adjoint_scatter_particle(const PConst<T> &pc, const AdjPtrs<T> &ap,
-                                                const FieldSrc<T> &fsrc, int64_t p, const int *c, const T *f,
-                                                const int *l, int lo_f, const int *sf, double *sL, int rfvol,
-                                                const XRun x0 = XRun{false, true, false, 0, 1},
-                                                const XRun x1 = XRun{false, true, false, 0, 1},
-                                                const XRun x2 = XRun{false, true, false, 0, 1})
+__device__ __attribute__((always_inline)) inline void adjoint_scatter_particle(const PConst<T> &pc, const AdjPtrs<T> &ap, int64_t p,
+                                                const int *c, const T *f, const int *l, int lo_f,
+                                                const int *sf, double *sL, int rfvol, const int *runs)
 {
     constexpr int NW = Shape<O, T>::NW;
     AxisW<O, T> aw[3];
     int on[3][NW], os[3][NW];
     adjoint_offsets<T, O, LOCAL>(pc, c, f, l, lo_f, sf, aw, on, os);
-    T dn[3][NW], ds[3][NW];
-#pragma unroll
-    for (int d = 0; d < 3; ++d)
-        axis_dweights<O>(f[d], dn[d], ds[d]);
-    T lxa[3] = {ap.lx[0][p], ap.lx[1][p], ap.lx[2][p]};
     constexpr int b = G == 1 ? 3 : 0;
-    // staggering per component: E_x(s,n,n) E_y(n,s,n) E_z(n,n,s) B_x(n,s,s) B_y(s,n,s) B_z(s,s,n)
+    auto run = [&](int k) { return xrun_unpack(runs ? runs[k] : XRUN_ALONE); };
+    // staggering: E_x(s,n,n) E_y(n,s,n) E_z(n,n,s) B_x(n,s,s) B_y(s,n,s) B_z(s,s,n)
     if (G != 1) {
-        gather_transpose<O, T, LOCAL, 1, 0, 0>(fsrc.c[0], ap.lE[0], sL + (0 - b) * rfvol, ap.vb[0][p], aw, dn, ds, on,
-                                               os, lxa, x0);
-        gather_transpose<O, T, LOCAL, 0, 1, 0>(fsrc.c[1], ap.lE[1], sL + (1 - b) * rfvol, ap.vb[1][p], aw, dn, ds, on,
-                                               os, lxa, x1);
-        gather_transpose<O, T, LOCAL, 0, 0, 1>(fsrc.c[2], ap.lE[2], sL + (2 - b) * rfvol, ap.vb[2][p], aw, dn, ds, on,
-                                               os, lxa, x2);
+        scatter_component<O, T, LOCAL, 1, 0, 0>(ap.lE[0], sL + (0 - b) * rfvol, ap.vb[0][p], aw, on, os, run(0));
+        scatter_component<O, T, LOCAL, 0, 1, 0>(ap.lE[1], sL + (1 - b) * rfvol, ap.vb[1][p], aw, on, os, run(1));
+        scatter_component<O, T, LOCAL, 0, 0, 1>(ap.lE[2], sL + (2 - b) * rfvol, ap.vb[2][p], aw, on, os, run(2));
     }
     if (G != 0) {
-        gather_transpose<O, T, LOCAL, 0, 1, 1>(fsrc.c[3], ap.lB[0], sL + (3 - b) * rfvol, ap.vb[3][p], aw, dn, ds, on,
-                                               os, lxa, x0);
-        gather_transpose<O, T, LOCAL, 1, 0, 1>(fsrc.c[4], ap.lB[1], sL + (4 - b) * rfvol, ap.vb[4][p], aw, dn, ds, on,
-                                               os, lxa, x1);
-        gather_transpose<O, T, LOCAL, 1, 1, 0>(fsrc.c[5], ap.lB[2], sL + (5 - b) * rfvol, ap.vb[5][p], aw, dn, ds, on,
-                                               os, lxa, x2);
+        const int k0 = G == 2 ? 3 : 0;
+        scatter_component<O, T, LOCAL, 0, 1, 1>(ap.lB[0], sL + (3 - b) * rfvol, ap.vb[3][p], aw, on, os, run(k0));
+        scatter_component<O, T, LOCAL, 1, 0, 1>(ap.lB[1], sL + (4 - b) * rfvol, ap.vb[4][p], aw, on, os,
+                                                run(k0 + 1));
+        scatter_component<O, T, LOCAL, 1, 1, 0>(ap.lB[2], sL + (5 - b) * rfvol, ap.vb[5][p], aw, on, os,
+                                                run(k0 + 2));
     }
+}
+
+// Packed lane runs of the components m0 .. m0+K-1 for a particle at cell
+// position pos (local or global) with offsets f; key 0 (no sharing) for an
+// inactive lane.  Call with the whole wave converged.
+template <typename T, int O, int K, bool GLOBAL>
+__device__ inline void component_runs(bool act, int m0, const int *pos, const T *f, const int *n, int *runs)
+{
+    constexpr int SX[6] = {1, 0, 0, 0, 1, 1}, SY[6] = {0, 1, 0, 1, 0, 1}, SZ[6] = {0, 0, 1, 1, 1, 0};
+    int bs[3];
 #pragma unroll
     for (int d = 0; d < 3; ++d)
-        ap.lx[d][p] = lxa[d];
+        bs[d] = f[d] >= T(0.5) ? Shape<O, T>::NB : Shape<O, T>::NB - 1;
+#pragma unroll
+    for (int k = 0; k < K; ++k) {
+        const int m = m0 + k;
+        // a lane's window of component m starts at its cell plus the
+        // component's first-node offset; lanes share rows when these starts
+        // are consecutive along x
+        const int st[3] = {pos[0] + (SX[m] ? bs[0] : Shape<O, T>::NB), pos[1] + (SY[m] ? bs[1] : Shape<O, T>::NB),
+                           pos[2] + (SZ[m] ? bs[2] : Shape<O, T>::NB)};
+        const int key = act ? (GLOBAL ? xrun_key_global(st, n) : xrun_key(st)) : 0;
+        runs[k] = xrun_pack(xrun(key));
+    }
 }
 
 // positions only (pass 2): a particle that fails the check was flagged by
@@ -1146,28 +1225,14 @@ __global__ void __launch_bounds__(256) k_adjoint_scatter(PConst<T> pc, PArr<T> s
     const int64_t p = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     int c[3] = {0, 0, 0};
     T f[3] = {T(0), T(0), T(0)};
-    int key[3] = {0, 0, 0};
     const bool act = p < sp.n && load_position(sp, p, pc.n, c, f);
-    if (act) {
-        constexpr int SX[6] = {1, 0, 0, 0, 1, 1}, SY[6] = {0, 1, 0, 1, 0, 1}, SZ[6] = {0, 0, 1, 1, 1, 0};
-        int bs[3];
-#pragma unroll
-        for (int d = 0; d < 3; ++d)
-            bs[d] = f[d] >= T(0.5) ? Shape<O, T>::NB : Shape<O, T>::NB - 1;
-#pragma unroll
-        for (int k = 0; k < 3; ++k) {
-            const int m = 3 * G + k;
-            const int st[3] = {c[0] + (SX[m] ? bs[0] : Shape<O, T>::NB), c[1] + (SY[m] ? bs[1] : Shape<O, T>::NB),
-                               c[2] + (SZ[m] ? bs[2] : Shape<O, T>::NB)};
-            key[k] = xrun_key_global(st, pc.n);
-        }
-    }
-    const XRun xr[3] = {xrun(key[0]), xrun(key[1]), xrun(key[2])};   // converged
+    int runs[3];
+    component_runs<T, O, 3, true>(act, 3 * G, c, f, pc.n, runs);   // converged
     if (act) {
         const int z3[3] = {0, 0, 0};
-        adjoint_scatter_particle<T, O, false, G>(pc, ap, global_fields(fp), p, c, f, z3, 0, z3, nullptr, 0, xr[0],
-                                                 xr[1], xr[2]);
+        adjoint_scatter_particle<T, O, false, G>(pc, ap, p, c, f, z3, 0, z3, nullptr, 0, runs);
     }
+    (void)fp;
 }
 
 // ---------------------------------------------------------------------------
@@ -1275,7 +1340,6 @@ __global__ void __launch_bounds__(STRAY_THREADS) k_adjoint_scatter_strays(PConst
     __shared__ int cnt;
     const TileSpan ts = tile_span(tg, tile_start, sp.n);
     const int np = (int)(ts.pe - ts.ps);
-    const FieldSrc<T> gf = global_fields(fp);
     const int z3[3] = {0, 0, 0};
     for (int j0 = 0; j0 < np; j0 += STRAY_CHUNK) {
         const int k = collect_strays(ts, j0, list, &cnt, CellStray<T>{tg, pc.n, ts, sp});
@@ -1284,17 +1348,17 @@ __global__ void __launch_bounds__(STRAY_THREADS) k_adjoint_scatter_strays(PConst
             int c[3];
             T f[3];
             if (load_position(sp, p, pc.n, c, f))
-                adjoint_scatter_particle<T, O, false, 2>(pc, ap, gf, p, c, f, z3, 0, z3, nullptr, 0);
+                adjoint_scatter_particle<T, O, false, 2>(pc, ap, p, c, f, z3, 0, z3, nullptr, 0, nullptr);
         }
         __syncthreads();
     }
 }
 
-// pass 2, tiled, for group G (0: E, 1: B): LDS holds FP64 accumulators of
-// the group's three adjoints and the group's fields with the gather halo;
-// the accumulators are flushed with one global atomic per non-zero value.
-// Strays are left to k_adjoint_scatter_strays.
-template <typename T, int O, int G>
+// pass 2, tiled: LDS holds FP64 accumulators of the six field adjoints with
+// the gather halo (no fields: the position part of the gather transpose is
+// done in pass 1); they are flushed with one global atomic per non-zero
+// value.  Strays are left to k_adjoint_scatter_strays.
+template <typename T, int O>
 __global__ void __launch_bounds__(AdjThreads<T>::value) k_adjoint_scatter_tile(PConst<T> pc, TileGeo tg, PArr<T> sp,
                                                                               FieldPtrs<T> fp, AdjPtrs<T> ap,
                                                                               const int *__restrict__ tile_start)
@@ -1302,69 +1366,36 @@ __global__ void __launch_bounds__(AdjThreads<T>::value) k_adjoint_scatter_tile(P
     extern __shared__ __align__(16) unsigned char smem_raw[];
     const int rfx = tg.rf[0], rfy = tg.rf[1];
     const int rfvol = rfx * rfy * tg.rf[2];
-    double *sL = reinterpret_cast<double *>(smem_raw);               // 3 * rfvol
-    T *sF = reinterpret_cast<T *>(smem_raw + 3 * rfvol * sizeof(double));   // 3 * rfvol
+    double *sL = reinterpret_cast<double *>(smem_raw);   // 6 * rfvol
     const TileSpan ts = tile_span(tg, tile_start, sp.n);
     if (ts.pe <= ts.ps)
         return;
-    T *const *gsrc = G == 0 ? fp.E : fp.B;
-    T *const *gdst = G == 0 ? ap.lE : ap.lB;
     const int tid = threadIdx.x, nth = blockDim.x;
-    for (int r = tid; r < rfvol; r += nth) {
-        const int gi = region_global(pc.n, ts.t0, tg.lo_f, r % rfx, (r / rfx) % rfy, r / (rfx * rfy));
-#pragma unroll
-        for (int m = 0; m < 3; ++m) {
-            sF[m * rfvol + r] = gsrc[m][gi];
-            sL[m * rfvol + r] = 0.0;
-        }
-    }
+    for (int r = tid; r < 6 * rfvol; r += nth)
+        sL[r] = 0.0;
     __syncthreads();
-    FieldSrc<T> lf;
-#pragma unroll
-    for (int m = 0; m < 3; ++m) {
-        lf.c[3 * G + m] = sF + m * rfvol;
-        lf.c[3 * (1 - G) + m] = nullptr;
-    }
     const int sf[3] = {1, rfx, rfx * rfy};
     const int np = (int)(ts.pe - ts.ps);
-    // staggering of the group's components along x, y, z
-    constexpr int SX[6] = {1, 0, 0, 0, 1, 1}, SY[6] = {0, 1, 0, 1, 0, 1}, SZ[6] = {0, 0, 1, 1, 1, 0};
     for (int j0 = 0; j0 < np; j0 += nth) {
         const int j = j0 + tid;
         int c[3] = {0, 0, 0}, l[3] = {0, 0, 0};
         T f[3] = {T(0), T(0), T(0)};
-        int key[3] = {0, 0, 0};
         const bool act = j < np && load_position(sp, ts.ps + j, pc.n, c, f) && tile_local(tg, pc.n, ts.t0, c, l);
-        if (act) {
-            // a lane's window of component k starts at its cell plus the
-            // component's first-node offset; lanes share rows when these
-            // starts are consecutive along x
-            int bs[3];
-#pragma unroll
-            for (int d = 0; d < 3; ++d)
-                bs[d] = f[d] >= T(0.5) ? Shape<O, T>::NB : Shape<O, T>::NB - 1;
-#pragma unroll
-            for (int k = 0; k < 3; ++k) {
-                const int m = 3 * G + k;
-                const int st[3] = {l[0] + (SX[m] ? bs[0] : Shape<O, T>::NB), l[1] + (SY[m] ? bs[1] : Shape<O, T>::NB),
-                                   l[2] + (SZ[m] ? bs[2] : Shape<O, T>::NB)};
-                key[k] = xrun_key(st);
-            }
-        }
-        const XRun xr[3] = {xrun(key[0]), xrun(key[1]), xrun(key[2])};   // converged
+        int runs[6];
+        component_runs<T, O, 6, false>(act, 0, l, f, pc.n, runs);   // converged
         if (act)
-            adjoint_scatter_particle<T, O, true, G>(pc, ap, lf, ts.ps + j, c, f, l, tg.lo_f, sf, sL, rfvol, xr[0],
-                                                    xr[1], xr[2]);
+            adjoint_scatter_particle<T, O, true, 2>(pc, ap, ts.ps + j, c, f, l, tg.lo_f, sf, sL, rfvol, runs);
     }
     __syncthreads();
-    for (int r = tid; r < 3 * rfvol; r += nth) {
+    for (int r = tid; r < 6 * rfvol; r += nth) {
         const T v = (T)sL[r];
         if (v != T(0)) {
             const int m = r / rfvol, rr = r - m * rfvol;
             const int gi = region_global(pc.n, ts.t0, tg.lo_f, rr % rfx, (rr / rfx) % rfy, rr / (rfx * rfy));
-            gatomic_add(gdst[m] + gi, v);
+            gatomic_add((m < 3 ? ap.lE[m] : ap.lB[m - 3]) + gi, v);
         }
     }
+    (void)fp;
 }
 
 // ---------------------------------------------------------------------------
@@ -1526,8 +1557,8 @@ hipError_t launch_adjoint_particles(int order, const PConst<T> &pc, const PArr<T
 }
 
 // LDS of the two tiled passes: pass 1 E, B (gather halo) and hatE (deposit
-// halo) in the working precision; pass 2 FP64 accumulators and fields of one
-// group of three components
+// halo) in the working precision; pass 2 FP64 accumulators of the six field
+// adjoints (gather halo)
 template <typename T>
 size_t adjoint_push_lds(const TileGeo &tg)
 {
@@ -1540,7 +1571,7 @@ template <typename T>
 size_t adjoint_scatter_lds(const TileGeo &tg)
 {
     const size_t rf = (size_t)tg.rf[0] * tg.rf[1] * tg.rf[2];
-    return 3 * rf * (sizeof(double) + sizeof(T));
+    return 6 * rf * sizeof(double);
 }
 
 template <typename T>
@@ -1554,10 +1585,9 @@ template <typename T, int O>
 static hipError_t launch_adj_tile_o(const PConst<T> &pc, const TileGeo &tg, const PArr<T> &sp, const FieldPtrs<T> &f,
                                     const AdjPtrs<T> &ap, const int *tile_start, int *err, hipStream_t st)
 {
-    static bool a1 = false, a2 = false, a3 = false;
+    static bool a1 = false, a2 = false;
     allow_big_lds(&k_adjoint_push_tile<T, O>, a1);
-    allow_big_lds(&k_adjoint_scatter_tile<T, O, 0>, a2);
-    allow_big_lds(&k_adjoint_scatter_tile<T, O, 1>, a3);
+    allow_big_lds(&k_adjoint_scatter_tile<T, O>, a2);
     const unsigned ntiles = (unsigned)(tg.nt[0] * tg.nt[1] * tg.nt[2]);
     const unsigned nth = AdjThreads<T>::value;
     const size_t l1 = adjoint_push_lds<T>(tg), l2 = adjoint_scatter_lds<T>(tg);
@@ -1565,9 +1595,7 @@ static hipError_t launch_adj_tile_o(const PConst<T> &pc, const TileGeo &tg, cons
                        err);
     hipLaunchKernelGGL((k_adjoint_push_strays<T, O>), dim3(ntiles), dim3(STRAY_THREADS), 0, st, pc, tg, sp, f, ap,
                        tile_start, err);
-    hipLaunchKernelGGL((k_adjoint_scatter_tile<T, O, 0>), dim3(ntiles), dim3(nth), l2, st, pc, tg, sp, f, ap,
-                       tile_start);
-    hipLaunchKernelGGL((k_adjoint_scatter_tile<T, O, 1>), dim3(ntiles), dim3(nth), l2, st, pc, tg, sp, f, ap,
+    hipLaunchKernelGGL((k_adjoint_scatter_tile<T, O>), dim3(ntiles), dim3(nth), l2, st, pc, tg, sp, f, ap,
                        tile_start);
     hipLaunchKernelGGL((k_adjoint_scatter_strays<T, O>), dim3(ntiles), dim3(STRAY_THREADS), 0, st, pc, tg, sp, f, ap,
                        tile_start);
