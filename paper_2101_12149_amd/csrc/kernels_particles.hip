@@ -11,7 +11,7 @@
 //  k_particles_global the same fused step without tiles (global memory and
 //                     global atomics, the paper's GPU deposition, Sec. 3.4.1)
 //  k_gather / k_push / k_deposit   the separate operations
-//  k_adjoint_push / k_adjoint_scatter (and their tiled forms)
+//  k_adjoint_push / k_adjoint_scatter_box (and their tiled forms)
 //                     transpose of the particle part of a step, two passes
 #include "pic_device.hpp"
 #include "pic_types.hpp"
@@ -1217,22 +1217,176 @@ __global__ void __launch_bounds__(256) k_adjoint_push(PConst<T> pc, PArr<T> sp, 
     adjoint_push_particle<T, O, false>(pc, sp, ap, global_fields(fp), ap.hat, p, c, f, u, z3, 0, z3, 0, z3, err);
 }
 
-template <typename T, int O, int G>
-__global__ void __launch_bounds__(256) k_adjoint_scatter(PConst<T> pc, PArr<T> sp, FieldPtrs<T> fp, AdjPtrs<T> ap)
+// Pass 2 without a binning: a workgroup takes BOX_CHUNK consecutive
+// particles.  When the cells of a segment of them fit a box whose six FP64
+// accumulator tiles (cells plus the gather halo) fit BOX_LDS, the segment
+// scatters into LDS (rows shared between lanes) and the box is flushed with
+// one global atomic per non-zero value; a segment that does not fit is
+// halved, and one of BOX_THREADS particles that still does not fit scatters
+// with global atomics.  Binned particles give compact boxes.
+// One 512-thread workgroup per CU (the order-3 FP64 scatter needs about 250
+// registers, so 8 waves per CU either way) with most of the LDS: a tile of
+// binned particles that drifted a cell or two since the binning still fits.
+constexpr int BOX_THREADS = 512;
+constexpr int BOX_CHUNK = 2048;
+constexpr int BOX_LDS = 144 * 1024;
+constexpr int BOX_HEAD = 256;   // reduction scratch ahead of the accumulators
+constexpr int BOX_MAX_CELLS = 40;
+static_assert((6 * (BOX_THREADS / 64) + 3) * (int)sizeof(int) <= BOX_HEAD, "box reduction scratch");   // box extent per axis (lane-run keys hold local coordinates below 56)
+
+__device__ inline int wave_min(int v)
 {
-    // group G of components; consecutive particles of a binned order sit in
-    // neighbouring cells, so their rows are shared as in the tiled pass
-    const int64_t p = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    int c[3] = {0, 0, 0};
-    T f[3] = {T(0), T(0), T(0)};
-    const bool act = p < sp.n && load_position(sp, p, pc.n, c, f);
-    int runs[3];
-    component_runs<T, O, 3, true>(act, 3 * G, c, f, pc.n, runs);   // converged
-    if (act) {
-        const int z3[3] = {0, 0, 0};
-        adjoint_scatter_particle<T, O, false, G>(pc, ap, p, c, f, z3, 0, z3, nullptr, 0, runs);
+#pragma unroll
+    for (int o = 32; o > 0; o >>= 1)
+        v = min(v, __shfl_xor(v, o, 64));
+    return v;
+}
+
+__device__ inline int wave_max(int v)
+{
+#pragma unroll
+    for (int o = 32; o > 0; o >>= 1)
+        v = max(v, __shfl_xor(v, o, 64));
+    return v;
+}
+
+// cell offset from the reference cell along one axis, wrapped into [-n/2, n/2)
+__device__ inline int box_rel(int c, int ref, int n)
+{
+    int r = c - ref;
+    if (r < -(n >> 1))
+        r += n;
+    else if (r >= n - (n >> 1))
+        r -= n;
+    return r;
+}
+
+template <typename T, int O>
+__global__ void __launch_bounds__(BOX_THREADS) k_adjoint_scatter_box(PConst<T> pc, PArr<T> sp, AdjPtrs<T> ap)
+{
+    extern __shared__ __align__(16) unsigned char smem_raw[];
+    int(*wred)[6] = reinterpret_cast<int(*)[6]>(smem_raw);   // per-wave minima and maxima
+    int *sref = reinterpret_cast<int *>(smem_raw) + 6 * (BOX_THREADS / 64);
+    double *sL = reinterpret_cast<double *>(smem_raw + BOX_HEAD);   // BOX_LDS bytes
+    constexpr int gl = O == 3 ? 2 : 1;   // gather halo below a cell
+    constexpr int gh = O == 3 ? 4 : 2;   // nodes of the halo on both sides together
+    const int tid = threadIdx.x, lane = tid & 63, wv = tid >> 6;
+    const int64_t base = (int64_t)blockIdx.x * BOX_CHUNK;
+    const int64_t end = base + BOX_CHUNK < sp.n ? base + BOX_CHUNK : sp.n;
+    int len = BOX_CHUNK;
+    for (int64_t s0 = base; s0 < end;) {
+        const int seg = (int)(end - s0 < len ? end - s0 : len);
+        // reference cell: the segment's first particle, clamped into the grid
+        if (tid == 0) {
+#pragma unroll
+            for (int d = 0; d < 3; ++d) {
+                const int v = sp.cell[d][s0];
+                sref[d] = v < 0 ? 0 : (v >= pc.n[d] ? pc.n[d] - 1 : v);
+            }
+        }
+        __syncthreads();
+        const int ref[3] = {sref[0], sref[1], sref[2]};
+        int mn[3] = {INT_MAX, INT_MAX, INT_MAX}, mx[3] = {INT_MIN, INT_MIN, INT_MIN};
+        for (int j = tid; j < seg; j += BOX_THREADS) {
+            int c[3];
+            T f[3];
+            if (load_position(sp, s0 + j, pc.n, c, f)) {
+#pragma unroll
+                for (int d = 0; d < 3; ++d) {
+                    const int r = box_rel(c[d], ref[d], pc.n[d]);
+                    mn[d] = min(mn[d], r);
+                    mx[d] = max(mx[d], r);
+                }
+            }
+        }
+#pragma unroll
+        for (int d = 0; d < 3; ++d) {
+            mn[d] = wave_min(mn[d]);
+            mx[d] = wave_max(mx[d]);
+        }
+        if (lane == 0) {
+#pragma unroll
+            for (int d = 0; d < 3; ++d) {
+                wred[wv][d] = mn[d];
+                wred[wv][3 + d] = mx[d];
+            }
+        }
+        __syncthreads();
+        int lo[3], rf[3];
+        bool any = true;
+        size_t vol = 1;
+#pragma unroll
+        for (int d = 0; d < 3; ++d) {
+            int a = wred[0][d], b = wred[0][3 + d];
+#pragma unroll
+            for (int w = 1; w < BOX_THREADS / 64; ++w) {
+                a = min(a, wred[w][d]);
+                b = max(b, wred[w][3 + d]);
+            }
+            any = any && a <= b;
+            lo[d] = a;
+            rf[d] = any ? b - a + 1 + gh : 0;
+            vol *= (size_t)rf[d];
+        }
+        __syncthreads();   // wred and sref are rewritten by the next segment
+        if (!any) {        // no valid particle in the segment
+            s0 += seg;
+            continue;
+        }
+        const bool fits = rf[0] - gh <= BOX_MAX_CELLS && rf[1] - gh <= BOX_MAX_CELLS &&
+                          rf[2] - gh <= BOX_MAX_CELLS && 6 * vol * sizeof(double) <= (size_t)BOX_LDS;
+        if (!fits && len > BOX_THREADS) {
+            len >>= 1;   // uniform: every thread read the same reductions
+            continue;
+        }
+        if (fits) {
+            const int rfvol = (int)vol;
+            for (int r = tid; r < 6 * rfvol; r += BOX_THREADS)
+                sL[r] = 0.0;
+            __syncthreads();
+            const int sf[3] = {1, rf[0], rf[0] * rf[1]};
+            for (int j0 = 0; j0 < seg; j0 += BOX_THREADS) {
+                const int j = j0 + tid;
+                int c[3] = {0, 0, 0}, l[3] = {0, 0, 0};
+                T f[3] = {T(0), T(0), T(0)};
+                const bool act = j < seg && load_position(sp, s0 + j, pc.n, c, f);
+                if (act) {
+#pragma unroll
+                    for (int d = 0; d < 3; ++d)
+                        l[d] = box_rel(c[d], ref[d], pc.n[d]) - lo[d];   // in [0, rf - gh)
+                }
+                int runs[6];
+                component_runs<T, O, 6, false>(act, 0, l, f, pc.n, runs);   // converged
+                if (act)
+                    adjoint_scatter_particle<T, O, true, 2>(pc, ap, s0 + j, c, f, l, gl, sf, sL, rfvol, runs);
+            }
+            __syncthreads();
+            const int org[3] = {ref[0] + lo[0], ref[1] + lo[1], ref[2] + lo[2]};
+            for (int r = tid; r < 6 * rfvol; r += BOX_THREADS) {
+                const T v = (T)sL[r];
+                if (v != T(0)) {
+                    const int m = r / rfvol, rr = r - m * rfvol;
+                    const int gi = region_global(pc.n, org, gl, rr % rf[0], (rr / rf[0]) % rf[1], rr / sf[2]);
+                    gatomic_add((m < 3 ? ap.lE[m] : ap.lB[m - 3]) + gi, v);
+                }
+            }
+            __syncthreads();   // sL is cleared by the next segment
+        } else {
+            for (int j0 = 0; j0 < seg; j0 += BOX_THREADS) {
+                const int j = j0 + tid;
+                int c[3] = {0, 0, 0};
+                T f[3] = {T(0), T(0), T(0)};
+                const bool act = j < seg && load_position(sp, s0 + j, pc.n, c, f);
+                int runs[6];
+                component_runs<T, O, 6, true>(act, 0, c, f, pc.n, runs);   // converged
+                if (act) {
+                    const int z3[3] = {0, 0, 0};
+                    adjoint_scatter_particle<T, O, false, 2>(pc, ap, s0 + j, c, f, z3, 0, z3, nullptr, 0, runs);
+                }
+            }
+        }
+        s0 += seg;
     }
-    (void)fp;
 }
 
 // ---------------------------------------------------------------------------
@@ -1543,15 +1697,16 @@ hipError_t launch_adjoint_particles(int order, const PConst<T> &pc, const PArr<T
     if (sp.n == 0)
         return hipSuccess;
     const AdjPtrs<T> ap = adj_ptrs<T>(hatE, lx, lu, lE, lB, vb);
-    const unsigned nb = nblk(sp.n, 256);
+    const unsigned nb = nblk(sp.n, 256), nc = nblk(sp.n, BOX_CHUNK);
+    static bool b1 = false, b3 = false;
     if (order == 1) {
+        allow_big_lds(&k_adjoint_scatter_box<T, 1>, b1);
         hipLaunchKernelGGL((k_adjoint_push<T, 1>), dim3(nb), dim3(256), 0, st, pc, sp, f, ap, err);
-        hipLaunchKernelGGL((k_adjoint_scatter<T, 1, 0>), dim3(nb), dim3(256), 0, st, pc, sp, f, ap);
-        hipLaunchKernelGGL((k_adjoint_scatter<T, 1, 1>), dim3(nb), dim3(256), 0, st, pc, sp, f, ap);
+        hipLaunchKernelGGL((k_adjoint_scatter_box<T, 1>), dim3(nc), dim3(BOX_THREADS), BOX_HEAD + BOX_LDS, st, pc, sp, ap);
     } else {
+        allow_big_lds(&k_adjoint_scatter_box<T, 3>, b3);
         hipLaunchKernelGGL((k_adjoint_push<T, 3>), dim3(nb), dim3(256), 0, st, pc, sp, f, ap, err);
-        hipLaunchKernelGGL((k_adjoint_scatter<T, 3, 0>), dim3(nb), dim3(256), 0, st, pc, sp, f, ap);
-        hipLaunchKernelGGL((k_adjoint_scatter<T, 3, 1>), dim3(nb), dim3(256), 0, st, pc, sp, f, ap);
+        hipLaunchKernelGGL((k_adjoint_scatter_box<T, 3>), dim3(nc), dim3(BOX_THREADS), BOX_HEAD + BOX_LDS, st, pc, sp, ap);
     }
     return hipGetLastError();
 }

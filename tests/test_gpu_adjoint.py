@@ -106,6 +106,50 @@ def test_adjoint_step_matches_oracle(order, dtype, tiled):
     assert rel_l2(dA.cpu().numpy(), odA) < tol
 
 
+def _block_cells(gen, n, lo, ext, grid):
+    """n cells drawn in the box lo .. lo + ext - 1 (periodic)."""
+    return torch.stack([(lo[d] + torch.randint(0, ext[d], (n,), generator=gen)) % int(grid.n[d])
+                        for d in range(3)]).to(torch.int32)
+
+
+@pytest.mark.parametrize("order", [1, 3])
+@pytest.mark.parametrize("dtype", ["f64", "f32"])
+def test_untiled_adjoint_box_segments_match_oracle(order, dtype):
+    """The per-particle reverse step accumulates a segment of consecutive
+    particles in an LDS box when their cells are compact.  Particles 0-1535
+    lie in one small block across the periodic corner, 1536-2047 in a distant
+    block, the rest anywhere: a segment holding both blocks is halved until
+    each lies in one block, and a segment of scattered particles falls back
+    to global atomics."""
+    g = wl.plasma_grid((12, 16, 20), order)
+    gen = torch.Generator().manual_seed(111)
+    a = ((10, 14, 18), (5, 4, 5))
+    b = ((5, 7, 9), (2, 2, 2))
+    cells = torch.cat([_block_cells(gen, 1024, *a, g), _block_cells(gen, 512, *a, g),
+                       _block_cells(gen, 512, *b, g),
+                       torch.stack([torch.randint(0, int(g.n[d]), (1024,), generator=gen) for d in range(3)])
+                       .to(torch.int32)], dim=1)
+    n = cells.shape[1]
+    sp = random_species(g, n, 112, u_th=0.2, dtype=dtype, cells=cells)
+    f = random_fields(g, 113, scale=0.3, dtype=dtype)
+    amp = torch.randn((16, 12), dtype=torch.float64, generator=torch.Generator().manual_seed(114))
+    src = wl.Source(4, amp.to(tdtype(dtype)), np.array([0.2, -0.7, 1.1, 0.4]))
+    lam = _random_lambda(g, n, 115, dtype)
+    olam = _oracle_lambda(lam)
+    dlam = NS(lx=dev(lam.lx), lu=dev(lam.lu), lE=dev(lam.lE), lB=dev(lam.lB))
+    dA = torch.zeros((16, 12), dtype=torch.float64, device="cuda")
+    ws = _lib.workspace(g, dtype, n)
+    _lib.pic_step_adjoint(g, dev(sp), dev(f), src.to(device="cuda"), 2, dlam, dA, ws)
+    torch.cuda.synchronize()
+    odA = np.zeros((16, 12))
+    oracle.step_adjoint(g, sp.numpy(), f.numpy(), src.numpy(), 2, olam, odA)
+    tol = 1e-12 if dtype == "f64" else 1e-4
+    for name in ("lx", "lu", "lE", "lB"):
+        r = rel_l2(_cpu(getattr(dlam, name)), getattr(olam, name))
+        assert r < tol, (name, r)
+    assert rel_l2(dA.cpu().numpy(), odA) < tol
+
+
 def test_energy_loss_and_seed():
     g = wl.plasma_grid((8, 12, 16), 3)
     f = random_fields(g, 111, scale=0.4)
