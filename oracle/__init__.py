@@ -37,7 +37,7 @@ def build():
 
 class _Grid(C.Structure):
     _fields_ = [("n", C.c_int32 * 3), ("d", C.c_double * 3), ("dt", C.c_double),
-                ("c", C.c_double), ("eps0", C.c_double), ("order", C.c_int32)]
+                ("c", C.c_double), ("eps0", C.c_double), ("order", C.c_int32), ("pusher", C.c_int32)]
 
 
 class _Species(C.Structure):
@@ -103,6 +103,9 @@ def _grid(g):
     s.n[:] = [int(v) for v in g.n]
     s.d[:] = [float(v) for v in g.d]
     s.dt, s.c, s.eps0, s.order = float(g.dt), float(g.c), float(g.eps0), int(g.order)
+    s.pusher = int(getattr(g, "pusher", 0))
+    if s.pusher not in (0, 1):
+        raise ValueError("pusher must be 0 (Boris) or 1 (Vay)")
     return s
 
 

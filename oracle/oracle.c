@@ -47,6 +47,7 @@ typedef struct {
     double d[3];
     double dt, c, eps0;
     int32_t order;
+    int32_t pusher; /* 0: Boris, 1: Vay */
 } or_grid;
 
 typedef struct {
@@ -254,6 +255,153 @@ static double gamma_of(const double u[3], double c)
     return sqrt(1.0 + (u[0] * u[0] + u[1] * u[1] + u[2] * u[2]) / (c * c));
 }
 
+static double dot3(const double a[3], const double b[3])
+{
+    return a[0] * b[0] + a[1] * b[1] + a[2] * b[2];
+}
+
+/* Vay's relativistic push (J.-L. Vay, Phys. Plasmas 15, 056701, 2008), the
+ * pusher the paper runs for relativistic beams (Sec. 4.2).  The magnetic
+ * force takes the mean of the old and the new velocity,
+ *     u1 - u0 = 2h E + h (u0/gamma0 + u1/gamma1) x B,      h = q dt / (2 m),
+ * which is implicit in u1.  Collecting the known terms in
+ *     w = u0 + 2h E + h (u0/gamma0) x B
+ * and writing tau = h B, t = tau / gamma1, it reads u1 - u1 x t = w, a
+ * linear system once gamma1 is known, solved by
+ *     u1 = (w + (w.t) t + w x t) / (1 + |t|^2).
+ * Its norm, |u1|^2 = (gamma1^2 |w|^2 + (w.tau)^2) / (gamma1^2 + |tau|^2),
+ * inserted in gamma1^2 = 1 + |u1|^2/c^2 gives a quadratic in G = gamma1^2,
+ *     G^2 - sigma G - X = 0,  sigma = 1 + |w|^2/c^2 - |tau|^2,
+ *                              X = |tau|^2 + (w.tau)^2/c^2,
+ * of which the positive root is the physical one (taken in the form that
+ * does not cancel when sigma < 0).                                       */
+static double vay_gamma2(double sigma, double X, double *D)
+{
+    *D = sqrt(sigma * sigma + 4.0 * X);
+    return sigma >= 0.0 ? 0.5 * (sigma + *D) : 2.0 * X / (*D - sigma);
+}
+
+static void vay(double h, double c, const double u0[3], const double E[3], const double B[3], double u1[3])
+{
+    double c2 = c * c, g0 = gamma_of(u0, c);
+    double v0[3], v0xB[3], w[3], tau[3];
+    for (int d = 0; d < 3; ++d)
+        v0[d] = u0[d] / g0;
+    cross(v0, B, v0xB);
+    for (int d = 0; d < 3; ++d) {
+        w[d] = u0[d] + 2.0 * h * E[d] + h * v0xB[d];
+        tau[d] = h * B[d];
+    }
+    double tau2 = dot3(tau, tau), wt = dot3(w, tau);
+    double D, G = vay_gamma2(1.0 + dot3(w, w) / c2 - tau2, tau2 + wt * wt / c2, &D);
+    double g1 = sqrt(G);
+    double t[3], wxt[3];
+    for (int d = 0; d < 3; ++d)
+        t[d] = tau[d] / g1;
+    cross(w, t, wxt);
+    double a = dot3(w, t), den = 1.0 + dot3(t, t);
+    for (int d = 0; d < 3; ++d)
+        u1[d] = (w[d] + a * t[d] + wxt[d]) / den;
+}
+
+/* Transpose of vay(): given ub = dL/du1, return dL/du0, dL/dE, dL/dB.  The
+ * forward quantities are evaluated again and the chain rule is applied to
+ * them in reverse order; the root G(sigma, X) has dG/dsigma = G/D and
+ * dG/dX = 1/D with D = sqrt(sigma^2 + 4 X). */
+static void vay_adjoint(double h, double c, const double u0[3], const double E[3], const double B[3],
+                        const double ub[3], double u0b[3], double Eb[3], double Bb[3])
+{
+    double c2 = c * c, g0 = gamma_of(u0, c);
+    double v0[3], v0xB[3], w[3], tau[3];
+    for (int d = 0; d < 3; ++d)
+        v0[d] = u0[d] / g0;
+    cross(v0, B, v0xB);
+    for (int d = 0; d < 3; ++d) {
+        w[d] = u0[d] + 2.0 * h * E[d] + h * v0xB[d];
+        tau[d] = h * B[d];
+    }
+    double tau2 = dot3(tau, tau), wt = dot3(w, tau);
+    double sigma = 1.0 + dot3(w, w) / c2 - tau2;
+    double D, G = vay_gamma2(sigma, tau2 + wt * wt / c2, &D);
+    double g1 = sqrt(G);
+    double t[3], wxt[3], q[3];
+    for (int d = 0; d < 3; ++d)
+        t[d] = tau[d] / g1;
+    cross(w, t, wxt);
+    double a = dot3(w, t), den = 1.0 + dot3(t, t), s = 1.0 / den;
+    for (int d = 0; d < 3; ++d)
+        q[d] = w[d] + a * t[d] + wxt[d];
+    /* u1 = s q */
+    double sb = dot3(ub, q), qb[3];
+    for (int d = 0; d < 3; ++d)
+        qb[d] = s * ub[d];
+    /* q = w + a t + w x t */
+    double wb[3], tb[3], tmp[3];
+    cross(t, qb, tmp); /* d((w x t).qb)/dw = t x qb */
+    for (int d = 0; d < 3; ++d)
+        wb[d] = qb[d] + tmp[d];
+    double ab = dot3(qb, t);
+    cross(qb, w, tmp); /* d((w x t).qb)/dt = qb x w */
+    for (int d = 0; d < 3; ++d)
+        tb[d] = a * qb[d] + tmp[d];
+    /* a = w.t */
+    for (int d = 0; d < 3; ++d) {
+        wb[d] += ab * t[d];
+        tb[d] += ab * w[d];
+    }
+    /* s = 1 / (1 + |t|^2) */
+    for (int d = 0; d < 3; ++d)
+        tb[d] += -2.0 * s * s * sb * t[d];
+    /* t = tau / g1 */
+    double taub[3], g1b = 0.0;
+    for (int d = 0; d < 3; ++d) {
+        taub[d] = tb[d] / g1;
+        g1b -= tb[d] * tau[d] / (g1 * g1);
+    }
+    /* g1 = sqrt(G), G = G(sigma, X) */
+    double Gb = g1b / (2.0 * g1);
+    double sigb = Gb * G / D, Xb = Gb / D;
+    /* X = |tau|^2 + (w.tau)^2 / c^2 */
+    double wtb = 2.0 * Xb * wt / c2;
+    for (int d = 0; d < 3; ++d)
+        taub[d] += 2.0 * Xb * tau[d];
+    /* sigma = 1 + |w|^2 / c^2 - |tau|^2 */
+    for (int d = 0; d < 3; ++d) {
+        wb[d] += 2.0 * sigb * w[d] / c2;
+        taub[d] -= 2.0 * sigb * tau[d];
+    }
+    /* w.tau */
+    for (int d = 0; d < 3; ++d) {
+        wb[d] += wtb * tau[d];
+        taub[d] += wtb * w[d];
+    }
+    /* tau = h B;  w = u0 + 2h E + h v0 x B */
+    double v0b[3], wxv[3];
+    cross(B, wb, v0b); /* d((v0 x B).wb)/dv0 = B x wb */
+    cross(wb, v0, wxv); /* d((v0 x B).wb)/dB = wb x v0 */
+    for (int d = 0; d < 3; ++d) {
+        Bb[d] = h * taub[d] + h * wxv[d];
+        Eb[d] = 2.0 * h * wb[d];
+        u0b[d] = wb[d];
+        v0b[d] *= h;
+    }
+    /* v0 = u0 / g0,  g0 = sqrt(1 + |u0|^2 / c^2) */
+    double g0b = -dot3(v0b, v0) / g0;
+    for (int d = 0; d < 3; ++d)
+        u0b[d] += v0b[d] / g0 + g0b * v0[d] / c2;
+    (void)E;
+}
+
+/* The momentum update the grid selects. */
+static void push_momentum(const or_grid *g, double h, const double u0[3], const double E[3], const double B[3],
+                          double u1[3])
+{
+    if (g->pusher == 1)
+        vay(h, g->c, u0, E, B, u1);
+    else
+        boris(h, g->c, u0, E, B, u1, NULL);
+}
+
 /* Displacement of one step in cell units: dt u / (gamma dx_d). */
 static void displacement(const or_grid *g, const double u[3], double disp[3])
 {
@@ -278,7 +426,7 @@ static void move_coord(int32_t *cell, double *off, double disp, int32_t n)
     *off = f;
 }
 
-/* Boris momentum update followed by the position update. */
+/* Momentum update (Boris or Vay) followed by the position update. */
 void or_push(const or_grid *g, or_species *s, double *const Ep[3], double *const Bp[3])
 {
     double h = s->q * g->dt / (2.0 * s->m);
@@ -290,7 +438,7 @@ void or_push(const or_grid *g, or_species *s, double *const Ep[3], double *const
             E[d] = Ep[d][p];
             B[d] = Bp[d][p];
         }
-        boris(h, g->c, u0, E, B, u1, NULL);
+        push_momentum(g, h, u0, E, B, u1);
         displacement(g, u1, disp);
         for (int d = 0; d < 3; ++d) {
             s->u[d][p] = u1[d];
@@ -595,7 +743,7 @@ void or_step(const or_grid *g, or_species *s, or_fields *f, const or_source *src
                 B[m] = gather_one(g, f->B[m], STAG_B[m], cell, off, NULL);
                 u0[m] = s->u[m][p];
             }
-            boris(h, g->c, u0, E, B, u1, NULL);
+            push_momentum(g, h, u0, E, B, u1);
             displacement(g, u1, dp);
             for (int d = 0; d < 3; ++d) {
                 s->u[d][p] = u1[d];
@@ -806,7 +954,10 @@ void or_step_adjoint(const or_grid *g, const or_species *s, const or_fields *f, 
             B[m] = gather_one(g, f->B[m], STAG_B[m], cell, off, NULL);
             u0[m] = s->u[m][p];
         }
-        boris(h, g->c, u0, E, B, u1, &T);
+        if (g->pusher == 1)
+            vay(h, g->c, u0, E, B, u1);
+        else
+            boris(h, g->c, u0, E, B, u1, &T);
         displacement(g, u1, dp);
         /* deposit transpose */
         double g0[3], g1[3];
@@ -827,9 +978,12 @@ void or_step_adjoint(const or_grid *g, const or_species *s, const or_fields *f, 
         double ub[3];
         for (int d = 0; d < 3; ++d)
             ub[d] = lam->lu[d][p] + v[d] / gm - u1[d] * uv / (gm * gm * gm * g->c * g->c);
-        /* Boris transpose */
+        /* momentum-update transpose */
         double u0b[3], Eb[3], Bb[3];
-        boris_adjoint(h, g->c, E, B, &T, ub, u0b, Eb, Bb);
+        if (g->pusher == 1)
+            vay_adjoint(h, g->c, u0, E, B, ub, u0b, Eb, Bb);
+        else
+            boris_adjoint(h, g->c, E, B, &T, ub, u0b, Eb, Bb);
         /* gather transpose */
         for (int m = 0; m < 3; ++m) {
             gather_adjoint_one(g, f->E[m], lam->lE[m], STAG_E[m], cell, off, Eb[m], lx0);

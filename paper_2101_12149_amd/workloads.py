@@ -34,6 +34,7 @@ class Grid:
     order: int = 3      # shape-function order: 1 or 3
     tile: tuple = (0, 0, 0)   # sort/LDS tile edge per direction (0: library default)
     slack: int = -1     # halo slack of the tiled particle kernel (-1: automatic)
+    pusher: int = 0     # momentum update: 0 Boris, 1 Vay
 
     @property
     def ncells(self) -> int:

@@ -6,6 +6,7 @@ Esirkepov coefficient, a wrong Boris rotation angle.  None of them re-types
 an oracle formula: they check closed forms, invariants, brute force and
 textbook values.
 """
+import dataclasses
 import math
 import os
 from fractions import Fraction
@@ -226,6 +227,79 @@ def test_boris_uniform_B_energy_angle_and_gyroradius():
     assert np.ptp(xs[:, 2]) == 0
 
 
+def _push_once(g, u0, E, B, q=-1.0):
+    """Momentum after one push of particles at rest in the middle of a large
+    cell (positions do not matter here); u0, E, B are (3, N)."""
+    n = u0.shape[1]
+    sp = species(np.full((3, n), 1), np.full((3, n), 0.5), np.array(u0, dtype=float), q=q)
+    oracle.push(g, sp, np.ascontiguousarray(E, dtype=float), np.ascontiguousarray(B, dtype=float))
+    return sp.u
+
+
+def _vay_grid(dt, pusher=1):
+    g = grid(n=(4, 4, 4), d=(1e3, 1e3, 1e3), dt=dt)
+    g.pusher = pusher
+    return g
+
+
+def test_vay_reduces_to_boris_without_magnetic_or_electric_field():
+    """With B = 0 both pushers are the plain kick u0 + (q/m) E dt; with E = 0
+    the mean-velocity force of Vay's pusher is the implicit-midpoint rotation
+    by the tangent-half-angle vector, the same map as Boris's rotation."""
+    rng = np.random.default_rng(21)
+    n = 64
+    u0 = rng.normal(0, 2.0, (3, n))
+    E = rng.normal(0, 1.0, (3, n))
+    B = rng.normal(0, 3.0, (3, n))
+    Z = np.zeros((3, n))
+    dt = 0.4
+    kick = u0 + (-1.0) * E * dt
+    np.testing.assert_allclose(_push_once(_vay_grid(dt), u0, E, Z), kick, rtol=1e-14, atol=1e-14)
+    np.testing.assert_allclose(_push_once(_vay_grid(dt), u0, Z, B), _push_once(_vay_grid(dt, 0), u0, Z, B),
+                               rtol=1e-13, atol=1e-13)
+
+
+def test_vay_keeps_the_force_free_drift_exactly():
+    """E = -v x B makes the Lorentz force vanish: a particle moving with v
+    keeps its momentum.  Vay's pusher reproduces this for any dt and gamma
+    (the property it was designed for); Boris's half kicks do not."""
+    rng = np.random.default_rng(22)
+    n = 64
+    v = rng.normal(0, 1.0, (3, n))
+    v *= rng.uniform(0.5, 0.995, n) / np.linalg.norm(v, axis=0)
+    gam = 1.0 / np.sqrt(1.0 - np.sum(v * v, axis=0))
+    u0 = gam * v
+    B = rng.normal(0, 2.0, (3, n))
+    E = -np.cross(v, B, axis=0)
+    dt = 0.5
+    u_vay = _push_once(_vay_grid(dt), u0, E, B)
+    np.testing.assert_allclose(u_vay, u0, rtol=0, atol=1e-12 * np.max(np.abs(u0)))
+    u_boris = _push_once(_vay_grid(dt, 0), u0, E, B)
+    assert np.max(np.abs(u_boris - u0)) > 1e-2
+
+
+def test_vay_solves_its_implicit_equation():
+    """The result satisfies the defining equation
+    u1 - u0 = (q dt/m) E + (q dt/2m) (u0/gamma0 + u1/gamma1) x B
+    to rounding, also where |q B dt / 2m| exceeds the new gamma (the
+    quadratic's coefficient sigma is negative there)."""
+    rng = np.random.default_rng(23)
+    n = 200
+    u0 = rng.normal(0, 1.5, (3, n))
+    E = rng.normal(0, 2.0, (3, n))
+    B = rng.normal(0, 1.0, (3, n)) * rng.choice([0.1, 1.0, 30.0], n)
+    dt = 0.6
+    u1 = _push_once(_vay_grid(dt), u0, E, B)
+    h = -1.0 * dt / 2
+    g0 = np.sqrt(1 + np.sum(u0 * u0, axis=0))
+    g1 = np.sqrt(1 + np.sum(u1 * u1, axis=0))
+    res = u1 - u0 - 2 * h * E - h * np.cross(u0 / g0 + u1 / g1, B, axis=0)
+    scale = np.abs(u0) + np.abs(u1) + np.abs(2 * h * E) + np.abs(h) * np.linalg.norm(B, axis=0) * 2
+    assert np.max(np.abs(res) / scale) < 1e-13
+    tau2 = h * h * np.sum(B * B, axis=0)
+    assert np.any(tau2 > g1 ** 2)   # the sigma < 0 branch was taken
+
+
 # --------------------------------------------------------------------------
 # Esirkepov
 
@@ -435,15 +509,16 @@ def _fd_tol(an, L, eps):
     return 1e-6 * abs(an) + 10 * np.finfo(float).eps * abs(L) / eps
 
 
+@pytest.mark.parametrize("pusher", [0, 1])
 @pytest.mark.parametrize("order", [3])
-def test_adjoint_matches_central_finite_differences(order):
+def test_adjoint_matches_central_finite_differences(order, pusher):
     """Gradient of the final field energy w.r.t. the initial momenta and the
     source amplitude map, against central differences with eps = 1e-6 along
     seeded random directions and single coordinates.  Fields start at zero,
     so the loss is made by the particles' own currents and the source and
     every checked derivative is far above the difference's rounding noise."""
     w = wl.differentiable((8, 8, 8), 1, 0.05, order, 3, "f64", 1234, amp0=2e-2, period=4)
-    g = w.grid
+    g = dataclasses.replace(w.grid, pusher=pusher)
     sp, f, src = w.species.numpy(), w.fields.numpy(), w.source.numpy()
     rng = np.random.default_rng(9)
     L, gu, gA, _, _ = oracle.rollout_grad(g, sp, f, src, 0, w.nsteps)
@@ -476,12 +551,13 @@ def test_adjoint_matches_central_finite_differences(order):
         assert 10 * np.finfo(float).eps * abs(L) / eps < 1e-6 * abs(an)   # noise below the bar
 
 
-def test_adjoint_position_and_field_gradients_by_finite_differences():
+@pytest.mark.parametrize("pusher", [0, 1])
+def test_adjoint_position_and_field_gradients_by_finite_differences(pusher):
     """dL/dx0 and dL/dE0, dL/dB0 from the reverse sweep against central
-    differences (pins the deposit transpose in both positions and the gather
-    transpose)."""
+    differences (pins the deposit transpose in both positions, the gather
+    transpose and the transpose of either momentum update)."""
     w = wl.differentiable((8, 8, 8), 1, 0.08, 3, 2, "f64", 4321, amp0=0.0)
-    g = w.grid
+    g = dataclasses.replace(w.grid, pusher=pusher)
     sp, f = w.species.numpy(), w.fields.numpy()
     rng = np.random.default_rng(10)
     f.E[:] = rng.normal(0, 0.1, f.E.shape)
