@@ -62,6 +62,18 @@ typedef enum {
 
 typedef enum { PIC_F32 = 0, PIC_F64 = 1 } pic_dtype;
 
+/* Momentum update of the particle push.
+ *   PIC_PUSH_BORIS  relativistic Boris rotation: half electric kick, magnetic
+ *                   rotation, half electric kick.
+ *   PIC_PUSH_VAY    Vay's pusher (J.-L. Vay, Phys. Plasmas 15, 056701, 2008),
+ *                   which the paper runs for relativistic beams (Sec. 4.2): the
+ *                   magnetic force takes the mean of the old and new velocity,
+ *                   u1 - u0 = (q dt/m) E + (q dt/2m) (u0/g0 + u1/g1) x B,
+ *                   solved in closed form; a particle in crossed fields with
+ *                   E + v x B = 0 keeps its momentum exactly.
+ * Both are followed by the same position update with gamma(u1). */
+typedef enum { PIC_PUSH_BORIS = 0, PIC_PUSH_VAY = 1 } pic_pusher;
+
 typedef struct {
     int32_t n[3];     /* cells per direction (periodic) */
     double d[3];      /* cell size */
@@ -74,6 +86,7 @@ typedef struct {
                          0 = the largest divisor of n not above 8 */
     int32_t slack;    /* cells of halo slack around a tile for particles that
                          drifted since the last sort; -1 = automatic */
+    int32_t pusher;   /* pic_pusher; anything else is PIC_E_UNSUPPORTED */
 } pic_grid;
 
 typedef struct {

@@ -223,6 +223,8 @@ pic_status check_grid(const pic_grid *g, GridInfo &gi)
         return fail(PIC_E_INVALID, "dt, c and eps0 must be positive and finite");
     if (g->order != 1 && g->order != 3)
         return fail(PIC_E_UNSUPPORTED, "shape order must be 1 or 3");
+    if (g->pusher != PIC_PUSH_BORIS && g->pusher != PIC_PUSH_VAY)
+        return fail(PIC_E_UNSUPPORTED, "pusher must be PIC_PUSH_BORIS or PIC_PUSH_VAY");
     if (g->dtype != PIC_F32 && g->dtype != PIC_F64)
         return fail(PIC_E_UNSUPPORTED, "dtype must be PIC_F32 or PIC_F64");
     const double inv = 1.0 / (g->d[0] * g->d[0]) + 1.0 / (g->d[1] * g->d[1]) + 1.0 / (g->d[2] * g->d[2]);
@@ -390,6 +392,7 @@ PConst<T> make_const(const pic_grid *g, const pic_species *s)
     pc.inv_c2 = (T)(1.0 / (g->c * g->c));
     pc.w0 = s ? (T)s->w0 : T(0);
     pc.lj = (T)(-g->dt / g->eps0);
+    pc.vay = g->pusher == PIC_PUSH_VAY ? 1 : 0;
     return pc;
 }
 

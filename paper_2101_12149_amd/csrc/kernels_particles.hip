@@ -52,6 +52,18 @@ __device__ inline int wrap_any(int v, int n)
     return r < 0 ? r + n : r;
 }
 
+// momentum update of the push: Boris or Vay (uniform across the launch)
+template <typename T>
+__device__ inline void push_momentum(const PConst<T> &pc, const T *u, const T *E, const T *B, T *u1)
+{
+    if (pc.vay) {
+        vay(pc.h, pc.inv_c2, u, E, B, u1);
+    } else {
+        BorisTape<T> tp;
+        boris(pc.h, pc.inv_c2, u, E, B, u1, tp);
+    }
+}
+
 template <typename T>
 __device__ inline bool finite3(const T *u)
 {
@@ -302,9 +314,8 @@ __device__ __attribute__((always_inline)) inline bool particle_advance(const PCo
     T E[3], B[3];
     gather_eb<O>(fsrc, aw, on, os, E, B);
 
-    BorisTape<T> tp;
     T u1[3];
-    boris(pc.h, pc.inv_c2, u, E, B, u1, tp);
+    push_momentum(pc, u, E, B, u1);
     const T ig = T(1) / sqrt(T(1) + (u1[0] * u1[0] + u1[1] * u1[1] + u1[2] * u1[2]) * pc.inv_c2);
     bool ok = true;
 #pragma unroll
@@ -802,9 +813,8 @@ __global__ void __launch_bounds__(256) k_push(PConst<T> pc, PArr<T> sp, const T 
     if (!load_particle(sp, p, pc.n, c, f, u, err))
         return;
     const T E[3] = {Ex[p], Ey[p], Ez[p]}, B[3] = {Bx[p], By[p], Bz[p]};
-    BorisTape<T> tp;
     T u1[3];
-    boris(pc.h, pc.inv_c2, u, E, B, u1, tp);
+    push_momentum(pc, u, E, B, u1);
     const T ig = T(1) / sqrt(T(1) + (u1[0] * u1[0] + u1[1] * u1[1] + u1[2] * u1[2]) * pc.inv_c2);
     T f1[3];
     int kap[3];
@@ -1036,9 +1046,8 @@ __device__ __attribute__((always_inline)) inline void adjoint_push_particle(cons
     int kap[3];
     bool ok = true;
     {
-        BorisTape<T> tp;
         T u1[3];
-        boris(pc.h, pc.inv_c2, u, E, B, u1, tp);
+        push_momentum(pc, u, E, B, u1);
         const T ig = T(1) / sqrt(T(1) + (u1[0] * u1[0] + u1[1] * u1[1] + u1[2] * u1[2]) * pc.inv_c2);
 #pragma unroll
         for (int d = 0; d < 3; ++d) {
@@ -1070,13 +1079,17 @@ __device__ __attribute__((always_inline)) inline void adjoint_push_particle(cons
         }
         esk_gather_adjoint<O>(e, f, f1, kap, jo, K, [&](int m, int idx) { return hsrc[m][idx]; }, g0, g1);
     }
-    // The Boris step again, for its tape: only E and B stay live across the
-    // deposit transpose.  The register operands keep the compiler from
-    // reusing the first evaluation; the inputs and so the values are the same.
+    // The momentum update again (for Boris, with its tape): only E and B stay
+    // live across the deposit transpose.  The register operands keep the
+    // compiler from reusing the first evaluation; the inputs and so the values
+    // are the same.
     asm volatile("" : "+v"(E[0]), "+v"(E[1]), "+v"(E[2]), "+v"(B[0]), "+v"(B[1]), "+v"(B[2]));
     BorisTape<T> tp;
     T u1[3];
-    boris(pc.h, pc.inv_c2, u, E, B, u1, tp);
+    if (pc.vay)
+        vay(pc.h, pc.inv_c2, u, E, B, u1);
+    else
+        boris(pc.h, pc.inv_c2, u, E, B, u1, tp);
     const T ig = T(1) / sqrt(T(1) + (u1[0] * u1[0] + u1[1] * u1[1] + u1[2] * u1[2]) * pc.inv_c2);
     T lxb[3], v[3], lxa[3];
     T uv = T(0);
@@ -1094,7 +1107,10 @@ __device__ __attribute__((always_inline)) inline void adjoint_push_particle(cons
     for (int d = 0; d < 3; ++d)
         ub[d] = ap.lu[d][p] + v[d] * ig - u1[d] * ig3;
     T u0b[3], Eb[3], Bb[3];
-    boris_adjoint(pc.h, pc.inv_c2, B, tp, ub, u0b, Eb, Bb);
+    if (pc.vay)
+        vay_adjoint(pc.h, pc.inv_c2, u, E, B, ub, u0b, Eb, Bb);
+    else
+        boris_adjoint(pc.h, pc.inv_c2, B, tp, ub, u0b, Eb, Bb);
 #pragma unroll
     for (int d = 0; d < 3; ++d) {
         ap.lu[d][p] = u0b[d];

@@ -273,6 +273,126 @@ __device__ inline void boris_adjoint(T h, T inv_c2, const T *B, const BorisTape<
 }
 
 // ---------------------------------------------------------------------------
+// Vay's relativistic push (Vay 2008; the paper's pusher for relativistic
+// beams, Sec. 4.2).  The magnetic force uses the mean of the old and new
+// velocities, an equation implicit in u1.  With the known part
+// w = u0 + 2h E + h (u0/g0) x B and tau = h B it is u1 - u1 x (tau/g1) = w:
+// for the new gamma, G = g1^2 solves G^2 - sigma G - X = 0 with
+// sigma = 1 + |w|^2/c^2 - |tau|^2 and X = |tau|^2 + (w.tau)^2/c^2 (its
+// positive root, in the form without cancellation for sigma < 0); then with
+// t = tau/g1 the linear system gives u1 = (w + (w.t) t + w x t) / (1 + |t|^2).
+
+template <typename T>
+__device__ inline T dot3(const T *a, const T *b)
+{
+    return a[0] * b[0] + a[1] * b[1] + a[2] * b[2];
+}
+
+// the known part w, tau = h B and the new gamma's square G (with D = sqrt(sigma^2 + 4X))
+template <typename T>
+__device__ inline void vay_setup(T h, T inv_c2, const T *u0, const T *E, const T *B, T *v0, T *w, T *tau, T &G,
+                                 T &D, T &sigma)
+{
+    const T ig0 = T(1) / sqrt(T(1) + dot3(u0, u0) * inv_c2);
+#pragma unroll
+    for (int d = 0; d < 3; ++d)
+        v0[d] = u0[d] * ig0;
+    T vb[3];
+    cross3(v0, B, vb);
+#pragma unroll
+    for (int d = 0; d < 3; ++d) {
+        w[d] = u0[d] + T(2) * h * E[d] + h * vb[d];
+        tau[d] = h * B[d];
+    }
+    const T tau2 = dot3(tau, tau), wt = dot3(w, tau);
+    sigma = T(1) + dot3(w, w) * inv_c2 - tau2;
+    const T X = tau2 + wt * wt * inv_c2;
+    D = sqrt(sigma * sigma + T(4) * X);
+    G = sigma >= T(0) ? T(0.5) * (sigma + D) : T(2) * X / (D - sigma);
+}
+
+template <typename T>
+__device__ inline void vay(T h, T inv_c2, const T *u0, const T *E, const T *B, T *u1)
+{
+    T v0[3], w[3], tau[3], G, D, sigma;
+    vay_setup(h, inv_c2, u0, E, B, v0, w, tau, G, D, sigma);
+    const T ig1 = T(1) / sqrt(G);
+    T t[3];
+#pragma unroll
+    for (int d = 0; d < 3; ++d)
+        t[d] = tau[d] * ig1;
+    T wxt[3];
+    cross3(w, t, wxt);
+    const T a = dot3(w, t), s = T(1) / (T(1) + dot3(t, t));
+#pragma unroll
+    for (int d = 0; d < 3; ++d)
+        u1[d] = s * (w[d] + a * t[d] + wxt[d]);
+}
+
+// Transpose of vay(): given ub = dL/du1, return dL/du0, dL/dE, dL/dB.  The
+// forward quantities are evaluated again; dG/dsigma = G/D, dG/dX = 1/D.
+template <typename T>
+__device__ inline void vay_adjoint(T h, T inv_c2, const T *u0, const T *E, const T *B, const T *ub, T *u0b, T *Eb,
+                                   T *Bb)
+{
+    T v0[3], w[3], tau[3], G, D, sigma;
+    vay_setup(h, inv_c2, u0, E, B, v0, w, tau, G, D, sigma);
+    const T g1 = sqrt(G), ig1 = T(1) / g1;
+    T t[3];
+#pragma unroll
+    for (int d = 0; d < 3; ++d)
+        t[d] = tau[d] * ig1;
+    T wxt[3];
+    cross3(w, t, wxt);
+    const T a = dot3(w, t), s = T(1) / (T(1) + dot3(t, t));
+    // u1 = s q, q = w + a t + w x t
+    T q[3], qb[3];
+#pragma unroll
+    for (int d = 0; d < 3; ++d) {
+        q[d] = w[d] + a * t[d] + wxt[d];
+        qb[d] = s * ub[d];
+    }
+    const T sb = dot3(ub, q);
+    T wb[3], tb[3], tmp[3];
+    cross3(t, qb, tmp);            // d((w x t).qb)/dw = t x qb
+#pragma unroll
+    for (int d = 0; d < 3; ++d)
+        wb[d] = qb[d] + tmp[d];
+    cross3(qb, w, tmp);            // d((w x t).qb)/dt = qb x w
+    const T ab = dot3(qb, t);      // dL/da, a = w.t
+    const T c1 = T(-2) * s * s * sb;   // s = 1/(1 + |t|^2)
+#pragma unroll
+    for (int d = 0; d < 3; ++d) {
+        tb[d] = a * qb[d] + tmp[d] + ab * w[d] + c1 * t[d];
+        wb[d] += ab * t[d];
+    }
+    // t = tau / g1, g1 = sqrt(G)
+    const T g1b = -dot3(tb, t) * ig1;
+    const T Gb = T(0.5) * g1b * ig1;
+    const T sigb = Gb * G / D, Xb = Gb / D;
+    const T wt = dot3(w, tau);
+    const T wtb = T(2) * Xb * wt * inv_c2;   // X = |tau|^2 + (w.tau)^2/c^2
+    T taub[3];
+#pragma unroll
+    for (int d = 0; d < 3; ++d) {
+        taub[d] = tb[d] * ig1 + T(2) * Xb * tau[d] - T(2) * sigb * tau[d] + wtb * w[d];
+        wb[d] += T(2) * sigb * w[d] * inv_c2 + wtb * tau[d];
+    }
+    // tau = h B; w = u0 + 2h E + h v0 x B; v0 = u0 / g0
+    T v0b[3], wxv[3];
+    cross3(B, wb, v0b);            // d((v0 x B).wb)/dv0 = B x wb
+    cross3(wb, v0, wxv);           // d((v0 x B).wb)/dB = wb x v0
+    const T ig0 = T(1) / sqrt(T(1) + dot3(u0, u0) * inv_c2);
+    const T g0b = -h * dot3(v0b, v0) * ig0;   // dL/dg0 through v0 = u0/g0
+#pragma unroll
+    for (int d = 0; d < 3; ++d) {
+        Bb[d] = h * (taub[d] + wxv[d]);
+        Eb[d] = T(2) * h * wb[d];
+        u0b[d] = wb[d] + h * v0b[d] * ig0 + g0b * v0[d] * inv_c2;
+    }
+}
+
+// ---------------------------------------------------------------------------
 // Position update in split representation, one axis: f += disp; the integer
 // part moves the cell (|disp| < 1 so the shift is -1, 0 or +1); an offset
 // that rounds to exactly 1 belongs to the next cell.

@@ -18,6 +18,7 @@ struct PConst {
     T jk[3];       // -q / (dt d_p d_q): Esirkepov prefactor per unit weight
     T w0;          // weight when the species has no weight array
     T lj;          // -dt / eps0: current adjoint from the field adjoint
+    int vay;       // momentum update: 0 Boris, 1 Vay
 };
 
 // Structure-of-arrays particle storage.

@@ -6,6 +6,8 @@ error over the array's scale).  FP32 split precision: rel-L2 of E, B, J
 starting from the FP32 state upcast exactly to FP64.  Sizes span several
 tiles with a ragged last tile where the grid allows it.
 """
+import dataclasses
+
 import numpy as np
 import pytest
 import torch
@@ -65,6 +67,37 @@ def test_push_matches_oracle(dtype):
     dxy = np.abs(gx - ox)
     dxy = np.minimum(dxy, np.abs(dxy - np.array(g.n)[:, None]))
     assert dxy.max() < (1e-13 if dtype == "f64" else 2e-6)
+
+
+@pytest.mark.parametrize("dtype", ["f64", "f32"])
+def test_vay_push_matches_oracle(dtype):
+    """Vay's momentum update in strong fields (|q B dt / 2m| up to ~1): the
+    oracle's Vay result within the tolerances of the Boris test, and far from
+    what Boris gives on the same input (the grid's pusher field is honoured)."""
+    g = dataclasses.replace(_grid(), pusher=1)
+    sp = random_species(g, 5000, 23, u_th=0.8, dtype=dtype)
+    rng = np.random.default_rng(24)
+    Ep = torch.tensor(rng.normal(0, 2.0, (3, 5000)), dtype=tdtype(dtype))
+    Bp = torch.tensor(rng.normal(0, 8.0, (3, 5000)), dtype=tdtype(dtype))
+    d_sp = dev(sp)
+    _lib.pic_push(g, d_sp, dev(Ep), dev(Bp))
+    torch.cuda.synchronize()
+    o = sp.numpy()
+    E64, B64 = np.ascontiguousarray(_cpu(Ep)), np.ascontiguousarray(_cpu(Bp))
+    oracle.push(g, o, E64, B64)
+    tol = F64_TOL if dtype == "f64" else 2e-6
+    assert max_rel(_cpu(d_sp.u), o.u) < tol
+    ob = sp.numpy()
+    oracle.push(dataclasses.replace(g, pusher=0), ob, E64, B64)
+    assert max_rel(_cpu(d_sp.u), ob.u) > 1e-3
+
+
+def test_unknown_pusher_is_rejected():
+    g = dataclasses.replace(_grid(), pusher=2)
+    sp = dev(random_species(g, 10, 25))
+    E = torch.zeros((3, 10), dtype=torch.float64, device="cuda")
+    with pytest.raises(_lib.PicError, match="pusher"):
+        _lib.pic_push(g, sp, E, E)
 
 
 def _displaced(g, sp, seed, amp=0.9):
@@ -244,6 +277,26 @@ def test_order3_tiled_f64_matches_oracle(sort_every):
     gt, ot = particle_table(gsp), particle_table(osp)
     assert np.array_equal(gt[:, :3], ot[:, :3])
     assert rel_l2(gt[:, 3:], ot[:, 3:]) < F64_TOL
+
+
+@pytest.mark.parametrize("dtype", ["f64", "f32"])
+def test_vay_steps_match_oracle(dtype):
+    """Relativistic plasma (u_th = 0.5c) in strong random fields, order 3,
+    Vay's pusher, tiled with re-sorting (FP64: 4 steps, fields and particles
+    within 1e-12; FP32: one step, E, B, J within rel-L2 1e-5)."""
+    nsteps = 4 if dtype == "f64" else 1
+    w = wl.uniform_plasma((16, 24, 20), 3, 0.5, 3, nsteps, dtype, 75, 2, shuffle=True)
+    w.grid = dataclasses.replace(w.grid, pusher=1)
+    w.fields = random_fields(w.grid, 76, scale=0.5, dtype=dtype)
+    gsp, gf, _ = _run_gpu_steps(w, nsteps, 2)
+    osp, of, _ = _run_oracle(w, nsteps)
+    tol = F64_TOL if dtype == "f64" else 1e-5
+    for name in ("E", "B", "J"):
+        assert rel_l2(_cpu(getattr(gf, name)), getattr(of, name)) < tol, name
+    if dtype == "f64":
+        gt, ot = particle_table(gsp), particle_table(osp)
+        assert np.array_equal(gt[:, :3], ot[:, :3])
+        assert rel_l2(gt[:, 3:], ot[:, 3:]) < F64_TOL
 
 
 def test_untiled_step_matches_oracle_particle_by_particle():
