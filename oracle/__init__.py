@@ -37,7 +37,8 @@ def build():
 
 class _Grid(C.Structure):
     _fields_ = [("n", C.c_int32 * 3), ("d", C.c_double * 3), ("dt", C.c_double),
-                ("c", C.c_double), ("eps0", C.c_double), ("order", C.c_int32), ("pusher", C.c_int32)]
+                ("c", C.c_double), ("eps0", C.c_double), ("order", C.c_int32), ("pusher", C.c_int32),
+                ("solver", C.c_int32)]
 
 
 class _Species(C.Structure):
@@ -106,6 +107,9 @@ def _grid(g):
     s.pusher = int(getattr(g, "pusher", 0))
     if s.pusher not in (0, 1):
         raise ValueError("pusher must be 0 (Boris) or 1 (Vay)")
+    s.solver = int(getattr(g, "solver", 0))
+    if s.solver not in (0, 1):
+        raise ValueError("solver must be 0 (Yee) or 1 (CKC)")
     return s
 
 

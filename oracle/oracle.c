@@ -48,6 +48,7 @@ typedef struct {
     double dt, c, eps0;
     int32_t order;
     int32_t pusher; /* 0: Boris, 1: Vay */
+    int32_t solver; /* 0: Yee, 1: Cole-Karkkainen-Cowan */
 } or_grid;
 
 typedef struct {
@@ -611,32 +612,117 @@ void or_rho(const or_grid *g, const or_species *s, double *rho)
  * One step: B -= dt/2 curlE; E += dt (c^2 curlB - J/eps0); source;
  *           B -= dt/2 curlE.                                           */
 
-static void curl_fwd(const or_grid *g, double *const F[3], double *out[3])
+/* Cole-Karkkainen-Cowan field solver (the paper's solver for the
+ * accelerator stage, Sec. 4.2; Cole 1997/2002, Karkkainen et al. 2006): the
+ * E update keeps Yee's differences, and in the B update every difference
+ * along axis a is averaged over its transverse neighbours p, q:
+ *   D_a -> alpha_a D_a + beta_ap (D_a[p+1] + D_a[p-1]) + beta_aq (D_a[q+1] + D_a[q-1])
+ *          + gamma_a (D_a[p+1,q+1] + D_a[p+1,q-1] + D_a[p-1,q+1] + D_a[p-1,q-1]).
+ * With delta = min cell size, r_a = (delta/d_a)^2, S = r_x r_y + r_y r_z + r_z r_x:
+ *   beta = (1 - r_x r_y r_z / S) / 8,  beta_ap = r_p beta,  beta_aq = r_q beta,
+ *   gamma_a = r_p r_q (1/16 - r_p r_q / (8 S)),
+ *   alpha_a = 1 - 2 beta_ap - 2 beta_aq - 4 gamma_a,
+ * for cubic cells 7/12, 1/12, 1/48; the step is stable up to c dt = delta
+ * and has no dispersion along an axis with d_a = delta at that step.      */
+static void ckc_coeffs(const or_grid *g, double co[3][4])
 {
-    /* out = curl F with forward differences (edges -> faces) */
+    double dl = g->d[0];
+    for (int a = 1; a < 3; ++a)
+        if (g->d[a] < dl)
+            dl = g->d[a];
+    double r[3];
+    for (int a = 0; a < 3; ++a)
+        r[a] = (dl / g->d[a]) * (dl / g->d[a]);
+    double S = r[0] * r[1] + r[1] * r[2] + r[2] * r[0];
+    double beta = (1.0 - r[0] * r[1] * r[2] / S) / 8.0;
+    for (int a = 0; a < 3; ++a) {
+        int p = (a + 1) % 3, q = (a + 2) % 3;
+        double bp = r[p] * beta, bq = r[q] * beta;
+        double gm = r[p] * r[q] * (1.0 / 16.0 - r[p] * r[q] / (8.0 * S));
+        co[a][0] = 1.0 - 2.0 * bp - 2.0 * bq - 4.0 * gm;
+        co[a][1] = bp;
+        co[a][2] = bq;
+        co[a][3] = gm;
+    }
+}
+
+/* Difference of component F along axis a at cell (i,j,k): forward
+ * (F[+a] - F) or backward (F - F[-a]), divided by d_a; with co != NULL
+ * averaged over the transverse neighbours as above. */
+static double diff_axis(const or_grid *g, const double *F, int a, int fwd, int64_t i, int64_t j, int64_t k,
+                        const double co[3][4])
+{
+    int64_t c0[3] = {i, j, k};
+    int p = (a + 1) % 3, q = (a + 2) % 3;
+    double sum = 0.0;
+    for (int sp = -1; sp <= 1; ++sp)
+        for (int sq = -1; sq <= 1; ++sq) {
+            double w;
+            if (!co)
+                w = (sp == 0 && sq == 0) ? 1.0 : 0.0;
+            else if (sp == 0 && sq == 0)
+                w = co[a][0];
+            else if (sq == 0)
+                w = co[a][1];
+            else if (sp == 0)
+                w = co[a][2];
+            else
+                w = co[a][3];
+            if (w == 0.0)
+                continue;
+            int64_t c[3] = {c0[0], c0[1], c0[2]};
+            c[p] += sp;
+            c[q] += sq;
+            int64_t o = idx3(g, c[0], c[1], c[2]);
+            int64_t cn[3] = {c[0], c[1], c[2]};
+            cn[a] += fwd ? 1 : -1;
+            int64_t on = idx3(g, cn[0], cn[1], cn[2]);
+            sum += w * (fwd ? F[on] - F[o] : F[o] - F[on]);
+        }
+    return sum / g->d[a];
+}
+
+/* out = curl F with forward differences (edges -> faces) or backward
+ * differences (faces -> edges), Yee's or the CKC-averaged ones. */
+static void curl_any(const or_grid *g, double *const F[3], double *out[3], int fwd, int ckc)
+{
+    double co[3][4];
+    ckc_coeffs(g, co);
+    const double(*cp)[4] = ckc ? (const double(*)[4])co : NULL;
     for (int64_t k = 0; k < g->n[2]; ++k)
         for (int64_t j = 0; j < g->n[1]; ++j)
             for (int64_t i = 0; i < g->n[0]; ++i) {
                 int64_t o = idx3(g, i, j, k);
-                int64_t xp = idx3(g, i + 1, j, k), yp = idx3(g, i, j + 1, k), zp = idx3(g, i, j, k + 1);
-                out[0][o] = (F[2][yp] - F[2][o]) / g->d[1] - (F[1][zp] - F[1][o]) / g->d[2];
-                out[1][o] = (F[0][zp] - F[0][o]) / g->d[2] - (F[2][xp] - F[2][o]) / g->d[0];
-                out[2][o] = (F[1][xp] - F[1][o]) / g->d[0] - (F[0][yp] - F[0][o]) / g->d[1];
+                out[0][o] = diff_axis(g, F[2], 1, fwd, i, j, k, cp) - diff_axis(g, F[1], 2, fwd, i, j, k, cp);
+                out[1][o] = diff_axis(g, F[0], 2, fwd, i, j, k, cp) - diff_axis(g, F[2], 0, fwd, i, j, k, cp);
+                out[2][o] = diff_axis(g, F[1], 0, fwd, i, j, k, cp) - diff_axis(g, F[0], 1, fwd, i, j, k, cp);
             }
+}
+
+/* The curl of E in the B update (the solver's) and of B in the E update. */
+static void curl_fwd(const or_grid *g, double *const F[3], double *out[3])
+{
+    curl_any(g, F, out, 1, g->solver == 1);
 }
 
 static void curl_bwd(const or_grid *g, double *const F[3], double *out[3])
 {
-    /* out = curl F with backward differences (faces -> edges) */
-    for (int64_t k = 0; k < g->n[2]; ++k)
-        for (int64_t j = 0; j < g->n[1]; ++j)
-            for (int64_t i = 0; i < g->n[0]; ++i) {
-                int64_t o = idx3(g, i, j, k);
-                int64_t xm = idx3(g, i - 1, j, k), ym = idx3(g, i, j - 1, k), zm = idx3(g, i, j, k - 1);
-                out[0][o] = (F[2][o] - F[2][ym]) / g->d[1] - (F[1][o] - F[1][zm]) / g->d[2];
-                out[1][o] = (F[0][o] - F[0][zm]) / g->d[2] - (F[2][o] - F[2][xm]) / g->d[0];
-                out[2][o] = (F[1][o] - F[1][xm]) / g->d[0] - (F[0][o] - F[0][ym]) / g->d[1];
-            }
+    curl_any(g, F, out, 0, 0);
+}
+
+/* Transposes: the transpose of the periodic forward difference is minus
+ * the backward one (and the curl flips the sign back), and the CKC
+ * averaging is symmetric and commutes with the differences, so
+ * curl_fwd^T = curl_bwd with the same averaging and curl_bwd^T = Yee's
+ * curl_fwd. */
+static void curl_fwd_T(const or_grid *g, double *const F[3], double *out[3])
+{
+    curl_any(g, F, out, 0, g->solver == 1);
+}
+
+static void curl_bwd_T(const or_grid *g, double *const F[3], double *out[3])
+{
+    curl_any(g, F, out, 1, 0);
 }
 
 static int64_t ncells(const or_grid *g)
@@ -798,6 +884,8 @@ double or_loss(const or_grid *g, const or_fields *f, or_adjoint *lam, int64_t np
  *
  * Field solve transpose (the periodic forward difference is minus the
  * transpose of the backward one, so curl_fwd^T = curl_bwd):
+ * (with the CKC solver the curls below that transpose the B update's carry
+ * its transverse averaging)
  *   lhatE = lE - dt/2 curl_bwd(lB);  dA += g(n) lhatE_x[:,:,k_s]
  *   lJ    = -dt/eps0 lhatE
  *   lB'   = lB + dt c^2 curl_fwd(lhatE)
@@ -920,7 +1008,7 @@ void or_step_adjoint(const or_grid *g, const or_species *s, const or_fields *f, 
     double *C[3] = {buf + 3 * nc, buf + 4 * nc, buf + 5 * nc};
     double *lJ[3] = {buf + 6 * nc, buf + 7 * nc, buf + 8 * nc};
     /* field solve transpose */
-    curl_bwd(g, lam->lB, C);
+    curl_fwd_T(g, lam->lB, C);
     for (int m = 0; m < 3; ++m)
         for (int64_t i = 0; i < nc; ++i)
             hatE[m][i] = lam->lE[m][i] - 0.5 * g->dt * C[m][i];
@@ -933,11 +1021,11 @@ void or_step_adjoint(const or_grid *g, const or_species *s, const or_fields *f, 
     for (int m = 0; m < 3; ++m)
         for (int64_t i = 0; i < nc; ++i)
             lJ[m][i] = -g->dt / g->eps0 * hatE[m][i];
-    curl_fwd(g, hatE, C);
+    curl_bwd_T(g, hatE, C);
     for (int m = 0; m < 3; ++m)
         for (int64_t i = 0; i < nc; ++i)
             lam->lB[m][i] += g->dt * g->c * g->c * C[m][i];
-    curl_bwd(g, lam->lB, C);
+    curl_fwd_T(g, lam->lB, C);
     for (int m = 0; m < 3; ++m)
         for (int64_t i = 0; i < nc; ++i)
             lam->lE[m][i] = hatE[m][i] - 0.5 * g->dt * C[m][i];

@@ -35,6 +35,7 @@ class Grid:
     tile: tuple = (0, 0, 0)   # sort/LDS tile edge per direction (0: library default)
     slack: int = -1     # halo slack of the tiled particle kernel (-1: automatic)
     pusher: int = 0     # momentum update: 0 Boris, 1 Vay
+    solver: int = 0     # field solver: 0 Yee, 1 Cole-Karkkainen-Cowan
 
     @property
     def ncells(self) -> int:

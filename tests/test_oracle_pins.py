@@ -393,6 +393,118 @@ def test_yee_discrete_plane_wave_eigenmode():
     assert abs(omega - np.linalg.norm(kvec)) * t > 1e-3
 
 
+def _ckc_published(d):
+    """Cole-Karkkainen-Cowan coefficients (alpha, beta_p, beta_q, gamma) per
+    derivative axis, in the published closed form (delta = min cell size)."""
+    d = np.asarray(d, float)
+    r = (d.min() / d) ** 2
+    S = r[0] * r[1] + r[1] * r[2] + r[2] * r[0]
+    beta = (1 - r.prod() / S) / 8
+    co = []
+    for a in range(3):
+        p, q = (a + 1) % 3, (a + 2) % 3
+        gm = r[p] * r[q] * (1 / 16 - r[p] * r[q] / (8 * S))
+        co.append((1 - 2 * r[p] * beta - 2 * r[q] * beta - 4 * gm, r[p] * beta, r[q] * beta, gm))
+    return co
+
+
+def test_ckc_published_coefficients_for_cubic_cells():
+    """The cubic-cell values of the published scheme: 7/12, 1/12, 1/48."""
+    for al, bp, bq, gm in _ckc_published((0.2, 0.2, 0.2)):
+        assert (al, bp, bq, gm) == pytest.approx((7 / 12, 1 / 12, 1 / 12, 1 / 48), rel=1e-14)
+
+
+def test_ckc_discrete_plane_wave_eigenmode():
+    """With the CKC solver the B update's difference along a carries the
+    transverse average A_a(k) = alpha + 2 beta_p cos(k_p d_p)
+    + 2 beta_q cos(k_q d_q) + 4 gamma cos cos, so a divergence-free E0 with
+    B0 = cos(omega dt/2) (K' x E0 / W), K'_a = K_a A_a, is an eigenmode with
+    sin(omega dt/2) = (c dt/2) sqrt(K . K').  Oblique k, unequal cells; the
+    Yee frequency for the same k is far off."""
+    g = grid(n=(16, 12, 20), d=(0.2, 0.25, 0.15), dt=0.12)
+    g.solver = 1
+    dd = np.array(g.d)
+    L = np.array(g.n) * dd
+    kvec = 2 * np.pi * np.array([3, -2, 4]) / L
+    K = 2 / dd * np.sin(kvec * dd / 2)
+    co = _ckc_published(g.d)
+    A = np.array([co[a][0] + 2 * co[a][1] * math.cos(kvec[(a + 1) % 3] * dd[(a + 1) % 3])
+                  + 2 * co[a][2] * math.cos(kvec[(a + 2) % 3] * dd[(a + 2) % 3])
+                  + 4 * co[a][3] * math.cos(kvec[(a + 1) % 3] * dd[(a + 1) % 3])
+                  * math.cos(kvec[(a + 2) % 3] * dd[(a + 2) % 3]) for a in range(3)])
+    Kp = K * A
+    E0 = np.cross(K, [0.3, 1.0, -0.4])
+    E0 /= np.linalg.norm(E0)
+    s = g.c * g.dt * math.sqrt(K @ Kp) / 2
+    assert s < 1
+    omega = 2 * math.asin(s) / g.dt
+    W = 2 * math.sin(omega * g.dt / 2) / g.dt
+    B0 = np.cross(Kp, E0) / W * math.cos(omega * g.dt / 2)
+    f = zero_fields(g)
+    for m in range(3):
+        f.E[m] = _mode(g, kvec, E0[m], STAG_E[m])
+        f.B[m] = _mode(g, kvec, B0[m], STAG_B[m])
+    nst = 40
+    for n in range(nst):
+        oracle.yee(g, f, None, n)
+    t = nst * g.dt
+    for m in range(3):
+        np.testing.assert_allclose(f.E[m], _mode(g, kvec, E0[m], STAG_E[m], omega * t), atol=1e-12)
+        np.testing.assert_allclose(f.B[m], _mode(g, kvec, B0[m], STAG_B[m], omega * t), atol=1e-12)
+    omega_yee = 2 * math.asin(g.c * g.dt * np.linalg.norm(K) / 2) / g.dt
+    assert abs(omega - omega_yee) * t > 1e-2
+
+
+def test_ckc_axis_wave_has_no_dispersion_at_the_magic_time_step():
+    """Along the axis with the smallest cell and c dt equal to that cell, a
+    wave of any wavelength moves at exactly c (the transverse average of a
+    transversely uniform wave is the identity: the coefficients sum to 1)."""
+    g = grid(n=(16, 8, 8), d=(0.2, 0.25, 0.3), dt=0.2)
+    g.solver = 1
+    for kx in (1, 5, 7):
+        kvec = np.array([2 * np.pi * kx / (16 * 0.2), 0.0, 0.0])
+        E0 = np.array([0.0, 1.0, 0.0])
+        omega = np.linalg.norm(kvec)      # exact, c = 1
+        W = 2 * math.sin(omega * g.dt / 2) / g.dt
+        K = np.array([2 / 0.2 * math.sin(kvec[0] * 0.2 / 2), 0, 0])
+        B0 = np.cross(K, E0) / W * math.cos(omega * g.dt / 2)
+        f = zero_fields(g)
+        for m in range(3):
+            f.E[m] = _mode(g, kvec, E0[m], STAG_E[m])
+            f.B[m] = _mode(g, kvec, B0[m], STAG_B[m])
+        for n in range(24):
+            oracle.yee(g, f, None, n)
+        np.testing.assert_allclose(f.E[1], _mode(g, kvec, 1.0, STAG_E[1], omega * 24 * g.dt), atol=1e-12)
+
+
+def _energy_after(g, nsteps, seed):
+    f = zero_fields(g)
+    rng = np.random.default_rng(seed)
+    f.E[:] = rng.normal(size=f.E.shape)
+    f.B[:] = rng.normal(size=f.B.shape)
+    e0 = np.sum(f.E ** 2) + np.sum(f.B ** 2)
+    for n in range(nsteps):
+        oracle.yee(g, f, None, n)
+    return (np.sum(f.E ** 2) + np.sum(f.B ** 2)) / e0
+
+
+def test_ckc_is_stable_up_to_the_smallest_cell_and_yee_is_not():
+    """The CKC step is stable up to c dt = min d (its extended stencil makes
+    the highest mode exactly marginal there), unstable just beyond; Yee's
+    limit is 1/sqrt(sum 1/d^2), well below.  Near the limit the plain field
+    energy of random fields oscillates by several times (the leapfrog keeps
+    a modified energy), so "stable" is a bound far below the growth."""
+    d = (0.3, 0.25, 0.35)
+    ckc_ok = grid(n=(8, 8, 8), d=d, dt=0.995 * 0.25)
+    ckc_ok.solver = 1
+    assert _energy_after(ckc_ok, 400, 31) < 20
+    ckc_bad = grid(n=(8, 8, 8), d=d, dt=1.03 * 0.25)
+    ckc_bad.solver = 1
+    assert _energy_after(ckc_bad, 60, 31) > 1e6
+    yee = grid(n=(8, 8, 8), d=d, dt=0.995 * 0.25)
+    assert _energy_after(yee, 60, 31) > 1e6
+
+
 def test_yee_source_adds_on_plane_and_keeps_divB():
     g = grid(n=(8, 8, 8))
     f = zero_fields(g)
@@ -475,9 +587,12 @@ def test_reductions_closed_forms():
 # --------------------------------------------------------------------------
 # adjoint
 
-def test_adjoint_field_solve_dot_product():
-    """With no particles the step is linear in (E, B): <M x, y> = <x, M^T y>."""
+@pytest.mark.parametrize("solver", [0, 1])
+def test_adjoint_field_solve_dot_product(solver):
+    """With no particles the step is linear in (E, B): <M x, y> = <x, M^T y>
+    (Yee, and CKC whose B update carries the transverse average)."""
     g = grid(n=(6, 5, 7))
+    g.solver = solver
     rng = np.random.default_rng(8)
     f = zero_fields(g)
     f.E[:] = rng.normal(size=f.E.shape)
@@ -551,13 +666,13 @@ def test_adjoint_matches_central_finite_differences(order, pusher):
         assert 10 * np.finfo(float).eps * abs(L) / eps < 1e-6 * abs(an)   # noise below the bar
 
 
-@pytest.mark.parametrize("pusher", [0, 1])
-def test_adjoint_position_and_field_gradients_by_finite_differences(pusher):
+@pytest.mark.parametrize("pusher,solver", [(0, 0), (1, 0), (0, 1)])
+def test_adjoint_position_and_field_gradients_by_finite_differences(pusher, solver):
     """dL/dx0 and dL/dE0, dL/dB0 from the reverse sweep against central
     differences (pins the deposit transpose in both positions, the gather
     transpose and the transpose of either momentum update)."""
     w = wl.differentiable((8, 8, 8), 1, 0.08, 3, 2, "f64", 4321, amp0=0.0)
-    g = dataclasses.replace(w.grid, pusher=pusher)
+    g = dataclasses.replace(w.grid, pusher=pusher, solver=solver)
     sp, f = w.species.numpy(), w.fields.numpy()
     rng = np.random.default_rng(10)
     f.E[:] = rng.normal(0, 0.1, f.E.shape)
