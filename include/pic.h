@@ -53,7 +53,7 @@ extern "C" {
 typedef enum {
     PIC_OK = 0,
     PIC_E_INVALID = 1,     /* null pointer, bad size, inconsistent argument */
-    PIC_E_CFL = 2,         /* c dt > 1/sqrt(sum 1/d^2): Yee step unstable */
+    PIC_E_CFL = 2,         /* c dt beyond the solver's stability limit */
     PIC_E_UNSUPPORTED = 3, /* order not in {1,3}, dtype unknown, tile too big */
     PIC_E_WORKSPACE = 4,   /* workspace missing or smaller than pic_workspace_bytes */
     PIC_E_STATE = 5,       /* corrupt particle state found on the device */
@@ -74,6 +74,20 @@ typedef enum { PIC_F32 = 0, PIC_F64 = 1 } pic_dtype;
  * Both are followed by the same position update with gamma(u1). */
 typedef enum { PIC_PUSH_BORIS = 0, PIC_PUSH_VAY = 1 } pic_pusher;
 
+/* Field solver of the leapfrog step.
+ *   PIC_SOLVER_YEE  Yee's FDTD (Sec. 4.1.1); stable for c dt <= 1/sqrt(sum 1/d^2).
+ *   PIC_SOLVER_CKC  Cole-Karkkainen-Cowan FDTD, the paper's solver for the
+ *                   accelerator stage (Sec. 4.2): the E update keeps Yee's
+ *                   differences, the B update averages each difference along
+ *                   axis a over its transverse neighbours with weights alpha_a
+ *                   (centre), beta_ap, beta_aq (edges), gamma_a (corners); with
+ *                   delta = min d, r_a = (delta/d_a)^2, S = sum of r_a r_b (a<b):
+ *                   beta = (1 - r_x r_y r_z/S)/8, beta_ap = r_p beta,
+ *                   gamma_a = r_p r_q (1/16 - r_p r_q/(8S)),
+ *                   alpha_a = 1 - 2 beta_ap - 2 beta_aq - 4 gamma_a
+ *                   (7/12, 1/12, 1/48 for cubic cells); stable for c dt <= delta. */
+typedef enum { PIC_SOLVER_YEE = 0, PIC_SOLVER_CKC = 1 } pic_solver;
+
 typedef struct {
     int32_t n[3];     /* cells per direction (periodic) */
     double d[3];      /* cell size */
@@ -87,6 +101,7 @@ typedef struct {
     int32_t slack;    /* cells of halo slack around a tile for particles that
                          drifted since the last sort; -1 = automatic */
     int32_t pusher;   /* pic_pusher; anything else is PIC_E_UNSUPPORTED */
+    int32_t solver;   /* pic_solver; anything else is PIC_E_UNSUPPORTED */
 } pic_grid;
 
 typedef struct {

@@ -29,7 +29,7 @@ class PicError(RuntimeError):
 class pic_grid(C.Structure):
     _fields_ = [("n", C.c_int32 * 3), ("d", C.c_double * 3), ("dt", C.c_double), ("c", C.c_double),
                 ("eps0", C.c_double), ("order", C.c_int32), ("dtype", C.c_int32), ("tile", C.c_int32 * 3),
-                ("slack", C.c_int32), ("pusher", C.c_int32)]
+                ("slack", C.c_int32), ("pusher", C.c_int32), ("solver", C.c_int32)]
 
 
 class pic_species(C.Structure):
@@ -135,6 +135,7 @@ def make_grid(grid, dtype):
     g.tile[:] = [int(v) for v in t]
     g.slack = int(getattr(grid, "slack", -1))
     g.pusher = int(getattr(grid, "pusher", 0))
+    g.solver = int(getattr(grid, "solver", 0))
     return g
 
 

@@ -5,6 +5,7 @@
 // asynchronously on the caller's stream.  The library allocates no device
 // memory: scratch space comes from the caller's workspace, carved at fixed
 // 256-byte-aligned offsets.
+#include <algorithm>
 #include <cmath>
 #include <cstdio>
 #include <cstring>
@@ -227,9 +228,17 @@ pic_status check_grid(const pic_grid *g, GridInfo &gi)
         return fail(PIC_E_UNSUPPORTED, "pusher must be PIC_PUSH_BORIS or PIC_PUSH_VAY");
     if (g->dtype != PIC_F32 && g->dtype != PIC_F64)
         return fail(PIC_E_UNSUPPORTED, "dtype must be PIC_F32 or PIC_F64");
-    const double inv = 1.0 / (g->d[0] * g->d[0]) + 1.0 / (g->d[1] * g->d[1]) + 1.0 / (g->d[2] * g->d[2]);
-    if (g->c * g->dt * std::sqrt(inv) > 1.0 + 1e-12)
-        return fail(PIC_E_CFL, "c dt exceeds the Yee CFL limit 1/sqrt(sum 1/d^2)");
+    if (g->solver != PIC_SOLVER_YEE && g->solver != PIC_SOLVER_CKC)
+        return fail(PIC_E_UNSUPPORTED, "solver must be PIC_SOLVER_YEE or PIC_SOLVER_CKC");
+    if (g->solver == PIC_SOLVER_YEE) {
+        const double inv = 1.0 / (g->d[0] * g->d[0]) + 1.0 / (g->d[1] * g->d[1]) + 1.0 / (g->d[2] * g->d[2]);
+        if (g->c * g->dt * std::sqrt(inv) > 1.0 + 1e-12)
+            return fail(PIC_E_CFL, "c dt exceeds the Yee CFL limit 1/sqrt(sum 1/d^2)");
+    } else {
+        const double dmin = std::min(g->d[0], std::min(g->d[1], g->d[2]));
+        if (g->c * g->dt > dmin * (1.0 + 1e-12))
+            return fail(PIC_E_CFL, "c dt exceeds the CKC CFL limit min(d)");
+    }
     gi.order = g->order;
     gi.dtype = g->dtype;
     gi.tsize = g->dtype == PIC_F64 ? sizeof(double) : sizeof(float);
@@ -457,8 +466,32 @@ pic_status check_source(const pic_source *src, const GridInfo &gi)
     return PIC_OK;
 }
 
-// One Yee step: B -= dt/2 curlE; E += dt (c^2 curlB - J/eps0) + source;
-// B -= dt/2 curlE.  zero_j clears J as it is consumed.
+// CKC weights of the B update's differences (alpha, beta_p, beta_q, gamma
+// per difference axis), from the published closed form in pic.h.
+template <typename T>
+void ckc_weights(const pic_grid *g, CurlArgs<T> &a)
+{
+    const double dl = std::min(g->d[0], std::min(g->d[1], g->d[2]));
+    double r[3];
+    for (int d = 0; d < 3; ++d)
+        r[d] = (dl / g->d[d]) * (dl / g->d[d]);
+    const double S = r[0] * r[1] + r[1] * r[2] + r[2] * r[0];
+    const double beta = (1.0 - r[0] * r[1] * r[2] / S) / 8.0;
+    for (int d = 0; d < 3; ++d) {
+        const int p = (d + 1) % 3, q = (d + 2) % 3;
+        const double bp = r[p] * beta, bq = r[q] * beta;
+        const double gm = r[p] * r[q] * (1.0 / 16.0 - r[p] * r[q] / (8.0 * S));
+        a.ck[d][0] = (T)(1.0 - 2.0 * bp - 2.0 * bq - 4.0 * gm);
+        a.ck[d][1] = (T)bp;
+        a.ck[d][2] = (T)bq;
+        a.ck[d][3] = (T)gm;
+    }
+    a.ckc = 1;
+}
+
+// One field step: B -= dt/2 curlE; E += dt (c^2 curlB - J/eps0) + source;
+// B -= dt/2 curlE (with the CKC solver the curl of E averages transversely).
+// zero_j clears J as it is consumed.
 template <typename T>
 pic_status yee_step(const pic_grid *g, const GridInfo &gi, const FieldPtrs<T> &f, const pic_source *src,
                     int64_t step, bool zero_j, hipStream_t st)
@@ -474,6 +507,8 @@ pic_status yee_step(const pic_grid *g, const GridInfo &gi, const FieldPtrs<T> &f
     b.cy = (T)(-0.5 * g->dt / g->d[1]);
     b.cz = (T)(-0.5 * g->dt / g->d[2]);
     b.kplane = -1;
+    if (g->solver == PIC_SOLVER_CKC)
+        ckc_weights<T>(g, b);
     CurlArgs<T> e{};
     for (int d = 0; d < 3; ++d) {
         e.out[d] = f.E[d];
@@ -719,6 +754,12 @@ pic_status adjoint_t(const pic_grid *g, const GridInfo &gi, const pic_species *s
     e.cy = a.cy;
     e.cz = a.cz;
     e.kplane = -1;
+    // transposes of the B update carry its CKC averaging (symmetric, and it
+    // commutes with the differences); the E update's transpose is Yee's
+    if (g->solver == PIC_SOLVER_CKC) {
+        ckc_weights<T>(g, a);
+        ckc_weights<T>(g, e);
+    }
     PIC_HIP(launch_fill<int>(err, 1, 0, st));
     {
         TimedScope tf(4, st);

@@ -13,7 +13,10 @@ namespace pic {
 //   curl_b(S)_x = (S_z - S_z[j-1])/dy - (S_y - S_y[k-1])/dz
 // The coefficients cx, cy, cz already hold (scale / d).
 
-template <typename T, bool FWD>
+// CKC: each difference along an axis is replaced by the weighted sum of the
+// same difference at the 3x3 cells around it in the transverse plane
+// (centre alpha, edges beta_p / beta_q, corners gamma), periodic.
+template <typename T, bool FWD, bool CKC>
 __global__ void __launch_bounds__(256) k_curl(CurlArgs<T> a)
 {
     const int i = blockIdx.x * blockDim.x + threadIdx.x;
@@ -23,33 +26,29 @@ __global__ void __launch_bounds__(256) k_curl(CurlArgs<T> a)
     if (i >= n0)
         return;
     const int64_t o = i + (int64_t)n0 * (j + (int64_t)n1 * k);
-    int64_t xs, ys, zs;   // neighbour offsets (+1 for forward, -1 for backward), periodic
-    if (FWD) {
-        xs = (i + 1 < n0) ? 1 : 1 - n0;
-        ys = (j + 1 < n1) ? n0 : (int64_t)n0 * (1 - n1);
-        zs = (k + 1 < n2) ? (int64_t)n0 * n1 : (int64_t)n0 * n1 * (1 - n2);
-    } else {
-        xs = (i > 0) ? -1 : n0 - 1;
-        ys = (j > 0) ? -(int64_t)n0 : (int64_t)n0 * (n1 - 1);
-        zs = (k > 0) ? -(int64_t)n0 * n1 : (int64_t)n0 * n1 * (n2 - 1);
-    }
+    // offsets of the +1 and -1 neighbours along each axis, periodic
+    const int64_t pl[3] = {(i + 1 < n0) ? 1 : 1 - n0, (j + 1 < n1) ? n0 : (int64_t)n0 * (1 - n1),
+                           (k + 1 < n2) ? (int64_t)n0 * n1 : (int64_t)n0 * n1 * (1 - n2)};
+    const int64_t mn[3] = {(i > 0) ? -1 : n0 - 1, (j > 0) ? -(int64_t)n0 : (int64_t)n0 * (n1 - 1),
+                           (k > 0) ? -(int64_t)n0 * n1 : (int64_t)n0 * n1 * (n2 - 1)};
+    // difference of S along axis ax at the cell o + c (c a transverse shift)
+    auto d1 = [&](const T *S, int ax, int64_t c) -> T {
+        return FWD ? S[o + c + pl[ax]] - S[o + c] : S[o + c] - S[o + c + mn[ax]];
+    };
+    auto diff = [&](const T *S, int ax) -> T {
+        if (!CKC)
+            return d1(S, ax, 0);
+        const int p = ax == 2 ? 0 : ax + 1, q = ax == 0 ? 2 : ax - 1;
+        const T *w = a.ck[ax];
+        return w[0] * d1(S, ax, 0) + w[1] * (d1(S, ax, pl[p]) + d1(S, ax, mn[p])) +
+               w[2] * (d1(S, ax, pl[q]) + d1(S, ax, mn[q])) +
+               w[3] * (d1(S, ax, pl[p] + pl[q]) + d1(S, ax, pl[p] + mn[q]) + d1(S, ax, mn[p] + pl[q]) +
+                       d1(S, ax, mn[p] + mn[q]));
+    };
     const T *Sx = a.src[0], *Sy = a.src[1], *Sz = a.src[2];
-    T dx_sy, dx_sz, dy_sx, dy_sz, dz_sx, dz_sy;
-    if (FWD) {
-        dx_sy = Sy[o + xs] - Sy[o];
-        dx_sz = Sz[o + xs] - Sz[o];
-        dy_sx = Sx[o + ys] - Sx[o];
-        dy_sz = Sz[o + ys] - Sz[o];
-        dz_sx = Sx[o + zs] - Sx[o];
-        dz_sy = Sy[o + zs] - Sy[o];
-    } else {
-        dx_sy = Sy[o] - Sy[o + xs];
-        dx_sz = Sz[o] - Sz[o + xs];
-        dy_sx = Sx[o] - Sx[o + ys];
-        dy_sz = Sz[o] - Sz[o + ys];
-        dz_sx = Sx[o] - Sx[o + zs];
-        dz_sy = Sy[o] - Sy[o + zs];
-    }
+    const T dx_sy = diff(Sy, 0), dx_sz = diff(Sz, 0);
+    const T dy_sx = diff(Sx, 1), dy_sz = diff(Sz, 1);
+    const T dz_sx = diff(Sx, 2), dz_sy = diff(Sy, 2);
     T vx = a.in[0][o] + (a.cy * dy_sz - a.cz * dz_sy);
     T vy = a.in[1][o] + (a.cz * dz_sx - a.cx * dx_sz);
     T vz = a.in[2][o] + (a.cx * dx_sy - a.cy * dy_sx);
@@ -79,10 +78,17 @@ hipError_t launch_curl(bool forward, const CurlArgs<T> &a, hipStream_t st)
 {
     const int bx = a.n[0] >= 256 ? 256 : (a.n[0] >= 128 ? 128 : 64);
     dim3 grid((a.n[0] + bx - 1) / bx, a.n[1], a.n[2]);
-    if (forward)
-        hipLaunchKernelGGL((k_curl<T, true>), grid, dim3(bx), 0, st, a);
-    else
-        hipLaunchKernelGGL((k_curl<T, false>), grid, dim3(bx), 0, st, a);
+    if (a.ckc) {
+        if (forward)
+            hipLaunchKernelGGL((k_curl<T, true, true>), grid, dim3(bx), 0, st, a);
+        else
+            hipLaunchKernelGGL((k_curl<T, false, true>), grid, dim3(bx), 0, st, a);
+    } else {
+        if (forward)
+            hipLaunchKernelGGL((k_curl<T, true, false>), grid, dim3(bx), 0, st, a);
+        else
+            hipLaunchKernelGGL((k_curl<T, false, false>), grid, dim3(bx), 0, st, a);
+    }
     return hipGetLastError();
 }
 

@@ -56,6 +56,8 @@ struct TileGeo {
 //         + jc * J                       (J may be null; zero_j clears J)
 //   out_x[kplane] += amp * ag            (plane source, amp may be null)
 //   dA[i + n0 j] += dag * out_x[kplane]  (source adjoint, dA may be null)
+//   with ckc set, every difference is the CKC transverse average of the
+//   differences at the 3x3 neighbours across its axis
 template <typename T>
 struct CurlArgs {
     T *out[3];
@@ -71,6 +73,8 @@ struct CurlArgs {
     double *dA;
     double dag;
     int n[3];
+    int ckc;          // differences averaged over transverse neighbours (CKC)
+    T ck[3][4];       // per difference axis a: alpha, beta_p, beta_q, gamma (p = a+1, q = a+2)
 };
 
 // ---------------------------------------------------------------------------

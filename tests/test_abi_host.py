@@ -125,3 +125,22 @@ def test_bad_tile_and_negative_steps():
         f.E[m] = f.B[m] = f.J[m] = 0x1000
     assert lib.pic_step(C.byref(g), C.byref(sp), C.byref(f), None, 0, -1, 0, None, None, 0, None, None) == 1
     assert lib.pic_step(C.byref(g), C.byref(sp), C.byref(f), None, 0, 1, 4, None, None, 0, None, None) == 1
+
+
+def test_solver_and_pusher_are_validated_with_each_solvers_cfl_limit():
+    """Yee is stable up to c dt = 1/sqrt(sum 1/d^2), CKC up to c dt = min d:
+    a step between the two is refused for Yee and accepted for CKC; unknown
+    solver or pusher codes are unsupported."""
+    import dataclasses
+    g = wl.Grid((16, 16, 16), (0.2, 0.25, 0.3), 0.19)
+    with pytest.raises(_lib.PicError) as e:
+        _lib.pic_tile_shape(g, "f64")
+    assert e.value.status == 2
+    assert _lib.pic_tile_count(dataclasses.replace(g, solver=1), "f64") > 0
+    with pytest.raises(_lib.PicError) as e:
+        _lib.pic_tile_shape(dataclasses.replace(g, solver=1, dt=0.203), "f64")
+    assert e.value.status == 2
+    for bad in (dict(solver=2), dict(pusher=-1)):
+        with pytest.raises(_lib.PicError) as e:
+            _lib.pic_tile_shape(dataclasses.replace(g, dt=0.05, **bad), "f64")
+        assert e.value.status == 3
