@@ -38,7 +38,7 @@ def build():
 class _Grid(C.Structure):
     _fields_ = [("n", C.c_int32 * 3), ("d", C.c_double * 3), ("dt", C.c_double),
                 ("c", C.c_double), ("eps0", C.c_double), ("order", C.c_int32), ("pusher", C.c_int32),
-                ("solver", C.c_int32)]
+                ("solver", C.c_int32), ("gather_filter", C.c_void_p)]
 
 
 class _Species(C.Structure):
@@ -110,6 +110,11 @@ def _grid(g):
     s.solver = int(getattr(g, "solver", 0))
     if s.solver not in (0, 1):
         raise ValueError("solver must be 0 (Yee) or 1 (CKC)")
+    gf = getattr(g, "gather_filter", None)
+    if gf is not None:
+        gf = np.ascontiguousarray(np.asarray(gf, dtype=np.float64).reshape(6, 4))
+        s._filter = gf            # kept alive with the struct
+        s.gather_filter = gf.ctypes.data
     return s
 
 

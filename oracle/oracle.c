@@ -49,6 +49,7 @@ typedef struct {
     int32_t order;
     int32_t pusher; /* 0: Boris, 1: Vay */
     int32_t solver; /* 0: Yee, 1: Cole-Karkkainen-Cowan */
+    const double *gather_filter; /* NULL, or double[6][4]: z taps per component */
 } or_grid;
 
 typedef struct {
@@ -197,18 +198,58 @@ static void particle_pos(const or_species *s, int64_t p, int32_t cell[3], double
     }
 }
 
+/* Digital filter of the fields before the gather (the paper applies the
+ * Godfrey filter there, Sec. 4.2, against the numerical Cherenkov
+ * instability): a symmetric stencil along z per component m (E_x..E_z,
+ * B_x..B_z),
+ *   F~(i,j,k) = w[m][0] F(i,j,k) + sum_{s=1..3} w[m][s] (F(i,j,k+s) + F(i,j,k-s)),
+ * periodic.  It is its own transpose.  The taps are the caller's.        */
+static void filter_z(const or_grid *g, const double w[4], const double *F, double *out)
+{
+    for (int64_t k = 0; k < g->n[2]; ++k)
+        for (int64_t j = 0; j < g->n[1]; ++j)
+            for (int64_t i = 0; i < g->n[0]; ++i) {
+                double v = w[0] * F[idx3(g, i, j, k)];
+                for (int sft = 1; sft <= 3; ++sft)
+                    v += w[sft] * (F[idx3(g, i, j, k + sft)] + F[idx3(g, i, j, k - sft)]);
+                out[idx3(g, i, j, k)] = v;
+            }
+}
+
+/* The six field components the gather reads: the fields themselves, or
+ * filtered copies in buf (freed by the caller) when the grid has a filter. */
+static double *gather_fields(const or_grid *g, const or_fields *f, const double *F[6])
+{
+    for (int m = 0; m < 3; ++m) {
+        F[m] = f->E[m];
+        F[3 + m] = f->B[m];
+    }
+    if (!g->gather_filter)
+        return NULL;
+    int64_t nc = (int64_t)g->n[0] * g->n[1] * g->n[2];
+    double *buf = (double *)malloc(sizeof(double) * 6 * (size_t)nc);
+    for (int m = 0; m < 6; ++m) {
+        filter_z(g, g->gather_filter + 4 * m, F[m], buf + m * nc);
+        F[m] = buf + m * nc;
+    }
+    return buf;
+}
+
 void or_gather(const or_grid *g, const or_species *s, const or_fields *f, double *Ep[3], double *Bp[3])
 {
+    const double *F[6];
+    double *fbuf = gather_fields(g, f, F);
 #pragma omp parallel for schedule(static)
     for (int64_t p = 0; p < s->n; ++p) {
         int32_t cell[3];
         double off[3];
         particle_pos(s, p, cell, off);
         for (int m = 0; m < 3; ++m) {
-            Ep[m][p] = gather_one(g, f->E[m], STAG_E[m], cell, off, NULL);
-            Bp[m][p] = gather_one(g, f->B[m], STAG_B[m], cell, off, NULL);
+            Ep[m][p] = gather_one(g, F[m], STAG_E[m], cell, off, NULL);
+            Bp[m][p] = gather_one(g, F[3 + m], STAG_B[m], cell, off, NULL);
         }
     }
+    free(fbuf);
 }
 
 /* ------------------------------------------------------------------ */
@@ -819,14 +860,16 @@ void or_step(const or_grid *g, or_species *s, or_fields *f, const or_source *src
         disp[d] = (double *)malloc(sizeof(double) * (size_t)(n > 0 ? n : 1));
     for (int32_t it = 0; it < nsteps; ++it) {
         int64_t step = step0 + it;
+        const double *F[6];
+        double *fbuf = gather_fields(g, f, F);
 #pragma omp parallel for schedule(static)
         for (int64_t p = 0; p < n; ++p) {
             int32_t cell[3];
             double off[3], E[3], B[3], u0[3], u1[3], dp[3];
             particle_pos(s, p, cell, off);
             for (int m = 0; m < 3; ++m) {
-                E[m] = gather_one(g, f->E[m], STAG_E[m], cell, off, NULL);
-                B[m] = gather_one(g, f->B[m], STAG_B[m], cell, off, NULL);
+                E[m] = gather_one(g, F[m], STAG_E[m], cell, off, NULL);
+                B[m] = gather_one(g, F[3 + m], STAG_B[m], cell, off, NULL);
                 u0[m] = s->u[m][p];
             }
             push_momentum(g, h, u0, E, B, u1);
@@ -836,6 +879,7 @@ void or_step(const or_grid *g, or_species *s, or_fields *f, const or_source *src
                 disp[d][p] = dp[d];
             }
         }
+        free(fbuf);
         for (int m = 0; m < 3; ++m)
             memset(f->J[m], 0, sizeof(double) * (size_t)nc);
         deposit_all(g, s, (const double *const *)disp, f->J);
@@ -1030,7 +1074,21 @@ void or_step_adjoint(const or_grid *g, const or_species *s, const or_fields *f, 
         for (int64_t i = 0; i < nc; ++i)
             lam->lE[m][i] = hatE[m][i] - 0.5 * g->dt * C[m][i];
 
-    /* particle part (serial: the gather transpose scatters into lE, lB) */
+    /* particle part (serial: the gather transpose scatters into lE, lB, or
+     * with a filter into the adjoints of the filtered fields, which the
+     * filter's transpose (itself) adds to lE, lB at the end) */
+    const double *F[6];
+    double *fbuf = gather_fields(g, f, F);
+    double *lF[6], *lfbuf = NULL;
+    for (int m = 0; m < 3; ++m) {
+        lF[m] = lam->lE[m];
+        lF[3 + m] = lam->lB[m];
+    }
+    if (fbuf) {
+        lfbuf = (double *)calloc(6 * (size_t)nc, sizeof(double));
+        for (int m = 0; m < 6; ++m)
+            lF[m] = lfbuf + m * nc;
+    }
     double h = s->q * g->dt / (2.0 * s->m);
     for (int64_t p = 0; p < n; ++p) {
         int32_t cell[3];
@@ -1038,8 +1096,8 @@ void or_step_adjoint(const or_grid *g, const or_species *s, const or_fields *f, 
         boris_tape T;
         particle_pos(s, p, cell, off);
         for (int m = 0; m < 3; ++m) {
-            E[m] = gather_one(g, f->E[m], STAG_E[m], cell, off, NULL);
-            B[m] = gather_one(g, f->B[m], STAG_B[m], cell, off, NULL);
+            E[m] = gather_one(g, F[m], STAG_E[m], cell, off, NULL);
+            B[m] = gather_one(g, F[3 + m], STAG_B[m], cell, off, NULL);
             u0[m] = s->u[m][p];
         }
         if (g->pusher == 1)
@@ -1074,13 +1132,23 @@ void or_step_adjoint(const or_grid *g, const or_species *s, const or_fields *f, 
             boris_adjoint(h, g->c, E, B, &T, ub, u0b, Eb, Bb);
         /* gather transpose */
         for (int m = 0; m < 3; ++m) {
-            gather_adjoint_one(g, f->E[m], lam->lE[m], STAG_E[m], cell, off, Eb[m], lx0);
-            gather_adjoint_one(g, f->B[m], lam->lB[m], STAG_B[m], cell, off, Bb[m], lx0);
+            gather_adjoint_one(g, F[m], lF[m], STAG_E[m], cell, off, Eb[m], lx0);
+            gather_adjoint_one(g, F[3 + m], lF[3 + m], STAG_B[m], cell, off, Bb[m], lx0);
         }
         for (int d = 0; d < 3; ++d) {
             lam->lx[d][p] = lx0[d];
             lam->lu[d][p] = u0b[d];
         }
     }
+    if (lfbuf) {
+        for (int m = 0; m < 6; ++m) {
+            double *dst = m < 3 ? lam->lE[m] : lam->lB[m - 3];
+            filter_z(g, g->gather_filter + 4 * m, lF[m], C[0]);
+            for (int64_t i = 0; i < nc; ++i)
+                dst[i] += C[0][i];
+        }
+    }
+    free(lfbuf);
+    free(fbuf);
     free(buf);
 }

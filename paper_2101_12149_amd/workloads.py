@@ -36,6 +36,7 @@ class Grid:
     slack: int = -1     # halo slack of the tiled particle kernel (-1: automatic)
     pusher: int = 0     # momentum update: 0 Boris, 1 Vay
     solver: int = 0     # field solver: 0 Yee, 1 Cole-Karkkainen-Cowan
+    gather_filter: Optional[tuple] = None   # 6 x 4 z taps per field component, or None
 
     @property
     def ncells(self) -> int:

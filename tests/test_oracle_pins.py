@@ -505,6 +505,48 @@ def test_ckc_is_stable_up_to_the_smallest_cell_and_yee_is_not():
     assert _energy_after(yee, 60, 31) > 1e6
 
 
+FILTER_TAPS = np.array([[0.5, 0.25, 0.0, 0.0], [0.6, 0.25, -0.05, 0.0], [0.4, 0.2, 0.1, 0.0],
+                        [0.7, 0.1, 0.05, 0.0], [0.55, 0.2, 0.05, -0.025], [0.5, 0.15, 0.05, 0.05]])
+
+
+def test_gather_filter_identity_taps_change_nothing():
+    g = grid(n=(8, 6, 10))
+    rng = np.random.default_rng(41)
+    f = zero_fields(g)
+    f.E[:] = rng.normal(size=f.E.shape)
+    f.B[:] = rng.normal(size=f.B.shape)
+    sp = random_species(g, 200, rng)
+    E0, B0 = oracle.gather(g, sp, f)
+    g.gather_filter = np.tile([1.0, 0.0, 0.0, 0.0], (6, 1))
+    E1, B1 = oracle.gather(g, sp, f)
+    assert np.array_equal(E0, E1) and np.array_equal(B0, B1)
+
+
+def test_gather_filter_transfer_function_on_a_z_mode():
+    """Fields that vary only along z as cos(2 pi q k / n_z) are eigenfunctions
+    of a symmetric z stencil: the filtered gather is the plain one times
+    H(q) = w0 + 2 sum_s w_s cos(2 pi q s / n_z), per component."""
+    g = grid(n=(6, 6, 16))
+    nz = g.n[2]
+    q = 3
+    f = zero_fields(g)
+    kz = np.arange(nz)
+    mode = np.cos(2 * np.pi * q * kz / nz + 0.4)[:, None, None] * np.ones((nz, g.n[1], g.n[0]))
+    for m in range(3):
+        f.E[m] = mode * (m + 1)
+        f.B[m] = mode * (m - 2.5)
+    rng = np.random.default_rng(42)
+    sp = random_species(g, 100, rng)
+    E0, B0 = oracle.gather(g, sp, f)
+    g.gather_filter = FILTER_TAPS
+    E1, B1 = oracle.gather(g, sp, f)
+    H = FILTER_TAPS[:, 0] + 2 * sum(FILTER_TAPS[:, s] * np.cos(2 * np.pi * q * s / nz) for s in (1, 2, 3))
+    for m in range(3):
+        np.testing.assert_allclose(E1[m], H[m] * E0[m], rtol=1e-12, atol=1e-13)
+        np.testing.assert_allclose(B1[m], H[3 + m] * B0[m], rtol=1e-12, atol=1e-13)
+    assert np.ptp(H) > 0.1      # the components really are filtered differently
+
+
 def test_yee_source_adds_on_plane_and_keeps_divB():
     g = grid(n=(8, 8, 8))
     f = zero_fields(g)
@@ -666,13 +708,15 @@ def test_adjoint_matches_central_finite_differences(order, pusher):
         assert 10 * np.finfo(float).eps * abs(L) / eps < 1e-6 * abs(an)   # noise below the bar
 
 
-@pytest.mark.parametrize("pusher,solver", [(0, 0), (1, 0), (0, 1)])
-def test_adjoint_position_and_field_gradients_by_finite_differences(pusher, solver):
+@pytest.mark.parametrize("pusher,solver,filt", [(0, 0, False), (1, 0, False), (0, 1, False), (1, 1, True)])
+def test_adjoint_position_and_field_gradients_by_finite_differences(pusher, solver, filt):
     """dL/dx0 and dL/dE0, dL/dB0 from the reverse sweep against central
     differences (pins the deposit transpose in both positions, the gather
-    transpose and the transpose of either momentum update)."""
+    transpose and the transpose of either momentum update, of the CKC field
+    solve and of the filter before the gather)."""
     w = wl.differentiable((8, 8, 8), 1, 0.08, 3, 2, "f64", 4321, amp0=0.0)
-    g = dataclasses.replace(w.grid, pusher=pusher, solver=solver)
+    g = dataclasses.replace(w.grid, pusher=pusher, solver=solver,
+                            gather_filter=FILTER_TAPS if filt else None)
     sp, f = w.species.numpy(), w.fields.numpy()
     rng = np.random.default_rng(10)
     f.E[:] = rng.normal(0, 0.1, f.E.shape)
