@@ -200,6 +200,8 @@ def main():
                     help="momentum update of the push (the workload's field and particle setup is unchanged)")
     ap.add_argument("--solver", choices=("yee", "ckc"), default="yee",
                     help="field solver (same time step as the workload's Yee setup)")
+    ap.add_argument("--gather-filter", action="store_true",
+                    help="filter E and B along z before the gather (binomial taps 1/4, 1/2, 1/4 on every component)")
     ap.add_argument("--calib-copy", action="store_true",
                     help="copy 1 GiB device-to-device first (HBM counter calibration)")
     ap.add_argument("--sort-sweep", action="store_true",
@@ -236,6 +238,8 @@ def main():
     w.grid.slack = args.slack
     w.grid.pusher = 1 if args.pusher == "vay" else 0
     w.grid.solver = 1 if args.solver == "ckc" else 0
+    if args.gather_filter:
+        w.grid.gather_filter = [[0.5, 0.25, 0.0, 0.0]] * 6
     sort_every = w.sort_every if args.sort_every is None else args.sort_every
     g = w.grid
     npart, ncell = w.species.n, g.ncells
@@ -268,7 +272,7 @@ def main():
            "vs_baseline": None, "dtype": w.dtype, "data": "synthetic",
            "config": {"workload": w.name, "cells": list(g.n), "particles": npart, "ppc": w.meta.get("ppc"),
                       "order": g.order, "u_th": w.meta.get("u_th"), "sort_every": sort_every,
-                      "pusher": args.pusher, "solver": args.solver,
+                      "pusher": args.pusher, "solver": args.solver, "gather_filter": bool(args.gather_filter),
                       "precision": "int32 cell + FP32 offset, FP32 fields/momenta, FP64 reductions"
                       if w.dtype == "f32" else "FP64"},
            "kernels": breakdown, "roofline": roofline}

@@ -102,7 +102,20 @@ typedef struct {
                          drifted since the last sort; -1 = automatic */
     int32_t pusher;   /* pic_pusher; anything else is PIC_E_UNSUPPORTED */
     int32_t solver;   /* pic_solver; anything else is PIC_E_UNSUPPORTED */
+    const double *gather_filter; /* NULL, or HOST double[6][4]: a filter of the
+                         fields before the gather (the place of the paper's
+                         Godfrey filter, Sec. 4.2), see below */
 } pic_grid;
+/* Gather filter.  With gather_filter != NULL, pic_step and pic_step_adjoint
+ * gather E and B through a symmetric stencil along z, per component m
+ * (E_x, E_y, E_z, B_x, B_y, B_z), w = gather_filter + 4 m:
+ *   F~(i,j,k) = w[0] F(i,j,k) + sum_{s=1..3} w[s] (F(i,j,k+s) + F(i,j,k-s)),
+ * periodic; the fields themselves are not changed, and the adjoint adds the
+ * filter's transpose (itself) of the gathered-field adjoints to lam->lE,
+ * lam->lB.  The taps are the caller's (Godfrey's tables, a binomial filter,
+ * ...); they must be finite.  The filtered fields and their adjoints take six
+ * more field arrays each in the workspace.  pic_gather has no workspace and
+ * refuses a grid with a filter (PIC_E_UNSUPPORTED). */
 
 typedef struct {
     int64_t n;          /* number of particles */

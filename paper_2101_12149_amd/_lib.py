@@ -9,6 +9,8 @@ import ctypes as C
 import os
 import threading
 
+import numpy as np
+
 import torch
 
 HERE = os.path.dirname(os.path.abspath(__file__))
@@ -29,7 +31,8 @@ class PicError(RuntimeError):
 class pic_grid(C.Structure):
     _fields_ = [("n", C.c_int32 * 3), ("d", C.c_double * 3), ("dt", C.c_double), ("c", C.c_double),
                 ("eps0", C.c_double), ("order", C.c_int32), ("dtype", C.c_int32), ("tile", C.c_int32 * 3),
-                ("slack", C.c_int32), ("pusher", C.c_int32), ("solver", C.c_int32)]
+                ("slack", C.c_int32), ("pusher", C.c_int32), ("solver", C.c_int32),
+                ("gather_filter", C.c_void_p)]
 
 
 class pic_species(C.Structure):
@@ -136,6 +139,11 @@ def make_grid(grid, dtype):
     g.slack = int(getattr(grid, "slack", -1))
     g.pusher = int(getattr(grid, "pusher", 0))
     g.solver = int(getattr(grid, "solver", 0))
+    gf = getattr(grid, "gather_filter", None)
+    if gf is not None:
+        gf = np.ascontiguousarray(np.asarray(gf, dtype=np.float64).reshape(6, 4))
+        g._filter = gf               # kept alive with the struct
+        g.gather_filter = gf.ctypes.data
     return g
 
 

@@ -144,6 +144,8 @@ int lds_limit()
 struct GridInfo {
     int n[3];
     int64_t ncell;
+    bool filt;          // fields filtered along z before the gather
+    double fw[6][4];    // the filter's taps per component
     int order;
     int dtype;
     size_t tsize;
@@ -230,6 +232,13 @@ pic_status check_grid(const pic_grid *g, GridInfo &gi)
         return fail(PIC_E_UNSUPPORTED, "dtype must be PIC_F32 or PIC_F64");
     if (g->solver != PIC_SOLVER_YEE && g->solver != PIC_SOLVER_CKC)
         return fail(PIC_E_UNSUPPORTED, "solver must be PIC_SOLVER_YEE or PIC_SOLVER_CKC");
+    gi.filt = g->gather_filter != nullptr;
+    for (int m = 0; m < 6; ++m)
+        for (int s = 0; s < 4; ++s) {
+            gi.fw[m][s] = gi.filt ? g->gather_filter[4 * m + s] : (s == 0 ? 1.0 : 0.0);
+            if (!std::isfinite(gi.fw[m][s]))
+                return fail(PIC_E_INVALID, "gather filter taps must be finite");
+        }
     if (g->solver == PIC_SOLVER_YEE) {
         const double inv = 1.0 / (g->d[0] * g->d[0]) + 1.0 / (g->d[1] * g->d[1]) + 1.0 / (g->d[2] * g->d[2]);
         if (g->c * g->dt * std::sqrt(inv) > 1.0 + 1e-12)
@@ -330,7 +339,8 @@ pic_status check_fields(const pic_fields *f, bool need_j)
 
 // workspace layout
 struct WsLayout {
-    size_t err, counts, bsum, key, rank, slot, scell, soff, su, sw, hatE, partials, red5, old_ts, total;
+    size_t err, counts, bsum, key, rank, slot, scell, soff, su, sw, hatE, partials, red5, old_ts, filt, lfilt,
+        total;
 };
 
 size_t al(size_t x)
@@ -371,6 +381,11 @@ WsLayout layout(const GridInfo &gi, int64_t np)
     o += 256;
     L.old_ts = o;
     o += al(sizeof(int) * ((size_t)gi.ntiles + 1));
+    // filtered E, B for the gather and their adjoints (only with a filter)
+    L.filt = o;
+    o += gi.filt ? 6 * al(gi.tsize * (size_t)gi.ncell) : 0;
+    L.lfilt = o;
+    o += gi.filt ? 6 * al(gi.tsize * (size_t)gi.ncell) : 0;
     L.total = o;
     return L;
 }
@@ -626,6 +641,36 @@ pic_status reduce_t(const pic_grid *g, const GridInfo &gi, const pic_species *sp
     return PIC_OK;
 }
 
+// The fields the particle kernels read: the caller's, or with a gather
+// filter the filtered copies in the workspace (J stays the caller's).
+template <typename T>
+FieldPtrs<T> gather_view(const GridInfo &gi, const FieldPtrs<T> &fp, char *w, const WsLayout &L)
+{
+    FieldPtrs<T> v = fp;
+    if (gi.filt) {
+        const size_t a = al(sizeof(T) * (size_t)gi.ncell);
+        for (int d = 0; d < 3; ++d) {
+            v.E[d] = reinterpret_cast<T *>(w + L.filt + d * a);
+            v.B[d] = reinterpret_cast<T *>(w + L.filt + (3 + d) * a);
+        }
+    }
+    return v;
+}
+
+// dst = filter(src) per component (add: dst += filter(src))
+template <typename T>
+pic_status filter_fields(const GridInfo &gi, const FieldPtrs<T> &src, const FieldPtrs<T> &dst, hipStream_t st,
+                         bool add = false)
+{
+    for (int m = 0; m < 6; ++m) {
+        const T *in = m < 3 ? src.E[m] : src.B[m - 3];
+        T *out = m < 3 ? dst.E[m] : dst.B[m - 3];
+        const T w[4] = {(T)gi.fw[m][0], (T)gi.fw[m][1], (T)gi.fw[m][2], (T)gi.fw[m][3]};
+        PIC_HIP(launch_filter_z<T>(in, out, w, add, gi.n, st));
+    }
+    return PIC_OK;
+}
+
 template <typename T>
 pic_status step_t(const pic_grid *g, const GridInfo &gi, pic_species *sp, pic_fields *f, const pic_source *src,
                   int64_t step0, int32_t nsteps, int32_t sort_every, int32_t *tile_start, void *ws,
@@ -636,6 +681,8 @@ pic_status step_t(const pic_grid *g, const GridInfo &gi, pic_species *sp, pic_fi
     const PConst<T> pc = make_const<T>(g, sp);
     const FieldPtrs<T> fp = fptrs<T>(f);
     const PArr<T> user = parr<T>(sp);
+    // the fields the particle kernels gather from (filtered copies with a filter)
+    const FieldPtrs<T> fpp = gather_view<T>(gi, fp, w, L);
     // per-particle stray marks of the tile kernels, in the sort's key buffer
     // (free once the sort of the step is done)
     unsigned char *stray = reinterpret_cast<unsigned char *>(w + L.key);
@@ -645,6 +692,10 @@ pic_status step_t(const pic_grid *g, const GridInfo &gi, pic_species *sp, pic_fi
     for (int32_t it = 0; it < nsteps; ++it) {
         const int64_t step = step0 + it;
         const bool sort_now = sort_every > 0 && (it == 0 || step % sort_every == 0);
+        if (gi.filt && sp->n > 0) {
+            TimedScope ts(1, st);
+            PIC_TRY_S(filter_fields<T>(gi, fp, fpp, st));
+        }
         if (sort_now && sp->n > 0) {
             PArr<T> sorted;
             {
@@ -655,20 +706,20 @@ pic_status step_t(const pic_grid *g, const GridInfo &gi, pic_species *sp, pic_fi
             }
             {
                 TimedScope ts(1, st);
-                PIC_HIP(launch_particles_tile<T>(gi.order, pc, gi.tg, sorted, user, fp, tile_start, stray, err, st));
+                PIC_HIP(launch_particles_tile<T>(gi.order, pc, gi.tg, sorted, user, fpp, tile_start, stray, err, st));
             }
             TimedScope ts(6, st);
-            PIC_HIP(launch_particles_strays<T>(gi.order, pc, gi.tg, sorted, user, fp, tile_start, stray, err, st));
+            PIC_HIP(launch_particles_strays<T>(gi.order, pc, gi.tg, sorted, user, fpp, tile_start, stray, err, st));
         } else if (tile_start && sp->n > 0) {
             {
                 TimedScope ts(1, st);
-                PIC_HIP(launch_particles_tile<T>(gi.order, pc, gi.tg, user, user, fp, tile_start, stray, err, st));
+                PIC_HIP(launch_particles_tile<T>(gi.order, pc, gi.tg, user, user, fpp, tile_start, stray, err, st));
             }
             TimedScope ts(6, st);
-            PIC_HIP(launch_particles_strays<T>(gi.order, pc, gi.tg, user, user, fp, tile_start, stray, err, st));
+            PIC_HIP(launch_particles_strays<T>(gi.order, pc, gi.tg, user, user, fpp, tile_start, stray, err, st));
         } else {
             TimedScope ts(1, st);
-            PIC_HIP(launch_particles_global<T>(gi.order, pc, user, fp, err, st));
+            PIC_HIP(launch_particles_global<T>(gi.order, pc, user, fpp, err, st));
         }
         pic_status s;
         {
@@ -712,6 +763,20 @@ pic_status adjoint_t(const pic_grid *g, const GridInfo &gi, const pic_species *s
         lB[d] = static_cast<T *>(lam->lB[d]);
         lx[d] = static_cast<T *>(lam->lx[d]);
         lu[d] = static_cast<T *>(lam->lu[d]);
+    }
+    // with a gather filter the particle part reads the filtered fields and
+    // scatters into the adjoints of the filtered fields (zeroed here), whose
+    // filter transpose is added to lE, lB at the end
+    const FieldPtrs<T> fpv = gather_view<T>(gi, fptrs<T>(f), w, L);
+    T *glE[3], *glB[3];
+    for (int d = 0; d < 3; ++d) {
+        glE[d] = lE[d];
+        glB[d] = lB[d];
+        if (gi.filt) {
+            const size_t a = al(sizeof(T) * (size_t)gi.ncell);
+            glE[d] = reinterpret_cast<T *>(w + L.lfilt + d * a);
+            glB[d] = reinterpret_cast<T *>(w + L.lfilt + (3 + d) * a);
+        }
     }
     const double c2 = g->c * g->c;
     // hatE = lE - dt/2 curl_b(lB);  dA += g(step) hatE_x[k_plane]
@@ -776,12 +841,29 @@ pic_status adjoint_t(const pic_grid *g, const GridInfo &gi, const pic_species *s
         // without a cause found in its code, so that request takes the
         // per-particle kernels, as does a tile whose regions exceed the LDS.
         const bool tiled_ok = !(gi.dtype == PIC_F64 && gi.order == 3) && adj_lds_bytes(gi) <= (size_t)lds_limit();
+        if (gi.filt) {
+            PIC_TRY_S(filter_fields<T>(gi, fptrs<T>(f), fpv, st));
+            for (int d = 0; d < 3; ++d) {
+                PIC_HIP(launch_fill<T>(glE[d], gi.ncell, T(0), st));
+                PIC_HIP(launch_fill<T>(glB[d], gi.ncell, T(0), st));
+            }
+        }
         if (tile_start && tiled_ok)
-            PIC_HIP(launch_adjoint_tile<T>(gi.order, pc, adjoint_geo(gi), parr<T>(sp), fptrs<T>(f), hat, lx, lu, lE,
-                                           lB, vb, tile_start, err, st));
+            PIC_HIP(launch_adjoint_tile<T>(gi.order, pc, adjoint_geo(gi), parr<T>(sp), fpv, hat, lx, lu, glE, glB,
+                                           vb, tile_start, err, st));
         else
-            PIC_HIP(launch_adjoint_particles<T>(gi.order, pc, parr<T>(sp), fptrs<T>(f), hat, lx, lu, lE, lB, vb,
-                                                err, st));
+            PIC_HIP(launch_adjoint_particles<T>(gi.order, pc, parr<T>(sp), fpv, hat, lx, lu, glE, glB, vb, err,
+                                                st));
+        if (gi.filt) {
+            FieldPtrs<T> lsrc{}, ldst{};
+            for (int d = 0; d < 3; ++d) {
+                lsrc.E[d] = glE[d];
+                lsrc.B[d] = glB[d];
+                ldst.E[d] = lE[d];
+                ldst.B[d] = lB[d];
+            }
+            PIC_TRY_S(filter_fields<T>(gi, lsrc, ldst, st, true));
+        }
     }
     int herr = 0;
     PIC_HIP(hipMemcpyAsync(&herr, err, sizeof(int), hipMemcpyDeviceToHost, st));
@@ -890,6 +972,8 @@ pic_status pic_gather(const pic_grid *grid, const pic_species *sp, const pic_fie
 {
     GridInfo gi;
     PIC_TRY(check_grid(grid, gi));
+    if (gi.filt)
+        return fail(PIC_E_UNSUPPORTED, "pic_gather has no workspace for the gather filter (pic_step applies it)");
     PIC_TRY(check_species(sp, "species"));
     PIC_TRY(check_fields(f, false));
     PIC_TRY(check_vec3(Ep, "Ep"));

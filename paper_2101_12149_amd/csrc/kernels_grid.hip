@@ -92,6 +92,44 @@ hipError_t launch_curl(bool forward, const CurlArgs<T> &a, hipStream_t st)
     return hipGetLastError();
 }
 
+// Symmetric filter along z (the fields before the gather): out = w0 F +
+// sum_{s=1..3} w_s (F[k+s] + F[k-s]), periodic in z; add: out += that.
+// One thread per cell, x fastest (coalesced; the z neighbours are whole
+// planes away and come from L2).
+template <typename T>
+__global__ void __launch_bounds__(256) k_filter_z(const T *__restrict__ in, T *__restrict__ out, T w0, T w1, T w2,
+                                                   T w3, int add, int nxy, int nz)
+{
+    const int64_t o = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (o >= (int64_t)nxy * nz)
+        return;
+    const int k = (int)(o / nxy);
+    const int64_t r = o - (int64_t)k * nxy;
+    auto at = [&](int kk) -> T {
+        kk = kk < 0 ? kk + nz : (kk >= nz ? kk - nz : kk);   // |shift| <= 3 < nz
+        return in[r + (int64_t)kk * nxy];
+    };
+    T v = w0 * in[o];
+    if (w1 != T(0))
+        v += w1 * (at(k + 1) + at(k - 1));
+    if (w2 != T(0))
+        v += w2 * (at(k + 2) + at(k - 2));
+    if (w3 != T(0))
+        v += w3 * (at(k + 3) + at(k - 3));
+    out[o] = add ? out[o] + v : v;
+}
+
+template <typename T>
+hipError_t launch_filter_z(const T *in, T *out, const T w[4], bool add, const int n[3], hipStream_t st)
+{
+    const int64_t nc = (int64_t)n[0] * n[1] * n[2];
+    if (nc == 0)
+        return hipSuccess;
+    hipLaunchKernelGGL((k_filter_z<T>), dim3((unsigned)((nc + 255) / 256)), dim3(256), 0, st, in, out, w[0], w[1],
+                       w[2], w[3], add ? 1 : 0, n[0] * n[1], n[2]);
+    return hipGetLastError();
+}
+
 template <typename T>
 __global__ void k_fill(T *p, int64_t n, T v)
 {
@@ -813,6 +851,7 @@ hipError_t launch_reduce(const PArr<T> *sp, const FieldPtrs<T> &f, int64_t ncell
 
 #define PIC_GINST(T)                                                                                             \
     template hipError_t launch_curl<T>(bool, const CurlArgs<T> &, hipStream_t);                                   \
+    template hipError_t launch_filter_z<T>(const T *, T *, const T[4], bool, const int[3], hipStream_t);         \
     template hipError_t launch_fill<T>(T *, int64_t, T, hipStream_t);                                             \
     template hipError_t launch_scale<T>(T *, const T *, int64_t, T, hipStream_t);                                 \
     template hipError_t launch_bin_count<T>(const PArr<T> &, const TileGeo &, int *, int *, int *, int *,         \

@@ -121,6 +121,9 @@ hipError_t launch_adjoint_tile(int order, const PConst<T> &pc, const TileGeo &tg
 
 template <typename T>
 hipError_t launch_curl(bool forward, const CurlArgs<T> &a, hipStream_t st);
+// out = (add ? out : 0) + symmetric z filter of in with taps w[0..3] (periodic)
+template <typename T>
+hipError_t launch_filter_z(const T *in, T *out, const T w[4], bool add, const int n[3], hipStream_t st);
 template <typename T>
 hipError_t launch_fill(T *p, int64_t n, T v, hipStream_t st);
 template <typename T>

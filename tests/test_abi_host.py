@@ -144,3 +144,20 @@ def test_solver_and_pusher_are_validated_with_each_solvers_cfl_limit():
         with pytest.raises(_lib.PicError) as e:
             _lib.pic_tile_shape(dataclasses.replace(g, dt=0.05, **bad), "f64")
         assert e.value.status == 3
+
+
+def test_gather_filter_takes_twelve_field_arrays_of_workspace():
+    """Filtered E, B and their adjoints: six field arrays each; non-finite
+    taps are refused."""
+    import dataclasses
+    import numpy as np
+    g = wl.plasma_grid((16, 16, 16), 3)
+    taps = np.tile([0.5, 0.25, 0.0, 0.0], (6, 1))
+    plain = _lib.pic_workspace_bytes(g, "f64", 1000)
+    filt = _lib.pic_workspace_bytes(dataclasses.replace(g, gather_filter=taps), "f64", 1000)
+    assert filt - plain == 12 * 16 ** 3 * 8
+    bad = taps.copy()
+    bad[2, 1] = np.nan
+    with pytest.raises(_lib.PicError) as e:
+        _lib.pic_tile_shape(dataclasses.replace(g, gather_filter=bad), "f64")
+    assert e.value.status == 1

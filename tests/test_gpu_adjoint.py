@@ -54,22 +54,28 @@ def _stale(sp, g, seed):
     return int(moved.sum())
 
 
-@pytest.mark.parametrize("pusher,solver", [(0, 0), (1, 0), (1, 1)])
+TAPS = np.array([[0.5, 0.25, 0.0, 0.0], [0.6, 0.25, -0.05, 0.0], [0.4, 0.2, 0.1, 0.0],
+                 [0.7, 0.1, 0.05, 0.0], [0.55, 0.2, 0.05, -0.025], [0.5, 0.15, 0.05, 0.05]])
+
+
+@pytest.mark.parametrize("pusher,solver,filt", [(0, 0, False), (1, 0, False), (1, 1, False), (1, 1, True)])
 @pytest.mark.parametrize("tiled", [False, True, "stale"])
 @pytest.mark.parametrize("order", [1, 3])
 @pytest.mark.parametrize("dtype", ["f64", "f32"])
-def test_adjoint_step_matches_oracle(order, dtype, tiled, pusher, solver):
+def test_adjoint_step_matches_oracle(order, dtype, tiled, pusher, solver, filt):
     """One reverse step with random adjoint inputs; the tiled variants bin the
     particles first and permute the results back.  "stale" then moves a third
     of the particles to other cells, so they lie outside the tile that the
     binning gives them and take the global path of the tiled transpose.
     pusher 1 runs Vay's momentum update and its transpose, solver 1 the CKC
-    field solve and its transpose."""
+    field solve and its transpose, filt the z filter before the gather and
+    its transpose."""
     if tiled and dtype == "f64" and order == 3:
         pytest.skip("tiled FP64 order-3 adjoint is switched off in the library (an earlier form returned wrong "
                     "position adjoints on the device; the request runs the per-particle kernels, covered by the "
                     "untiled case)")
-    g = dataclasses.replace(wl.plasma_grid((12, 16, 20), order), pusher=pusher, solver=solver)
+    g = dataclasses.replace(wl.plasma_grid((12, 16, 20), order), pusher=pusher, solver=solver,
+                            gather_filter=TAPS if filt else None)
     n = 3000
     sp = random_species(g, n, 101, u_th=0.2, dtype=dtype)
     f = random_fields(g, 102, scale=0.3, dtype=dtype)
