@@ -131,6 +131,37 @@ def cpu_baseline():
                       f"after 1 warm-up step ({dt:.1f} s)"}
 
 
+MICRO_MODES = ("lds_add_f32", "lds_add_f64", "lds_add_u32", "lds_add_u64", "lds_read_f32", "lds_read_f64",
+               "lds_write_f32", "lds_write_f64", "global_add_f32", "global_add_f64")
+
+
+def atomic_micro():
+    """LDS and global atomic / access throughput (libpic355_micro.so), in
+    lane-operations per clock per CU at the 2.4 GHz peak clock: 8 workgroups
+    of 256 threads per CU, 64 x 32 operations per lane on in-bounds indices
+    (stride 1: consecutive words per lane; 2 and 17 spread lanes over the
+    banks).  LDS arrays hold 8192 elements; global ones 8192 per workgroup."""
+    import ctypes as C
+    lib = C.CDLL(os.path.join(os.path.dirname(os.path.abspath(__file__)), "paper_2101_12149_amd",
+                              "libpic355_micro.so"))
+    lib.picmb_run.argtypes = [C.c_int, C.c_int, C.c_int, C.c_int, C.c_int, C.POINTER(C.c_double),
+                              C.POINTER(C.c_double)]
+    cus, clk = 256, 2.4e9
+    res = []
+    for mode, name in enumerate(MICRO_MODES):
+        for stride in (1, 2, 17):
+            ms, ops = C.c_double(), C.c_double()
+            rc = lib.picmb_run(mode, cus * 8, 64, stride, 8192, C.byref(ms), C.byref(ops))
+            if rc != 0:
+                raise RuntimeError(f"picmb_run({name}, stride {stride}) failed with {rc}")
+            rate = ops.value / (ms.value * 1e-3)
+            res.append({"op": name, "stride": stride, "ms": round(ms.value, 4),
+                        "lane_ops_per_clk_per_cu": round(rate / cus / clk, 3)})
+            log(f"[micro] {name:15s} stride {stride:2d}: {ms.value:8.3f} ms, "
+                f"{rate / cus / clk:7.3f} lane-ops/clk/CU")
+    return {"probe": "atomic and LDS throughput", "cus": cus, "clock_GHz": 2.4, "results": res}
+
+
 def stray_fraction(w, ts):
     """Fraction of the particles whose cell lies outside their tile's LDS
     region (tile + slack) under the binning ts: the particles the stray
@@ -204,6 +235,8 @@ def main():
                     help="filter E and B along z before the gather (binomial taps 1/4, 1/2, 1/4 on every component)")
     ap.add_argument("--calib-copy", action="store_true",
                     help="copy 1 GiB device-to-device first (HBM counter calibration)")
+    ap.add_argument("--atomic-micro", action="store_true",
+                    help="LDS / global atomic throughput probe instead of the step benchmark")
     ap.add_argument("--sort-sweep", action="store_true",
                     help="sweep the sort interval and the tile size instead of the benchmark line")
     ap.add_argument("--sweep-intervals", default="1,2,4,8,16")
@@ -222,6 +255,9 @@ def main():
 
     if args.sort_sweep:
         sort_sweep(args)
+        return
+    if args.atomic_micro:
+        print(json.dumps(atomic_micro()))
         return
 
     if args.calib_copy:

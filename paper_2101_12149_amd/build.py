@@ -15,6 +15,8 @@ CSRC = os.path.join(HERE, "csrc")
 BUILD = os.path.join(HERE, "_build")
 LIB = os.path.join(HERE, "libpic355.so")
 SOURCES = ["kernels_particles.hip", "kernels_grid.hip", "capi.hip"]
+MICRO_SRC = "microbench.hip"
+MICRO_LIB = os.path.join(HERE, "libpic355_micro.so")
 ARCH = os.environ.get("PIC355_ARCH", "gfx950")
 
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
@@ -35,19 +37,26 @@ def _compile(src):
     return obj
 
 
-def build(verbose=False):
-    """Compile every HIP source for the target arch and link the library."""
-    os.makedirs(BUILD, exist_ok=True)
-    with ThreadPoolExecutor(max_workers=len(SOURCES)) as ex:
-        objs = list(ex.map(_compile, SOURCES))
-    tmp = LIB + ".tmp"
+def _link(objs, lib):
+    tmp = lib + ".tmp"
     cmd = [HIPCC, f"--offload-arch={ARCH}", "-shared", "-fPIC", "-o", tmp] + objs
     r = subprocess.run(cmd, capture_output=True, text=True)
     if r.returncode != 0:
         raise RuntimeError(f"link failed:\n{r.stderr}")
-    os.replace(tmp, LIB)
+    os.replace(tmp, lib)
+
+
+def build(verbose=False):
+    """Compile every HIP source for the target arch and link the library
+    (and the separate atomic-throughput probe the benchmark script loads)."""
+    os.makedirs(BUILD, exist_ok=True)
+    with ThreadPoolExecutor(max_workers=len(SOURCES) + 1) as ex:
+        objs = list(ex.map(_compile, SOURCES + [MICRO_SRC]))
+    _link(objs[:-1], LIB)
+    _link(objs[-1:], MICRO_LIB)
     if verbose:
         print("built", LIB)
+        print("built", MICRO_LIB)
     return LIB
 
 

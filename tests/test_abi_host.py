@@ -161,3 +161,13 @@ def test_gather_filter_takes_twelve_field_arrays_of_workspace():
     with pytest.raises(_lib.PicError) as e:
         _lib.pic_tile_shape(dataclasses.replace(g, gather_filter=bad), "f64")
     assert e.value.status == 1
+
+
+def test_atomic_probe_library_loads():
+    """The throughput probe that bench.py --atomic-micro runs is built beside
+    the library and exports its two entry points (nothing is launched here)."""
+    lib = C.CDLL(os.path.join(ROOT, "paper_2101_12149_amd", "libpic355_micro.so"))
+    assert lib.picmb_num_modes() == 10
+    assert hasattr(lib, "picmb_run")
+    ms, ops = C.c_double(), C.c_double()
+    assert lib.picmb_run(99, 1, 1, 1, 1, C.byref(ms), C.byref(ops)) == -1   # bad mode: refused before any call
