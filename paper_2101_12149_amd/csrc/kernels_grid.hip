@@ -13,42 +13,12 @@ namespace pic {
 //   curl_b(S)_x = (S_z - S_z[j-1])/dy - (S_y - S_y[k-1])/dz
 // The coefficients cx, cy, cz already hold (scale / d).
 
-// CKC: each difference along an axis is replaced by the weighted sum of the
-// same difference at the 3x3 cells around it in the transverse plane
-// (centre alpha, edges beta_p / beta_q, corners gamma), periodic.
-template <typename T, bool FWD, bool CKC>
-__global__ void __launch_bounds__(256) k_curl(CurlArgs<T> a)
+// The part of an update after the curl: out = in + curl terms (+ J, source,
+// source adjoint), for cell o = (i, j, k).
+template <typename T>
+__device__ inline void curl_finish(const CurlArgs<T> &a, int i, int j, int k, int64_t o, T dx_sy, T dx_sz, T dy_sx,
+                                   T dy_sz, T dz_sx, T dz_sy)
 {
-    const int i = blockIdx.x * blockDim.x + threadIdx.x;
-    const int j = blockIdx.y;
-    const int k = blockIdx.z;
-    const int n0 = a.n[0], n1 = a.n[1], n2 = a.n[2];
-    if (i >= n0)
-        return;
-    const int64_t o = i + (int64_t)n0 * (j + (int64_t)n1 * k);
-    // offsets of the +1 and -1 neighbours along each axis, periodic
-    const int64_t pl[3] = {(i + 1 < n0) ? 1 : 1 - n0, (j + 1 < n1) ? n0 : (int64_t)n0 * (1 - n1),
-                           (k + 1 < n2) ? (int64_t)n0 * n1 : (int64_t)n0 * n1 * (1 - n2)};
-    const int64_t mn[3] = {(i > 0) ? -1 : n0 - 1, (j > 0) ? -(int64_t)n0 : (int64_t)n0 * (n1 - 1),
-                           (k > 0) ? -(int64_t)n0 * n1 : (int64_t)n0 * n1 * (n2 - 1)};
-    // difference of S along axis ax at the cell o + c (c a transverse shift)
-    auto d1 = [&](const T *S, int ax, int64_t c) -> T {
-        return FWD ? S[o + c + pl[ax]] - S[o + c] : S[o + c] - S[o + c + mn[ax]];
-    };
-    auto diff = [&](const T *S, int ax) -> T {
-        if (!CKC)
-            return d1(S, ax, 0);
-        const int p = ax == 2 ? 0 : ax + 1, q = ax == 0 ? 2 : ax - 1;
-        const T *w = a.ck[ax];
-        return w[0] * d1(S, ax, 0) + w[1] * (d1(S, ax, pl[p]) + d1(S, ax, mn[p])) +
-               w[2] * (d1(S, ax, pl[q]) + d1(S, ax, mn[q])) +
-               w[3] * (d1(S, ax, pl[p] + pl[q]) + d1(S, ax, pl[p] + mn[q]) + d1(S, ax, mn[p] + pl[q]) +
-                       d1(S, ax, mn[p] + mn[q]));
-    };
-    const T *Sx = a.src[0], *Sy = a.src[1], *Sz = a.src[2];
-    const T dx_sy = diff(Sy, 0), dx_sz = diff(Sz, 0);
-    const T dy_sx = diff(Sx, 1), dy_sz = diff(Sz, 1);
-    const T dz_sx = diff(Sx, 2), dz_sy = diff(Sy, 2);
     T vx = a.in[0][o] + (a.cy * dy_sz - a.cz * dz_sy);
     T vy = a.in[1][o] + (a.cz * dz_sx - a.cx * dx_sz);
     T vz = a.in[2][o] + (a.cx * dx_sy - a.cy * dy_sx);
@@ -64,31 +34,128 @@ __global__ void __launch_bounds__(256) k_curl(CurlArgs<T> a)
     }
     if (k == a.kplane) {
         if (a.amp)
-            vx += a.amp[i + (int64_t)n0 * j] * a.ag;
+            vx += a.amp[i + (int64_t)a.n[0] * j] * a.ag;
         if (a.dA)
-            a.dA[i + (int64_t)n0 * j] += a.dag * (double)vx;
+            a.dA[i + (int64_t)a.n[0] * j] += a.dag * (double)vx;
     }
     a.out[0][o] = vx;
     a.out[1][o] = vy;
     a.out[2][o] = vz;
 }
 
+template <typename T, bool FWD>
+__global__ void __launch_bounds__(256) k_curl(CurlArgs<T> a)
+{
+    const int i = blockIdx.x * blockDim.x + threadIdx.x;
+    const int j = blockIdx.y;
+    const int k = blockIdx.z;
+    const int n0 = a.n[0], n1 = a.n[1], n2 = a.n[2];
+    if (i >= n0)
+        return;
+    const int64_t o = i + (int64_t)n0 * (j + (int64_t)n1 * k);
+    int64_t xs, ys, zs;   // neighbour offsets (+1 for forward, -1 for backward), periodic
+    if (FWD) {
+        xs = (i + 1 < n0) ? 1 : 1 - n0;
+        ys = (j + 1 < n1) ? n0 : (int64_t)n0 * (1 - n1);
+        zs = (k + 1 < n2) ? (int64_t)n0 * n1 : (int64_t)n0 * n1 * (1 - n2);
+    } else {
+        xs = (i > 0) ? -1 : n0 - 1;
+        ys = (j > 0) ? -(int64_t)n0 : (int64_t)n0 * (n1 - 1);
+        zs = (k > 0) ? -(int64_t)n0 * n1 : (int64_t)n0 * n1 * (n2 - 1);
+    }
+    const T *Sx = a.src[0], *Sy = a.src[1], *Sz = a.src[2];
+    // forward: S[o + s] - S[o]; backward: S[o] - S[o + s] (s the -1 offset)
+    auto d = [&](const T *S, int64_t s) -> T { return FWD ? S[o + s] - S[o] : S[o] - S[o + s]; };
+    curl_finish(a, i, j, k, o, d(Sy, xs), d(Sz, xs), d(Sx, ys), d(Sz, ys), d(Sx, zs), d(Sy, zs));
+}
+
+// CKC form: each difference along an axis is the weighted sum of the same
+// difference at the 3 x 3 cells around it across the axis (centre alpha,
+// edges beta_p / beta_q, corners gamma).  A workgroup takes a 64 x 4 x 4 block
+// of cells; the three source components of the block plus one cell on every
+// side (periodic) are staged in LDS, and each difference is read from there
+// (54 differences per cell).
+constexpr int CKC_TX = 64, CKC_TY = 4, CKC_TZ = 4;
+
+template <typename T, bool FWD>
+__global__ void __launch_bounds__(CKC_TX *CKC_TY) k_curl_ckc(CurlArgs<T> a)
+{
+    constexpr int LX = CKC_TX + 2, LY = CKC_TY + 2, LZ = CKC_TZ + 2, LV = LX * LY * LZ;
+    __shared__ T s[3 * LV];
+    const int n0 = a.n[0], n1 = a.n[1], n2 = a.n[2];
+    const int x0 = blockIdx.x * CKC_TX, y0 = blockIdx.y * CKC_TY, z0 = blockIdx.z * CKC_TZ;
+    // periodic index of v >= -1 (a block can pass the end of a grid smaller
+    // than itself more than once: the rare modulo)
+    auto wrap = [](int v, int n) {
+        v = v < 0 ? v + n : v;
+        v = v >= n ? v - n : v;
+        return v >= n ? v % n : v;
+    };
+    // every load of the staging is issued before any LDS store, so that the
+    // loads overlap (divisions by compile-time constants only)
+    constexpr int NTH = CKC_TX * CKC_TY, NPER = (3 * LV + NTH - 1) / NTH;
+    const int tid = threadIdx.x + CKC_TX * threadIdx.y;
+    T v[NPER];
+#pragma unroll
+    for (int t = 0; t < NPER; ++t) {
+        const int r = tid + t * NTH;
+        if (r < 3 * LV) {
+            const int c = r / LV, q = r - c * LV;
+            const int lx = q % LX, ly = (q / LX) % LY, lz = q / (LX * LY);
+            const int gx = wrap(x0 - 1 + lx, n0), gy = wrap(y0 - 1 + ly, n1), gz = wrap(z0 - 1 + lz, n2);
+            v[t] = a.src[c][gx + (int64_t)n0 * (gy + (int64_t)n1 * gz)];
+        }
+    }
+#pragma unroll
+    for (int t = 0; t < NPER; ++t) {
+        const int r = tid + t * NTH;
+        if (r < 3 * LV)
+            s[r] = v[t];
+    }
+    __syncthreads();
+    const int i = x0 + threadIdx.x, j = y0 + threadIdx.y;
+    if (i >= n0 || j >= n1)
+        return;   // no barrier follows
+    constexpr int st[3] = {1, LX, LX * LY};
+    // difference of component c along axis ax at LDS cell l, averaged across ax
+    auto diff = [&](int c, int ax, int l) -> T {
+        const T *S = s + c * LV;
+        const int p = ax == 2 ? 0 : ax + 1, q = ax == 0 ? 2 : ax - 1;
+        const int sa = FWD ? st[ax] : -st[ax];
+        auto d1 = [&](int m) -> T { return FWD ? S[m + sa] - S[m] : S[m] - S[m + sa]; };
+        const T *w = a.ck[ax];
+        const int sp = st[p], sq = st[q];
+        return w[0] * d1(l) + w[1] * (d1(l + sp) + d1(l - sp)) + w[2] * (d1(l + sq) + d1(l - sq)) +
+               w[3] * (d1(l + sp + sq) + d1(l + sp - sq) + d1(l - sp + sq) + d1(l - sp - sq));
+    };
+    for (int tz = 0; tz < CKC_TZ; ++tz) {
+        const int k = z0 + tz;
+        if (k >= n2)
+            break;
+        const int l = (threadIdx.x + 1) + LX * ((threadIdx.y + 1) + LY * (tz + 1));
+        const int64_t o = i + (int64_t)n0 * (j + (int64_t)n1 * k);
+        curl_finish(a, i, j, k, o, diff(1, 0, l), diff(2, 0, l), diff(0, 1, l), diff(2, 1, l), diff(0, 2, l),
+                    diff(1, 2, l));
+    }
+}
+
 template <typename T>
 hipError_t launch_curl(bool forward, const CurlArgs<T> &a, hipStream_t st)
 {
+    if (a.ckc) {
+        dim3 grid((a.n[0] + CKC_TX - 1) / CKC_TX, (a.n[1] + CKC_TY - 1) / CKC_TY, (a.n[2] + CKC_TZ - 1) / CKC_TZ);
+        if (forward)
+            hipLaunchKernelGGL((k_curl_ckc<T, true>), grid, dim3(CKC_TX, CKC_TY), 0, st, a);
+        else
+            hipLaunchKernelGGL((k_curl_ckc<T, false>), grid, dim3(CKC_TX, CKC_TY), 0, st, a);
+        return hipGetLastError();
+    }
     const int bx = a.n[0] >= 256 ? 256 : (a.n[0] >= 128 ? 128 : 64);
     dim3 grid((a.n[0] + bx - 1) / bx, a.n[1], a.n[2]);
-    if (a.ckc) {
-        if (forward)
-            hipLaunchKernelGGL((k_curl<T, true, true>), grid, dim3(bx), 0, st, a);
-        else
-            hipLaunchKernelGGL((k_curl<T, false, true>), grid, dim3(bx), 0, st, a);
-    } else {
-        if (forward)
-            hipLaunchKernelGGL((k_curl<T, true, false>), grid, dim3(bx), 0, st, a);
-        else
-            hipLaunchKernelGGL((k_curl<T, false, false>), grid, dim3(bx), 0, st, a);
-    }
+    if (forward)
+        hipLaunchKernelGGL((k_curl<T, true>), grid, dim3(bx), 0, st, a);
+    else
+        hipLaunchKernelGGL((k_curl<T, false>), grid, dim3(bx), 0, st, a);
     return hipGetLastError();
 }
 

@@ -92,6 +92,28 @@ def test_vay_push_matches_oracle(dtype):
     assert max_rel(_cpu(d_sp.u), ob.u) > 1e-3
 
 
+@pytest.mark.parametrize("dtype", ["f64", "f32"])
+def test_vay_push_with_magnetic_rotation_beyond_gamma(dtype):
+    """|q B dt / 2m| well above the new gamma (the quadratic's sigma < 0,
+    where the root is taken in its cancellation-free form): still the
+    oracle's result."""
+    g = dataclasses.replace(_grid(), pusher=1)
+    sp = random_species(g, 4000, 28, u_th=0.3, dtype=dtype)
+    rng = np.random.default_rng(29)
+    Ep = torch.tensor(rng.normal(0, 1.0, (3, 4000)), dtype=tdtype(dtype))
+    Bp = torch.tensor(rng.normal(0, 200.0, (3, 4000)), dtype=tdtype(dtype))
+    tau2 = (0.5 * g.dt) ** 2 * (Bp.double() ** 2).sum(0)
+    d_sp = dev(sp)
+    _lib.pic_push(g, d_sp, dev(Ep), dev(Bp))
+    torch.cuda.synchronize()
+    o = sp.numpy()
+    oracle.push(g, o, np.ascontiguousarray(_cpu(Ep)), np.ascontiguousarray(_cpu(Bp)))
+    gam = np.sqrt(1 + np.sum(o.u ** 2, axis=0))
+    assert np.mean(tau2.numpy() > gam ** 2) > 0.9
+    tol = F64_TOL if dtype == "f64" else 2e-6
+    assert max_rel(_cpu(d_sp.u), o.u) < tol
+
+
 def test_unknown_pusher_is_rejected():
     g = dataclasses.replace(_grid(), pusher=2)
     sp = dev(random_species(g, 10, 25))
