@@ -117,7 +117,7 @@ def cpu_baseline():
     import oracle
     from paper_2101_12149_amd import workloads as wl
     n = (96, 96, 96)
-    ppc, nsteps = 8, 3
+    ppc, nsteps = 8, 5
     w = wl.uniform_plasma(n, ppc, 0.05, 3, nsteps, "f64", 1002, 4)
     sp, f = w.species.numpy(), w.fields.numpy()
     oracle.step(w.grid, sp, f, None, 0, 1)   # warm (page-in, thread start)
