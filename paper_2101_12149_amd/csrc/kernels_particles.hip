@@ -1413,10 +1413,18 @@ struct AdjThreads {
     static constexpr int value = sizeof(T) == 4 ? 1024 : 512;
 };
 
+// threads of the tiled pass 1: 512 leaves the order-3 FP32 pass 256
+// registers (1024 capped it at 128 and spilled 29 to scratch; 25.9 against
+// 27.1 ms at 256^3 / 8 ppc)
+template <typename T>
+struct PushThreads {
+    static constexpr int value = 512;
+};
+
 // pass 1, tiled: LDS holds E, B with the gather halo and hatE with the
 // deposit halo; strays are left to k_adjoint_push_strays
 template <typename T, int O>
-__global__ void __launch_bounds__(AdjThreads<T>::value) k_adjoint_push_tile(PConst<T> pc, TileGeo tg, PArr<T> sp,
+__global__ void __launch_bounds__(PushThreads<T>::value) k_adjoint_push_tile(PConst<T> pc, TileGeo tg, PArr<T> sp,
                                                                            FieldPtrs<T> fp, AdjPtrs<T> ap,
                                                                            const int *__restrict__ tile_start,
                                                                            int *err)
@@ -1762,8 +1770,8 @@ static hipError_t launch_adj_tile_o(const PConst<T> &pc, const TileGeo &tg, cons
     const unsigned ntiles = (unsigned)(tg.nt[0] * tg.nt[1] * tg.nt[2]);
     const unsigned nth = AdjThreads<T>::value;
     const size_t l1 = adjoint_push_lds<T>(tg), l2 = adjoint_scatter_lds<T>(tg);
-    hipLaunchKernelGGL((k_adjoint_push_tile<T, O>), dim3(ntiles), dim3(nth), l1, st, pc, tg, sp, f, ap, tile_start,
-                       err);
+    hipLaunchKernelGGL((k_adjoint_push_tile<T, O>), dim3(ntiles), dim3(PushThreads<T>::value), l1, st, pc, tg, sp,
+                       f, ap, tile_start, err);
     hipLaunchKernelGGL((k_adjoint_push_strays<T, O>), dim3(ntiles), dim3(STRAY_THREADS), 0, st, pc, tg, sp, f, ap,
                        tile_start, err);
     hipLaunchKernelGGL((k_adjoint_scatter_tile<T, O>), dim3(ntiles), dim3(nth), l2, st, pc, tg, sp, f, ap,
