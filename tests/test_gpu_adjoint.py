@@ -230,12 +230,16 @@ def _gpu_loss(pb, u0, amp):
         return ro.rollout_loss(u0, amp, pb).item()
 
 
+@pytest.mark.parametrize("options", [False, True])
 @pytest.mark.parametrize("tiled", [False, True])
-def test_rollout_gradient_matches_oracle_reverse_sweep(tiled):
+def test_rollout_gradient_matches_oracle_reverse_sweep(tiled, options):
     """Reduced differentiable workload (16^3, 2 ppc, order 3, FP64, 8 steps,
     checkpoint every 3): torch autograd through the GPU rollout against the
-    oracle's own forward + reverse sweep."""
+    oracle's own forward + reverse sweep; with options, Vay's pusher, the CKC
+    solver and the gather filter."""
     w = wl.differentiable((16, 16, 16), 2, 0.05, 3, 8, "f64", 1234, checkpoint_every=3, amp0=5e-3, period=6)
+    if options:
+        w.grid = dataclasses.replace(w.grid, pusher=1, solver=1, gather_filter=TAPS)
     pb = _problem(w, tiled)
     u0 = pb.species.u.clone().requires_grad_(True)
     amp = pb.source.amp.clone().requires_grad_(True)
