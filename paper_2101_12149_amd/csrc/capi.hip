@@ -340,8 +340,12 @@ pic_status check_fields(const pic_fields *f, bool need_j)
 // workspace layout
 struct WsLayout {
     size_t err, counts, bsum, key, rank, slot, scell, soff, su, sw, hatE, partials, red5, old_ts, filt, lfilt,
-        total;
+        gcnt, glist, gflag, total;
 };
+
+// guest list slots per tile (a tile's particles that left their home region
+// beyond this many go to the stray kernel)
+constexpr int GUEST_CAP = 256;
 
 size_t al(size_t x)
 {
@@ -386,6 +390,13 @@ WsLayout layout(const GridInfo &gi, int64_t np)
     o += gi.filt ? 6 * al(gi.tsize * (size_t)gi.ncell) : 0;
     L.lfilt = o;
     o += gi.filt ? 6 * al(gi.tsize * (size_t)gi.ncell) : 0;
+    // guest lists, counts and per-particle flags, two of each (by step parity)
+    L.gcnt = o;
+    o += 2 * al(sizeof(int) * (size_t)gi.ntiles);
+    L.glist = o;
+    o += 2 * al(2 * sizeof(int) * (size_t)gi.ntiles * GUEST_CAP);
+    L.gflag = o;
+    o += 2 * al(n);
     L.total = o;
     return L;
 }
@@ -686,6 +697,17 @@ pic_status step_t(const pic_grid *g, const GridInfo &gi, pic_species *sp, pic_fi
     // per-particle stray marks of the tile kernels, in the sort's key buffer
     // (free once the sort of the step is done)
     unsigned char *stray = reinterpret_cast<unsigned char *>(w + L.key);
+    // guest buffers by step parity: the lists a step builds are the next
+    // step's; none are read at the first step of a call or after a sort
+    // (a sort renumbers the particles)
+    int *gcnt[2];
+    int2 *glist[2];
+    unsigned char *gflag[2];
+    for (int b = 0; b < 2; ++b) {
+        gcnt[b] = reinterpret_cast<int *>(w + L.gcnt + b * al(sizeof(int) * (size_t)gi.ntiles));
+        glist[b] = reinterpret_cast<int2 *>(w + L.glist + b * al(2 * sizeof(int) * (size_t)gi.ntiles * GUEST_CAP));
+        gflag[b] = reinterpret_cast<unsigned char *>(w + L.gflag + b * al((size_t)(sp->n > 0 ? sp->n : 0)));
+    }
     PIC_HIP(launch_fill<int>(err, 1, 0, st));
     for (int d = 0; d < 3; ++d)
         PIC_HIP(launch_fill<T>(fp.J[d], gi.ncell, T(0), st));
@@ -695,6 +717,22 @@ pic_status step_t(const pic_grid *g, const GridInfo &gi, pic_species *sp, pic_fi
         if (gi.filt && sp->n > 0) {
             TimedScope ts(1, st);
             PIC_TRY_S(filter_fields<T>(gi, fp, fpp, st));
+        }
+        // guests only where particles drift far between sorts (no re-sort, or
+        // sorts more than 8 steps apart); otherwise the kernel without them
+        GuestArgs ga{};
+        if (sort_every == 0 || sort_every > 8) {
+            const int cur = (int)(it & 1), nxt = 1 - cur;
+            const bool read = it > 0 && !sort_now;
+            ga.cnt = read ? gcnt[cur] : nullptr;
+            ga.list = read ? glist[cur] : nullptr;
+            ga.flag = read ? gflag[cur] : nullptr;
+            ga.cnt_next = gcnt[nxt];
+            ga.list_next = glist[nxt];
+            ga.flag_next = gflag[nxt];
+            ga.cap = GUEST_CAP;
+            if (tile_start && sp->n > 0)
+                PIC_HIP(launch_fill<int>(ga.cnt_next, gi.ntiles, 0, st));
         }
         if (sort_now && sp->n > 0) {
             PArr<T> sorted;
@@ -706,17 +744,17 @@ pic_status step_t(const pic_grid *g, const GridInfo &gi, pic_species *sp, pic_fi
             }
             {
                 TimedScope ts(1, st);
-                PIC_HIP(launch_particles_tile<T>(gi.order, pc, gi.tg, sorted, user, fpp, tile_start, stray, err, st));
+                PIC_HIP(launch_particles_tile<T>(gi.order, pc, gi.tg, sorted, user, fpp, tile_start, stray, ga, err, st));
             }
             TimedScope ts(6, st);
-            PIC_HIP(launch_particles_strays<T>(gi.order, pc, gi.tg, sorted, user, fpp, tile_start, stray, err, st));
+            PIC_HIP(launch_particles_strays<T>(gi.order, pc, gi.tg, sorted, user, fpp, tile_start, stray, ga, err, st));
         } else if (tile_start && sp->n > 0) {
             {
                 TimedScope ts(1, st);
-                PIC_HIP(launch_particles_tile<T>(gi.order, pc, gi.tg, user, user, fpp, tile_start, stray, err, st));
+                PIC_HIP(launch_particles_tile<T>(gi.order, pc, gi.tg, user, user, fpp, tile_start, stray, ga, err, st));
             }
             TimedScope ts(6, st);
-            PIC_HIP(launch_particles_strays<T>(gi.order, pc, gi.tg, user, user, fpp, tile_start, stray, err, st));
+            PIC_HIP(launch_particles_strays<T>(gi.order, pc, gi.tg, user, user, fpp, tile_start, stray, ga, err, st));
         } else {
             TimedScope ts(1, st);
             PIC_HIP(launch_particles_global<T>(gi.order, pc, user, fpp, err, st));

@@ -120,6 +120,7 @@ __device__ inline FieldSrc<T> global_fields(const FieldPtrs<T> &fp)
 }
 
 struct TileSpan {
+    int t;       // logical tile index (x fastest)
     int t0[3];
     int64_t ps, pe;
 };
@@ -131,6 +132,7 @@ __device__ inline TileSpan tile_span(const TileGeo &tg, const int *tile_start, i
     if (tg.xcd_map)
         t = (t & 7) * (ntiles >> 3) + (t >> 3);
     TileSpan s;
+    s.t = t;
     s.t0[0] = (t % tg.nt[0]) * tg.t[0];
     s.t0[1] = ((t / tg.nt[0]) % tg.nt[1]) * tg.t[1];
     s.t0[2] = (t / (tg.nt[0] * tg.nt[1])) * tg.t[2];
@@ -157,6 +159,36 @@ __device__ inline bool tile_local(const TileGeo &tg, const int *n, const int *t0
         inside = inside && v >= -tg.slack && v < tg.t[d] + tg.slack;
     }
     return inside;
+}
+
+// logical tile of a cell, and the first cell of a tile
+__device__ __attribute__((always_inline)) inline int cell_tile(const TileGeo &tg, const int *c)
+{
+    return c[0] / tg.t[0] + tg.nt[0] * (c[1] / tg.t[1] + tg.nt[1] * (c[2] / tg.t[2]));
+}
+
+__device__ __attribute__((always_inline)) inline void tile_origin(const TileGeo &tg, int t, int *t0)
+{
+    t0[0] = (t % tg.nt[0]) * tg.t[0];
+    t0[1] = ((t / tg.nt[0]) % tg.nt[1]) * tg.t[1];
+    t0[2] = (t / (tg.nt[0] * tg.nt[1])) * tg.t[2];
+}
+
+// Status of a moved particle for the next step: 0 if its new cell c1 is in
+// its home tile's region (or no list slot is free, which leaves it to the
+// stray kernel), 1 once it is listed as a guest of the tile holding c1.
+__device__ __attribute__((always_inline)) inline unsigned char guest_next(const GuestArgs &g, const TileGeo &tg, const int *n, int64_t p, int home,
+                                           const int *home_t0, const int *c1)
+{
+    int l[3];
+    if (tile_local(tg, n, home_t0, c1, l) || p > 0x7fffffff)
+        return 0;
+    const int host = cell_tile(tg, c1);
+    const int slot = atomicAdd(g.cnt_next + host, 1);
+    if (slot >= g.cap)
+        return 0;
+    g.list_next[(int64_t)host * g.cap + slot] = make_int2((int)p, home);
+    return 1;
 }
 
 __device__ inline int region_global(const int *n, const int *t0, int lo, int rx, int ry, int rz)
@@ -599,10 +631,10 @@ __device__ __attribute__((always_inline)) inline void deposit_still_shared(const
 // stray[p] records whether particle p was left to k_particles_strays: when
 // the step runs in place the cells are overwritten, so the stray kernel
 // cannot tell the strays from the cells any more.
-template <typename T, int O>
+template <typename T, int O, bool G>
 __global__ void __launch_bounds__(TileThreads<T>::value) k_particles_tile(PConst<T> pc, TileGeo tg, PArr<T> in, PArr<T> out,
                                                         FieldPtrs<T> fp, const int *__restrict__ tile_start,
-                                                        unsigned char *__restrict__ stray, int *err)
+                                                        unsigned char *__restrict__ stray, GuestArgs g, int *err)
 {
     extern __shared__ __align__(16) unsigned char smem_raw[];
     T *sF = reinterpret_cast<T *>(smem_raw);
@@ -621,7 +653,9 @@ __global__ void __launch_bounds__(TileThreads<T>::value) k_particles_tile(PConst
     cq.pk = cq.j + cq.cap;
     cq.cnt = cq.pk + cq.cap;
     const TileSpan ts = tile_span(tg, tile_start, in.n);
-    if (ts.pe <= ts.ps)
+    // guests of this tile (G: the kernel also builds the next step's lists)
+    const int ng = (G && g.cnt) ? (g.cnt[ts.t] < g.cap ? g.cnt[ts.t] : g.cap) : 0;
+    if (ts.pe <= ts.ps && ng == 0)
         return;   // uniform across the workgroup
 
     const int tid = threadIdx.x, nth = blockDim.x;
@@ -648,31 +682,63 @@ __global__ void __launch_bounds__(TileThreads<T>::value) k_particles_tile(PConst
     const int np = (int)(ts.pe - ts.ps);
     // coalesced: the tile's particles are stored rank-major (one particle
     // per cell, cell after cell, then the next rank), so consecutive lanes
-    // read consecutive memory and sit in distinct neighbouring cells
-    for (int j0 = 0; j0 < np; j0 += nth) {
+    // read consecutive memory and sit in distinct neighbouring cells.  After
+    // them come the tile's guests (particles binned elsewhere whose cell lies
+    // in this tile), through the same path.
+    for (int j0 = 0; j0 < np + ng; j0 += nth) {
         const int j = j0 + tid;
         int key = 0;   // non-zero: a particle that stays in its cell, deposited below
         int l[3] = {0, 0, 0};
         T f[3] = {T(0), T(0), T(0)}, f1[3] = {T(0), T(0), T(0)}, w = T(0);
-        if (j < np) {
-            const int64_t p = ts.ps + j;
+        if (j < np + ng) {
+            const bool own = j < np;
+            int64_t p = ts.ps + j;
+            int home = ts.t;
+            if (!own) {
+                const int2 e = g.list[(int64_t)ts.t * g.cap + (j - np)];
+                p = e.x;
+                home = e.y;
+            }
             int c[3];
             T u[3];
-            unsigned char st = 0;
+            unsigned char st = 0, gn = 0;   // stray mark; guest status next step
+            bool moved = true;             // this launch writes the particle's next status
             if (!load_particle(in, p, pc.n, c, f, u, err)) {
                 copy_particle(in, out, p);
             } else if (!tile_local(tg, pc.n, ts.t0, c, l)) {
-                st = 1;
+                if (own) {
+                    // outside the region: a guest of the tile holding its cell,
+                    // or the stray kernel's (which writes its status)
+                    moved = false;
+                    st = (G && g.flag && g.flag[p]) ? 0 : 1;
+                } else {
+                    atomicOr(err, 2);   // cannot happen: the list was built from this cell in this call
+                    copy_particle(in, out, p);
+                }
             } else {
                 int kap[3];
                 if (particle_advance<T, O, true>(pc, in, out, lf, p, c, f, u, l, tg.lo_f, sf, f1, kap, w, err)) {
                     if ((kap[0] | kap[1] | kap[2]) == 0)
                         key = xrun_key(l);
-                    else if (!cq.push(j, l, kap, f, f1))
+                    else if (!cq.push((int)(p - ts.ps), l, kap, f, f1))
                         deposit_local_full<T, O>(pc, f, f1, kap, l, tg.lo_j, sj, w, sJ, rjvol);
+                    // a particle that changed cells, or a guest (outside its home
+                    // region), gets its status for the next step
+                    if (G && ((kap[0] | kap[1] | kap[2]) || !own)) {
+                        int c1[3], ht0[3] = {ts.t0[0], ts.t0[1], ts.t0[2]};
+#pragma unroll
+                        for (int d = 0; d < 3; ++d)
+                            c1[d] = wrap_any(c[d] + kap[d], pc.n[d]);
+                        if (!own)
+                            tile_origin(tg, home, ht0);
+                        gn = guest_next(g, tg, pc.n, p, home, ht0, c1);
+                    }
                 }
             }
-            stray[p] = st;
+            if (own)
+                stray[p] = st;
+            if (G && moved)
+                g.flag_next[p] = gn;
         }
         // the wave is converged here: find the runs, then deposit
         const XRun xr = xrun(key);
@@ -719,7 +785,8 @@ __global__ void __launch_bounds__(TileThreads<T>::value) k_particles_tile(PConst
 template <typename T, int O>
 __global__ void __launch_bounds__(STRAY_THREADS) k_particles_strays(PConst<T> pc, TileGeo tg, PArr<T> in, PArr<T> out,
                                                                     FieldPtrs<T> fp, const int *__restrict__ tile_start,
-                                                                    const unsigned char *__restrict__ stray, int *err)
+                                                                    const unsigned char *__restrict__ stray,
+                                                                    GuestArgs g, int *err)
 {
     __shared__ int list[STRAY_CHUNK];
     __shared__ int cnt;
@@ -737,6 +804,8 @@ __global__ void __launch_bounds__(STRAY_THREADS) k_particles_strays(PConst<T> pc
                 copy_particle(in, out, p);
             else
                 particle_step_global<T, O>(pc, in, out, fp, p, c, f, u, err);
+            if (g.flag_next)
+                g.flag_next[p] = 0;   // next step: the home tile's again, or a stray
         }
         __syncthreads();   // the list is rewritten by the next chunk
     }
@@ -1606,39 +1675,45 @@ static void allow_big_lds(K *kernel, bool &done)
 
 template <typename T, int O>
 static hipError_t launch_tile_o(const PConst<T> &pc, const TileGeo &tg, const PArr<T> &in, const PArr<T> &out,
-                                const FieldPtrs<T> &f, const int *tile_start, unsigned char *stray, int *err,
-                                hipStream_t st)
+                                const FieldPtrs<T> &f, const int *tile_start, unsigned char *stray,
+                                const GuestArgs &g, int *err, hipStream_t st)
 {
-    static bool attr_set = false;
-    allow_big_lds(&k_particles_tile<T, O>, attr_set);
+    static bool attr_plain = false, attr_guests = false;
     const size_t lds = tile_lds_bytes<T>(O, tg);
     const unsigned ntiles = (unsigned)(tg.nt[0] * tg.nt[1] * tg.nt[2]);
-    hipLaunchKernelGGL((k_particles_tile<T, O>), dim3(ntiles), dim3(TileThreads<T>::value), lds, st, pc, tg, in, out,
-                       f, tile_start, stray, err);
+    if (g.flag_next) {
+        allow_big_lds(&k_particles_tile<T, O, true>, attr_guests);
+        hipLaunchKernelGGL((k_particles_tile<T, O, true>), dim3(ntiles), dim3(TileThreads<T>::value), lds, st, pc, tg,
+                           in, out, f, tile_start, stray, g, err);
+    } else {
+        allow_big_lds(&k_particles_tile<T, O, false>, attr_plain);
+        hipLaunchKernelGGL((k_particles_tile<T, O, false>), dim3(ntiles), dim3(TileThreads<T>::value), lds, st, pc,
+                           tg, in, out, f, tile_start, stray, g, err);
+    }
     return hipGetLastError();
 }
 
 template <typename T>
 hipError_t launch_particles_tile(int order, const PConst<T> &pc, const TileGeo &tg, const PArr<T> &in,
                                  const PArr<T> &out, const FieldPtrs<T> &f, const int *tile_start,
-                                 unsigned char *stray, int *err, hipStream_t st)
+                                 unsigned char *stray, const GuestArgs &g, int *err, hipStream_t st)
 {
-    return order == 1 ? launch_tile_o<T, 1>(pc, tg, in, out, f, tile_start, stray, err, st)
-                      : launch_tile_o<T, 3>(pc, tg, in, out, f, tile_start, stray, err, st);
+    return order == 1 ? launch_tile_o<T, 1>(pc, tg, in, out, f, tile_start, stray, g, err, st)
+                      : launch_tile_o<T, 3>(pc, tg, in, out, f, tile_start, stray, g, err, st);
 }
 
 template <typename T>
 hipError_t launch_particles_strays(int order, const PConst<T> &pc, const TileGeo &tg, const PArr<T> &in,
                                    const PArr<T> &out, const FieldPtrs<T> &f, const int *tile_start,
-                                   const unsigned char *stray, int *err, hipStream_t st)
+                                   const unsigned char *stray, const GuestArgs &g, int *err, hipStream_t st)
 {
     const unsigned ntiles = (unsigned)(tg.nt[0] * tg.nt[1] * tg.nt[2]);
     if (order == 1)
         hipLaunchKernelGGL((k_particles_strays<T, 1>), dim3(ntiles), dim3(STRAY_THREADS), 0, st, pc, tg, in, out, f,
-                           tile_start, stray, err);
+                           tile_start, stray, g, err);
     else
         hipLaunchKernelGGL((k_particles_strays<T, 3>), dim3(ntiles), dim3(STRAY_THREADS), 0, st, pc, tg, in, out, f,
-                           tile_start, stray, err);
+                           tile_start, stray, g, err);
     return hipGetLastError();
 }
 
@@ -1798,10 +1873,10 @@ hipError_t launch_adjoint_tile(int order, const PConst<T> &pc, const TileGeo &tg
     template size_t tile_lds_bytes<T>(int, const TileGeo &);                                                       \
     template hipError_t launch_particles_tile<T>(int, const PConst<T> &, const TileGeo &, const PArr<T> &,         \
                                                  const PArr<T> &, const FieldPtrs<T> &, const int *,               \
-                                                 unsigned char *, int *, hipStream_t);                             \
+                                                 unsigned char *, const GuestArgs &, int *, hipStream_t);          \
     template hipError_t launch_particles_strays<T>(int, const PConst<T> &, const TileGeo &, const PArr<T> &,       \
                                                    const PArr<T> &, const FieldPtrs<T> &, const int *,             \
-                                                   const unsigned char *, int *, hipStream_t);                     \
+                                                   const unsigned char *, const GuestArgs &, int *, hipStream_t);                     \
     template hipError_t launch_particles_global<T>(int, const PConst<T> &, const PArr<T> &, const FieldPtrs<T> &,  \
                                                    int *, hipStream_t);                                            \
     template hipError_t launch_gather<T>(int, const PConst<T> &, const PArr<T> &, const FieldPtrs<T> &,            \

@@ -77,6 +77,21 @@ struct CurlArgs {
     T ck[3][4];       // per difference axis a: alpha, beta_p, beta_q, gamma (p = a+1, q = a+2)
 };
 
+// Guests: a particle whose cell, after a step, lies outside the region
+// (tile + slack) of its binned ("home") tile is handed to the tile that holds
+// its cell for the next step, whose kernel moves it with its LDS fields and
+// current; without a free list slot it goes to the stray kernel instead.
+// Lists and flags are double-buffered by step.
+struct GuestArgs {
+    const int *cnt;              // guests per tile this step (null: no guests this step)
+    const int2 *list;            // [tile * cap + i]: (particle, home tile)
+    const unsigned char *flag;   // per particle: 1 = handled by a host tile this step (null: none)
+    int *cnt_next;               // guests per tile next step, zeroed before the launch
+    int2 *list_next;
+    unsigned char *flag_next;    // written for every particle the launch moves
+    int cap;                     // list slots per tile
+};
+
 // ---------------------------------------------------------------------------
 // launchers (return hipSuccess or the launch error)
 
@@ -85,12 +100,12 @@ struct CurlArgs {
 template <typename T>
 hipError_t launch_particles_tile(int order, const PConst<T> &pc, const TileGeo &tg, const PArr<T> &in,
                                  const PArr<T> &out, const FieldPtrs<T> &f, const int *tile_start,
-                                 unsigned char *stray, int *err, hipStream_t st);
+                                 unsigned char *stray, const GuestArgs &g, int *err, hipStream_t st);
 // the particles the tile kernel marked in `stray`, on global memory
 template <typename T>
 hipError_t launch_particles_strays(int order, const PConst<T> &pc, const TileGeo &tg, const PArr<T> &in,
                                    const PArr<T> &out, const FieldPtrs<T> &f, const int *tile_start,
-                                   const unsigned char *stray, int *err, hipStream_t st);
+                                   const unsigned char *stray, const GuestArgs &g, int *err, hipStream_t st);
 template <typename T>
 hipError_t launch_particles_global(int order, const PConst<T> &pc, const PArr<T> &sp, const FieldPtrs<T> &f,
                                    int *err, hipStream_t st);

@@ -450,7 +450,9 @@ def test_untiled_step_matches_oracle_particle_by_particle():
 
 def test_stale_binning_uses_the_fallback_path_correctly():
     """Sort once, then step many times without re-sorting at a high thermal
-    speed: particles leave their tile's LDS region and take the global path."""
+    speed: particles leave their tile's LDS region and are moved as guests of
+    the tile that holds their cell (or, the first step after the sort, on the
+    global path)."""
     w = wl.uniform_plasma((16, 16, 16), 2, 0.3, 3, 8, "f64", 75, 0, shuffle=True)
     g = w.grid
     sp = dev(w.species)
@@ -531,6 +533,29 @@ def test_dense_hot_tiles_overflow_the_crossing_queue(dtype):
         J = _cpu(gf.J)
         divJ = sum((J[m] - np.roll(J[m], 1, axis=2 - m)) / g.d[m] for m in range(3))
         assert np.linalg.norm(drho + divJ) / np.linalg.norm(drho) < 1e-6
+
+
+def test_guest_lists_overflow_to_the_stray_path():
+    """64 ppc at u_th = 0.9c on 16^3, sorted once and then stepped without
+    re-sorting: thousands of particles per tile leave their home region each
+    step, more than a tile's guest list holds, so the rest take the stray
+    kernel.  FP64 within 1e-12 over three steps."""
+    w = wl.uniform_plasma((16, 16, 16), 64, 0.9, 3, 3, "f64", 87, 0)
+    g = w.grid
+    sp = dev(w.species)
+    ts = torch.zeros(_lib.pic_tile_count(g, "f64") + 1, dtype=torch.int32, device="cuda")
+    ws = _lib.workspace(g, "f64", sp.n)
+    _lib.pic_sort_tiles(g, sp, ts, ws)
+    torch.cuda.synchronize()
+    w2 = wl.Workload(w.name, g, wl.Species(sp.cell.cpu(), sp.off.cpu(), sp.u.cpu(), None, sp.w0, sp.q, sp.m),
+                     w.fields, None, 3, 0, "f64", 87)
+    gsp, gf, _ = _run_gpu_steps(w2, 3, 0, tiled=True, tile_start=ts)
+    osp, of, _ = _run_oracle(w2, 3)
+    for name in ("E", "B", "J"):
+        assert rel_l2(_cpu(getattr(gf, name)), getattr(of, name)) < F64_TOL, name
+    assert np.array_equal(gsp.cell.cpu().numpy(), osp.cell)
+    assert max_rel(_cpu(gsp.u), osp.u) < F64_TOL
+    assert max_rel(_cpu(gsp.off), osp.off) < 1e-13
 
 
 def test_laser_plasma_reduced_with_empty_tiles_and_source():
