@@ -890,8 +890,8 @@ pic_status adjoint_t(const pic_grid *g, const GridInfo &gi, const pic_species *s
             PIC_HIP(launch_adjoint_tile<T>(gi.order, pc, adjoint_geo(gi), parr<T>(sp), fpv, hat, lx, lu, glE, glB,
                                            vb, tile_start, err, st));
         else
-            PIC_HIP(launch_adjoint_particles<T>(gi.order, pc, parr<T>(sp), fpv, hat, lx, lu, glE, glB, vb, err,
-                                                st));
+            PIC_HIP(launch_adjoint_particles<T>(gi.order, pc, parr<T>(sp), fpv, hat, lx, lu, glE, glB, vb, tile_start,
+                                                gi.ntiles, err, st));
         if (gi.filt) {
             FieldPtrs<T> lsrc{}, ldst{};
             for (int d = 0; d < 3; ++d) {

@@ -1347,7 +1347,8 @@ __device__ inline int box_rel(int c, int ref, int n)
 }
 
 template <typename T, int O>
-__global__ void __launch_bounds__(BOX_THREADS) k_adjoint_scatter_box(PConst<T> pc, PArr<T> sp, AdjPtrs<T> ap)
+__global__ void __launch_bounds__(BOX_THREADS) k_adjoint_scatter_box(PConst<T> pc, PArr<T> sp, AdjPtrs<T> ap,
+                                                                    const int *__restrict__ tile_start)
 {
     extern __shared__ __align__(16) unsigned char smem_raw[];
     int(*wred)[6] = reinterpret_cast<int(*)[6]>(smem_raw);   // per-wave minima and maxima
@@ -1356,8 +1357,18 @@ __global__ void __launch_bounds__(BOX_THREADS) k_adjoint_scatter_box(PConst<T> p
     constexpr int gl = O == 3 ? 2 : 1;   // gather halo below a cell
     constexpr int gh = O == 3 ? 4 : 2;   // nodes of the halo on both sides together
     const int tid = threadIdx.x, lane = tid & 63, wv = tid >> 6;
-    const int64_t base = (int64_t)blockIdx.x * BOX_CHUNK;
-    const int64_t end = base + BOX_CHUNK < sp.n ? base + BOX_CHUNK : sp.n;
+    // a workgroup's particles: one tile's range of a binning (split into
+    // segments of BOX_CHUNK), or without one a fixed chunk
+    int64_t base, end;
+    if (tile_start) {
+        base = tile_start[blockIdx.x];
+        end = tile_start[blockIdx.x + 1];
+        base = base < 0 ? 0 : (base > sp.n ? sp.n : base);
+        end = end < base ? base : (end > sp.n ? sp.n : end);
+    } else {
+        base = (int64_t)blockIdx.x * BOX_CHUNK;
+        end = base + BOX_CHUNK < sp.n ? base + BOX_CHUNK : sp.n;
+    }
     int len = BOX_CHUNK;
     for (int64_t s0 = base; s0 < end;) {
         const int seg = (int)(end - s0 < len ? end - s0 : len);
@@ -1791,21 +1802,24 @@ static AdjPtrs<T> adj_ptrs(T *const hatE[3], T *const lx[3], T *const lu[3], T *
 template <typename T>
 hipError_t launch_adjoint_particles(int order, const PConst<T> &pc, const PArr<T> &sp, const FieldPtrs<T> &f,
                                     T *const hatE[3], T *const lx[3], T *const lu[3], T *const lE[3],
-                                    T *const lB[3], T *const vb[6], int *err, hipStream_t st)
+                                    T *const lB[3], T *const vb[6], const int *tile_start, int ntiles, int *err,
+                                    hipStream_t st)
 {
     if (sp.n == 0)
         return hipSuccess;
     const AdjPtrs<T> ap = adj_ptrs<T>(hatE, lx, lu, lE, lB, vb);
-    const unsigned nb = nblk(sp.n, 256), nc = nblk(sp.n, BOX_CHUNK);
+    const unsigned nb = nblk(sp.n, 256), nc = tile_start ? (unsigned)ntiles : nblk(sp.n, BOX_CHUNK);
     static bool b1 = false, b3 = false;
     if (order == 1) {
         allow_big_lds(&k_adjoint_scatter_box<T, 1>, b1);
         hipLaunchKernelGGL((k_adjoint_push<T, 1>), dim3(nb), dim3(256), 0, st, pc, sp, f, ap, err);
-        hipLaunchKernelGGL((k_adjoint_scatter_box<T, 1>), dim3(nc), dim3(BOX_THREADS), BOX_HEAD + BOX_LDS, st, pc, sp, ap);
+        hipLaunchKernelGGL((k_adjoint_scatter_box<T, 1>), dim3(nc), dim3(BOX_THREADS), BOX_HEAD + BOX_LDS, st, pc, sp, ap,
+                           tile_start);
     } else {
         allow_big_lds(&k_adjoint_scatter_box<T, 3>, b3);
         hipLaunchKernelGGL((k_adjoint_push<T, 3>), dim3(nb), dim3(256), 0, st, pc, sp, f, ap, err);
-        hipLaunchKernelGGL((k_adjoint_scatter_box<T, 3>), dim3(nc), dim3(BOX_THREADS), BOX_HEAD + BOX_LDS, st, pc, sp, ap);
+        hipLaunchKernelGGL((k_adjoint_scatter_box<T, 3>), dim3(nc), dim3(BOX_THREADS), BOX_HEAD + BOX_LDS, st, pc, sp, ap,
+                           tile_start);
     }
     return hipGetLastError();
 }
@@ -1887,7 +1901,8 @@ hipError_t launch_adjoint_tile(int order, const PConst<T> &pc, const TileGeo &tg
                                           const FieldPtrs<T> &, int *, hipStream_t);                               \
     template hipError_t launch_adjoint_particles<T>(int, const PConst<T> &, const PArr<T> &, const FieldPtrs<T> &, \
                                                     T *const[3], T *const[3], T *const[3], T *const[3],            \
-                                                    T *const[3], T *const[6], int *, hipStream_t);                 \
+                                                    T *const[3], T *const[6], const int *, int, int *,              \
+                                                    hipStream_t);                                                  \
     template size_t adjoint_lds_bytes<T>(int, const TileGeo &);                                                    \
     template hipError_t launch_adjoint_tile<T>(int, const PConst<T> &, const TileGeo &, const PArr<T> &,           \
                                                const FieldPtrs<T> &, T *const[3], T *const[3], T *const[3],        \

@@ -120,10 +120,13 @@ hipError_t launch_deposit(int order, const PConst<T> &pc, const PArr<T> &before,
                           const FieldPtrs<T> &f, int *err, hipStream_t st);
 // adjoint launchers: vb[6] is per-particle scratch (T[n] each) that carries
 // the adjoints of the gathered E and B from the first pass to the second
+// (the per-particle passes; with tile_start, a binning of sp, the scatter
+// takes one tile's particles per workgroup)
 template <typename T>
 hipError_t launch_adjoint_particles(int order, const PConst<T> &pc, const PArr<T> &sp, const FieldPtrs<T> &f,
                                     T *const hatE[3], T *const lx[3], T *const lu[3], T *const lE[3],
-                                    T *const lB[3], T *const vb[6], int *err, hipStream_t st);
+                                    T *const lB[3], T *const vb[6], const int *tile_start, int ntiles, int *err,
+                                    hipStream_t st);
 template <typename T>
 size_t tile_lds_bytes(int order, const TileGeo &tg);
 template <typename T>

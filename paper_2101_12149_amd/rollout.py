@@ -9,11 +9,13 @@ from its checkpoint keeping every step's input state, then the steps are
 reversed with pic_step_adjoint.  Returns dL/du0 and dL/damp.
 
 With `tiled` (the default) the particles are binned by tile once, before the
-first step (pic_sort_tiles, keeping the permutation); every forward step and
-every adjoint step then runs the tile kernels on that binning, and dL/du0 is
-scattered back to the order of u0.  Particles are not re-sorted inside the
-rollout, so one binning serves the whole reverse sweep.  All arithmetic runs
-in the library's kernels; this module only orders the calls and holds device
+first step (pic_sort_tiles, keeping the permutation), and the forward steps
+run the tile kernels on that binning.  Each replay segment of the reverse
+sweep bins its checkpoint afresh, so that the adjoint steps never run on a
+binning more than k steps old: the particle adjoints are gathered into the
+segment's order before its steps and scattered back after them, and dL/du0
+is scattered back to the order of u0 at the end.  All arithmetic runs in the
+library's kernels; this module only orders the calls and holds device
 buffers.
 """
 import torch
@@ -100,15 +102,29 @@ class PICRollout(torch.autograd.Function):
             dA = torch.zeros(src.amp.shape, dtype=torch.float64, device=src.amp.device)
         for (s0, sp0, f0) in reversed(ctx.checkpoints):
             n = min(pb.k, pb.nsteps - s0)
+            sp, f = sp0.clone(), f0.clone()
+            seg = None
+            if pb.tiled:
+                # a fresh binning for the segment; the particle adjoints follow
+                # the particles into its order (new j <- old seg[j])
+                seg = torch.empty(sp.n, dtype=torch.int32, device=sp.off.device)
+                _lib.pic_sort_tiles(pb.grid, sp, pb.tile_start, pb.ws, perm=seg)
+                seg = seg.long()
+                lam.lx = lam.lx[:, seg].contiguous()
+                lam.lu = lam.lu[:, seg].contiguous()
             # replay the segment, keeping the input state of every step
             states = []
-            sp, f = sp0.clone(), f0.clone()
             for i in range(n):
                 states.append((sp.clone(), f.clone()))
                 _advance(pb, sp, f, src, s0 + i, 1)
             for i in reversed(range(n)):
                 sp_n, f_n = states[i]
                 _lib.pic_step_adjoint(pb.grid, sp_n, f_n, src, s0 + i, lam, dA, pb.ws, tile_start=pb.tile_start)
+            if seg is not None:
+                for name in ("lx", "lu"):
+                    back = torch.empty_like(getattr(lam, name))
+                    back[:, seg] = getattr(lam, name)
+                    setattr(lam, name, back)
         ctx.checkpoints = None
         if ctx.perm is not None:
             du0 = torch.empty_like(lam.lu)
