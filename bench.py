@@ -36,7 +36,7 @@ FLOPS_PER_PARTICLE = {3: 2028, 1: 411}
 # calibrated HBM bytes per launch of the FP32 tile kernel at 256^3 / 8 ppc,
 # from the FETCH_SIZE / WRITE_SIZE passes (scaled by a 1 GiB copy); only
 # figures taken on the current kernel are listed
-MEASURED_TRAFFIC = {"uniform256_o3_f32": 12.51e9}
+MEASURED_TRAFFIC = {"uniform256_o3_f32": 12.50e9}
 
 
 def log(*a):
@@ -82,18 +82,17 @@ def run_forward(w, steps, warmup, sort_every, label):
     return dict(ms=ev_ms, wall_ms=wall * 1e3, kernels=kt, diag=diag[:steps].cpu().numpy(), ws=ws, ts=ts)
 
 
-def run_adjoint(w, nrep, tile_start, sort_every):
-    """Adjoint steps on the state the forward run ended in.  A workload that
-    keeps one binning (sort_every 0: the differentiable rollout) bins its
-    particles afresh at every replay segment of the reverse sweep, so the
-    state is re-binned and advanced two steps (the middle of a 5-step
-    segment) before the timing, untimed."""
+def run_adjoint(w, nrep, tile_start):
+    """Adjoint steps as the differentiable rollout runs them: its reverse
+    sweep bins each replay segment afresh at the segment's checkpoint, so the
+    state the forward run ended in is re-binned and advanced two steps (the
+    middle of a 5-step segment), untimed, before the adjoint steps are timed."""
     import torch
     from paper_2101_12149_amd import _lib
     g = w.grid
     sp, f = w.species, w.fields
     ws = _lib.workspace(g, w.dtype, sp.n)
-    if sort_every == 0 and tile_start is not None:
+    if tile_start is not None:
         _lib.pic_sort_tiles(g, sp, tile_start, ws)
         _lib.pic_step(g, sp, f, None, 0, 2, 0, tile_start, ws)
         torch.cuda.synchronize()
@@ -326,7 +325,7 @@ def main():
 
     if not args.no_adjoint:
         nrep = max(3, min(10, args.steps // 4))
-        adj = run_adjoint(w, nrep, fw["ts"], sort_every)
+        adj = run_adjoint(w, nrep, fw["ts"])
         adj_ms = adj["ms"] / nrep
         out["adjoint"] = {"ms_per_step": adj_ms, "particle_steps_per_s": npart / (adj_ms * 1e-3),
                           "ratio_adjoint_over_forward": adj_ms / ms_step,
