@@ -133,10 +133,27 @@ def cpu_baseline():
     oracle.step(w.grid, sp, f, None, 1, nsteps)
     dt = time.perf_counter() - t0
     npart = sp.cell.shape[1]
-    return {"value": npart * nsteps / dt, "unit": "particle-steps/s", "cores": oracle.num_threads(),
+    cores = oracle.num_threads()
+    # the same oracle on one thread, on a smaller box of the same plasma
+    n1, nsteps1 = (32, 32, 32), 3
+    w1 = wl.uniform_plasma(n1, ppc, 0.05, 3, nsteps1, "f64", 1002, 4)
+    sp1, f1 = w1.species.numpy(), w1.fields.numpy()
+    oracle.set_num_threads(1)
+    try:
+        oracle.step(w1.grid, sp1, f1, None, 0, 1)
+        t0 = time.perf_counter()
+        oracle.step(w1.grid, sp1, f1, None, 1, nsteps1)
+        dt1 = time.perf_counter() - t0
+    finally:
+        oracle.set_num_threads(cores)
+    npart1 = sp1.cell.shape[1]
+    return {"value": npart * nsteps / dt, "unit": "particle-steps/s", "cores": cores,
             "kind": "oracle",
             "sample": f"uniform plasma {n[0]}^3, {ppc} ppc ({npart} particles), order 3, FP64, {nsteps} steps "
-                      f"after 1 warm-up step ({dt:.1f} s)"}
+                      f"after 1 warm-up step ({dt:.1f} s)",
+            "value_1thread": npart1 * nsteps1 / dt1,
+            "sample_1thread": f"uniform plasma {n1[0]}^3, {ppc} ppc ({npart1} particles), order 3, FP64, "
+                              f"{nsteps1} steps after 1 warm-up step, 1 thread ({dt1:.1f} s)"}
 
 
 MICRO_MODES = ("lds_add_f32", "lds_add_f64", "lds_add_u32", "lds_add_u64", "lds_read_f32", "lds_read_f64",

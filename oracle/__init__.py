@@ -69,6 +69,7 @@ def _load():
             lib = C.CDLL(_SO)
             P = C.POINTER
             lib.or_num_threads.restype = C.c_int
+            lib.or_set_num_threads.argtypes = [C.c_int]
             lib.or_shape.restype = C.c_double
             lib.or_shape.argtypes = [C.c_int, C.c_double]
             lib.or_dshape.restype = C.c_double
@@ -180,6 +181,12 @@ def _vec3(arrs):
 
 def num_threads():
     return int(_load().or_num_threads())
+
+
+def set_num_threads(n):
+    """Thread count of the oracle's later parallel loops (OpenMP); only
+    the summation order of the per-thread current buffers depends on it."""
+    _load().or_set_num_threads(int(n))
 
 
 def shape(order, r):

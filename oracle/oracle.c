@@ -86,6 +86,18 @@ int or_num_threads(void)
 #endif
 }
 
+/* Set the thread count of later parallel loops (n >= 1).  Only the order in
+   which the per-thread current buffers are summed depends on it. */
+void or_set_num_threads(int n)
+{
+#ifdef _OPENMP
+    if (n >= 1)
+        omp_set_num_threads(n);
+#else
+    (void)n;
+#endif
+}
+
 /* ------------------------------------------------------------------ */
 /* indexing                                                            */
 

@@ -581,6 +581,28 @@ def test_full_step_gauss_residual_is_invariant():
         np.testing.assert_allclose(residual(), r0, rtol=0, atol=1e-12 * np.abs(r0).max())
 
 
+def test_step_does_not_depend_on_the_thread_count_beyond_rounding():
+    """The oracle's parallel loops (particles split over threads, private
+    current buffers summed afterwards) give the same step on 1 and on 4
+    threads up to the summation order of the buffers: a race or a lost
+    buffer would show as an O(1) difference."""
+    outs = []
+    nt0 = oracle.num_threads()
+    try:
+        for nt in (1, 4):
+            oracle.set_num_threads(nt)
+            w = wl.uniform_plasma((8, 8, 8), 4, 0.05, 3, 3, "f64", 91)
+            sp, f = w.species.numpy(), w.fields.numpy()
+            oracle.step(w.grid, sp, f, None, 0, 3)
+            outs.append((sp.cell.copy(), sp.off.copy(), sp.u.copy(), f.E.copy(), f.B.copy(), f.J.copy()))
+    finally:
+        oracle.set_num_threads(nt0)
+    (c1, o1, u1, E1, B1, J1), (c4, o4, u4, E4, B4, J4) = outs
+    np.testing.assert_array_equal(c1, c4)
+    for a, b in ((o1, o4), (u1, u4), (E1, E4), (B1, B4), (J1, J4)):
+        np.testing.assert_allclose(a, b, rtol=0, atol=1e-13 * np.abs(a).max())
+
+
 def test_cold_plasma_oscillation_frequency():
     """Regular cold plasma, all electrons given the same tiny velocity: J and E
     stay uniform and E obeys the leapfrog oscillator
