@@ -1017,33 +1017,96 @@ __device__ __attribute__((always_inline)) inline void gather_grad(const T *F, T 
     lxa[2] += vb * gz;
 }
 
-template <int O, typename T, bool LOCAL, int SX, int SY, int SZ>
-__device__ __attribute__((always_inline)) inline void scatter_component(T *Lglob, double *sL, T vb, const AxisW<O, T> *aw,
-                                         const int (*on)[Shape<O, T>::NW], const int (*os)[Shape<O, T>::NW],
-                                         const XRun &xr)
+// How the LDS scatter of a component shares rows between lanes:
+//   SM_RUNS   the component's own window (its start on a staggered axis
+//             depends on the half of the cell the particle is in), rows
+//             shared along lane runs of equal window starts;
+//   SM_WIDE   on every staggered axis the NW + 1 nodes that either half of
+//             the cell can reach, the one the particle does not reach with
+//             a zero weight: the window starts at a fixed node relative to
+//             the cell, so all six components share one run structure and
+//             lanes in consecutive cells always form runs;
+//   SM_ALONE  the component's own window, one lane per particle, no sharing.
+enum ScatterMode { SM_RUNS = 0, SM_WIDE = 1, SM_ALONE = 2 };
+
+// weights of one axis on the window the scatter mode takes
+template <int O, typename T, int S, int SM>
+__device__ __attribute__((always_inline)) inline void scatter_axis(const AxisW<O, T> &a,
+                                                                   T (&w)[Shape<O, T>::NW + (SM == SM_WIDE && S ? 1 : 0)])
 {
     constexpr int NW = Shape<O, T>::NW;
-    const T *wx = SX ? aw[0].ws : aw[0].wn;
-    const T *wy = SY ? aw[1].ws : aw[1].wn;
-    const T *wz = SZ ? aw[2].ws : aw[2].wn;
-    const int *xo = SX ? os[0] : on[0];
-    const int *yo = SY ? os[1] : on[1];
-    const int *zo = SZ ? os[2] : on[2];
+    if constexpr (SM == SM_WIDE && S) {
+        // the half-cell window starts at bs = NB (upper half) or NB - 1
+        const bool up = a.bs == Shape<O, T>::NB;
+        w[0] = up ? T(0) : a.ws[0];
 #pragma unroll
-    for (int k = 0; k < NW; ++k)
+        for (int i = 1; i < NW; ++i)
+            w[i] = up ? a.ws[i - 1] : a.ws[i];
+        w[NW] = up ? a.ws[NW - 1] : T(0);
+    } else {
 #pragma unroll
-        for (int j = 0; j < NW; ++j) {
-            const int rowo = yo[j] + zo[k];
-            const T wyz = wy[j] * wz[k] * vb;
-            T r[NW];
+        for (int i = 0; i < NW; ++i)
+            w[i] = S ? a.ws[i] : a.wn[i];
+    }
+}
+
+template <int O, typename T, bool LOCAL, int SM, int SX, int SY, int SZ>
+__device__ __attribute__((always_inline)) inline void scatter_component(T *Lglob, double *sL, T vb, const AxisW<O, T> *aw,
+                                         const int (*on)[Shape<O, T>::NW], const int (*os)[Shape<O, T>::NW],
+                                         const int *sf, const XRun &xr)
+{
+    constexpr int NW = Shape<O, T>::NW;
+    if constexpr (LOCAL && SM == SM_WIDE) {
+        constexpr int NX = NW + (SX ? 1 : 0), NY = NW + (SY ? 1 : 0), NZ = NW + (SZ ? 1 : 0);
+        T wx[NX], wy[NY], wz[NZ];
+        scatter_axis<O, T, SX, SM>(aw[0], wx);
+        scatter_axis<O, T, SY, SM>(aw[1], wy);
+        scatter_axis<O, T, SZ, SM>(aw[2], wz);
+        // first node: the nodal window's, one node lower on a staggered axis
+        const int x0 = on[0][0] - (SX ? sf[0] : 0);
+        const int y0 = on[1][0] - (SY ? sf[1] : 0);
+        const int z0 = on[2][0] - (SZ ? sf[2] : 0);
 #pragma unroll
-            for (int i = 0; i < NW; ++i)
-                r[i] = wx[i] * wyz;
-            if (LOCAL)
-                xrow_add<NW>(sL + rowo + xo[0], r, xr);   // LDS x offsets are consecutive
-            else
-                xrow_apply<NW>(r, xr, [&](int i, T v) { gatomic_add(Lglob + rowo + xo[i], v); });
-        }
+        for (int k = 0; k < NZ; ++k)
+#pragma unroll
+            for (int j = 0; j < NY; ++j) {
+                const int rowo = y0 + j * sf[1] + z0 + k * sf[2];
+                const T wyz = wy[j] * wz[k] * vb;
+                T r[NX];
+#pragma unroll
+                for (int i = 0; i < NX; ++i)
+                    r[i] = wx[i] * wyz;
+                xrow_add<NX>(sL + rowo + x0, r, xr);   // LDS x offsets are consecutive
+            }
+    } else {
+        const T *wx = SX ? aw[0].ws : aw[0].wn;
+        const T *wy = SY ? aw[1].ws : aw[1].wn;
+        const T *wz = SZ ? aw[2].ws : aw[2].wn;
+        const int *xo = SX ? os[0] : on[0];
+        const int *yo = SY ? os[1] : on[1];
+        const int *zo = SZ ? os[2] : on[2];
+#pragma unroll
+        for (int k = 0; k < NW; ++k)
+#pragma unroll
+            for (int j = 0; j < NW; ++j) {
+                const int rowo = yo[j] + zo[k];
+                const T wyz = wy[j] * wz[k] * vb;
+                T r[NW];
+#pragma unroll
+                for (int i = 0; i < NW; ++i)
+                    r[i] = wx[i] * wyz;
+                if constexpr (LOCAL && SM == SM_ALONE) {
+#pragma unroll
+                    for (int i = 0; i < NW; ++i)
+                        latomic_add(sL + rowo + xo[i], (double)r[i]);
+                } else if constexpr (LOCAL) {
+                    xrow_add<NW>(sL + rowo + xo[0], r, xr);   // LDS x offsets are consecutive
+                } else {
+                    xrow_apply<NW>(r, xr, [&](int i, T v) { gatomic_add(Lglob + rowo + xo[i], v); });
+                }
+            }
+    }
+    (void)sf;
 }
 
 // lane runs packed in an int: a1 | last << 1 | send << 2 | d << 3 | len << 6
@@ -1216,10 +1279,11 @@ __device__ __attribute__((always_inline)) inline void adjoint_push_particle(cons
 }
 
 // pass 2 for one particle: the scatter of the gather transpose for the
-// components of group G (0: E, 1: B, 2: both).  The LDS accumulators hold the
-// group's components at sL + (m - 3 G0) * rfvol (G0 = 1 for group B alone);
-// runs[k] are the packed lane runs of the group's k-th component (null: none).
-template <typename T, int O, bool LOCAL, int G>
+// components of group G (0: E, 1: B, 2: both), shared as scatter mode SM
+// says.  The LDS accumulators hold the group's components at
+// sL + (m - 3 G0) * rfvol (G0 = 1 for group B alone); runs[k] are the packed
+// lane runs of the group's k-th component (null: none).
+template <typename T, int O, bool LOCAL, int G, int SM = SM_RUNS>
 __device__ __attribute__((always_inline)) inline void adjoint_scatter_particle(const PConst<T> &pc, const AdjPtrs<T> &ap, int64_t p,
                                                 const int *c, const T *f, const int *l, int lo_f,
                                                 const int *sf, double *sL, int rfvol, const int *runs)
@@ -1232,17 +1296,18 @@ __device__ __attribute__((always_inline)) inline void adjoint_scatter_particle(c
     auto run = [&](int k) { return xrun_unpack(runs ? runs[k] : XRUN_ALONE); };
     // staggering: E_x(s,n,n) E_y(n,s,n) E_z(n,n,s) B_x(n,s,s) B_y(s,n,s) B_z(s,s,n)
     if (G != 1) {
-        scatter_component<O, T, LOCAL, 1, 0, 0>(ap.lE[0], sL + (0 - b) * rfvol, ap.vb[0][p], aw, on, os, run(0));
-        scatter_component<O, T, LOCAL, 0, 1, 0>(ap.lE[1], sL + (1 - b) * rfvol, ap.vb[1][p], aw, on, os, run(1));
-        scatter_component<O, T, LOCAL, 0, 0, 1>(ap.lE[2], sL + (2 - b) * rfvol, ap.vb[2][p], aw, on, os, run(2));
+        scatter_component<O, T, LOCAL, SM, 1, 0, 0>(ap.lE[0], sL + (0 - b) * rfvol, ap.vb[0][p], aw, on, os, sf, run(0));
+        scatter_component<O, T, LOCAL, SM, 0, 1, 0>(ap.lE[1], sL + (1 - b) * rfvol, ap.vb[1][p], aw, on, os, sf, run(1));
+        scatter_component<O, T, LOCAL, SM, 0, 0, 1>(ap.lE[2], sL + (2 - b) * rfvol, ap.vb[2][p], aw, on, os, sf, run(2));
     }
     if (G != 0) {
         const int k0 = G == 2 ? 3 : 0;
-        scatter_component<O, T, LOCAL, 0, 1, 1>(ap.lB[0], sL + (3 - b) * rfvol, ap.vb[3][p], aw, on, os, run(k0));
-        scatter_component<O, T, LOCAL, 1, 0, 1>(ap.lB[1], sL + (4 - b) * rfvol, ap.vb[4][p], aw, on, os,
-                                                run(k0 + 1));
-        scatter_component<O, T, LOCAL, 1, 1, 0>(ap.lB[2], sL + (5 - b) * rfvol, ap.vb[5][p], aw, on, os,
-                                                run(k0 + 2));
+        scatter_component<O, T, LOCAL, SM, 0, 1, 1>(ap.lB[0], sL + (3 - b) * rfvol, ap.vb[3][p], aw, on, os, sf,
+                                                    run(k0));
+        scatter_component<O, T, LOCAL, SM, 1, 0, 1>(ap.lB[1], sL + (4 - b) * rfvol, ap.vb[4][p], aw, on, os, sf,
+                                                    run(k0 + 1));
+        scatter_component<O, T, LOCAL, SM, 1, 1, 0>(ap.lB[2], sL + (5 - b) * rfvol, ap.vb[5][p], aw, on, os, sf,
+                                                    run(k0 + 2));
     }
 }
 
@@ -1268,6 +1333,22 @@ __device__ inline void component_runs(bool act, int m0, const int *pos, const T 
         const int key = act ? (GLOBAL ? xrun_key_global(st, n) : xrun_key(st)) : 0;
         runs[k] = xrun_pack(xrun(key));
     }
+}
+
+// Lane runs of the fixed (SM_WIDE) windows: every component's window starts
+// at a fixed node relative to the cell, so one run structure, that of the
+// cells, serves all six.  Call with the whole wave converged.
+__device__ inline XRun wide_runs(bool act, const int *pos)
+{
+    return xrun(act ? xrun_key(pos) : 0);
+}
+
+// The length of this lane's run (counted up to 4, as at the run's last lane).
+// Call with the whole wave converged.
+__device__ inline int run_length(const XRun &xr)
+{
+    const int l1 = dpp_shift_int<-1>(xr.len), l2 = dpp_shift_int<-2>(xr.len), l3 = dpp_shift_int<-3>(xr.len);
+    return xr.d == 0 ? xr.len : xr.d == 1 ? l1 : xr.d == 2 ? l2 : xr.d == 3 ? l3 : 4;
 }
 
 // positions only (pass 2): a particle that fails the check was flagged by
@@ -1616,21 +1697,36 @@ __global__ void __launch_bounds__(STRAY_THREADS) k_adjoint_scatter_strays(PConst
 // the gather halo (no fields: the position part of the gather transpose is
 // done in pass 1); they are flushed with one global atomic per non-zero
 // value.  Strays are left to k_adjoint_scatter_strays.
+//
+// The rows are shared along lane runs on fixed windows (SM_WIDE).  A run
+// shorter than a window row (particles that left their binned cell since
+// the sort break the one-lane-per-cell order) would make the whole wave
+// issue extra atomic instructions for its last lane, so the lanes of such
+// runs put their particle in an LDS queue instead (qcap entries after the
+// accumulators) and are scattered after the main loop, one lane per
+// particle.
 template <typename T, int O>
 __global__ void __launch_bounds__(AdjThreads<T>::value) k_adjoint_scatter_tile(PConst<T> pc, TileGeo tg, PArr<T> sp,
                                                                               FieldPtrs<T> fp, AdjPtrs<T> ap,
-                                                                              const int *__restrict__ tile_start)
+                                                                              const int *__restrict__ tile_start,
+                                                                              int qcap)
 {
+    constexpr int NW = Shape<O, T>::NW;
     extern __shared__ __align__(16) unsigned char smem_raw[];
     const int rfx = tg.rf[0], rfy = tg.rf[1];
     const int rfvol = rfx * rfy * tg.rf[2];
     double *sL = reinterpret_cast<double *>(smem_raw);   // 6 * rfvol
+    int *qcnt = reinterpret_cast<int *>(sL + 6 * rfvol);
+    int *qj = qcnt + 4;                                   // qcap entries
     const TileSpan ts = tile_span(tg, tile_start, sp.n);
     if (ts.pe <= ts.ps)
         return;
     const int tid = threadIdx.x, nth = blockDim.x;
+    const int lane = tid & 63;
     for (int r = tid; r < 6 * rfvol; r += nth)
         sL[r] = 0.0;
+    if (tid == 0)
+        *qcnt = 0;
     __syncthreads();
     const int sf[3] = {1, rfx, rfx * rfy};
     const int np = (int)(ts.pe - ts.ps);
@@ -1639,10 +1735,45 @@ __global__ void __launch_bounds__(AdjThreads<T>::value) k_adjoint_scatter_tile(P
         int c[3] = {0, 0, 0}, l[3] = {0, 0, 0};
         T f[3] = {T(0), T(0), T(0)};
         const bool act = j < np && load_position(sp, ts.ps + j, pc.n, c, f) && tile_local(tg, pc.n, ts.t0, c, l);
-        int runs[6];
-        component_runs<T, O, 6, false>(act, 0, l, f, pc.n, runs);   // converged
-        if (act)
-            adjoint_scatter_particle<T, O, true, 2>(pc, ap, ts.ps + j, c, f, l, tg.lo_f, sf, sL, rfvol, runs);
+        // the wave is converged here
+        XRun xr = wide_runs(act, l);
+        // a window row has up to NW + 1 taps: a run of fewer than NW lanes
+        // leaves nodes to its last lane
+        const bool want = act && run_length(xr) < NW;
+        const unsigned long long m = __ballot(want);
+        bool mine = act;
+        if (m != 0) {
+            const int leader = __ffsll((long long)m) - 1;
+            int base = 0;
+            if (lane == leader)
+                base = atomicAdd(qcnt, __popcll(m));
+            base = __shfl(base, leader);
+            if (want) {
+                const int i = base + __popcll(m & ((1ull << lane) - 1ull));
+                if (i < qcap) {
+                    qj[i] = j;
+                    mine = false;
+                }
+            }
+            xr = wide_runs(mine, l);
+        }
+        if (mine) {
+            const int pr = xrun_pack(xr);
+            const int runs[6] = {pr, pr, pr, pr, pr, pr};
+            adjoint_scatter_particle<T, O, true, 2, SM_WIDE>(pc, ap, ts.ps + j, c, f, l, tg.lo_f, sf, sL, rfvol,
+                                                              runs);
+        }
+    }
+    __syncthreads();
+    // the queued particles, one lane each
+    const int nq = *qcnt < qcap ? *qcnt : qcap;
+    for (int i = tid; i < nq; i += nth) {
+        const int j = qj[i];
+        int c[3] = {0, 0, 0}, l[3] = {0, 0, 0};
+        T f[3] = {T(0), T(0), T(0)};
+        if (load_position(sp, ts.ps + j, pc.n, c, f) && tile_local(tg, pc.n, ts.t0, c, l))
+            adjoint_scatter_particle<T, O, true, 2, SM_ALONE>(pc, ap, ts.ps + j, c, f, l, tg.lo_f, sf, sL, rfvol,
+                                                               nullptr);
     }
     __syncthreads();
     for (int r = tid; r < 6 * rfvol; r += nth) {
@@ -1835,6 +1966,9 @@ size_t adjoint_push_lds(const TileGeo &tg)
     return 6 * rf * sizeof(T) + 3 * rj * sizeof(T);
 }
 
+// dynamic LDS one workgroup of the tiled adjoint scatter may take
+constexpr size_t ADJ_QUEUE_LDS = 160 * 1024;
+
 template <typename T>
 size_t adjoint_scatter_lds(const TileGeo &tg)
 {
@@ -1859,12 +1993,17 @@ static hipError_t launch_adj_tile_o(const PConst<T> &pc, const TileGeo &tg, cons
     const unsigned ntiles = (unsigned)(tg.nt[0] * tg.nt[1] * tg.nt[2]);
     const unsigned nth = AdjThreads<T>::value;
     const size_t l1 = adjoint_push_lds<T>(tg), l2 = adjoint_scatter_lds<T>(tg);
+    // the LDS the accumulators leave holds the scatter's queue (16 bytes of
+    // counter, then 4 per entry, up to 16384)
+    const size_t room = l2 + 16 < ADJ_QUEUE_LDS ? (ADJ_QUEUE_LDS - l2 - 16) / 4 : 0;
+    const int qcap = (int)(room < 16384 ? room : 16384);
+    const size_t l2q = l2 + 16 + 4 * (size_t)qcap;
     hipLaunchKernelGGL((k_adjoint_push_tile<T, O>), dim3(ntiles), dim3(PushThreads<T>::value), l1, st, pc, tg, sp,
                        f, ap, tile_start, err);
     hipLaunchKernelGGL((k_adjoint_push_strays<T, O>), dim3(ntiles), dim3(STRAY_THREADS), 0, st, pc, tg, sp, f, ap,
                        tile_start, err);
-    hipLaunchKernelGGL((k_adjoint_scatter_tile<T, O>), dim3(ntiles), dim3(nth), l2, st, pc, tg, sp, f, ap,
-                       tile_start);
+    hipLaunchKernelGGL((k_adjoint_scatter_tile<T, O>), dim3(ntiles), dim3(nth), l2q, st, pc, tg, sp, f, ap,
+                       tile_start, qcap);
     hipLaunchKernelGGL((k_adjoint_scatter_strays<T, O>), dim3(ntiles), dim3(STRAY_THREADS), 0, st, pc, tg, sp, f, ap,
                        tile_start);
     return hipGetLastError();
