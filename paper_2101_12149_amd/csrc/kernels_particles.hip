@@ -1351,6 +1351,31 @@ __device__ inline int run_length(const XRun &xr)
     return xr.d == 0 ? xr.len : xr.d == 1 ? l1 : xr.d == 2 ? l2 : xr.d == 3 ? l3 : 4;
 }
 
+// Puts index j of every lane with `want` into an LDS queue (counter qcnt,
+// entries qj, capacity qcap) with one atomic per wave; returns whether this
+// lane's index went in, and in `any` whether the wave queued any.  Call with
+// the whole wave converged.
+__device__ inline bool queue_push_wave(bool want, int j, int *qcnt, int *qj, int qcap, bool &any)
+{
+    const int lane = threadIdx.x & 63;
+    const unsigned long long m = __ballot(want);
+    any = m != 0;
+    if (m == 0)
+        return false;   // uniform across the wave
+    const int leader = __ffsll((long long)m) - 1;
+    int base = 0;
+    if (lane == leader)
+        base = atomicAdd(qcnt, __popcll(m));
+    base = __shfl(base, leader);
+    if (!want)
+        return false;
+    const int i = base + __popcll(m & ((1ull << lane) - 1ull));
+    if (i >= qcap)
+        return false;
+    qj[i] = j;
+    return true;
+}
+
 // positions only (pass 2): a particle that fails the check was flagged by
 // pass 1 and is skipped
 template <typename T>
@@ -1397,8 +1422,9 @@ constexpr int BOX_THREADS = 512;
 constexpr int BOX_CHUNK = 2048;
 constexpr int BOX_LDS = 144 * 1024;
 constexpr int BOX_HEAD = 256;   // reduction scratch ahead of the accumulators
-constexpr int BOX_MAX_CELLS = 40;
-static_assert((6 * (BOX_THREADS / 64) + 3) * (int)sizeof(int) <= BOX_HEAD, "box reduction scratch");   // box extent per axis (lane-run keys hold local coordinates below 56)
+constexpr int BOX_MAX_CELLS = 40;   // box extent per axis (lane-run keys hold local coordinates below 56)
+static_assert((6 * (BOX_THREADS / 64) + 3) * (int)sizeof(int) <= BOX_HEAD, "box reduction scratch");
+static_assert(BOX_HEAD + BOX_LDS <= 160 * 1024, "box scatter LDS");
 
 __device__ inline int wave_min(int v)
 {
@@ -1722,7 +1748,6 @@ __global__ void __launch_bounds__(AdjThreads<T>::value) k_adjoint_scatter_tile(P
     if (ts.pe <= ts.ps)
         return;
     const int tid = threadIdx.x, nth = blockDim.x;
-    const int lane = tid & 63;
     for (int r = tid; r < 6 * rfvol; r += nth)
         sL[r] = 0.0;
     if (tid == 0)
@@ -1739,24 +1764,11 @@ __global__ void __launch_bounds__(AdjThreads<T>::value) k_adjoint_scatter_tile(P
         XRun xr = wide_runs(act, l);
         // a window row has up to NW + 1 taps: a run of fewer than NW lanes
         // leaves nodes to its last lane
-        const bool want = act && run_length(xr) < NW;
-        const unsigned long long m = __ballot(want);
-        bool mine = act;
-        if (m != 0) {
-            const int leader = __ffsll((long long)m) - 1;
-            int base = 0;
-            if (lane == leader)
-                base = atomicAdd(qcnt, __popcll(m));
-            base = __shfl(base, leader);
-            if (want) {
-                const int i = base + __popcll(m & ((1ull << lane) - 1ull));
-                if (i < qcap) {
-                    qj[i] = j;
-                    mine = false;
-                }
-            }
-            xr = wide_runs(mine, l);
-        }
+        bool any = false;
+        const bool queued = queue_push_wave(act && run_length(xr) < NW, j, qcnt, qj, qcap, any);
+        const bool mine = act && !queued;
+        if (any)
+            xr = wide_runs(mine, l);   // the runs of the lanes that stay
         if (mine) {
             const int pr = xrun_pack(xr);
             const int runs[6] = {pr, pr, pr, pr, pr, pr};
