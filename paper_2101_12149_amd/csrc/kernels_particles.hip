@@ -1351,6 +1351,16 @@ __device__ inline int run_length(const XRun &xr)
     return xr.d == 0 ? xr.len : xr.d == 1 ? l1 : xr.d == 2 ? l2 : xr.d == 3 ? l3 : 4;
 }
 
+// A wave of the tiled adjoint scatter queues its short-run lanes (and shares
+// rows on fixed windows) only while it has at most this many: a 64-lane
+// wave's rows cost about 384 FP64 LDS add instructions on per-component
+// windows with short runs present, about 242 on fixed windows plus about 6
+// per queued lane and the fixed windows' extra arithmetic.  Measured at
+// 8 ppc (256^3) and 2 ppc (512^3), FP32: 24 -> 62.8 / 177.3 ms per adjoint
+// step, 32 -> 61.0 / 179.0, 48 -> 60.1 / 180.8, 64 (never the per-component
+// path) -> 62.4 / 190.6.
+constexpr int SCATTER_QUEUE_MAX = 32;
+
 // Puts index j of every lane with `want` into an LDS queue (counter qcnt,
 // entries qj, capacity qcap) with one atomic per wave; returns whether this
 // lane's index went in, and in `any` whether the wave queued any.  Call with
@@ -1764,16 +1774,29 @@ __global__ void __launch_bounds__(AdjThreads<T>::value) k_adjoint_scatter_tile(P
         XRun xr = wide_runs(act, l);
         // a window row has up to NW + 1 taps: a run of fewer than NW lanes
         // leaves nodes to its last lane
-        bool any = false;
-        const bool queued = queue_push_wave(act && run_length(xr) < NW, j, qcnt, qj, qcap, any);
-        const bool mine = act && !queued;
-        if (any)
-            xr = wide_runs(mine, l);   // the runs of the lanes that stay
-        if (mine) {
-            const int pr = xrun_pack(xr);
-            const int runs[6] = {pr, pr, pr, pr, pr, pr};
-            adjoint_scatter_particle<T, O, true, 2, SM_WIDE>(pc, ap, ts.ps + j, c, f, l, tg.lo_f, sf, sL, rfvol,
-                                                              runs);
+        const bool shortrun = act && run_length(xr) < NW;
+        if (__popcll(__ballot(shortrun)) > SCATTER_QUEUE_MAX) {
+            // sparse wave (the high ranks of the rank-major order, low
+            // densities): queueing would cost more than the extra atomic
+            // instructions of the short runs, so the wave takes each
+            // component's own window and runs
+            int runs[6];
+            component_runs<T, O, 6, false>(act, 0, l, f, pc.n, runs);
+            if (act)
+                adjoint_scatter_particle<T, O, true, 2, SM_RUNS>(pc, ap, ts.ps + j, c, f, l, tg.lo_f, sf, sL, rfvol,
+                                                                  runs);
+        } else {
+            bool any = false;
+            const bool queued = queue_push_wave(shortrun, j, qcnt, qj, qcap, any);
+            const bool mine = act && !queued;
+            if (any)
+                xr = wide_runs(mine, l);   // the runs of the lanes that stay
+            if (mine) {
+                const int pr = xrun_pack(xr);
+                const int runs[6] = {pr, pr, pr, pr, pr, pr};
+                adjoint_scatter_particle<T, O, true, 2, SM_WIDE>(pc, ap, ts.ps + j, c, f, l, tg.lo_f, sf, sL,
+                                                                  rfvol, runs);
+            }
         }
     }
     __syncthreads();
