@@ -117,6 +117,73 @@ def test_adjoint_step_matches_oracle(order, dtype, tiled, pusher, solver, filt):
     assert rel_l2(dA.cpu().numpy(), odA) < tol
 
 
+def _dense_species(g, ppc, seed, dtype, layout):
+    """ppc particles per cell.  "lattice": every cell holds ppc = 8 particles
+    on a 2x2x2 sub-lattice with a small jitter, so that the rank-major order
+    of a binning puts whole rows of cells in consecutive lanes; "poisson":
+    random cells (mean ppc) and offsets."""
+    n = ppc * int(np.prod(g.n))
+    if layout == "poisson":
+        return random_species(g, n, seed, u_th=0.1, dtype=dtype)
+    gen = torch.Generator().manual_seed(seed)
+    nx, ny = int(g.n[0]), int(g.n[1])
+    idx = torch.arange(n) // ppc
+    cell = torch.stack([idx % nx, (idx // nx) % ny, idx // (nx * ny)]).to(torch.int32)
+    k = torch.arange(n) % ppc
+    base = torch.stack([k & 1, (k >> 1) & 1, (k >> 2) & 1]).to(torch.float64) * 0.5 + 0.25
+    off = base + (torch.rand((3, n), generator=gen, dtype=torch.float64) - 0.5) * 0.1
+    u = torch.randn((3, n), generator=gen, dtype=torch.float64) * 0.1
+    w = torch.rand(n, generator=gen, dtype=torch.float64) + 0.5
+    return wl.Species(cell.contiguous(), off, u, w, 0.7, -1.0, 1.0).to(dtype=tdtype(dtype))
+
+
+@pytest.mark.parametrize("layout", ["lattice", "lattice_moved", "poisson"])
+@pytest.mark.parametrize("order,dtype", [(3, "f32"), (1, "f32"), (1, "f64")])
+def test_tiled_adjoint_on_dense_tiles_matches_oracle(order, dtype, layout):
+    """Tiled reverse step at 8 particles per cell, where the waves of the
+    field-adjoint scatter share rows on fixed windows: a regular lattice
+    (whole runs of lanes), the same with a tenth of the particles moved one
+    cell along x after the binning (short runs, queued and scattered one
+    lane each), and random placement (sparse high ranks, whose waves take
+    each component's own window)."""
+    g = wl.plasma_grid((16, 16, 16), order)
+    sp = _dense_species(g, 8, 301, dtype, "poisson" if layout == "poisson" else "lattice")
+    n = sp.cell.shape[1]
+    f = random_fields(g, 302, scale=0.3, dtype=dtype)
+    lam = _random_lambda(g, n, 304, dtype)
+    olam = _oracle_lambda(lam)
+    dsp = dev(sp)
+    dlam = NS(lx=dev(lam.lx), lu=dev(lam.lu), lE=dev(lam.lE), lB=dev(lam.lB))
+    ws = _lib.workspace(g, dtype, n)
+    ts = torch.zeros(_lib.pic_tile_count(g, dtype) + 1, dtype=torch.int32, device="cuda")
+    perm = torch.empty(n, dtype=torch.int32, device="cuda")
+    _lib.pic_sort_tiles(g, dsp, ts, ws, perm=perm)
+    pl = perm.long()
+    dlam.lx = dlam.lx[:, pl].contiguous()
+    dlam.lu = dlam.lu[:, pl].contiguous()
+    if layout == "lattice_moved":
+        gen = torch.Generator().manual_seed(305)
+        moved = torch.rand(n, generator=gen) < 0.1
+        step = torch.where(torch.rand(n, generator=gen) < 0.5, -1, 1).to(torch.int32)
+        c = dsp.cell[0].cpu()
+        c = torch.where(moved, (c + step) % int(g.n[0]), c)
+        dsp.cell[0].copy_(c.to(dsp.cell.device))
+        back = torch.empty_like(dsp.cell)
+        back[:, pl] = dsp.cell
+        sp.cell = back.cpu()
+    _lib.pic_step_adjoint(g, dsp, dev(f), None, 2, dlam, None, ws, tile_start=ts)
+    torch.cuda.synchronize()
+    for name in ("lx", "lu"):
+        back = torch.empty_like(getattr(dlam, name))
+        back[:, pl] = getattr(dlam, name)
+        setattr(dlam, name, back)
+    oracle.step_adjoint(g, sp.numpy(), f.numpy(), None, 2, olam, None)
+    tol = 1e-12 if dtype == "f64" else 1e-4
+    for name in ("lx", "lu", "lE", "lB"):
+        r = rel_l2(_cpu(getattr(dlam, name)), getattr(olam, name))
+        assert r < tol, (name, r)
+
+
 @pytest.mark.parametrize("tiled", [False, True])
 @pytest.mark.parametrize("dtype", ["f64", "f32"])
 def test_adjoint_on_the_smallest_grid_with_every_option(dtype, tiled):
