@@ -1612,7 +1612,10 @@ struct AdjThreads {
 
 // threads of the tiled pass 1: 512 leaves the order-3 FP32 pass 256
 // registers (1024 capped it at 128 and spilled 29 to scratch; 25.9 against
-// 27.1 ms at 256^3 / 8 ppc)
+// 27.1 ms at 256^3 / 8 ppc).  768 (a cap of 170, of which the pass takes
+// 159) saved 0.2-0.5 ms per adjoint step at 8 ppc but cost 1 ms on the
+// laser box, whose tiles hold about 1024 particles: a second batch of 768
+// threads runs a third full.
 template <typename T>
 struct PushThreads {
     static constexpr int value = 512;
