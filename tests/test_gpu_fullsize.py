@@ -28,17 +28,17 @@ BOX = 12      # cells per box edge
 MARGIN = 8    # local cells around a box: old cells within 4 of the box, their windows and one field step
 
 
-def _local_grid(g):
-    return NS(n=(BOX + 2 * MARGIN,) * 3, d=tuple(g.d), dt=g.dt, c=g.c, eps0=g.eps0, order=g.order,
+def _local_grid(g, margin=MARGIN):
+    return NS(n=(BOX + 2 * margin,) * 3, d=tuple(g.d), dt=g.dt, c=g.c, eps0=g.eps0, order=g.order,
               pusher=getattr(g, "pusher", 0), solver=getattr(g, "solver", 0))
 
 
-def _slice(a, lo):
+def _slice(a, lo, margin=MARGIN):
     """(3, nz, ny, nx) device array -> local (3, L, L, L) float64 host copy
-    of cells lo - MARGIN .. lo + BOX + MARGIN (the box is away from the
+    of cells lo - margin .. lo + BOX + margin (the box is away from the
     periodic boundary)."""
-    L = BOX + 2 * MARGIN
-    z0, y0, x0 = lo[2] - MARGIN, lo[1] - MARGIN, lo[0] - MARGIN
+    L = BOX + 2 * margin
+    z0, y0, x0 = lo[2] - margin, lo[1] - margin, lo[0] - margin
     return np.ascontiguousarray(a[:, z0:z0 + L, y0:y0 + L, x0:x0 + L].to(torch.float64).cpu().numpy())
 
 
@@ -50,12 +50,12 @@ def _select(cell, lo, pad):
     return torch.nonzero(m).flatten()
 
 
-def _local_species(sp, idx, lo, cell=None, off=None):
+def _local_species(sp, idx, lo, cell=None, off=None, margin=MARGIN):
     """Host FP64 copy of particles idx with cells in the local frame."""
     cell = sp.cell if cell is None else cell
     off = sp.off if off is None else off
-    c = cell[:, idx].cpu().numpy().astype(np.int64) - (np.array(lo)[:, None] - MARGIN)
-    assert c.min() >= 0 and c.max() < BOX + 2 * MARGIN
+    c = cell[:, idx].cpu().numpy().astype(np.int64) - (np.array(lo)[:, None] - margin)
+    assert c.min() >= 0 and c.max() < BOX + 2 * margin
     w = None if sp.w is None else np.ascontiguousarray(sp.w[idx].to(torch.float64).cpu().numpy())
     return NS(cell=np.ascontiguousarray(c.astype(np.int32)),
               off=np.ascontiguousarray(off[:, idx].to(torch.float64).cpu().numpy()),
@@ -63,12 +63,12 @@ def _local_species(sp, idx, lo, cell=None, off=None):
               w=w, w0=sp.w0, q=sp.q, m=sp.m)
 
 
-def _boxes(w, rng, nbox):
+def _boxes(w, rng, nbox, margin=MARGIN):
     n = np.array(w.grid.n)
-    lo_min = np.full(3, MARGIN)
+    lo_min = np.full(3, margin)
     if w.source is not None:     # keep the boxes clear of the source plane and inside the plasma
-        lo_min[2] = max(lo_min[2], w.source.k_plane + MARGIN + 40)
-    return [tuple(int(rng.integers(lo_min[d], n[d] - BOX - MARGIN)) for d in range(3)) for _ in range(nbox)]
+        lo_min[2] = max(lo_min[2], w.source.k_plane + margin + 40)
+    return [tuple(int(rng.integers(lo_min[d], n[d] - BOX - margin)) for d in range(3)) for _ in range(nbox)]
 
 
 @pytest.mark.parametrize("name", ["uniform256_o3_f32", "uniform256_o3_f64", "laser128x128x1024_o3_f32",
@@ -126,3 +126,77 @@ def test_full_size_two_steps_match_oracle_in_sampled_boxes(name):
         checked += len(k["inner"])
     assert checked > 1000
     print(f"[fullsize] {name}: {checked} particles checked in {len(boxes)} boxes", flush=True)
+
+
+AMARGIN = 10   # local cells around a box for the adjoint: its stencils chain to about 8 cells
+
+
+def _local_lambda(lam, idx, lo):
+    """Oracle adjoint state on the local box: particle adjoints of particles
+    idx, field adjoints of the local cells (FP64 host copies)."""
+    L = BOX + 2 * AMARGIN
+    a = oracle.Adjoint(NS(n=(L, L, L)), int(idx.numel()))
+    a.lx[:] = lam.lx[:, idx].to(torch.float64).cpu().numpy()
+    a.lu[:] = lam.lu[:, idx].to(torch.float64).cpu().numpy()
+    a.lE[:] = _slice(lam.lE, lo, AMARGIN)
+    a.lB[:] = _slice(lam.lB, lo, AMARGIN)
+    return a
+
+
+@pytest.mark.parametrize("name", ["uniform256_o3_f32", "stress512_o3_f32"])
+def test_full_size_adjoint_step_matches_oracle_in_sampled_boxes(name):
+    """The tiled FP32 reverse step as the benchmark times it (particles
+    re-binned, two steps on that binning, then one adjoint step with seeded
+    random adjoint inputs), checked in a few boxes of cells: the oracle's
+    adjoint step on a local copy of the box plus a margin (the GPU's state,
+    fields and adjoint inputs there) gives the field adjoints of the box and
+    the particle adjoints of the particles in it.  A value in the box depends
+    only on data within the field-solve, deposit and gather stencils, chained
+    to about 8 cells, so a margin of 10 keeps the local copy's wrap out of it.  8 ppc runs
+    most scatter waves on fixed windows, 2 ppc most on per-component runs."""
+    w = wl.named(name, device="cuda")
+    g, sp, f = w.grid, w.species, w.fields
+    dt = w.dtype
+    print(f"[fullsize-adjoint] {name}: {sp.n} particles, grid {g.n}", flush=True)
+    ws = _lib.workspace(g, dt, sp.n)
+    ts = torch.zeros(_lib.pic_tile_count(g, dt) + 1, dtype=torch.int32, device="cuda")
+    _lib.pic_sort_tiles(g, sp, ts, ws)
+    _lib.pic_step(g, sp, f, None, 0, 2, 0, ts, ws)
+    gen = torch.Generator(device="cuda").manual_seed(sum(map(ord, name)))
+    tdt = sp.off.dtype
+    lam = NS(lx=torch.randn(sp.off.shape, generator=gen, device="cuda", dtype=tdt),
+             lu=torch.randn(sp.u.shape, generator=gen, device="cuda", dtype=tdt),
+             lE=torch.randn(f.E.shape, generator=gen, device="cuda", dtype=tdt),
+             lB=torch.randn(f.B.shape, generator=gen, device="cuda", dtype=tdt))
+    torch.cuda.synchronize()
+    rng = np.random.default_rng(sum(map(ord, name)) + 1)
+    boxes = _boxes(w, rng, 3, AMARGIN)
+    lg = _local_grid(g, AMARGIN)
+    keep = []
+    for lo in boxes:
+        near = _select(sp.cell, lo, AMARGIN)    # every particle of the local box
+        inner = _select(sp.cell, lo, 0)
+        keep.append(dict(lo=lo, near=near, inner=inner, sp=_local_species(sp, near, lo, margin=AMARGIN),
+                         E=_slice(f.E, lo, AMARGIN), B=_slice(f.B, lo, AMARGIN), lam=_local_lambda(lam, near, lo)))
+    _lib.pic_step_adjoint(g, sp, f, None, 2, lam, None, ws, tile_start=ts)
+    torch.cuda.synchronize()
+    m = AMARGIN
+    inner_sl = (slice(None), slice(m, m + BOX), slice(m, m + BOX), slice(m, m + BOX))
+    tol = 1e-4
+    checked = 0
+    for k in keep:
+        lo = k["lo"]
+        lf = NS(E=k["E"], B=k["B"], J=np.zeros_like(k["E"]))
+        ol = k["lam"]
+        oracle.step_adjoint(lg, k["sp"], lf, None, 2, ol, None)
+        assert rel_l2(_slice(lam.lE, lo, m)[inner_sl], ol.lE[inner_sl]) < tol, (name, lo, "lE")
+        assert rel_l2(_slice(lam.lB, lo, m)[inner_sl], ol.lB[inner_sl]) < tol, (name, lo, "lB")
+        # the particles of the box, found in the local list
+        pos = {int(p): i for i, p in enumerate(k["near"].tolist())}
+        sel = np.array([pos[int(p)] for p in k["inner"].tolist()])
+        for nm in ("lx", "lu"):
+            gpu = getattr(lam, nm)[:, k["inner"]].to(torch.float64).cpu().numpy()
+            assert rel_l2(gpu, getattr(ol, nm)[:, sel]) < tol, (name, lo, nm)
+        checked += len(k["inner"])
+    assert checked > 1000
+    print(f"[fullsize-adjoint] {name}: {checked} particles checked in {len(boxes)} boxes", flush=True)
