@@ -143,7 +143,7 @@ def _local_lambda(lam, idx, lo):
     return a
 
 
-@pytest.mark.parametrize("name", ["uniform256_o3_f32", "stress512_o3_f32"])
+@pytest.mark.parametrize("name", ["uniform256_o3_f32", "stress512_o3_f32", "laser128x128x1024_o3_f32"])
 def test_full_size_adjoint_step_matches_oracle_in_sampled_boxes(name):
     """The tiled FP32 reverse step as the benchmark times it (particles
     re-binned, two steps on that binning, then one adjoint step with seeded
@@ -153,7 +153,9 @@ def test_full_size_adjoint_step_matches_oracle_in_sampled_boxes(name):
     the particle adjoints of the particles in it.  A value in the box depends
     only on data within the field-solve, deposit and gather stencils, chained
     to about 8 cells, so a margin of 10 keeps the local copy's wrap out of it.  8 ppc runs
-    most scatter waves on fixed windows, 2 ppc most on per-component runs."""
+    most scatter waves on fixed windows, 2 ppc most on per-component runs; the
+    laser box has weighted particles of a cold beam (its boxes lie in the
+    plasma, away from the source plane)."""
     w = wl.named(name, device="cuda")
     g, sp, f = w.grid, w.species, w.fields
     dt = w.dtype
