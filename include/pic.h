@@ -17,8 +17,9 @@
  *     are host memory and are only read during the call.  The library never
  *     keeps a pointer after returning and never allocates device memory.
  *   - Every call is asynchronous on `stream` (a hipStream_t; NULL = the null
- *     stream), except where a status has to be read back (pic_step reads a
- *     device error word at its end and so synchronises the stream).
+ *     stream), except where a status has to be read back: pic_sort_tiles,
+ *     pic_gather, pic_push, pic_deposit, pic_step and pic_step_adjoint read a
+ *     device error word at their end and so synchronise the stream.
  *   - Grid: n[3] cells, periodic in all three directions, spacing d[3].
  *     Field arrays hold n0*n1*n2 values, x fastest: index i + n0*(j + n1*k).
  *     Staggering of element [i,j,k] (in cells):
@@ -31,8 +32,17 @@
  *   - State at step n is (x^n, u^{n-1/2}, E^n, B^n).
  *
  * Errors: every argument check is synchronous and runs before any launch; on
- * a non-OK status no output has been touched.  pic_last_error() returns a
- * thread-local message.  No C++ exception crosses this ABI.
+ * a non-OK status from these checks no output has been touched.  Corrupt
+ * particle state is found on the device (a cell outside [0,n), an offset
+ * outside [0,1), a non-finite momentum, a displacement of a cell or more in
+ * one step): the calls that read the error word back return PIC_E_STATE
+ * after their kernels ran, the offending particles left unchanged (or, in
+ * pic_deposit, their current left out) and the others processed.
+ * pic_gather, pic_push and pic_deposit have no workspace and share one error
+ * word per device: two of these calls that overlap on one device (other
+ * streams or host threads) may report each other's state errors.
+ * pic_last_error() returns a thread-local message.  No C++ exception crosses
+ * this ABI.
  */
 #ifndef PIC355_PIC_H
 #define PIC355_PIC_H
@@ -183,17 +193,25 @@ PIC_API pic_status pic_sort_tiles(const pic_grid *grid, pic_species *sp, int32_t
 
 /* Field gather (Sec. 3.1, Sec. 4.2): E and B at every particle, each
  * component interpolated from its own staggered location with the
- * order-`order` B-spline in all three directions.  Ep, Bp: T[n] x 3 outputs. */
+ * order-`order` B-spline in all three directions.  Ep, Bp: T[n] x 3 outputs
+ * (zero for a particle with a corrupt cell or offset, and PIC_E_STATE).
+ * Synchronises the stream to read the device error word. */
 PIC_API pic_status pic_gather(const pic_grid *grid, const pic_species *sp, const pic_fields *f, void *const Ep[3],
                       void *const Bp[3], void *stream);
 
-/* Relativistic Boris push u^{n-1/2} -> u^{n+1/2} with the given per-particle
- * fields, then the position update x += dt u/gamma with periodic wrap. */
+/* Relativistic Boris (or Vay, per grid->pusher) push u^{n-1/2} -> u^{n+1/2}
+ * with the given per-particle fields, then the position update
+ * x += dt u/gamma with periodic wrap.  A particle with corrupt state or a
+ * displacement of a cell or more is left unchanged (PIC_E_STATE).
+ * Synchronises the stream to read the device error word. */
 PIC_API pic_status pic_push(const pic_grid *grid, pic_species *sp, void *const Ep[3], void *const Bp[3], void *stream);
 
 /* Esirkepov charge-conserving current deposition (Sec. 3.4.1, 4.1.1):
  * J += current of the particles moving from `before` to `after` (same n,
- * same order of particles, displacement below one cell per direction). */
+ * same order of particles, displacement below one cell per direction).
+ * A particle with corrupt state in either, or that moved more than one cell
+ * along an axis, deposits nothing (PIC_E_STATE).  Synchronises the stream to
+ * read the device error word. */
 PIC_API pic_status pic_deposit(const pic_grid *grid, const pic_species *before, const pic_species *after, pic_fields *f,
                        void *stream);
 

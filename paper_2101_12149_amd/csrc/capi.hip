@@ -117,8 +117,11 @@ void timer_flush()
     g_timer.pending.clear();
 }
 
-// error word of the calls that take no workspace (their device-side state
-// checks are not reported; see pic.h)
+// Error word of the calls that take no workspace (pic_gather, pic_push,
+// pic_deposit): cleared on the caller's stream before their launch and read
+// back after it.  One word per device, shared by those calls: calls that
+// overlap on one device (other streams or threads) may see each other's
+// errors.
 __device__ int g_sink_err;
 
 int *sink_err()
@@ -127,6 +130,26 @@ int *sink_err()
     if (hipGetSymbolAddress(reinterpret_cast<void **>(&p), HIP_SYMBOL(g_sink_err)) != hipSuccess)
         return nullptr;
     return p;
+}
+
+// clears the error word on the stream (before the launch)
+pic_status sink_begin(int *err, hipStream_t st)
+{
+    const hipError_t e = launch_fill<int>(err, 1, 0, st);
+    if (e != hipSuccess)
+        return hip_fail(e, "clearing the device error word");
+    return PIC_OK;
+}
+
+// reads the error word back after the launch (synchronises the stream)
+pic_status sink_end(int *err, hipStream_t st, const char *what)
+{
+    int herr = 0;
+    PIC_HIP(hipMemcpyAsync(&herr, err, sizeof(int), hipMemcpyDeviceToHost, st));
+    PIC_HIP(hipStreamSynchronize(st));
+    if (herr)
+        return fail(PIC_E_STATE, what);
+    return PIC_OK;
 }
 
 // LDS bytes one workgroup may use; gfx950 has 160 KiB per CU, which is also
@@ -874,10 +897,10 @@ pic_status adjoint_t(const pic_grid *g, const GridInfo &gi, const pic_species *s
     if (sp->n > 0) {
         TimedScope tp(5, st);
         const PConst<T> pc = make_const<T>(g, sp);
-        // The tiled FP64 order-3 transpose stays switched off: an earlier
-        // fused form of it returned wrong position adjoints on the device
-        // without a cause found in its code, so that request takes the
-        // per-particle kernels, as does a tile whose regions exceed the LDS.
+        // FP64 order 3 has no tiled transpose (the library does not build
+        // one): that request takes the per-particle push and the segment-box
+        // scatter with the binning, as does a tile whose regions exceed the
+        // LDS.
         const bool tiled_ok = !(gi.dtype == PIC_F64 && gi.order == 3) && adj_lds_bytes(gi) <= (size_t)lds_limit();
         if (gi.filt) {
             PIC_TRY_S(filter_fields<T>(gi, fptrs<T>(f), fpv, st));
@@ -1008,104 +1031,123 @@ pic_status pic_sort_tiles(const pic_grid *grid, pic_species *sp, int32_t *tile_s
 pic_status pic_gather(const pic_grid *grid, const pic_species *sp, const pic_fields *f, void *const Ep[3],
                       void *const Bp[3], void *stream)
 {
-    GridInfo gi;
-    PIC_TRY(check_grid(grid, gi));
-    if (gi.filt)
-        return fail(PIC_E_UNSUPPORTED, "pic_gather has no workspace for the gather filter (pic_step applies it)");
-    PIC_TRY(check_species(sp, "species"));
-    PIC_TRY(check_fields(f, false));
-    PIC_TRY(check_vec3(Ep, "Ep"));
-    PIC_TRY(check_vec3(Bp, "Bp"));
-    int *err = sink_err();
-    if (!err)
-        return fail(PIC_E_DEVICE, "cannot resolve the device error word");
-    hipStream_t st = static_cast<hipStream_t>(stream);
-    if (gi.dtype == PIC_F64) {
-        double *e[3], *b[3];
-        for (int d = 0; d < 3; ++d) {
-            e[d] = static_cast<double *>(Ep[d]);
-            b[d] = static_cast<double *>(Bp[d]);
+    try {
+        GridInfo gi;
+        PIC_TRY(check_grid(grid, gi));
+        if (gi.filt)
+            return fail(PIC_E_UNSUPPORTED, "pic_gather has no workspace for the gather filter (pic_step applies it)");
+        PIC_TRY(check_species(sp, "species"));
+        PIC_TRY(check_fields(f, false));
+        PIC_TRY(check_vec3(Ep, "Ep"));
+        PIC_TRY(check_vec3(Bp, "Bp"));
+        int *err = sink_err();
+        if (!err)
+            return fail(PIC_E_DEVICE, "cannot resolve the device error word");
+        hipStream_t st = static_cast<hipStream_t>(stream);
+        PIC_TRY(sink_begin(err, st));
+        if (gi.dtype == PIC_F64) {
+            double *e[3], *b[3];
+            for (int d = 0; d < 3; ++d) {
+                e[d] = static_cast<double *>(Ep[d]);
+                b[d] = static_cast<double *>(Bp[d]);
+            }
+            PIC_HIP(launch_gather<double>(gi.order, make_const<double>(grid, sp), parr<double>(sp), fptrs<double>(f),
+                                          e, b, err, st));
+        } else {
+            float *e[3], *b[3];
+            for (int d = 0; d < 3; ++d) {
+                e[d] = static_cast<float *>(Ep[d]);
+                b[d] = static_cast<float *>(Bp[d]);
+            }
+            PIC_HIP(launch_gather<float>(gi.order, make_const<float>(grid, sp), parr<float>(sp), fptrs<float>(f), e,
+                                         b, err, st));
         }
-        PIC_HIP(launch_gather<double>(gi.order, make_const<double>(grid, sp), parr<double>(sp), fptrs<double>(f), e,
-                                      b, err, st));
-    } else {
-        float *e[3], *b[3];
-        for (int d = 0; d < 3; ++d) {
-            e[d] = static_cast<float *>(Ep[d]);
-            b[d] = static_cast<float *>(Bp[d]);
-        }
-        PIC_HIP(launch_gather<float>(gi.order, make_const<float>(grid, sp), parr<float>(sp), fptrs<float>(f), e, b,
-                                     err, st));
+        return sink_end(err, st, "particle with a cell outside the grid or an offset outside [0,1)");
+    } catch (...) {
+        return fail(PIC_E_DEVICE, "unexpected host exception");
     }
-    return PIC_OK;
 }
 
 pic_status pic_push(const pic_grid *grid, pic_species *sp, void *const Ep[3], void *const Bp[3], void *stream)
 {
-    GridInfo gi;
-    PIC_TRY(check_grid(grid, gi));
-    PIC_TRY(check_species(sp, "species"));
-    PIC_TRY(check_vec3(Ep, "Ep"));
-    PIC_TRY(check_vec3(Bp, "Bp"));
-    int *err = sink_err();
-    if (!err)
-        return fail(PIC_E_DEVICE, "cannot resolve the device error word");
-    hipStream_t st = static_cast<hipStream_t>(stream);
-    if (gi.dtype == PIC_F64) {
-        double *e[3], *b[3];
-        for (int d = 0; d < 3; ++d) {
-            e[d] = static_cast<double *>(Ep[d]);
-            b[d] = static_cast<double *>(Bp[d]);
+    try {
+        GridInfo gi;
+        PIC_TRY(check_grid(grid, gi));
+        PIC_TRY(check_species(sp, "species"));
+        PIC_TRY(check_vec3(Ep, "Ep"));
+        PIC_TRY(check_vec3(Bp, "Bp"));
+        int *err = sink_err();
+        if (!err)
+            return fail(PIC_E_DEVICE, "cannot resolve the device error word");
+        hipStream_t st = static_cast<hipStream_t>(stream);
+        PIC_TRY(sink_begin(err, st));
+        if (gi.dtype == PIC_F64) {
+            double *e[3], *b[3];
+            for (int d = 0; d < 3; ++d) {
+                e[d] = static_cast<double *>(Ep[d]);
+                b[d] = static_cast<double *>(Bp[d]);
+            }
+            PIC_HIP(launch_push<double>(make_const<double>(grid, sp), parr<double>(sp), e, b, err, st));
+        } else {
+            float *e[3], *b[3];
+            for (int d = 0; d < 3; ++d) {
+                e[d] = static_cast<float *>(Ep[d]);
+                b[d] = static_cast<float *>(Bp[d]);
+            }
+            PIC_HIP(launch_push<float>(make_const<float>(grid, sp), parr<float>(sp), e, b, err, st));
         }
-        PIC_HIP(launch_push<double>(make_const<double>(grid, sp), parr<double>(sp), e, b, err, st));
-    } else {
-        float *e[3], *b[3];
-        for (int d = 0; d < 3; ++d) {
-            e[d] = static_cast<float *>(Ep[d]);
-            b[d] = static_cast<float *>(Bp[d]);
-        }
-        PIC_HIP(launch_push<float>(make_const<float>(grid, sp), parr<float>(sp), e, b, err, st));
+        return sink_end(err, st, "corrupt particle state (cell, offset, momentum or a displacement >= 1 cell)");
+    } catch (...) {
+        return fail(PIC_E_DEVICE, "unexpected host exception");
     }
-    return PIC_OK;
 }
 
 pic_status pic_deposit(const pic_grid *grid, const pic_species *before, const pic_species *after, pic_fields *f,
                        void *stream)
 {
-    GridInfo gi;
-    PIC_TRY(check_grid(grid, gi));
-    PIC_TRY(check_species(before, "before"));
-    PIC_TRY(check_species(after, "after"));
-    if (before->n != after->n)
-        return fail(PIC_E_INVALID, "before and after hold different particle counts");
-    if (!f)
-        return fail(PIC_E_INVALID, "fields is NULL");
-    for (int d = 0; d < 3; ++d)
-        if (!f->J[d])
-            return fail(PIC_E_INVALID, "NULL current array");
-    int *err = sink_err();
-    if (!err)
-        return fail(PIC_E_DEVICE, "cannot resolve the device error word");
-    hipStream_t st = static_cast<hipStream_t>(stream);
-    if (gi.dtype == PIC_F64)
-        PIC_HIP(launch_deposit<double>(gi.order, make_const<double>(grid, before), parr<double>(before),
-                                       parr<double>(after), fptrs<double>(f), err, st));
-    else
-        PIC_HIP(launch_deposit<float>(gi.order, make_const<float>(grid, before), parr<float>(before),
-                                      parr<float>(after), fptrs<float>(f), err, st));
-    return PIC_OK;
+    try {
+        GridInfo gi;
+        PIC_TRY(check_grid(grid, gi));
+        PIC_TRY(check_species(before, "before"));
+        PIC_TRY(check_species(after, "after"));
+        if (before->n != after->n)
+            return fail(PIC_E_INVALID, "before and after hold different particle counts");
+        if (!f)
+            return fail(PIC_E_INVALID, "fields is NULL");
+        for (int d = 0; d < 3; ++d)
+            if (!f->J[d])
+                return fail(PIC_E_INVALID, "NULL current array");
+        int *err = sink_err();
+        if (!err)
+            return fail(PIC_E_DEVICE, "cannot resolve the device error word");
+        hipStream_t st = static_cast<hipStream_t>(stream);
+        PIC_TRY(sink_begin(err, st));
+        if (gi.dtype == PIC_F64)
+            PIC_HIP(launch_deposit<double>(gi.order, make_const<double>(grid, before), parr<double>(before),
+                                           parr<double>(after), fptrs<double>(f), err, st));
+        else
+            PIC_HIP(launch_deposit<float>(gi.order, make_const<float>(grid, before), parr<float>(before),
+                                          parr<float>(after), fptrs<float>(f), err, st));
+        return sink_end(err, st, "corrupt particle state or a displacement of a cell or more (its current is left out)");
+    } catch (...) {
+        return fail(PIC_E_DEVICE, "unexpected host exception");
+    }
 }
 
 pic_status pic_yee(const pic_grid *grid, pic_fields *f, const pic_source *src, int64_t step, void *stream)
 {
-    GridInfo gi;
-    PIC_TRY(check_grid(grid, gi));
-    PIC_TRY(check_fields(f, true));
-    PIC_TRY(check_source(src, gi));
-    hipStream_t st = static_cast<hipStream_t>(stream);
-    if (gi.dtype == PIC_F64)
-        return yee_step<double>(grid, gi, fptrs<double>(f), src, step, false, st);
-    return yee_step<float>(grid, gi, fptrs<float>(f), src, step, false, st);
+    try {
+        GridInfo gi;
+        PIC_TRY(check_grid(grid, gi));
+        PIC_TRY(check_fields(f, true));
+        PIC_TRY(check_source(src, gi));
+        hipStream_t st = static_cast<hipStream_t>(stream);
+        if (gi.dtype == PIC_F64)
+            return yee_step<double>(grid, gi, fptrs<double>(f), src, step, false, st);
+        return yee_step<float>(grid, gi, fptrs<float>(f), src, step, false, st);
+    } catch (...) {
+        return fail(PIC_E_DEVICE, "unexpected host exception");
+    }
 }
 
 // A binning handed in by the caller must at least span the particles: its
@@ -1183,19 +1225,23 @@ pic_status pic_step_adjoint(const pic_grid *grid, const pic_species *state_n, co
 pic_status pic_reduce(const pic_grid *grid, const pic_species *sp, const pic_fields *f, double *out, void *ws,
                       size_t ws_bytes, void *stream)
 {
-    GridInfo gi;
-    WsLayout L;
-    PIC_TRY(check_grid(grid, gi));
-    if (sp)
-        PIC_TRY(check_species(sp, "species"));
-    PIC_TRY(check_fields(f, false));
-    if (!out)
-        return fail(PIC_E_INVALID, "out is NULL");
-    PIC_TRY(check_ws(gi, sp ? sp->n : 0, ws, ws_bytes, L));
-    hipStream_t st = static_cast<hipStream_t>(stream);
-    if (gi.dtype == PIC_F64)
-        return reduce_t<double>(grid, gi, sp, f, out, static_cast<char *>(ws), L, st);
-    return reduce_t<float>(grid, gi, sp, f, out, static_cast<char *>(ws), L, st);
+    try {
+        GridInfo gi;
+        WsLayout L;
+        PIC_TRY(check_grid(grid, gi));
+        if (sp)
+            PIC_TRY(check_species(sp, "species"));
+        PIC_TRY(check_fields(f, false));
+        if (!out)
+            return fail(PIC_E_INVALID, "out is NULL");
+        PIC_TRY(check_ws(gi, sp ? sp->n : 0, ws, ws_bytes, L));
+        hipStream_t st = static_cast<hipStream_t>(stream);
+        if (gi.dtype == PIC_F64)
+            return reduce_t<double>(grid, gi, sp, f, out, static_cast<char *>(ws), L, st);
+        return reduce_t<float>(grid, gi, sp, f, out, static_cast<char *>(ws), L, st);
+    } catch (...) {
+        return fail(PIC_E_DEVICE, "unexpected host exception");
+    }
 }
 
 pic_status pic_timing(int enable, double *ms, int64_t *count, int n)
@@ -1219,24 +1265,28 @@ pic_status pic_timing(int enable, double *ms, int64_t *count, int n)
 pic_status pic_energy_loss(const pic_grid *grid, const pic_fields *f, int64_t n_particles, double s,
                            pic_adjoint *lam, double *out, void *ws, size_t ws_bytes, void *stream)
 {
-    GridInfo gi;
-    WsLayout L;
-    PIC_TRY(check_grid(grid, gi));
-    PIC_TRY(check_fields(f, false));
-    if (!lam || !out)
-        return fail(PIC_E_INVALID, "lam and out must not be NULL");
-    if (n_particles < 0)
-        return fail(PIC_E_INVALID, "n_particles must be >= 0");
-    for (int d = 0; d < 3; ++d)
-        if (!lam->lE[d] || !lam->lB[d] || (n_particles > 0 && (!lam->lx[d] || !lam->lu[d])))
-            return fail(PIC_E_INVALID, "NULL adjoint array");
-    if (!std::isfinite(s))
-        return fail(PIC_E_INVALID, "seed scale must be finite");
-    PIC_TRY(check_ws(gi, 0, ws, ws_bytes, L));
-    hipStream_t st = static_cast<hipStream_t>(stream);
-    if (gi.dtype == PIC_F64)
-        return energy_loss_t<double>(grid, gi, f, n_particles, s, lam, out, static_cast<char *>(ws), L, st);
-    return energy_loss_t<float>(grid, gi, f, n_particles, s, lam, out, static_cast<char *>(ws), L, st);
+    try {
+        GridInfo gi;
+        WsLayout L;
+        PIC_TRY(check_grid(grid, gi));
+        PIC_TRY(check_fields(f, false));
+        if (!lam || !out)
+            return fail(PIC_E_INVALID, "lam and out must not be NULL");
+        if (n_particles < 0)
+            return fail(PIC_E_INVALID, "n_particles must be >= 0");
+        for (int d = 0; d < 3; ++d)
+            if (!lam->lE[d] || !lam->lB[d] || (n_particles > 0 && (!lam->lx[d] || !lam->lu[d])))
+                return fail(PIC_E_INVALID, "NULL adjoint array");
+        if (!std::isfinite(s))
+            return fail(PIC_E_INVALID, "seed scale must be finite");
+        PIC_TRY(check_ws(gi, 0, ws, ws_bytes, L));
+        hipStream_t st = static_cast<hipStream_t>(stream);
+        if (gi.dtype == PIC_F64)
+            return energy_loss_t<double>(grid, gi, f, n_particles, s, lam, out, static_cast<char *>(ws), L, st);
+        return energy_loss_t<float>(grid, gi, f, n_particles, s, lam, out, static_cast<char *>(ws), L, st);
+    } catch (...) {
+        return fail(PIC_E_DEVICE, "unexpected host exception");
+    }
 }
 
 const char *pic_last_error(void)

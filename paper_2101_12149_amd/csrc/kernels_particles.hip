@@ -703,14 +703,19 @@ __global__ void __launch_bounds__(TileThreads<T>::value) k_particles_tile(PConst
             T u[3];
             unsigned char st = 0, gn = 0;   // stray mark; guest status next step
             bool moved = true;             // this launch writes the particle's next status
-            if (!load_particle(in, p, pc.n, c, f, u, err)) {
+            if (G && own && g.flag && g.flag[p]) {
+                // listed as a guest of another tile this step: that tile moves
+                // it, possibly before this one runs (the step is in place), so
+                // its cell must not be read here at all
+                moved = false;
+            } else if (!load_particle(in, p, pc.n, c, f, u, err)) {
                 copy_particle(in, out, p);
             } else if (!tile_local(tg, pc.n, ts.t0, c, l)) {
                 if (own) {
-                    // outside the region: a guest of the tile holding its cell,
-                    // or the stray kernel's (which writes its status)
+                    // outside the region and not listed as a guest: the stray
+                    // kernel's (which writes its status)
                     moved = false;
-                    st = (G && g.flag && g.flag[p]) ? 0 : 1;
+                    st = 1;
                 } else {
                     atomicOr(err, 2);   // cannot happen: the list was built from this cell in this call
                     copy_particle(in, out, p);
@@ -2056,8 +2061,14 @@ hipError_t launch_adjoint_tile(int order, const PConst<T> &pc, const TileGeo &tg
     if (sp.n == 0)
         return hipSuccess;
     const AdjPtrs<T> ap = adj_ptrs<T>(hatE, lx, lu, lE, lB, vb);
-    return order == 1 ? launch_adj_tile_o<T, 1>(pc, tg, sp, f, ap, tile_start, err, st)
-                      : launch_adj_tile_o<T, 3>(pc, tg, sp, f, ap, tile_start, err, st);
+    if (order == 1)
+        return launch_adj_tile_o<T, 1>(pc, tg, sp, f, ap, tile_start, err, st);
+    // FP64 order 3 has no tiled form (its pass 1 needs 256 registers and
+    // spills; the caller runs the per-particle kernels with the binning)
+    if constexpr (sizeof(T) == 8)
+        return hipErrorNotSupported;
+    else
+        return launch_adj_tile_o<T, 3>(pc, tg, sp, f, ap, tile_start, err, st);
 }
 
 #define PIC_INST(T)                                                                                               \

@@ -69,11 +69,9 @@ def test_adjoint_step_matches_oracle(order, dtype, tiled, pusher, solver, filt):
     binning gives them and take the global path of the tiled transpose.
     pusher 1 runs Vay's momentum update and its transpose, solver 1 the CKC
     field solve and its transpose, filt the z filter before the gather and
-    its transpose."""
-    if tiled and dtype == "f64" and order == 3:
-        pytest.skip("tiled FP64 order-3 adjoint is switched off in the library (an earlier form returned wrong "
-                    "position adjoints on the device; the request runs the per-particle kernels, covered by the "
-                    "untiled case)")
+    its transpose.  FP64 order 3 has no tiled form: with a binning (fresh or
+    stale) it runs the per-particle push and the segment-box scatter on the
+    binned order."""
     g = dataclasses.replace(wl.plasma_grid((12, 16, 20), order), pusher=pusher, solver=solver,
                             gather_filter=TAPS if filt else None)
     n = 3000
@@ -188,11 +186,9 @@ def test_tiled_adjoint_on_dense_tiles_matches_oracle(order, dtype, layout):
 @pytest.mark.parametrize("dtype", ["f64", "f32"])
 def test_adjoint_on_the_smallest_grid_with_every_option(dtype, tiled):
     """One reverse step on 4 x 5 x 7 cells (regions and stencils wrap the
-    box more than once) with Vay, CKC and the gather filter, order 3."""
+    box more than once) with Vay, CKC and the gather filter, order 3 (FP64
+    with a binning: the per-particle kernels on the binned order)."""
     g = dataclasses.replace(wl.plasma_grid((4, 5, 7), 3), pusher=1, solver=1, gather_filter=TAPS)
-    if tiled and dtype == "f64":
-        pytest.skip("tiled FP64 order-3 adjoint is switched off in the library (the request runs the "
-                    "per-particle kernels, covered by the untiled case)")
     n = 600
     sp = random_species(g, n, 121, u_th=0.3, dtype=dtype)
     f = random_fields(g, 122, scale=0.3, dtype=dtype)

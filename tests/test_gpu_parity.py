@@ -578,6 +578,49 @@ def test_guests_across_a_sort_inside_one_call(dtype):
         assert rel_l2(gt[:, 3:], ot[:, 3:]) < F64_TOL
 
 
+def test_guests_that_step_back_home_on_many_tiles():
+    """Regression test of the in-place guest step: a particle listed as a
+    guest of another tile must be skipped by its home tile even when the host
+    tile has already moved it back inside the home region.  64^3 FP64 order 3
+    (8x8x4 tiles, 1024 of them, so a tile and its lower z neighbour run 512
+    workgroups apart), 1 ppc at u_th = 0.4c gyrating in a uniform B_x = 3
+    (gyro-diameter ~2.4 cells across z), sorted at the first step only
+    (sort_every 20) and stepped 12 times in one call.  The oracle's
+    trajectory shows thousands of particles re-entering their home region
+    from outside; the GPU state matches the oracle within 1e-12."""
+    n = (64, 64, 64)
+    w = wl.uniform_plasma(n, 1, 0.4, 3, 12, "f64", 95, 20, shuffle=True)
+    w.fields.B[0].fill_(3.0)
+    g = w.grid
+    tile, slack = _lib.pic_tile_shape(g, "f64")
+    assert tuple(tile) == (8, 8, 4) and slack == 1
+    gsp, gf, _ = _run_gpu_steps(w, 12, 20)
+    # the oracle one step at a time, counting re-entries into the home region
+    # (home: the tile of the cell at the sort of step 0)
+    osp, of = w.species.numpy(), w.fields.numpy()
+    t = np.array(tile)[:, None]
+    nn = np.array(n)[:, None]
+    t0 = (osp.cell // t) * t
+
+    def inside(cell):
+        v = cell - t0
+        v = np.where(v < -slack, v + nn, np.where(v >= t + slack, v - nn, v))
+        return np.all((v >= -slack) & (v < t + slack), axis=0)
+
+    prev, back = inside(osp.cell), 0
+    for s in range(12):
+        oracle.step(g, osp, of, None, s, 1)
+        cur = inside(osp.cell)
+        back += int(np.sum(~prev & cur))
+        prev = cur
+    assert back > 1000, back
+    for name in ("E", "B", "J"):
+        assert rel_l2(_cpu(getattr(gf, name)), getattr(of, name)) < F64_TOL, name
+    gt, ot = particle_table(gsp), particle_table(osp)
+    assert np.array_equal(gt[:, :3], ot[:, :3])
+    assert rel_l2(gt[:, 3:], ot[:, 3:]) < F64_TOL
+
+
 def test_laser_plasma_reduced_with_empty_tiles_and_source():
     """Laser workload shape at reduced size: vacuum tiles without particles,
     a density up-ramp with per-particle weights, the soft source."""
@@ -626,3 +669,53 @@ def test_corrupt_momentum_reports_state_error():
     with pytest.raises(_lib.PicError) as ei:
         _run_gpu_steps(w, 1, 1)
     assert ei.value.name == "PIC_E_STATE"
+
+
+def test_unit_calls_report_corrupt_state():
+    """pic_gather, pic_push and pic_deposit read their device error word back:
+    a corrupt particle gives PIC_E_STATE, the other particles are processed,
+    and the next clean call returns OK (the word is cleared per call)."""
+    g = _grid()
+    sp = random_species(g, 2000, 31, u_th=0.2)
+    f = random_fields(g, 32)
+    bad = sp.clone()
+    bad.cell[1, 7] = int(g.n[1])            # cell outside the grid
+    d_bad, d_f = dev(bad), dev(f)
+    Ep = torch.zeros((3, sp.n), dtype=torch.float64, device="cuda")
+    Bp = torch.zeros_like(Ep)
+    with pytest.raises(_lib.PicError) as ei:
+        _lib.pic_gather(g, d_bad, d_f, Ep, Bp)
+    assert ei.value.name == "PIC_E_STATE"
+    oE, oB = oracle.gather(g, sp.numpy(), f.numpy())
+    keep = np.arange(sp.n) != 7
+    assert max_rel(_cpu(Ep)[:, keep], oE[:, keep]) < F64_TOL
+    assert np.all(_cpu(Ep)[:, 7] == 0.0) and np.all(_cpu(Bp)[:, 7] == 0.0)
+    _lib.pic_gather(g, dev(sp), d_f, Ep, Bp)   # clean call after an error: OK
+    # push: a non-finite momentum leaves that particle unchanged
+    nanp = sp.clone()
+    nanp.u[2, 11] = float("nan")
+    d_nan = dev(nanp)
+    with pytest.raises(_lib.PicError) as ei:
+        _lib.pic_push(g, d_nan, Ep, Bp)
+    assert ei.value.name == "PIC_E_STATE"
+    assert torch.equal(d_nan.cell[:, 11].cpu(), nanp.cell[:, 11])
+    o = sp.numpy()
+    oracle.push(g, o, np.ascontiguousarray(_cpu(Ep)), np.ascontiguousarray(_cpu(Bp)))
+    keep = np.arange(sp.n) != 11
+    assert max_rel(_cpu(d_nan.u)[:, keep], o.u[:, keep]) < F64_TOL
+    # deposit: a particle that moved two cells deposits nothing
+    before = sp.clone()
+    after = sp.clone()
+    after.cell[0, 3] = (after.cell[0, 3] + 2) % int(g.n[0])
+    fj = dev(wl.Fields.zeros(g))
+    with pytest.raises(_lib.PicError) as ei:
+        _lib.pic_deposit(g, dev(before), dev(after), fj)
+    assert ei.value.name == "PIC_E_STATE"
+    keep = torch.arange(sp.n) != 3
+    b2 = wl.Species(before.cell[:, keep].contiguous(), before.off[:, keep].contiguous(),
+                    before.u[:, keep].contiguous(), before.w[keep].contiguous(), before.w0)
+    a2 = wl.Species(after.cell[:, keep].contiguous(), after.off[:, keep].contiguous(),
+                    after.u[:, keep].contiguous(), after.w[keep].contiguous(), after.w0)
+    of = wl.Fields.zeros(g).numpy()
+    oracle.deposit(g, b2.numpy(), a2.numpy(), of)
+    assert rel_l2(_cpu(fj.J), of.J) < F64_TOL
