@@ -78,6 +78,7 @@ def _load():
             lib.or_push.argtypes = [P(_Grid), P(_Species), C.c_void_p * 3, C.c_void_p * 3]
             lib.or_deposit.argtypes = [P(_Grid), P(_Species), P(_Species), P(_Fields)]
             lib.or_rho.argtypes = [P(_Grid), P(_Species), C.c_void_p]
+            lib.or_ckc_coeffs.argtypes = [P(_Grid), C.c_void_p]
             lib.or_yee.argtypes = [P(_Grid), P(_Fields), P(_Source), C.c_int64]
             lib.or_reduce.argtypes = [P(_Grid), P(_Species), P(_Fields), C.c_void_p]
             lib.or_step.argtypes = [P(_Grid), P(_Species), P(_Fields), P(_Source), C.c_int64,
@@ -231,6 +232,16 @@ def rho(grid, sp):
     g, s = _grid(grid), _species(sp)
     lib.or_rho(C.byref(g), C.byref(s), _ptr(out))
     return out
+
+
+def ckc_coeffs(grid):
+    """(3, 4) array: (alpha, beta_p, beta_q, gamma) of the CKC averaging of
+    the differences along x, y, z (p, q = the next two axes cyclically)."""
+    lib = _load()
+    out = np.zeros(12)
+    g = _grid(grid)
+    lib.or_ckc_coeffs(C.byref(g), _ptr(out))
+    return out.reshape(3, 4)
 
 
 def yee(grid, fields, src=None, step=0):

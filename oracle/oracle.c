@@ -699,6 +699,17 @@ static void ckc_coeffs(const or_grid *g, double co[3][4])
     }
 }
 
+/* The coefficients above, co[a][0..3] = (alpha_a, beta_ap, beta_aq,
+ * gamma_a) for a = x, y, z (exported so that the tests can check them). */
+void or_ckc_coeffs(const or_grid *g, double co[12])
+{
+    double c3[3][4];
+    ckc_coeffs(g, c3);
+    for (int a = 0; a < 3; ++a)
+        for (int s = 0; s < 4; ++s)
+            co[4 * a + s] = c3[a][s];
+}
+
 /* Difference of component F along axis a at cell (i,j,k): forward
  * (F[+a] - F) or backward (F - F[-a]), divided by d_a; with co != NULL
  * averaged over the transverse neighbours as above. */

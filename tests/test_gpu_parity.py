@@ -70,6 +70,40 @@ def test_push_matches_oracle(dtype):
 
 
 @pytest.mark.parametrize("dtype", ["f64", "f32"])
+def test_push_offset_that_rounds_to_one_stays_in_the_cell(dtype):
+    """Offset 0 moved by a tiny negative displacement: offset + 1 rounds to 1
+    in the working precision, and the position update keeps the particle in
+    its cell with offset 0 (FP64: the oracle's result bit for bit, including
+    the representable case 1 - 2^-53 one cell down; FP32: the same point as
+    the oracle's to 1e-7 of a cell, offsets in [0, 1))."""
+    g = wl.plasma_grid((8, 8, 8), 3)
+    disp = np.array([-1e-17, -2.0 ** -54, -2.0 ** -53, -1e-300, -1e-9, -2.0 ** -25])
+    n = disp.size
+    u = np.zeros((3, n))
+    u[0] = disp * g.d[0] / g.dt
+    sp = wl.Species(torch.full((3, n), 3, dtype=torch.int32), torch.zeros((3, n), dtype=torch.float64),
+                    torch.tensor(u), None, 1.0).to(dtype=tdtype(dtype))
+    d_sp = dev(sp)
+    z = torch.zeros((3, n), dtype=tdtype(dtype), device="cuda")
+    _lib.pic_push(g, d_sp, z, z)
+    torch.cuda.synchronize()
+    o = sp.numpy()
+    zo = np.zeros((3, n))
+    oracle.push(g, o, zo, zo)
+    off = _cpu(d_sp.off)
+    cell = d_sp.cell.cpu().numpy()
+    assert np.all((off >= 0) & (off < 1))
+    if dtype == "f64":
+        assert np.array_equal(cell, o.cell)
+        assert np.array_equal(off, o.off)
+        assert list(cell[0, :4]) == [3, 3, 2, 3]
+    else:
+        x, ox = cell + off, o.cell + o.off
+        assert np.abs(x - ox).max() < 1e-7
+        assert list(cell[0, :2]) == [3, 3] and off[0, 0] == 0.0
+
+
+@pytest.mark.parametrize("dtype", ["f64", "f32"])
 def test_vay_push_matches_oracle(dtype):
     """Vay's momentum update in strong fields (|q B dt / 2m| up to ~1): the
     oracle's Vay result within the tolerances of the Boris test, and far from

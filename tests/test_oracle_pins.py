@@ -236,6 +236,36 @@ def _push_once(g, u0, E, B, q=-1.0):
     return sp.u
 
 
+def _tiny_moves(g, disp):
+    """Particles at offset 0 of cell 3 (all axes) moved by the given tiny
+    displacements (cell units) along x: E = B = 0, u chosen so that
+    dt u / (gamma d_x) is disp (gamma = 1 to rounding at these speeds)."""
+    disp = np.asarray(disp, dtype=float)
+    n = disp.size
+    u = np.zeros((3, n))
+    u[0] = disp * g.d[0] / g.dt
+    sp = species(np.full((3, n), 3), np.zeros((3, n)), u)
+    z = np.zeros((3, n))
+    oracle.push(g, sp, z, z)
+    return sp
+
+
+def test_position_update_offset_that_rounds_to_one_moves_to_the_next_cell():
+    """A position just below a cell face seen from the cell above: offset 0
+    moved by -1e-17 or by -2^-54 gives xi + 1 that rounds to exactly 1 in
+    FP64 (the second a tie, rounded to even), so the offset would be 1; the
+    update keeps the particle in its cell with offset 0 (the same point to
+    rounding).  At -2^-53 the sum 1 - 2^-53 is representable: the particle
+    moves down one cell with that offset.  The offset stays in [0, 1)."""
+    g = grid(n=(8, 8, 8), d=(0.3, 0.25, 0.35), dt=0.05)
+    sp = _tiny_moves(g, [-1e-17, -2.0 ** -54, -2.0 ** -53, -1e-300])
+    assert np.all((sp.off >= 0) & (sp.off < 1))
+    assert list(sp.cell[0]) == [3, 3, 2, 3]
+    assert sp.off[0, 0] == 0.0 and sp.off[0, 1] == 0.0 and sp.off[0, 3] == 0.0
+    assert sp.off[0, 2] == 1.0 - 2.0 ** -53
+    assert np.all(sp.cell[1:] == 3) and np.all(sp.off[1:] == 0.0)
+
+
 def _vay_grid(dt, pusher=1):
     g = grid(n=(4, 4, 4), d=(1e3, 1e3, 1e3), dt=dt)
     g.pusher = pusher
@@ -393,45 +423,62 @@ def test_yee_discrete_plane_wave_eigenmode():
     assert abs(omega - np.linalg.norm(kvec)) * t > 1e-3
 
 
-def _ckc_published(d):
-    """Cole-Karkkainen-Cowan coefficients (alpha, beta_p, beta_q, gamma) per
-    derivative axis, in the published closed form (delta = min cell size)."""
-    d = np.asarray(d, float)
-    r = (d.min() / d) ** 2
-    S = r[0] * r[1] + r[1] * r[2] + r[2] * r[0]
-    beta = (1 - r.prod() / S) / 8
-    co = []
+def _ckc_grid(d, dt=None):
+    g = grid(n=(8, 8, 8), d=d, dt=dt if dt is not None else 0.5 * min(d))
+    g.solver = 1
+    return g
+
+
+def test_ckc_coefficients_for_cubic_cells_are_the_published_values():
+    """The oracle's own CKC weights for cubic cells are the published ones
+    (Cole; Karkkainen et al.): centre 7/12, each edge neighbour 1/12, each
+    corner 1/48, for the differences along every axis."""
+    for d in ((0.2, 0.2, 0.2), (1.0, 1.0, 1.0)):
+        co = oracle.ckc_coeffs(_ckc_grid(d))
+        for a in range(3):
+            assert tuple(co[a]) == pytest.approx((7 / 12, 1 / 12, 1 / 12, 1 / 48), rel=1e-14, abs=1e-16)
+
+
+def _ckc_symbol(co, kd):
+    """Transverse average of the difference along each axis for the wave
+    vector kd = k * d (per axis), from the given weights."""
+    A = []
     for a in range(3):
         p, q = (a + 1) % 3, (a + 2) % 3
-        gm = r[p] * r[q] * (1 / 16 - r[p] * r[q] / (8 * S))
-        co.append((1 - 2 * r[p] * beta - 2 * r[q] * beta - 4 * gm, r[p] * beta, r[q] * beta, gm))
-    return co
+        al, bp, bq, gm = co[a]
+        A.append(al + 2 * bp * np.cos(kd[p]) + 2 * bq * np.cos(kd[q]) + 4 * gm * np.cos(kd[p]) * np.cos(kd[q]))
+    return A
 
 
-def test_ckc_published_coefficients_for_cubic_cells():
-    """The cubic-cell values of the published scheme: 7/12, 1/12, 1/48."""
-    for al, bp, bq, gm in _ckc_published((0.2, 0.2, 0.2)):
-        assert (al, bp, bq, gm) == pytest.approx((7 / 12, 1 / 12, 1 / 12, 1 / 48), rel=1e-14)
+@pytest.mark.parametrize("d", [(0.2, 0.25, 0.3), (0.3, 0.2, 0.25), (0.1, 0.3, 0.3), (0.5, 1.0, 1.0)])
+def test_ckc_coefficients_make_the_smallest_cell_the_exact_stability_limit(d):
+    """What the CKC weights are built for, on unequal cells: they sum to one
+    per axis (a transversely uniform difference is unchanged), and at
+    c dt = min d the amplification symbol (c dt)^2 sum_a sin^2(k_a d_a/2)
+    A_a(k) / d_a^2 stays at or below 1 over the whole Brillouin zone and
+    reaches 1 (marginal stability: c dt = min d is the exact limit).  Weights
+    with the two edge neighbours swapped, or the corner term's S dependence
+    dropped, exceed 1 (by 5-26 %) on these cells."""
+    co = oracle.ckc_coeffs(_ckc_grid(d))
+    for a in range(3):
+        assert co[a][0] + 2 * co[a][1] + 2 * co[a][2] + 4 * co[a][3] == pytest.approx(1.0, abs=1e-15)
+    dl = min(d)
+    k = np.linspace(0.0, np.pi, 65)
+    kd = np.meshgrid(k, k, k, indexing="ij")
+    A = _ckc_symbol(co, kd)
+    amp = sum((dl / d[a]) ** 2 * np.sin(kd[a] / 2) ** 2 * A[a] for a in range(3))
+    assert amp.max() <= 1.0 + 1e-12
+    assert amp.max() >= 1.0 - 1e-12
+    assert amp.min() >= -1e-15
 
 
-def test_ckc_discrete_plane_wave_eigenmode():
-    """With the CKC solver the B update's difference along a carries the
-    transverse average A_a(k) = alpha + 2 beta_p cos(k_p d_p)
-    + 2 beta_q cos(k_q d_q) + 4 gamma cos cos, so a divergence-free E0 with
-    B0 = cos(omega dt/2) (K' x E0 / W), K'_a = K_a A_a, is an eigenmode with
-    sin(omega dt/2) = (c dt/2) sqrt(K . K').  Oblique k, unequal cells; the
-    Yee frequency for the same k is far off."""
-    g = grid(n=(16, 12, 20), d=(0.2, 0.25, 0.15), dt=0.12)
-    g.solver = 1
+def _ckc_eigenmode(g, kvec, co, nst=40):
+    """Propagate the discrete CKC eigenmode for wave vector kvec with the
+    oracle's field solve and compare with its analytic phase; co gives the
+    weights of the expected dispersion."""
     dd = np.array(g.d)
-    L = np.array(g.n) * dd
-    kvec = 2 * np.pi * np.array([3, -2, 4]) / L
     K = 2 / dd * np.sin(kvec * dd / 2)
-    co = _ckc_published(g.d)
-    A = np.array([co[a][0] + 2 * co[a][1] * math.cos(kvec[(a + 1) % 3] * dd[(a + 1) % 3])
-                  + 2 * co[a][2] * math.cos(kvec[(a + 2) % 3] * dd[(a + 2) % 3])
-                  + 4 * co[a][3] * math.cos(kvec[(a + 1) % 3] * dd[(a + 1) % 3])
-                  * math.cos(kvec[(a + 2) % 3] * dd[(a + 2) % 3]) for a in range(3)])
+    A = np.array(_ckc_symbol(co, kvec * dd))
     Kp = K * A
     E0 = np.cross(K, [0.3, 1.0, -0.4])
     E0 /= np.linalg.norm(E0)
@@ -444,7 +491,6 @@ def test_ckc_discrete_plane_wave_eigenmode():
     for m in range(3):
         f.E[m] = _mode(g, kvec, E0[m], STAG_E[m])
         f.B[m] = _mode(g, kvec, B0[m], STAG_B[m])
-    nst = 40
     for n in range(nst):
         oracle.yee(g, f, None, n)
     t = nst * g.dt
@@ -452,6 +498,35 @@ def test_ckc_discrete_plane_wave_eigenmode():
         np.testing.assert_allclose(f.E[m], _mode(g, kvec, E0[m], STAG_E[m], omega * t), atol=1e-12)
         np.testing.assert_allclose(f.B[m], _mode(g, kvec, B0[m], STAG_B[m], omega * t), atol=1e-12)
     omega_yee = 2 * math.asin(g.c * g.dt * np.linalg.norm(K) / 2) / g.dt
+    return omega, omega_yee, t
+
+
+def test_ckc_discrete_plane_wave_eigenmode_cubic_cells():
+    """Cubic cells, with the expected dispersion from the published weights
+    7/12, 1/12, 1/48 (not from the oracle): the difference along a carries
+    the transverse average A_a(k) = alpha + 2 beta (cos k_p d + cos k_q d)
+    + 4 gamma cos k_p d cos k_q d, so a divergence-free E0 with
+    B0 = cos(omega dt/2) (K' x E0 / W), K'_a = K_a A_a, is an eigenmode with
+    sin(omega dt/2) = (c dt/2) sqrt(K . K'), at c dt = 0.9 d (beyond Yee's
+    limit d/sqrt(3)); Yee's frequency for the same k is far off."""
+    g = grid(n=(16, 12, 20), d=(0.2, 0.2, 0.2), dt=0.9 * 0.2)
+    g.solver = 1
+    L = np.array(g.n) * np.array(g.d)
+    kvec = 2 * np.pi * np.array([3, -2, 4]) / L
+    co = [(7 / 12, 1 / 12, 1 / 12, 1 / 48)] * 3
+    omega, omega_yee, t = _ckc_eigenmode(g, kvec, co)
+    assert abs(omega - omega_yee) * t > 1e-2
+
+
+def test_ckc_discrete_plane_wave_eigenmode_unequal_cells():
+    """The same eigenmode on unequal cells with the oracle's weights (held by
+    the stability-limit test above): the field solve applies each weight to
+    the right neighbours of the right difference."""
+    g = grid(n=(16, 12, 20), d=(0.2, 0.25, 0.15), dt=0.12)
+    g.solver = 1
+    L = np.array(g.n) * np.array(g.d)
+    kvec = 2 * np.pi * np.array([3, -2, 4]) / L
+    omega, omega_yee, t = _ckc_eigenmode(g, kvec, oracle.ckc_coeffs(g))
     assert abs(omega - omega_yee) * t > 1e-2
 
 
@@ -563,6 +638,38 @@ def test_yee_source_adds_on_plane_and_keeps_divB():
 
 # --------------------------------------------------------------------------
 # full step
+
+def test_laser_source_radiates_a0_after_the_discrete_dispersion_correction():
+    """The laser workload's soft source in vacuum (a plane wave: its waist
+    made huge) radiates a pulse of peak amplitude a0 m c omega_L / |q| (= a0
+    in these units) each way.  For a sheet that adds S g(n) to E_x every
+    step, the discrete Yee wave equation gives the exact ratio of radiated to
+    continuum amplitude 1 / cos(kappa dz / 2), with kappa from
+    sin(omega dt / 2) = (c dt / dz) sin(kappa dz / 2) (about 1.02 at 16
+    cells per wavelength).  The envelope peaks (analytic signal of E_x along
+    z) of the forward and the backward pulse match a0 / cos(kappa dz / 2)
+    within 0.2 %, and differ from the uncorrected a0 by more than 1 %."""
+    from scipy.signal import hilbert
+    nz, nsteps, a0 = 1536, 650, 2.0
+    w = wl.laser_plasma((4, 4, nz), ppc=2, order=3, nsteps=nsteps, dtype="f64", ramp=(nz, nz), k_source=2,
+                        waist_lambda=1e7, a0=a0)
+    assert w.species.n == 0
+    g = w.grid
+    f, src = w.fields.numpy(), w.source.numpy()
+    for n in range(nsteps):
+        oracle.yee(g, f, src, n)
+    env = np.abs(hilbert(f.E[0][:, 0, 0]))
+    omega = 1.0   # the workload's laser frequency (omega_L = 1)
+    dz, dt = g.d[2], g.dt
+    kappa = 2 * math.asin(dz / (g.c * dt) * math.sin(omega * dt / 2)) / dz
+    want = a0 / math.cos(kappa * dz / 2)
+    fwd, bwd = env[: nz // 2].max(), env[nz // 2:].max()
+    assert abs(fwd / want - 1) < 2e-3 and abs(bwd / want - 1) < 2e-3, (fwd, bwd, want)
+    assert abs(fwd / a0 - 1) > 1e-2
+    # the transverse field is uniform (a plane wave) and only E_x, B_y carry it
+    assert np.allclose(f.E[0], f.E[0][:, :1, :1], atol=1e-12)
+    assert np.abs(f.E[1]).max() < 1e-12 and np.abs(f.E[2]).max() < 1e-12
+
 
 def test_full_step_gauss_residual_is_invariant():
     w = wl.uniform_plasma((8, 8, 8), 2, 0.05, 3, 4, "f64", 77)
