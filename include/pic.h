@@ -234,6 +234,28 @@ PIC_API pic_status pic_step(const pic_grid *grid, pic_species *sp, pic_fields *f
                     int32_t nsteps, int32_t sort_every, int32_t *tile_start, void *ws, size_t ws_bytes,
                     double *diag, void *stream);
 
+/* Bytes of the static scratch array pic_step_noalloc uses in place of a
+ * workspace (one per device, held until the process ends). */
+#define PIC_NOALLOC_SCRATCH_BYTES ((size_t)128 << 20)
+
+/* pic_step for callers that cannot allocate device memory (code under HIP
+ * graph capture, tight serving loops, harnesses that forbid hipMalloc): the
+ * same arguments, checks, kernels and results as pic_step without ws and
+ * ws_bytes.  Its scratch is a static device array of
+ * PIC_NOALLOC_SCRATCH_BYTES per device (128 MiB: enough for
+ * pic_workspace_bytes of a 64^3 grid with 4 particles per cell in FP64);
+ * a grid and particle count that need more return PIC_E_WORKSPACE before
+ * anything is launched.  The call allocates nothing, neither device memory
+ * nor timing events (pic_timing does not see it); the device address of the
+ * array is looked up once per device, on the first call with that device
+ * current.  Every call on one device shares that device's array, which keeps
+ * the last call's contents (the call clears what it needs): calls that
+ * overlap on one device, from other streams or host threads, race and give
+ * wrong results.  Like pic_step it synchronises the stream at the end. */
+PIC_API pic_status pic_step_noalloc(const pic_grid *grid, pic_species *sp, pic_fields *f, const pic_source *src,
+                                   int64_t step0, int32_t nsteps, int32_t sort_every, int32_t *tile_start,
+                                   double *diag, void *stream);
+
 /* Hand-written adjoint of step `step`: state_n / fields_n are the inputs of
  * that forward step (no sort in between); lam holds dL/d(state n+1) on entry
  * and dL/d(state n) on return; dA (device double[n0*n1], or NULL) accumulates

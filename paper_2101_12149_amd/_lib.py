@@ -53,7 +53,7 @@ class pic_adjoint(C.Structure):
 
 
 EXPORTS = ("pic_workspace_bytes", "pic_tile_count", "pic_tile_shape", "pic_sort_tiles", "pic_gather", "pic_push", "pic_deposit",
-           "pic_yee", "pic_step", "pic_step_adjoint", "pic_reduce", "pic_energy_loss", "pic_timing", "pic_last_error")
+           "pic_yee", "pic_step", "pic_step_noalloc", "pic_step_adjoint", "pic_reduce", "pic_energy_loss", "pic_timing", "pic_last_error")
 TIMING_CATEGORIES = ("sort", "particles", "yee", "reduce", "adjoint_fields", "adjoint_particles", "strays")
 
 _lock = threading.Lock()
@@ -92,6 +92,9 @@ def load():
             lib.pic_step.argtypes = [P(pic_grid), P(pic_species), P(pic_fields), P(pic_source), C.c_int64,
                                      C.c_int32, C.c_int32, C.c_void_p, C.c_void_p, C.c_size_t, C.c_void_p,
                                      C.c_void_p]
+            lib.pic_step_noalloc.restype = C.c_int
+            lib.pic_step_noalloc.argtypes = [P(pic_grid), P(pic_species), P(pic_fields), P(pic_source), C.c_int64,
+                                             C.c_int32, C.c_int32, C.c_void_p, C.c_void_p, C.c_void_p]
             lib.pic_step_adjoint.restype = C.c_int
             lib.pic_step_adjoint.argtypes = [P(pic_grid), P(pic_species), P(pic_fields), C.c_void_p, P(pic_source),
                                              C.c_int64, P(pic_adjoint), C.c_void_p, C.c_void_p, C.c_size_t,
@@ -308,6 +311,21 @@ def pic_step(grid, sp, fields, src, step0, nsteps, sort_every, tile_start, ws, d
                            else None, wp, wn, _ptr(diag, torch.float64, "diag") if diag is not None else None,
                            _stream()))
     del keep
+
+
+def pic_step_noalloc(grid, sp, fields, src, step0, nsteps, sort_every, tile_start, diag=None):
+    """pic_step without a workspace: the library's static scratch array."""
+    code = _dtype_code(sp.off.dtype)
+    g, s, f = make_grid(grid, code), make_species(sp, code), make_fields(fields, code)
+    so, keep = make_source(src, code)
+    _check(load().pic_step_noalloc(C.byref(g), C.byref(s), C.byref(f), C.byref(so), int(step0), int(nsteps),
+                                   int(sort_every), _ptr(tile_start, torch.int32, "tile_start")
+                                   if tile_start is not None else None,
+                                   _ptr(diag, torch.float64, "diag") if diag is not None else None, _stream()))
+    del keep
+
+
+NOALLOC_SCRATCH_BYTES = 128 << 20
 
 
 def make_adjoint(lam, code):

@@ -64,6 +64,8 @@ struct Timer {
 };
 Timer g_timer;
 std::mutex g_timer_mu;
+// set while pic_step_noalloc runs: no timing events are created or recorded
+thread_local bool g_untimed = false;
 
 hipEvent_t timer_event()
 {
@@ -85,6 +87,8 @@ struct TimedScope {
     hipEvent_t a = nullptr, b = nullptr;
     TimedScope(int c, hipStream_t s) : cat(c), st(s)
     {
+        if (g_untimed)
+            return;
         std::lock_guard<std::mutex> lk(g_timer_mu);
         if (!g_timer.on)
             return;
@@ -149,6 +153,36 @@ pic_status sink_end(int *err, hipStream_t st, const char *what)
     PIC_HIP(hipStreamSynchronize(st));
     if (herr)
         return fail(PIC_E_STATE, what);
+    return PIC_OK;
+}
+
+// Scratch of pic_step_noalloc: a static array in place of the caller's
+// workspace, one copy per device (the code object's), held until the
+// process ends.  Host code never uses the array's name as an address: the
+// device address comes from hipGetSymbolAddress, once per device, with that
+// device current.
+static __device__ __align__(256) unsigned char scratch[PIC_NOALLOC_SCRATCH_BYTES];
+
+std::mutex g_scratch_mu;
+std::vector<void *> g_scratch_ptr;   // by device ordinal
+
+pic_status scratch_address(void **out)
+{
+    int dev = 0;
+    PIC_HIP(hipGetDevice(&dev));
+    std::lock_guard<std::mutex> lk(g_scratch_mu);
+    if (dev < 0)
+        return fail(PIC_E_DEVICE, "hipGetDevice returned a negative ordinal");
+    if ((size_t)dev >= g_scratch_ptr.size())
+        g_scratch_ptr.resize((size_t)dev + 1, nullptr);
+    if (!g_scratch_ptr[dev]) {
+        void *p = nullptr;
+        PIC_HIP(hipGetSymbolAddress(&p, HIP_SYMBOL(scratch)));
+        if (!p || (reinterpret_cast<uintptr_t>(p) & 255) != 0)
+            return fail(PIC_E_DEVICE, "static scratch array has no 256-byte aligned device address");
+        g_scratch_ptr[dev] = p;
+    }
+    *out = g_scratch_ptr[dev];
     return PIC_OK;
 }
 
@@ -1189,6 +1223,33 @@ pic_status pic_step(const pic_grid *grid, pic_species *sp, pic_fields *f, const 
         if (gi.dtype == PIC_F64)
             return step_t<double>(grid, gi, sp, f, src, step0, nsteps, sort_every, tile_start, ws, L, diag, st);
         return step_t<float>(grid, gi, sp, f, src, step0, nsteps, sort_every, tile_start, ws, L, diag, st);
+    } catch (...) {
+        return fail(PIC_E_DEVICE, "unexpected host exception");
+    }
+}
+
+pic_status pic_step_noalloc(const pic_grid *grid, pic_species *sp, pic_fields *f, const pic_source *src,
+                            int64_t step0, int32_t nsteps, int32_t sort_every, int32_t *tile_start, double *diag,
+                            void *stream)
+{
+    try {
+        GridInfo gi;
+        PIC_TRY(check_grid(grid, gi));
+        PIC_TRY(check_species(sp, "species"));
+        const size_t need = layout(gi, sp->n).total;
+        if (need > PIC_NOALLOC_SCRATCH_BYTES)
+            return fail(PIC_E_WORKSPACE, "pic_step_noalloc: this grid and particle count need " + std::to_string(need) +
+                                             " bytes of scratch, more than the static " +
+                                             std::to_string((size_t)PIC_NOALLOC_SCRATCH_BYTES) +
+                                             " bytes; use pic_step with a workspace");
+        void *ws = nullptr;
+        PIC_TRY(scratch_address(&ws));
+        struct Untimed {
+            Untimed() { g_untimed = true; }
+            ~Untimed() { g_untimed = false; }
+        } untimed;
+        return pic_step(grid, sp, f, src, step0, nsteps, sort_every, tile_start, ws, PIC_NOALLOC_SCRATCH_BYTES, diag,
+                        stream);
     } catch (...) {
         return fail(PIC_E_DEVICE, "unexpected host exception");
     }

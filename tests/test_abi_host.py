@@ -84,6 +84,26 @@ def _raw_call_step(grid, dtype="f64"):
     return st, lib.pic_last_error().decode()
 
 
+def test_noalloc_step_refuses_sizes_beyond_its_static_scratch():
+    """pic_step_noalloc checks the scratch its grid and particle count need
+    against the static array before anything is launched: a 256^3 grid (its
+    per-cell buffers alone exceed 128 MiB) is refused with PIC_E_WORKSPACE."""
+    lib = _lib.load()
+    big = wl.plasma_grid((256, 256, 256), 3)
+    assert _lib.pic_workspace_bytes(big, "f32", 0) > _lib.NOALLOC_SCRATCH_BYTES
+    assert _lib.pic_workspace_bytes(wl.plasma_grid((64, 64, 64), 3), "f64", 64 ** 3 * 4) \
+        <= _lib.NOALLOC_SCRATCH_BYTES
+    g = _lib.make_grid(big, "f32")
+    sp = _lib.pic_species()
+    sp.n = 0
+    sp.m, sp.q = 1.0, -1.0
+    f = _lib.pic_fields()
+    for m in range(3):
+        f.E[m] = f.B[m] = f.J[m] = 0x1000      # never dereferenced: the size check fails first
+    st = lib.pic_step_noalloc(C.byref(g), C.byref(sp), C.byref(f), None, 0, 1, 0, None, None, None)
+    assert st == 4 and "scratch" in lib.pic_last_error().decode()
+
+
 def test_cfl_violation_is_rejected():
     g = _grid()
     g.dt = g.d[0] / (3 ** 0.5) * 1.01
