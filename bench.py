@@ -62,17 +62,18 @@ def run_forward(w, steps, warmup, sort_every, label):
     ws = _lib.workspace(g, dtype, sp.n)
     ts = torch.zeros(_lib.pic_tile_count(g, dtype) + 1, dtype=torch.int32, device="cuda")
     diag = torch.zeros((max(steps, warmup, 1), 5), dtype=torch.float64, device="cuda")
+    src = w.source
     log(f"[{label}] warmup {warmup} steps, {sp.n} particles")
     if sort_every == 0:   # a workload that keeps one binning (the rollout's) is sorted once, untimed
         _lib.pic_sort_tiles(g, sp, ts, ws)
-    _lib.pic_step(g, sp, f, None, 0, warmup, sort_every, ts, ws, diag[:max(warmup, 1)])
+    _lib.pic_step(g, sp, f, src, 0, warmup, sort_every, ts, ws, diag[:max(warmup, 1)])
     torch.cuda.synchronize()
     _lib.pic_timing(True)
     e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
     torch.cuda.synchronize()
     t0 = time.perf_counter()
     e0.record()
-    _lib.pic_step(g, sp, f, None, warmup, steps, sort_every, ts, ws, diag[:steps])
+    _lib.pic_step(g, sp, f, src, warmup, steps, sort_every, ts, ws, diag[:steps])
     e1.record()
     torch.cuda.synchronize()
     wall = time.perf_counter() - t0
@@ -92,9 +93,10 @@ def run_adjoint(w, nrep, tile_start):
     g = w.grid
     sp, f = w.species, w.fields
     ws = _lib.workspace(g, w.dtype, sp.n)
+    src = w.source
     if tile_start is not None:
         _lib.pic_sort_tiles(g, sp, tile_start, ws)
-        _lib.pic_step(g, sp, f, None, 0, 2, 0, tile_start, ws)
+        _lib.pic_step(g, sp, f, src, 0, 2, 0, tile_start, ws)
         torch.cuda.synchronize()
 
     class Lam:
@@ -106,18 +108,121 @@ def run_adjoint(w, nrep, tile_start):
     lam.lE = f.E.clone()
     lam.lB = f.B.clone()
     dA = None
-    _lib.pic_step_adjoint(g, sp, f, None, 0, lam, dA, ws, tile_start=tile_start)   # warm
+    if src is not None:   # the source map's gradient is accumulated in FP64, as the rollout does
+        dA = torch.zeros(tuple(src.amp.shape), dtype=torch.float64, device=src.amp.device)
+    _lib.pic_step_adjoint(g, sp, f, src, 0, lam, dA, ws, tile_start=tile_start)   # warm
     torch.cuda.synchronize()
     _lib.pic_timing(True)
     e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
     e0.record()
     for r in range(nrep):
-        _lib.pic_step_adjoint(g, sp, f, None, r, lam, dA, ws, tile_start=tile_start)
+        _lib.pic_step_adjoint(g, sp, f, src, r, lam, dA, ws, tile_start=tile_start)
     e1.record()
     torch.cuda.synchronize()
     kt = _lib.pic_timing(False)
     del tdt
     return dict(ms=e0.elapsed_time(e1), kernels=kt)
+
+
+def kernel_roofs(kernels, npart, ncell, tsize, has_w, order):
+    """The fused tile kernel's mean launch time and its HBM and ALU
+    fractions from the algorithmic bytes and flops per particle-step."""
+    ms, n = kernels["particles"]
+    avg = ms / max(n, 1)
+    alg_bytes = particle_bytes(npart, tsize, has_w) + field_bytes(ncell, tsize)
+    gbs = alg_bytes / (avg * 1e-3) / 1e9
+    tfs = FLOPS_PER_PARTICLE[order] * npart / (avg * 1e-3) / 1e12
+    return {"kernel": "k_particles_tile", "avg_ms": round(avg, 4), "alg_bytes_per_particle": round(alg_bytes / npart, 2),
+            "hbm_GBps": round(gbs, 1), "hbm_frac": round(gbs / HBM_PEAK_GBS, 4), "alu_TFLOPs": round(tfs, 2),
+            "alu_frac": round(tfs / VALU_PEAK_TFLOPS, 4)}
+
+
+def run_rollout(w, label):
+    """The differentiable rollout as a user runs it: forward (checkpoints
+    every w.checkpoint_every steps, one binning) for the loss, then the
+    reverse sweep (re-binning and replay per segment, adjoint steps) for
+    dL/du0 and dL/damp.  Wall time of each half, synchronised."""
+    import torch
+    from paper_2101_12149_amd import rollout
+    pb = rollout.Problem(w.grid, w.species, w.fields, w.source, w.nsteps, w.checkpoint_every or 5, w.dtype)
+    u0 = w.species.u.clone().requires_grad_(True)
+    amp = w.source.amp.clone().requires_grad_(True) if w.source is not None else None
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    loss = rollout.rollout_loss(u0, amp, pb)
+    torch.cuda.synchronize()
+    t1 = time.perf_counter()
+    loss.backward()
+    torch.cuda.synchronize()
+    t2 = time.perf_counter()
+    fwd, bwd = (t1 - t0) * 1e3, (t2 - t1) * 1e3
+    log(f"[{label}] rollout {w.nsteps} steps: forward {fwd:.1f} ms, reverse sweep {bwd:.1f} ms")
+    return {"steps": w.nsteps, "checkpoint_every": pb.k, "forward_ms": round(fwd, 3), "backward_ms": round(bwd, 3),
+            "ratio_backward_over_forward": round(bwd / fwd, 4),
+            "grad_u0_norm": float(u0.grad.double().norm()),
+            "grad_amp_norm": float(amp.grad.double().norm()) if amp is not None else None}
+
+
+# the other workloads, each with its own step count: (name, timed steps,
+# warm-up steps, timed adjoint steps, rollout window in steps or 0)
+CONFIGS = (("uniform32_o1_f64", 10, 2, 3, 0),
+           ("laser128x128x1024_o3_f32", 40, 4, 5, 0),
+           ("diff64_o3_f64", 20, 2, 5, 20),
+           ("stress512_o3_f32", 40, 4, 3, 20))
+
+
+def bench_config(name, steps, warmup, nadj, window):
+    import torch
+    from paper_2101_12149_amd import workloads as wl
+    w = wl.named(name, device="cuda")
+    g = w.grid
+    npart, ncell = w.species.n, g.ncells
+    tsize = 4 if w.dtype == "f32" else 8
+    init = (w.species.clone(), w.fields.clone()) if window else None
+    fw = run_forward(w, steps, warmup, w.sort_every, name)
+    ms = fw["ms"] / steps
+    row = {"cells": list(g.n), "particles": npart, "dtype": w.dtype, "order": g.order, "sort_every": w.sort_every,
+           "steps": steps, "warmup": warmup, "ms_per_step": round(ms, 4),
+           "particle_steps_per_s": npart * steps / (fw["ms"] * 1e-3),
+           "kernels_ms_per_step": {k: round(v[0] / steps, 4) for k, v in fw["kernels"].items() if v[1]},
+           "dominant": kernel_roofs(fw["kernels"], npart, ncell, tsize, w.species.w is not None, g.order)}
+    adj = run_adjoint(w, nadj, fw["ts"])
+    adj_ms = adj["ms"] / nadj
+    row["adjoint"] = {"steps": nadj, "ms_per_step": round(adj_ms, 4), "ratio_adjoint_over_forward": adj_ms / ms,
+                      "ratio_with_replay": (adj_ms + ms) / ms,
+                      "kernels_ms_per_step": {k: round(v[0] / nadj, 4) for k, v in adj["kernels"].items() if v[1]}}
+    del fw
+    if window:
+        w.species, w.fields = init
+        w.nsteps = window
+        w.checkpoint_every = w.checkpoint_every or 5
+        del init
+        torch.cuda.empty_cache()
+        row["rollout"] = run_rollout(w, name)
+    del w
+    torch.cuda.empty_cache()
+    return row
+
+
+def cpu_configs():
+    """The oracle on the two small workloads in full: the 32^3 order-1 plasma
+    (10 steps) and the 64^3 differentiable plasma's 20 forward steps."""
+    import oracle
+    from paper_2101_12149_amd import workloads as wl
+    rows = {}
+    for name, warm, steps in (("uniform32_o1_f64", 0, 10), ("diff64_o3_f64", 0, 20)):
+        w = wl.named(name)
+        sp, f = w.species.numpy(), w.fields.numpy()
+        src = w.source.numpy() if w.source is not None else None
+        if warm:
+            oracle.step(w.grid, sp, f, src, 0, warm)
+        t0 = time.perf_counter()
+        oracle.step(w.grid, sp, f, src, warm, steps)
+        dt = time.perf_counter() - t0
+        rows[name] = {"value": sp.cell.shape[1] * steps / dt, "unit": "particle-steps/s", "steps": steps,
+                      "warmup": warm, "seconds": round(dt, 2), "cores": oracle.num_threads()}
+        log(f"[cpu] {name}: {steps} steps in {dt:.2f} s")
+    return rows
 
 
 def cpu_baseline():
@@ -250,6 +355,8 @@ def main():
     ap.add_argument("--no-fp64", action="store_true")
     ap.add_argument("--no-adjoint", action="store_true")
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-configs", action="store_true",
+                    help="leave out the other workloads (32^3, laser, 64^3 differentiable, 512^3)")
     ap.add_argument("--tile", type=int, default=0)
     ap.add_argument("--slack", type=int, default=-1)
     ap.add_argument("--pusher", choices=("boris", "vay"), default="boris",
@@ -364,9 +471,16 @@ def main():
         del w64, fw64
         torch.cuda.empty_cache()
 
+    if not args.no_configs and args.workload == "uniform256_o3_f32":
+        out["configs"] = {}
+        for name, k, wu, nadj, window in CONFIGS:
+            out["configs"][name] = bench_config(name, k, wu, nadj, window)
+
     if not args.no_cpu_baseline:
         log("[cpu] timing the oracle on a bounded sample")
         out["cpu_baseline"] = cpu_baseline()
+        if not args.no_configs:
+            out["cpu_baseline"]["configs"] = cpu_configs()
     print(json.dumps(out), flush=True)
 
 
