@@ -288,6 +288,26 @@ PIC_API pic_status pic_energy_loss(const pic_grid *grid, const pic_fields *f, in
 PIC_API pic_status pic_reduce(const pic_grid *grid, const pic_species *sp, const pic_fields *f, double *out, void *ws,
                       size_t ws_bytes, void *stream);
 
+/* Gauss-law residual, a diagnostic of charge conservation (Sec. 2.6
+ * reductions, FP64): the species' charge density at the nodes with the
+ * order-`order` B-spline, rho(i,j,k) = sum_p q w_p S(x-i) S(y-j) S(z-k) / dV,
+ * accumulated in FP64 (shape weights evaluated in FP64 from the offsets),
+ * plus the immobile neutralising background -(sum_p q w_p)/(ncell dV); the
+ * divergence of E at the nodes with the backward differences that take
+ * edge fields to nodes, div E(i,j,k) = sum_d (E_d[i,j,k] - E_d[.. - 1 along
+ * d]) / d_d (periodic).  out (device double[3]):
+ *   out[0] = sqrt(sum over nodes (div E - rho/eps0)^2),
+ *   out[1] = sqrt(sum over nodes (rho/eps0)^2)  (rho with the background),
+ *   out[2] = sum over nodes rho dV (the species' charge).
+ * With Esirkepov's deposit and the Yee update the residual field does not
+ * change from step to step beyond rounding (no Poisson solve is needed).
+ * The deposit uses per-particle global atomics (a diagnostic, not the hot
+ * path).  Needs the workspace; a particle with a cell outside [0,n) or an
+ * offset outside [0,1) is left out and the call returns PIC_E_STATE (it
+ * synchronises the stream to read the error word). */
+PIC_API pic_status pic_gauss_residual(const pic_grid *grid, const pic_species *sp, const pic_fields *f, double *out,
+                                      void *ws, size_t ws_bytes, void *stream);
+
 /* Kernel timing with HIP events recorded on the caller's stream around the
  * launches of pic_step and pic_step_adjoint, by category:
  *   0 sort (binning + scan + scatter)   1 fused particle (tile) kernel

@@ -81,6 +81,7 @@ def _load():
             lib.or_ckc_coeffs.argtypes = [P(_Grid), C.c_void_p]
             lib.or_yee.argtypes = [P(_Grid), P(_Fields), P(_Source), C.c_int64]
             lib.or_reduce.argtypes = [P(_Grid), P(_Species), P(_Fields), C.c_void_p]
+            lib.or_gauss.argtypes = [P(_Grid), P(_Species), P(_Fields), C.c_void_p, C.c_void_p]
             lib.or_step.argtypes = [P(_Grid), P(_Species), P(_Fields), P(_Source), C.c_int64,
                                     C.c_int32, C.c_void_p]
             lib.or_loss.restype = C.c_double
@@ -260,6 +261,17 @@ def reduce(grid, sp, fields):
     s = _species(sp) if sp is not None else None
     lib.or_reduce(C.byref(g), C.byref(s) if s is not None else None, C.byref(f), _ptr(out))
     return out
+
+
+def gauss(grid, sp, fields):
+    """Gauss-law residual: (res (nz, ny, nx) = div E - rho/eps0 per node with
+    the neutralising background, [|res|_2, |rho/eps0|_2, species charge])."""
+    lib = _load()
+    res = np.zeros((int(grid.n[2]), int(grid.n[1]), int(grid.n[0])))
+    out = np.zeros(3)
+    g, s, f = _grid(grid), _species(sp), _fields(fields, grid)
+    lib.or_gauss(C.byref(g), C.byref(s), C.byref(f), _ptr(res), _ptr(out))
+    return res, out
 
 
 def step(grid, sp, fields, src=None, step0=0, nsteps=1):

@@ -866,6 +866,44 @@ void or_reduce(const or_grid *g, const or_species *s, const or_fields *f, double
     out[4] = P;
 }
 
+/* Gauss-law residual (diagnostic of charge conservation).  Charge density
+ * at the nodes from or_rho plus a uniform background equal to minus its
+ * mean (the immobile neutralising ions); divergence of the edge field E at
+ * the nodes by backward differences, div E(i,j,k) = sum_d (E_d(node) -
+ * E_d(node - e_d)) / d_d.  res (may be NULL) receives div E - rho/eps0 per
+ * node; out[0] = its 2-norm over the nodes, out[1] = the 2-norm of rho/eps0,
+ * out[2] = sum of the species' rho times dV.                            */
+void or_gauss(const or_grid *g, const or_species *s, const or_fields *f, double *res, double out[3])
+{
+    int64_t nc = ncells(g);
+    double dV = g->d[0] * g->d[1] * g->d[2];
+    double *rho = (double *)calloc((size_t)nc, sizeof(double));
+    or_rho(g, s, rho);
+    double mean = 0;
+    for (int64_t i = 0; i < nc; ++i)
+        mean += rho[i];
+    out[2] = mean * dV;
+    mean /= (double)nc;
+    double sr = 0, sq = 0;
+    for (int64_t k = 0; k < g->n[2]; ++k)
+        for (int64_t j = 0; j < g->n[1]; ++j)
+            for (int64_t i = 0; i < g->n[0]; ++i) {
+                int64_t o = idx3(g, i, j, k);
+                double div = (f->E[0][o] - f->E[0][idx3(g, i - 1, j, k)]) / g->d[0] +
+                             (f->E[1][o] - f->E[1][idx3(g, i, j - 1, k)]) / g->d[1] +
+                             (f->E[2][o] - f->E[2][idx3(g, i, j, k - 1)]) / g->d[2];
+                double rt = (rho[o] - mean) / g->eps0;
+                double r = div - rt;
+                if (res)
+                    res[o] = r;
+                sr += r * r;
+                sq += rt * rt;
+            }
+    out[0] = sqrt(sr);
+    out[1] = sqrt(sq);
+    free(rho);
+}
+
 /* ------------------------------------------------------------------ */
 /* One full PIC step, in the order gather -> push -> deposit -> field
  * solve (Sec. 3.1 fuses gather and push; the step order is the standard
@@ -1097,9 +1135,11 @@ void or_step_adjoint(const or_grid *g, const or_species *s, const or_fields *f, 
         for (int64_t i = 0; i < nc; ++i)
             lam->lE[m][i] = hatE[m][i] - 0.5 * g->dt * C[m][i];
 
-    /* particle part (serial: the gather transpose scatters into lE, lB, or
-     * with a filter into the adjoints of the filtered fields, which the
-     * filter's transpose (itself) adds to lE, lB at the end) */
+    /* particle part: the gather transpose scatters into lE, lB (or, with a
+     * filter, into the adjoints of the filtered fields, which the filter's
+     * transpose (itself) adds to lE, lB at the end); particles are split
+     * over threads, each scattering into private buffers that are added to
+     * the targets afterwards in thread order (as the forward's current) */
     const double *F[6];
     double *fbuf = gather_fields(g, f, F);
     double *lF[6], *lfbuf = NULL;
@@ -1113,6 +1153,21 @@ void or_step_adjoint(const or_grid *g, const or_species *s, const or_fields *f, 
             lF[m] = lfbuf + m * nc;
     }
     double h = s->q * g->dt / (2.0 * s->m);
+    int nt = 1;
+#ifdef _OPENMP
+    nt = omp_get_max_threads();
+#endif
+    double *priv = (double *)calloc((size_t)nt * 6 * (size_t)nc, sizeof(double));
+#pragma omp parallel num_threads(nt)
+    {
+    int t = 0;
+#ifdef _OPENMP
+    t = omp_get_thread_num();
+#endif
+    double *lFt[6];
+    for (int m = 0; m < 6; ++m)
+        lFt[m] = priv + ((size_t)t * 6 + m) * nc;
+#pragma omp for schedule(static)
     for (int64_t p = 0; p < n; ++p) {
         int32_t cell[3];
         double off[3], E[3], B[3], u0[3], u1[3], dp[3];
@@ -1155,14 +1210,22 @@ void or_step_adjoint(const or_grid *g, const or_species *s, const or_fields *f, 
             boris_adjoint(h, g->c, E, B, &T, ub, u0b, Eb, Bb);
         /* gather transpose */
         for (int m = 0; m < 3; ++m) {
-            gather_adjoint_one(g, F[m], lF[m], STAG_E[m], cell, off, Eb[m], lx0);
-            gather_adjoint_one(g, F[3 + m], lF[3 + m], STAG_B[m], cell, off, Bb[m], lx0);
+            gather_adjoint_one(g, F[m], lFt[m], STAG_E[m], cell, off, Eb[m], lx0);
+            gather_adjoint_one(g, F[3 + m], lFt[3 + m], STAG_B[m], cell, off, Bb[m], lx0);
         }
         for (int d = 0; d < 3; ++d) {
             lam->lx[d][p] = lx0[d];
             lam->lu[d][p] = u0b[d];
         }
     }
+    }
+    for (int t = 0; t < nt; ++t)
+        for (int m = 0; m < 6; ++m) {
+            const double *src = priv + ((size_t)t * 6 + m) * nc;
+            for (int64_t i = 0; i < nc; ++i)
+                lF[m][i] += src[i];
+        }
+    free(priv);
     if (lfbuf) {
         for (int m = 0; m < 6; ++m) {
             double *dst = m < 3 ? lam->lE[m] : lam->lB[m - 3];

@@ -52,8 +52,9 @@ class pic_adjoint(C.Structure):
     _fields_ = [("lx", C.c_void_p * 3), ("lu", C.c_void_p * 3), ("lE", C.c_void_p * 3), ("lB", C.c_void_p * 3)]
 
 
-EXPORTS = ("pic_workspace_bytes", "pic_tile_count", "pic_tile_shape", "pic_sort_tiles", "pic_gather", "pic_push", "pic_deposit",
-           "pic_yee", "pic_step", "pic_step_noalloc", "pic_step_adjoint", "pic_reduce", "pic_energy_loss", "pic_timing", "pic_last_error")
+EXPORTS = ("pic_workspace_bytes", "pic_tile_count", "pic_tile_shape", "pic_sort_tiles", "pic_gather", "pic_push",
+           "pic_deposit", "pic_yee", "pic_step", "pic_step_noalloc", "pic_step_adjoint", "pic_reduce",
+           "pic_gauss_residual", "pic_energy_loss", "pic_timing", "pic_last_error")
 TIMING_CATEGORIES = ("sort", "particles", "yee", "reduce", "adjoint_fields", "adjoint_particles", "strays")
 
 _lock = threading.Lock()
@@ -102,6 +103,9 @@ def load():
             lib.pic_reduce.restype = C.c_int
             lib.pic_reduce.argtypes = [P(pic_grid), P(pic_species), P(pic_fields), C.c_void_p, C.c_void_p,
                                        C.c_size_t, C.c_void_p]
+            lib.pic_gauss_residual.restype = C.c_int
+            lib.pic_gauss_residual.argtypes = [P(pic_grid), P(pic_species), P(pic_fields), C.c_void_p, C.c_void_p,
+                                               C.c_size_t, C.c_void_p]
             lib.pic_energy_loss.restype = C.c_int
             lib.pic_energy_loss.argtypes = [P(pic_grid), P(pic_fields), C.c_int64, C.c_double, P(pic_adjoint),
                                             C.c_void_p, C.c_void_p, C.c_size_t, C.c_void_p]
@@ -363,6 +367,18 @@ def pic_reduce(grid, sp, fields, ws, out=None):
     wp, wn = _ws_ptr(ws)
     _check(load().pic_reduce(C.byref(g), C.byref(s) if s is not None else None, C.byref(f),
                              _ptr(out, torch.float64, "out"), wp, wn, _stream()))
+    return out
+
+
+def pic_gauss_residual(grid, sp, fields, ws, out=None):
+    """(|div E - rho/eps0|_2, |rho/eps0|_2, species charge) as a device double[3]."""
+    code = _dtype_code(sp.off.dtype)
+    g, s, f = make_grid(grid, code), make_species(sp, code), make_fields(fields, code, need_j=False)
+    if out is None:
+        out = torch.zeros(3, dtype=torch.float64, device=sp.off.device)
+    wp, wn = _ws_ptr(ws)
+    _check(load().pic_gauss_residual(C.byref(g), C.byref(s), C.byref(f), _ptr(out, torch.float64, "out"), wp, wn,
+                                     _stream()))
     return out
 
 

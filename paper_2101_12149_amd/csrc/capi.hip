@@ -990,6 +990,28 @@ pic_status energy_loss_t(const pic_grid *g, const GridInfo &gi, const pic_fields
     return PIC_OK;
 }
 
+// Gauss-law residual: the species' charge density goes to the adjoint's
+// hatE buffer (unused outside the adjoint; 3 T per cell >= one double)
+template <typename T>
+pic_status gauss_t(const pic_grid *g, const GridInfo &gi, const pic_species *sp, const pic_fields *f, double *out,
+                   char *ws, const WsLayout &L, hipStream_t st)
+{
+    int *err = reinterpret_cast<int *>(ws + L.err);
+    double *rho = reinterpret_cast<double *>(ws + L.hatE);
+    double *red5 = reinterpret_cast<double *>(ws + L.red5);
+    PIC_HIP(launch_fill<int>(err, 1, 0, st));
+    PIC_HIP(launch_fill<double>(rho, gi.ncell, 0.0, st));
+    PIC_TRY_S(reduce_t<T>(g, gi, sp, f, red5, ws, L, st));   // red5[3] = sum q w
+    PIC_HIP(launch_gauss<T>(gi.order, parr<T>(sp), fptrs<T>(f), gi.n, g->d, sp->q, sp->w0, g->eps0, rho, red5 + 3,
+                            reinterpret_cast<double *>(ws + L.partials), reduce_max_blocks(), out, err, st));
+    int herr = 0;
+    PIC_HIP(hipMemcpyAsync(&herr, err, sizeof(int), hipMemcpyDeviceToHost, st));
+    PIC_HIP(hipStreamSynchronize(st));
+    if (herr)
+        return fail(PIC_E_STATE, "particle with a cell outside the grid or an offset outside [0,1)");
+    return PIC_OK;
+}
+
 pic_status check_vec3(void *const v[3], const char *name)
 {
     if (!v)
@@ -1300,6 +1322,27 @@ pic_status pic_reduce(const pic_grid *grid, const pic_species *sp, const pic_fie
         if (gi.dtype == PIC_F64)
             return reduce_t<double>(grid, gi, sp, f, out, static_cast<char *>(ws), L, st);
         return reduce_t<float>(grid, gi, sp, f, out, static_cast<char *>(ws), L, st);
+    } catch (...) {
+        return fail(PIC_E_DEVICE, "unexpected host exception");
+    }
+}
+
+pic_status pic_gauss_residual(const pic_grid *grid, const pic_species *sp, const pic_fields *f, double *out,
+                              void *ws, size_t ws_bytes, void *stream)
+{
+    try {
+        GridInfo gi;
+        WsLayout L;
+        PIC_TRY(check_grid(grid, gi));
+        PIC_TRY(check_species(sp, "species"));
+        PIC_TRY(check_fields(f, false));
+        if (!out)
+            return fail(PIC_E_INVALID, "out is NULL");
+        PIC_TRY(check_ws(gi, sp->n, ws, ws_bytes, L));
+        hipStream_t st = static_cast<hipStream_t>(stream);
+        if (gi.dtype == PIC_F64)
+            return gauss_t<double>(grid, gi, sp, f, out, static_cast<char *>(ws), L, st);
+        return gauss_t<float>(grid, gi, sp, f, out, static_cast<char *>(ws), L, st);
     } catch (...) {
         return fail(PIC_E_DEVICE, "unexpected host exception");
     }

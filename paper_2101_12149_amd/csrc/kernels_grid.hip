@@ -2,6 +2,7 @@
 // their transposes), the counting sort that bins particles by tile-major
 // cell (Sec. 3.4.2), and the FP64 reductions (Sec. 2.6).  All of them are
 // bound by HBM bandwidth: coalesced x-fastest access, one pass per update.
+#include "pic_device.hpp"
 #include "pic_types.hpp"
 
 namespace pic {
@@ -916,6 +917,129 @@ hipError_t launch_reduce(const PArr<T> *sp, const FieldPtrs<T> &f, int64_t ncell
     return hipGetLastError();
 }
 
+// ---------------------------------------------------------------------------
+// Gauss-law residual (diagnostic).  The species' charge density at the nodes
+// with the order-O B-spline, rho(i,j,k) = sum_p q w_p S S S / dV, accumulated
+// in FP64 (weights evaluated in FP64 from the offsets) with global atomics;
+// then, per node, r = div E - (rho + rho_bg)/eps0 with the backward
+// differences that take edge fields to nodes and the immobile neutralising
+// background rho_bg = -(sum_p q w_p)/(ncell dV), summed as r^2,
+// ((rho + rho_bg)/eps0)^2 and rho.
+
+template <typename T, int O>
+__global__ void __launch_bounds__(256) k_rho(PArr<T> sp, int nx, int ny, int nz, double qdv, double w0, double *rho,
+                                             int *err)
+{
+    using S = Shape<O, double>;
+    constexpr int NW = S::NW;
+    const int64_t p = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (p >= sp.n)
+        return;
+    const int n[3] = {nx, ny, nz};
+    int c[3];
+    double wt[3][NW];
+    bool ok = true;
+#pragma unroll
+    for (int d = 0; d < 3; ++d) {
+        c[d] = sp.cell[d][p];
+        const T f = sp.off[d][p];
+        ok = ok && c[d] >= 0 && c[d] < n[d] && f >= T(0) && f < T(1);
+        S::w((double)f, wt[d]);
+    }
+    if (!ok) {
+        atomicOr(err, 1);
+        return;
+    }
+    const double qw = qdv * (sp.w ? (double)sp.w[p] : w0);
+    int ix[NW], iy[NW], iz[NW];
+#pragma unroll
+    for (int a = 0; a < NW; ++a) {
+        int v = c[0] + S::NB + a;
+        ix[a] = v < 0 ? v + nx : (v >= nx ? v - nx : v);
+        v = c[1] + S::NB + a;
+        iy[a] = v < 0 ? v + ny : (v >= ny ? v - ny : v);
+        v = c[2] + S::NB + a;
+        iz[a] = v < 0 ? v + nz : (v >= nz ? v - nz : v);
+    }
+#pragma unroll
+    for (int k = 0; k < NW; ++k)
+#pragma unroll
+        for (int j = 0; j < NW; ++j) {
+            const double wyz = qw * wt[1][j] * wt[2][k];
+            const int64_t row = (int64_t)nx * (iy[j] + (int64_t)ny * iz[k]);
+#pragma unroll
+            for (int i = 0; i < NW; ++i)
+                atomicAdd(rho + row + ix[i], wyz * wt[0][i]);
+        }
+}
+
+template <typename T>
+__global__ void __launch_bounds__(RED_T) k_gauss(FieldPtrs<T> f, const double *rho, const double *qsum, int nx,
+                                                 int ny, int nz, double idx, double idy, double idz, double bg_scale,
+                                                 double inv_eps0, double *partials)
+{
+    __shared__ double sh[(RED_T / 64) * 5];
+    const int64_t nxy = (int64_t)nx * ny, ncell = nxy * nz;
+    const double bg = bg_scale * qsum[0];   // -(sum q w)/(ncell dV)
+    double v[5] = {0, 0, 0, 0, 0};
+    for (int64_t o = (int64_t)blockIdx.x * RED_T + threadIdx.x; o < ncell; o += (int64_t)gridDim.x * RED_T) {
+        const int i = (int)(o % nx), j = (int)((o / nx) % ny), k = (int)(o / nxy);
+        const int64_t ox = i > 0 ? o - 1 : o + nx - 1;
+        const int64_t oy = j > 0 ? o - nx : o + nxy - nx;
+        const int64_t oz = k > 0 ? o - nxy : o + ncell - nxy;
+        const double div = ((double)f.E[0][o] - (double)f.E[0][ox]) * idx +
+                           ((double)f.E[1][o] - (double)f.E[1][oy]) * idy +
+                           ((double)f.E[2][o] - (double)f.E[2][oz]) * idz;
+        const double rt = (rho[o] + bg) * inv_eps0;
+        const double r = div - rt;
+        v[0] += r * r;
+        v[1] += rt * rt;
+        v[2] += rho[o];
+    }
+    block_sum5(v, sh, partials + 5 * (int64_t)blockIdx.x);
+}
+
+__global__ void __launch_bounds__(RED_T) k_gauss_final(const double *partials, int nb, double dV, double *out)
+{
+    __shared__ double sh[(RED_T / 64) * 5];
+    __shared__ double tot[5];
+    const int per = (nb + RED_T - 1) / RED_T;
+    double v[5] = {0, 0, 0, 0, 0};
+    for (int b = threadIdx.x * per; b < (threadIdx.x + 1) * per && b < nb; ++b)
+#pragma unroll
+        for (int k = 0; k < 3; ++k)
+            v[k] += partials[5 * b + k];
+    block_sum5(v, sh, tot);
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        out[0] = sqrt(tot[0]);
+        out[1] = sqrt(tot[1]);
+        out[2] = tot[2] * dV;
+    }
+}
+
+template <typename T>
+hipError_t launch_gauss(int order, const PArr<T> &sp, const FieldPtrs<T> &f, const int n[3], const double d[3],
+                        double q, double w0, double eps0, double *rho, const double *qsum, double *partials,
+                        int max_blocks, double *out, int *err, hipStream_t st)
+{
+    const double dV = d[0] * d[1] * d[2];
+    const int64_t ncell = (int64_t)n[0] * n[1] * n[2];
+    if (sp.n > 0) {
+        const unsigned nb = (unsigned)((sp.n + 255) / 256);
+        if (order == 3)
+            hipLaunchKernelGGL((k_rho<T, 3>), dim3(nb), dim3(256), 0, st, sp, n[0], n[1], n[2], q / dV, w0, rho, err);
+        else
+            hipLaunchKernelGGL((k_rho<T, 1>), dim3(nb), dim3(256), 0, st, sp, n[0], n[1], n[2], q / dV, w0, rho, err);
+    }
+    int nb = (int)((ncell + RED_T * 8 - 1) / (RED_T * 8));
+    nb = nb < 1 ? 1 : (nb > max_blocks ? max_blocks : nb);
+    hipLaunchKernelGGL((k_gauss<T>), dim3(nb), dim3(RED_T), 0, st, f, rho, qsum, n[0], n[1], n[2], 1.0 / d[0],
+                       1.0 / d[1], 1.0 / d[2], -1.0 / ((double)ncell * dV), 1.0 / eps0, partials);
+    hipLaunchKernelGGL(k_gauss_final, dim3(1), dim3(RED_T), 0, st, partials, nb, dV, out);
+    return hipGetLastError();
+}
+
 #define PIC_GINST(T)                                                                                             \
     template hipError_t launch_curl<T>(bool, const CurlArgs<T> &, hipStream_t);                                   \
     template hipError_t launch_filter_z<T>(const T *, T *, const T[4], bool, const int[3], hipStream_t);         \
@@ -928,7 +1052,10 @@ hipError_t launch_reduce(const PArr<T> *sp, const FieldPtrs<T> &f, int64_t ncell
     template hipError_t launch_scatter<T>(const PArr<T> &, const PArr<T> &, const int *, const int *, const int *, \
                                           const int *, const int *, const int *, int, int, int *, hipStream_t);   \
     template hipError_t launch_reduce<T>(const PArr<T> *, const FieldPtrs<T> &, int64_t, double *, int,           \
-                                         const double[7], double *, hipStream_t);
+                                         const double[7], double *, hipStream_t);                                 \
+    template hipError_t launch_gauss<T>(int, const PArr<T> &, const FieldPtrs<T> &, const int[3], const double[3], \
+                                        double, double, double, double *, const double *, double *, int, double *, \
+                                        int *, hipStream_t);
 
 PIC_GINST(float)
 PIC_GINST(double)

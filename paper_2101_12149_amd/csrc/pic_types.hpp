@@ -168,6 +168,16 @@ template <typename T>
 hipError_t launch_reduce(const PArr<T> *sp, const FieldPtrs<T> &f, int64_t ncell, double *partials,
                          int max_blocks, const double scale[7], double *out, hipStream_t st);
 
+// Gauss-law residual: rho (double[ncell], zeroed by the caller) receives the
+// species' nodal charge density; qsum points at the species' total charge
+// sum q w (device); out[0] = |div E - rho_total/eps0|_2 over the nodes,
+// out[1] = |rho_total/eps0|_2, out[2] = sum of rho dV (the species' charge),
+// rho_total including the uniform neutralising background.
+template <typename T>
+hipError_t launch_gauss(int order, const PArr<T> &sp, const FieldPtrs<T> &f, const int n[3], const double d[3],
+                        double q, double w0, double eps0, double *rho, const double *qsum, double *partials,
+                        int max_blocks, double *out, int *err, hipStream_t st);
+
 // blocks used by the scan for n elements, and by the reduction
 int64_t scan_blocks(int64_t n);
 int reduce_max_blocks();

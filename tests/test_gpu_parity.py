@@ -597,8 +597,10 @@ def test_guests_across_a_sort_inside_one_call(dtype):
     """Sorting every 10 steps turns the guest lists on: 12 steps in one call
     at u_th = 0.3c build and read lists on steps 1-9, drop them at the sort
     on step 10 (which renumbers the particles) and build them again there
-    for step 11.  FP64 within 1e-12; FP32 within rel-L2 1e-5 after the same
-    12 steps (fields) against the oracle started from the same state."""
+    for step 11.  FP64 within 1e-12; FP32 within rel-L2 1e-4 after the same
+    12 steps (fields) against the oracle started from the same state: the
+    one-step bound 1e-5 accumulated over 12 steps, at most linearly on a
+    horizon of 3.6 / omega_p (the FP32 tolerance readings of the design)."""
     w = wl.uniform_plasma((16, 16, 24), 2, 0.3, 3, 12, dtype, 89, 10, shuffle=True)
     w.fields = random_fields(w.grid, 90, scale=0.05, dtype=dtype)
     gsp, gf, _ = _run_gpu_steps(w, 12, 10)

@@ -672,20 +672,48 @@ def test_laser_source_radiates_a0_after_the_discrete_dispersion_correction():
 
 
 def test_full_step_gauss_residual_is_invariant():
+    """Esirkepov's current and the Yee update keep div E - rho/eps0 fixed
+    node by node (no Poisson solve: the initial residual is thermal noise)."""
     w = wl.uniform_plasma((8, 8, 8), 2, 0.05, 3, 4, "f64", 77)
     g = w.grid
     sp, f = w.species.numpy(), w.fields.numpy()
-
-    def residual():
-        rho = oracle.rho(g, sp)
-        rho = rho - rho.mean()                 # immobile neutralising ions
-        return _div_edges(g, f.E) - rho / g.eps0
-
-    r0 = residual()
-    assert np.abs(r0).max() > 1e-3             # thermal noise, no Poisson solve
+    r0, s0 = oracle.gauss(g, sp, f)
+    assert np.abs(r0).max() > 1e-3
     for n in range(4):
         oracle.step(g, sp, f, None, n, 1)
-        np.testing.assert_allclose(residual(), r0, rtol=0, atol=1e-12 * np.abs(r0).max())
+        r, s = oracle.gauss(g, sp, f)
+        np.testing.assert_allclose(r, r0, rtol=0, atol=1e-12 * np.abs(r0).max())
+        assert abs(s[0] - s0[0]) < 1e-12 * s0[0]
+
+
+def test_gauss_residual_of_a_lattice_potential_and_of_one_particle():
+    """Without particles, E = -grad phi on the edges of a cosine mode phi
+    gives div E = sum_d K_d^2 phi with K_d = (2/d_d) sin(k_d d_d/2), the
+    discrete Laplacian's eigenvalue (a wrong sign, index or axis in the
+    divergence fails); with E = 0 and one particle, the residual is minus
+    its nodal density over eps0 less the mean, which sums to zero, and the
+    species' charge is q w (partition of unity)."""
+    g = grid(n=(8, 10, 12), order=3)
+    k = [2 * math.pi * m / (n * d) for m, n, d in zip((1, 2, 3), g.n, g.d)]
+    z, y, x = np.meshgrid(*(np.arange(n) * d for n, d in zip(g.n[::-1], g.d[::-1])), indexing="ij")
+    phi = np.cos(k[0] * x + k[1] * y + k[2] * z)
+    f = zero_fields(g)
+    for m, ax in ((0, 2), (1, 1), (2, 0)):
+        f.E[m] = -(np.roll(phi, -1, axis=ax) - phi) / g.d[m]
+    none = species(np.zeros((3, 0)), np.zeros((3, 0)), np.zeros((3, 0)))
+    res, out = oracle.gauss(g, none, f)
+    lam = sum((2.0 / d * math.sin(kd * d / 2)) ** 2 for kd, d in zip(k, g.d))
+    np.testing.assert_allclose(res, lam * phi, rtol=0, atol=1e-12 * lam)
+    assert abs(out[0] - lam * np.linalg.norm(phi)) < 1e-12 * out[0] and out[1] == 0 and out[2] == 0
+    one = species([[3], [4], [5]], [[0.3], [0.6], [0.9]], np.zeros((3, 1)), w=np.array([2.5]), q=-1.5)
+    res, out = oracle.gauss(g, one, zero_fields(g))
+    dV = float(np.prod(g.d))
+    assert abs(out[2] - (-1.5 * 2.5)) < 1e-14
+    assert abs(res.sum()) < 1e-12 * np.abs(res).max()
+    # the particle's own node (3, 4, 5) carries S(0.3) S(0.6) S(0.9)
+    s3 = oracle.shape(3, 0.3) * oracle.shape(3, 0.6) * oracle.shape(3, 0.9)
+    rt = ((-1.5 * 2.5 / dV) * s3 - (-1.5 * 2.5 / dV) / res.size) / g.eps0
+    assert abs(res[5, 4, 3] + rt) < 1e-12 * abs(rt)
 
 
 def test_step_does_not_depend_on_the_thread_count_beyond_rounding():
