@@ -1831,6 +1831,220 @@ __global__ void __launch_bounds__(AdjThreads<T>::value) k_adjoint_scatter_tile(P
 }
 
 // ---------------------------------------------------------------------------
+// pass 2, tiled, accumulated per cell.  The scatter of a particle's gathered-
+// field adjoints is the outer product vb wx (x) wy (x) wz on its window; the
+// particles of one cell share that window (on a staggered axis the NW + 1
+// nodes either half of the cell reaches, as in SM_WIDE), so one thread per
+// cell of the tile sums its particles' outer products in registers, one
+// component at a time, and adds the sum into the component's FP64 LDS
+// accumulator once per cell with rows shared along x (the lanes of a wave
+// are consecutive cells of the tile, so the runs are the tile's rows of
+// cells).  Per particle this costs the weights and the multiply-adds of
+// the outer product; the LDS rows are paid once per cell instead of once
+// per particle.
+//
+// Which particles sit in which cell comes from a counting sort of the
+// tile's particles in LDS (a chunk of up to `cap` at a time): count per
+// cell, scan, list of in-tile indices per cell.  Particles in the tile's
+// slack cells (they left the tile since the binning) are listed after the
+// cells and scattered one lane each; particles beyond the slack are the
+// stray kernel's.  Each component is flushed to the global field adjoint
+// (one global atomic per non-zero value) before the next one reuses the
+// accumulator, so the LDS holds one component at a time.
+constexpr int CELL_THREADS = 512;
+
+// exclusive prefix sum of in[0..n) into out[0..n) by the whole workgroup;
+// sh: LDS scratch of blockDim.x / 64 + 1 ints
+__device__ inline void block_exclusive_scan(const int *in, int *out, int n, int *sh)
+{
+    const int tid = threadIdx.x, nth = blockDim.x, lane = tid & 63, wv = tid >> 6;
+    const int per = (n + nth - 1) / nth, b = tid * per, e = b + per < n ? b + per : n;
+    int sum = 0;
+    for (int i = b; i < e; ++i)
+        sum += in[i];
+    int incl = sum;
+    for (int off = 1; off < 64; off <<= 1) {
+        const int v = __shfl_up(incl, off, 64);
+        if (lane >= off)
+            incl += v;
+    }
+    if (lane == 63)
+        sh[wv] = incl;
+    __syncthreads();
+    if (tid == 0) {
+        int acc = 0;
+        for (int w = 0; w < nth / 64; ++w) {
+            const int v = sh[w];
+            sh[w] = acc;
+            acc += v;
+        }
+    }
+    __syncthreads();
+    int run = sh[wv] + incl - sum;
+    for (int i = b; i < e; ++i) {
+        const int v = in[i];
+        out[i] = run;
+        run += v;
+    }
+}
+
+// One component (staggering SX, SY, SZ) of the per-cell scatter into the
+// LDS accumulator sA, then its slack-cell particles one lane each.
+template <typename T, int O, int SX, int SY, int SZ>
+__device__ __attribute__((always_inline)) inline void cell_scatter_component(
+    const PConst<T> &pc, const TileGeo &tg, const TileSpan &ts, const PArr<T> &sp, const T *__restrict__ vbm,
+    const int *list, const int *cstart, const int *ccnt, int tc, double *sA, const int *sf)
+{
+    constexpr int NW = Shape<O, T>::NW, NB = Shape<O, T>::NB;
+    constexpr int NX = NW + SX, NY = NW + SY, NZ = NW + SZ;
+    const int nth = blockDim.x;
+    for (int g0 = 0; g0 < tc; g0 += nth) {
+        const int lc = g0 + (int)threadIdx.x;
+        const bool cell = lc < tc;
+        int l[3] = {0, 0, 0}, s = 0, k = 0;
+        if (cell) {
+            l[0] = lc % tg.t[0];
+            l[1] = (lc / tg.t[0]) % tg.t[1];
+            l[2] = lc / (tg.t[0] * tg.t[1]);
+            s = cstart[lc];
+            k = ccnt[lc];
+        }
+        T acc[NZ][NY][NX];
+#pragma unroll
+        for (int c = 0; c < NZ; ++c)
+#pragma unroll
+            for (int b = 0; b < NY; ++b)
+#pragma unroll
+                for (int a = 0; a < NX; ++a)
+                    acc[c][b][a] = T(0);
+        for (int i = 0; i < k; ++i) {
+            const int64_t p = ts.ps + list[s + i];
+            AxisW<O, T> aw[3];
+#pragma unroll
+            for (int d = 0; d < 3; ++d)
+                axis_weights<O>(sp.off[d][p], aw[d]);
+            const T v = vbm[p];
+            T wx[NX], wy[NY], wz[NZ];
+            scatter_axis<O, T, SX, SM_WIDE>(aw[0], wx);
+            scatter_axis<O, T, SY, SM_WIDE>(aw[1], wy);
+            scatter_axis<O, T, SZ, SM_WIDE>(aw[2], wz);
+#pragma unroll
+            for (int c = 0; c < NZ; ++c)
+#pragma unroll
+                for (int b = 0; b < NY; ++b) {
+                    const T wyz = wy[b] * wz[c] * v;
+#pragma unroll
+                    for (int a = 0; a < NX; ++a)
+                        acc[c][b][a] += wx[a] * wyz;
+                }
+        }
+        // the wave is converged here: runs of consecutive cells along x
+        const XRun xr = xrun(cell ? xrun_key(l) : 0);
+        if (__ballot(k > 0) != 0 && cell) {
+            const int x0 = l[0] + tg.lo_f + NB - SX;
+            const int y0 = l[1] + tg.lo_f + NB - SY;
+            const int z0 = l[2] + tg.lo_f + NB - SZ;
+#pragma unroll
+            for (int c = 0; c < NZ; ++c)
+#pragma unroll
+                for (int b = 0; b < NY; ++b)
+                    xrow_add<NX>(sA + x0 + sf[1] * (y0 + b) + sf[2] * (z0 + c), acc[c][b], xr);
+        }
+    }
+    // particles in the slack cells, one lane each on their own windows
+    const int no = ccnt[tc], so = cstart[tc];
+    for (int i = threadIdx.x; i < no; i += nth) {
+        const int64_t p = ts.ps + list[so + i];
+        int c[3], l[3];
+        T f[3];
+        load_position(sp, p, pc.n, c, f);
+        tile_local(tg, pc.n, ts.t0, c, l);
+        AxisW<O, T> aw[3];
+        int on[3][NW], os[3][NW];
+        adjoint_offsets<T, O, true>(pc, c, f, l, tg.lo_f, sf, aw, on, os);
+        scatter_component<O, T, true, SM_ALONE, SX, SY, SZ>(nullptr, sA, vbm[p], aw, on, os, sf,
+                                                              xrun_unpack(XRUN_ALONE));
+    }
+}
+
+template <typename T, int O>
+__global__ void __launch_bounds__(CELL_THREADS) __attribute__((amdgpu_waves_per_eu(4))) k_adjoint_scatter_cells(PConst<T> pc, TileGeo tg, PArr<T> sp,
+                                                                        AdjPtrs<T> ap,
+                                                                        const int *__restrict__ tile_start, int cap)
+{
+    extern __shared__ __align__(16) unsigned char smem_raw[];
+    const int rfx = tg.rf[0], rfy = tg.rf[1];
+    const int rfvol = rfx * rfy * tg.rf[2];
+    const int tc = tg.t[0] * tg.t[1] * tg.t[2];
+    double *sA = reinterpret_cast<double *>(smem_raw);   // rfvol: one component
+    int *ccnt = reinterpret_cast<int *>(sA + rfvol);     // tc + 1 (the last: slack cells)
+    int *cstart = ccnt + (tc + 1);                        // tc + 1
+    int *keys = cstart + (tc + 1);                        // cap
+    int *list = keys + cap;                               // cap
+    int *sh = list + cap;                                 // scan scratch
+    const TileSpan ts = tile_span(tg, tile_start, sp.n);
+    if (ts.pe <= ts.ps)
+        return;
+    const int tid = threadIdx.x, nth = blockDim.x;
+    const int sf[3] = {1, rfx, rfx * rfy};
+    const int np = (int)(ts.pe - ts.ps);
+    for (int r = tid; r < rfvol; r += nth)
+        sA[r] = 0.0;
+    for (int j0 = 0; j0 < np; j0 += cap) {
+        const int je = np < j0 + cap ? np : j0 + cap;
+        // counting sort of the chunk by cell
+        for (int i = tid; i <= tc; i += nth)
+            ccnt[i] = 0;
+        __syncthreads();
+        for (int j = j0 + tid; j < je; j += nth) {
+            int c[3], l[3];
+            T f[3];
+            int key = -1;
+            if (load_position(sp, ts.ps + j, pc.n, c, f) && tile_local(tg, pc.n, ts.t0, c, l)) {
+                const bool in = l[0] >= 0 && l[0] < tg.t[0] && l[1] >= 0 && l[1] < tg.t[1] && l[2] >= 0 &&
+                                l[2] < tg.t[2];
+                const int slot = in ? l[0] + tg.t[0] * (l[1] + tg.t[1] * l[2]) : tc;
+                key = (slot << 16) | atomicAdd(ccnt + slot, 1);
+            }
+            keys[j - j0] = key;
+        }
+        __syncthreads();
+        block_exclusive_scan(ccnt, cstart, tc + 1, sh);
+        __syncthreads();
+        for (int j = j0 + tid; j < je; j += nth) {
+            const int key = keys[j - j0];
+            if (key >= 0)
+                list[cstart[key >> 16] + (key & 0xffff)] = j;
+        }
+        __syncthreads();
+        for (int m = 0; m < 6; ++m) {
+            const T *vbm = ap.vb[m];
+            // staggering: E_x(s,n,n) E_y(n,s,n) E_z(n,n,s) B_x(n,s,s) B_y(s,n,s) B_z(s,s,n)
+            switch (m) {
+            case 0: cell_scatter_component<T, O, 1, 0, 0>(pc, tg, ts, sp, vbm, list, cstart, ccnt, tc, sA, sf); break;
+            case 1: cell_scatter_component<T, O, 0, 1, 0>(pc, tg, ts, sp, vbm, list, cstart, ccnt, tc, sA, sf); break;
+            case 2: cell_scatter_component<T, O, 0, 0, 1>(pc, tg, ts, sp, vbm, list, cstart, ccnt, tc, sA, sf); break;
+            case 3: cell_scatter_component<T, O, 0, 1, 1>(pc, tg, ts, sp, vbm, list, cstart, ccnt, tc, sA, sf); break;
+            case 4: cell_scatter_component<T, O, 1, 0, 1>(pc, tg, ts, sp, vbm, list, cstart, ccnt, tc, sA, sf); break;
+            default: cell_scatter_component<T, O, 1, 1, 0>(pc, tg, ts, sp, vbm, list, cstart, ccnt, tc, sA, sf); break;
+            }
+            __syncthreads();
+            // flush the component and clear the accumulator for the next
+            T *dst = m < 3 ? ap.lE[m] : ap.lB[m - 3];
+            for (int r = tid; r < rfvol; r += nth) {
+                const T v = (T)sA[r];
+                sA[r] = 0.0;
+                if (v != T(0)) {
+                    const int gi = region_global(pc.n, ts.t0, tg.lo_f, r % rfx, (r / rfx) % rfy, r / (rfx * rfy));
+                    gatomic_add(dst + gi, v);
+                }
+            }
+            __syncthreads();
+        }
+    }
+}
+
+// ---------------------------------------------------------------------------
 // launchers
 
 static inline unsigned nblk(int64_t n, int b)
@@ -2045,8 +2259,29 @@ static hipError_t launch_adj_tile_o(const PConst<T> &pc, const TileGeo &tg, cons
                        f, ap, tile_start, err);
     hipLaunchKernelGGL((k_adjoint_push_strays<T, O>), dim3(ntiles), dim3(STRAY_THREADS), 0, st, pc, tg, sp, f, ap,
                        tile_start, err);
-    hipLaunchKernelGGL((k_adjoint_scatter_tile<T, O>), dim3(ntiles), dim3(nth), l2q, st, pc, tg, sp, f, ap,
-                       tile_start, qcap);
+    bool cells = false;
+    if constexpr (sizeof(T) == 4) {
+        // per-cell accumulation: one component's accumulators, the cell
+        // counts and starts, and the chunk's keys and lists, within half the
+        // LDS of a CU so that two workgroups share it
+        static bool a3 = false;
+        const size_t rf = (size_t)tg.rf[0] * tg.rf[1] * tg.rf[2];
+        const size_t tc = (size_t)tg.t[0] * tg.t[1] * tg.t[2];
+        const size_t fixed = rf * sizeof(double) + 4 * (2 * (tc + 1) + CELL_THREADS / 64 + 4);
+        const size_t half = 80 * 1024;
+        const size_t cap = fixed < half ? (half - fixed) / 8 : 0;
+        if (cap >= 1024) {
+            const int c = (int)(cap < 16384 ? cap : 16384);
+            const size_t l3 = fixed + 8 * (size_t)c;
+            allow_big_lds(&k_adjoint_scatter_cells<T, O>, a3);
+            hipLaunchKernelGGL((k_adjoint_scatter_cells<T, O>), dim3(ntiles), dim3(CELL_THREADS), l3, st, pc, tg, sp,
+                               ap, tile_start, c);
+            cells = true;
+        }
+    }
+    if (!cells)
+        hipLaunchKernelGGL((k_adjoint_scatter_tile<T, O>), dim3(ntiles), dim3(nth), l2q, st, pc, tg, sp, f, ap,
+                           tile_start, qcap);
     hipLaunchKernelGGL((k_adjoint_scatter_strays<T, O>), dim3(ntiles), dim3(STRAY_THREADS), 0, st, pc, tg, sp, f, ap,
                        tile_start);
     return hipGetLastError();
