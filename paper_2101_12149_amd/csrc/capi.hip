@@ -765,6 +765,11 @@ pic_status step_t(const pic_grid *g, const GridInfo &gi, pic_species *sp, pic_fi
         glist[b] = reinterpret_cast<int2 *>(w + L.glist + b * al(2 * sizeof(int) * (size_t)gi.ntiles * GUEST_CAP));
         gflag[b] = reinterpret_cast<unsigned char *>(w + L.gflag + b * al((size_t)(sp->n > 0 ? sp->n : 0)));
     }
+    // new offsets between the tile kernel's phases when it runs in place:
+    // the sorted copy's offset arrays, free on a step without a sort
+    T *scratch[3];
+    for (int d = 0; d < 3; ++d)
+        scratch[d] = reinterpret_cast<T *>(w + L.soff + d * al(gi.tsize * (size_t)(sp->n > 0 ? sp->n : 0)));
     PIC_HIP(launch_fill<int>(err, 1, 0, st));
     for (int d = 0; d < 3; ++d)
         PIC_HIP(launch_fill<T>(fp.J[d], gi.ncell, T(0), st));
@@ -801,14 +806,16 @@ pic_status step_t(const pic_grid *g, const GridInfo &gi, pic_species *sp, pic_fi
             }
             {
                 TimedScope ts(1, st);
-                PIC_HIP(launch_particles_tile<T>(gi.order, pc, gi.tg, sorted, user, fpp, tile_start, stray, ga, err, st));
+                PIC_HIP(launch_particles_tile<T>(gi.order, pc, gi.tg, sorted, user, fpp, tile_start, stray, ga, scratch,
+                                                 err, st));
             }
             TimedScope ts(6, st);
             PIC_HIP(launch_particles_strays<T>(gi.order, pc, gi.tg, sorted, user, fpp, tile_start, stray, ga, err, st));
         } else if (tile_start && sp->n > 0) {
             {
                 TimedScope ts(1, st);
-                PIC_HIP(launch_particles_tile<T>(gi.order, pc, gi.tg, user, user, fpp, tile_start, stray, ga, err, st));
+                PIC_HIP(launch_particles_tile<T>(gi.order, pc, gi.tg, user, user, fpp, tile_start, stray, ga, scratch,
+                                                 err, st));
             }
             TimedScope ts(6, st);
             PIC_HIP(launch_particles_strays<T>(gi.order, pc, gi.tg, user, user, fpp, tile_start, stray, ga, err, st));

@@ -322,7 +322,7 @@ __device__ __attribute__((always_inline)) inline void deposit_local_full(const P
 // w, or flags the error word and returns false for a displacement of a cell
 // or more.  With LOCAL the fields come from the LDS tile (positions l[]
 // relative to the tile), otherwise from global memory.
-template <typename T, int O, bool LOCAL>
+template <typename T, int O, bool LOCAL, bool WOFF = true>
 __device__ __attribute__((always_inline)) inline bool particle_advance(const PConst<T> &pc, const PArr<T> &in, const PArr<T> &out,
                                         const FieldSrc<T> &fsrc, int64_t p, const int *c, const T *f,
                                         const T *u, const int *l, int lo_f, const int *sf, T *f1, int *kap,
@@ -365,7 +365,8 @@ __device__ __attribute__((always_inline)) inline bool particle_advance(const PCo
 #pragma unroll
     for (int d = 0; d < 3; ++d) {
         out.cell[d][p] = wrap_once(c[d] + kap[d], pc.n[d]);
-        out.off[d][p] = f1[d];
+        if (WOFF)
+            out.off[d][p] = f1[d];
         out.u[d][p] = u1[d];
     }
     if (out.w && out.w != in.w)
@@ -782,6 +783,506 @@ __global__ void __launch_bounds__(TileThreads<T>::value) k_particles_tile(PConst
         if (v != T(0) && rx < rjx) {
             const int gi = region_global(pc.n, ts.t0, tg.lo_j, rx, (rr / jpx) % rjy, rr / (jpx * rjy));
             gatomic_add(fp.J[m] + gi, v);
+        }
+    }
+}
+
+// exclusive prefix sum of in[0..n) into out[0..n) by the whole workgroup;
+// sh: LDS scratch of blockDim.x / 64 + 1 ints
+__device__ inline void block_exclusive_scan(const int *in, int *out, int n, int *sh)
+{
+    const int tid = threadIdx.x, nth = blockDim.x, lane = tid & 63, wv = tid >> 6;
+    const int per = (n + nth - 1) / nth, b = tid * per, e = b + per < n ? b + per : n;
+    int sum = 0;
+    for (int i = b; i < e; ++i)
+        sum += in[i];
+    int incl = sum;
+    for (int off = 1; off < 64; off <<= 1) {
+        const int v = __shfl_up(incl, off, 64);
+        if (lane >= off)
+            incl += v;
+    }
+    if (lane == 63)
+        sh[wv] = incl;
+    __syncthreads();
+    if (tid == 0) {
+        int acc = 0;
+        for (int w = 0; w < nth / 64; ++w) {
+            const int v = sh[w];
+            sh[w] = acc;
+            acc += v;
+        }
+    }
+    __syncthreads();
+    int run = sh[wv] + incl - sum;
+    for (int i = b; i < e; ++i) {
+        const int v = in[i];
+        out[i] = run;
+        run += v;
+    }
+}
+
+// ---------------------------------------------------------------------------
+// The tile step in two phases, the deposit of the particles that stay in
+// their cells accumulated per cell.
+//
+// Phase A, one thread per particle (rank-major, coalesced): gather from the
+// LDS field tile, push, move; a particle that changed cells goes to the LDS
+// crossing queue (its full-window current is added per component in phase
+// B; when the queue is full, at once to global memory), one that stayed is
+// listed under its cell (an LDS counting sort: count per cell, scan, list)
+// and its new offsets go to `f1s` (the caller's offsets when the step does
+// not run in place, else scratch, since phase B still reads the old ones).
+//
+// Phase B, per current component: one thread per cell of the tile (two or
+// more per cell when the workgroup has more threads than the tile has
+// cells, each taking every second, ... particle of the list) sums its
+// particles' narrow-window Esirkepov values in registers and adds the sum
+// to the component's FP64 LDS accumulator once, with rows shared along the
+// tile's rows of cells; still particles in the slack cells and the queued
+// crossers follow one lane each; the component is flushed to global memory
+// (one atomic per non-zero value) before the next one reuses the
+// accumulator.  The per-particle values are those of the one-pass kernel
+// (formed in the working precision, summed in FP64 in the LDS); only the
+// order of the sums changes.  Particles are taken in chunks of `kc` (the
+// list capacity); each chunk runs both phases.
+
+template <typename T>
+struct Off3 {
+    T *o[3];
+};
+
+// LDS layout of k_particles_cells (byte offsets), shared by the launcher
+struct CellsLds {
+    size_t f, a, cnt, start, sh, keys, list, qf0, qf1, qj, qpk, qcnt, total;
+};
+
+__host__ __device__ inline CellsLds cells_lds(const TileGeo &tg, int nth, int kc, int tsize)
+{
+    auto al16 = [](size_t x) { return (x + 15) & ~size_t(15); };
+    const size_t rf = (size_t)tg.rf[0] * tg.rf[1] * tg.rf[2];
+    const size_t rj = (size_t)tg.jp * tg.rj[1] * tg.rj[2];
+    const size_t tc = (size_t)tg.t[0] * tg.t[1] * tg.t[2];
+    CellsLds L;
+    size_t o = 0;
+    L.f = o;
+    o = al16(o + 6 * rf * tsize);
+    L.a = o;
+    o = al16(o + rj * sizeof(double));
+    L.qf0 = o;
+    o = al16(o + 3 * (size_t)tg.qcap * tsize);
+    L.qf1 = o;
+    o = al16(o + 3 * (size_t)tg.qcap * tsize);
+    L.cnt = o;
+    o += 4 * (tc + 1);
+    L.start = o;
+    o += 4 * (tc + 1);
+    L.sh = o;
+    o += 4 * ((size_t)nth / 64 + 4);
+    L.keys = o;
+    o += 4 * (size_t)kc;
+    L.list = o;
+    o += 4 * (size_t)kc;
+    L.qj = o;
+    o += 4 * (size_t)tg.qcap;
+    L.qpk = o;
+    o += 4 * (size_t)tg.qcap;
+    L.qcnt = o;
+    o += 16;
+    L.total = o;
+    return L;
+}
+
+// particle index of entry j of a tile's chunk list: own particles first,
+// then the tile's guests
+__device__ __attribute__((always_inline)) inline int64_t tile_particle(const TileSpan &ts, const GuestArgs &g, int np,
+                                                                       int j)
+{
+    return j < np ? ts.ps + j : (int64_t)g.list[(int64_t)ts.t * g.cap + (j - np)].x;
+}
+
+// Narrow-window Esirkepov values of component M of a particle that stays in
+// its cell, as rows along x: v(kz, ky, ix) for ix < NX, ky < RY, kz < RZ,
+// passed to add(kz, ky, ix, value) (esk_scatter_still's values, regrouped).
+template <typename T, int O, int M>
+struct StillRows {
+    static constexpr int NW = Shape<O, T>::NW;
+    static constexpr int NX = M == 0 ? NW - 1 : NW;
+    static constexpr int RY = M == 1 ? NW - 1 : NW;
+    static constexpr int RZ = M == 2 ? NW - 1 : NW;
+    template <typename AddFn>
+    __device__ __attribute__((always_inline)) static inline void apply(const PConst<T> &pc, const T *f0, const T *f1,
+                                                                       T w, AddFn &&add)
+    {
+        const T half = T(0.5), third = T(1) / T(3);
+        T S0[3][NW], DS[3][NW];
+#pragma unroll
+        for (int d = 0; d < 3; ++d)
+            esk_axis_still<O>(f0[d], f1[d], S0[d], DS[d]);
+        T P[NW - 1];
+        {
+            const T K = pc.jk[M] * w;
+            T run = T(0);
+#pragma unroll
+            for (int a = 0; a < NW - 1; ++a) {
+                run += DS[M][a];
+                P[a] = K * run;
+            }
+        }
+        // C for (p, q) at (b, c): S0p (S0q + DSq/2) + DSp (S0q/2 + DSq/3)
+        auto cw = [&](int pp, int qq, int b, int c) -> T {
+            return S0[pp][b] * (S0[qq][c] + half * DS[qq][c]) + DS[pp][b] * (half * S0[qq][c] + third * DS[qq][c]);
+        };
+        if constexpr (M == 0) {
+#pragma unroll
+            for (int c = 0; c < NW; ++c)
+#pragma unroll
+                for (int b = 0; b < NW; ++b) {
+                    const T C = cw(1, 2, b, c);
+#pragma unroll
+                    for (int a = 0; a < NW - 1; ++a)
+                        add(c, b, a, P[a] * C);
+                }
+        } else if constexpr (M == 1) {
+#pragma unroll
+            for (int b = 0; b < NW; ++b)
+#pragma unroll
+                for (int a = 0; a < NW - 1; ++a)
+#pragma unroll
+                    for (int c = 0; c < NW; ++c)
+                        add(b, a, c, P[a] * cw(2, 0, b, c));
+        } else {
+#pragma unroll
+            for (int a = 0; a < NW - 1; ++a)
+#pragma unroll
+                for (int c = 0; c < NW; ++c)
+#pragma unroll
+                    for (int b = 0; b < NW; ++b)
+                        add(a, c, b, P[a] * cw(0, 1, b, c));
+        }
+    }
+};
+
+// Esirkepov full-window current of component M into the component's LDS
+// accumulator
+template <typename T, int O, int M>
+__device__ __attribute__((always_inline)) inline void deposit_local_comp(const PConst<T> &pc, const T *f0, const T *f1,
+                                                                         const int *kap, const int *l, int lo_j,
+                                                                         const int *sj, T w, double *sA)
+{
+    constexpr int NW = Shape<O, T>::NW;
+    EskAxis<O, T> e[3];
+    T K[3];
+    int jo[3][NW + 1];
+#pragma unroll
+    for (int d = 0; d < 3; ++d) {
+        esk_axis<O>(f0[d], f1[d], kap[d], e[d]);
+        K[d] = pc.jk[d] * w;
+        axis_offsets_local<NW + 1>(l[d] + lo_j, e[d].lo, sj[d], jo[d]);
+    }
+    esk_scatter<O, T, double, M>(e, jo, K, [&](int, int idx, double v) { latomic_add(sA + idx, v); });
+}
+
+// Esirkepov full-window current straight into global memory (a crosser
+// that found the queue full)
+template <typename T, int O>
+__device__ __attribute__((always_inline)) inline void deposit_global_full(const PConst<T> &pc, const FieldPtrs<T> &fp,
+                                                                          const int *c, const T *f0, const T *f1,
+                                                                          const int *kap, T w)
+{
+    constexpr int NW = Shape<O, T>::NW;
+    const int gs[3] = {1, pc.n[0], pc.n[0] * pc.n[1]};
+    EskAxis<O, T> e[3];
+    T K[3];
+    int jo[3][NW + 1];
+#pragma unroll
+    for (int d = 0; d < 3; ++d) {
+        esk_axis<O>(f0[d], f1[d], kap[d], e[d]);
+        K[d] = pc.jk[d] * w;
+        axis_offsets_global<NW + 1>(c[d], e[d].lo, pc.n[d], gs[d], jo[d]);
+    }
+    esk_scatter<O, T, T>(e, jo, K, [&](int m, int idx, T v) { gatomic_add(fp.J[m] + idx, v); });
+}
+
+// Phase B for component M: the per-cell sums of the listed still particles,
+// the still particles of the slack cells, the queued crossers; `last`
+// copies the new offsets of the listed particles from scratch to `out`.
+template <typename T, int O, int M>
+__device__ __attribute__((always_inline)) inline void cells_component(
+    const PConst<T> &pc, const TileGeo &tg, const TileSpan &ts, const GuestArgs &g, int np, const PArr<T> &in,
+    const PArr<T> &out, const Off3<T> &f1s, const int *list, const int *cstart, const int *ccnt, int tc,
+    const CrossQueue<T> &cq, int nq, double *sA, const int *sj, bool last, int groups)
+{
+    using R = StillRows<T, O, M>;
+    constexpr int NB = Shape<O, T>::NB;
+    const int nth = blockDim.x, tid = threadIdx.x;
+    const bool copy = last && f1s.o[0] != out.off[0];
+    for (int lc0 = 0; lc0 < tc; lc0 += nth) {
+        const int part = tc < nth ? tid / tc : 0;
+        const int lc = lc0 + (tc < nth ? tid % tc : tid);
+        const bool cell = part < groups && lc < tc;   // groups * tc <= nth
+        int l[3] = {0, 0, 0}, s = 0, k = 0;
+        if (cell) {
+            l[0] = lc % tg.t[0];
+            l[1] = (lc / tg.t[0]) % tg.t[1];
+            l[2] = lc / (tg.t[0] * tg.t[1]);
+            s = cstart[lc];
+            k = ccnt[lc];
+        }
+        T acc[R::RZ][R::RY][R::NX];
+#pragma unroll
+        for (int c = 0; c < R::RZ; ++c)
+#pragma unroll
+            for (int b = 0; b < R::RY; ++b)
+#pragma unroll
+                for (int a = 0; a < R::NX; ++a)
+                    acc[c][b][a] = T(0);
+        // the next particle's loads are issued before this one's arithmetic
+        int64_t pn = 0;
+        T f0n[3] = {T(0), T(0), T(0)}, f1n[3] = {T(0), T(0), T(0)}, wn = pc.w0;
+        if (part < k) {
+            pn = tile_particle(ts, g, np, list[s + part]);
+#pragma unroll
+            for (int d = 0; d < 3; ++d) {
+                f0n[d] = in.off[d][pn];
+                f1n[d] = f1s.o[d][pn];
+            }
+            if (in.w)
+                wn = in.w[pn];
+        }
+        for (int i = part; i < k; i += groups) {
+            const int64_t p = pn;
+            const T f0[3] = {f0n[0], f0n[1], f0n[2]}, f1[3] = {f1n[0], f1n[1], f1n[2]}, w = wn;
+            if (i + groups < k) {
+                pn = tile_particle(ts, g, np, list[s + i + groups]);
+#pragma unroll
+                for (int d = 0; d < 3; ++d) {
+                    f0n[d] = in.off[d][pn];
+                    f1n[d] = f1s.o[d][pn];
+                }
+                if (in.w)
+                    wn = in.w[pn];
+            }
+            R::apply(pc, f0, f1, w, [&](int c, int b, int a, T v) { acc[c][b][a] += v; });
+            if (copy) {
+#pragma unroll
+                for (int d = 0; d < 3; ++d)
+                    out.off[d][p] = f1[d];
+            }
+        }
+        // the wave is converged here: runs of consecutive cells along x
+        const XRun xr = xrun(cell ? xrun_key(l) : 0);
+        if (__ballot(k > part) != 0 && cell) {
+            const int x0 = l[0] + tg.lo_j + NB, y0 = l[1] + tg.lo_j + NB, z0 = l[2] + tg.lo_j + NB;
+#pragma unroll
+            for (int c = 0; c < R::RZ; ++c)
+#pragma unroll
+                for (int b = 0; b < R::RY; ++b)
+                    xrow_add<R::NX>(sA + x0 + sj[1] * (y0 + b) + sj[2] * (z0 + c), acc[c][b], xr);
+        }
+    }
+    // still particles of the slack cells, one lane each
+    const int no = ccnt[tc], so = cstart[tc];
+    for (int i = tid; i < no; i += nth) {
+        const int64_t p = tile_particle(ts, g, np, list[so + i]);
+        int c[3], l[3];
+        T f0[3], f1[3];
+#pragma unroll
+        for (int d = 0; d < 3; ++d) {
+            c[d] = in.cell[d][p];
+            f0[d] = in.off[d][p];
+            f1[d] = f1s.o[d][p];
+        }
+        tile_local(tg, pc.n, ts.t0, c, l);
+        const T w = in.w ? in.w[p] : pc.w0;
+        const int x0 = l[0] + tg.lo_j + NB, y0 = l[1] + tg.lo_j + NB, z0 = l[2] + tg.lo_j + NB;
+        R::apply(pc, f0, f1, w, [&](int cc, int b, int a, T v) {
+            latomic_add(sA + x0 + a + sj[1] * (y0 + b) + sj[2] * (z0 + cc), (double)v);
+        });
+        if (copy) {
+#pragma unroll
+            for (int d = 0; d < 3; ++d)
+                out.off[d][p] = f1[d];
+        }
+    }
+    // the queued crossers of this chunk, one lane each
+    for (int k = tid; k < nq; k += nth) {
+        const int64_t p = ts.ps + cq.j[k];
+        int l[3], kap[3];
+        CrossQueue<T>::unpack(cq.pk[k], l, kap);
+        T f0[3], f1[3];
+#pragma unroll
+        for (int d = 0; d < 3; ++d) {
+            f0[d] = cq.f0[d * cq.cap + k];
+            f1[d] = cq.f1[d * cq.cap + k];
+        }
+        const T w = in.w ? in.w[p] : pc.w0;
+        deposit_local_comp<T, O, M>(pc, f0, f1, kap, l, tg.lo_j, sj, w, sA);
+    }
+}
+
+template <typename T, int O, bool G>
+__global__ void __launch_bounds__(TileThreads<T>::value) k_particles_cells(PConst<T> pc, TileGeo tg, PArr<T> in,
+                                                                           PArr<T> out, FieldPtrs<T> fp,
+                                                                           const int *__restrict__ tile_start,
+                                                                           unsigned char *__restrict__ stray,
+                                                                           GuestArgs g, Off3<T> f1s, int kc,
+                                                                           int *err)
+{
+    extern __shared__ __align__(16) unsigned char smem_raw[];
+    const int tid = threadIdx.x, nth = blockDim.x;
+    const CellsLds Ld = cells_lds(tg, nth, kc, (int)sizeof(T));
+    T *sF = reinterpret_cast<T *>(smem_raw + Ld.f);
+    double *sA = reinterpret_cast<double *>(smem_raw + Ld.a);
+    int *ccnt = reinterpret_cast<int *>(smem_raw + Ld.cnt);
+    int *cstart = reinterpret_cast<int *>(smem_raw + Ld.start);
+    int *sh = reinterpret_cast<int *>(smem_raw + Ld.sh);
+    int *keys = reinterpret_cast<int *>(smem_raw + Ld.keys);
+    int *list = reinterpret_cast<int *>(smem_raw + Ld.list);
+    CrossQueue<T> cq;
+    cq.cap = tg.qcap;
+    cq.f0 = reinterpret_cast<T *>(smem_raw + Ld.qf0);
+    cq.f1 = reinterpret_cast<T *>(smem_raw + Ld.qf1);
+    cq.j = reinterpret_cast<int *>(smem_raw + Ld.qj);
+    cq.pk = reinterpret_cast<int *>(smem_raw + Ld.qpk);
+    cq.cnt = reinterpret_cast<int *>(smem_raw + Ld.qcnt);
+    const int rfx = tg.rf[0], rfy = tg.rf[1];
+    const int rfvol = rfx * rfy * tg.rf[2];
+    const int rjx = tg.rj[0], rjy = tg.rj[1], jpx = tg.jp;
+    const int rjvol = jpx * rjy * tg.rj[2];
+    const int tc = tg.t[0] * tg.t[1] * tg.t[2];
+    const TileSpan ts = tile_span(tg, tile_start, in.n);
+    const int ng = (G && g.cnt) ? (g.cnt[ts.t] < g.cap ? g.cnt[ts.t] : g.cap) : 0;
+    if (ts.pe <= ts.ps && ng == 0)
+        return;   // uniform across the workgroup
+    for (int r = tid; r < rfvol; r += nth) {
+        const int gi = region_global(pc.n, ts.t0, tg.lo_f, r % rfx, (r / rfx) % rfy, r / (rfx * rfy));
+#pragma unroll
+        for (int m = 0; m < 3; ++m) {
+            sF[m * rfvol + r] = fp.E[m][gi];
+            sF[(3 + m) * rfvol + r] = fp.B[m][gi];
+        }
+    }
+    for (int r = tid; r < rjvol; r += nth)
+        sA[r] = 0.0;
+    FieldSrc<T> lf;
+#pragma unroll
+    for (int m = 0; m < 6; ++m)
+        lf.c[m] = sF + m * rfvol;
+    const int sf[3] = {1, rfx, rfx * rfy};
+    const int sj[3] = {1, jpx, jpx * rjy};
+    const int np = (int)(ts.pe - ts.ps);
+    for (int jb = 0; jb < np + ng; jb += kc) {
+        const int je = np + ng < jb + kc ? np + ng : jb + kc;
+        for (int i = tid; i <= tc; i += nth)
+            ccnt[i] = 0;
+        if (tid == 0)
+            *cq.cnt = 0;
+        __syncthreads();   // also: the field tile is staged
+        // phase A
+        for (int j = jb + tid; j < je; j += nth) {
+            int key = -1;
+            const bool own = j < np;
+            int64_t p = ts.ps + j;
+            int home = ts.t;
+            if (!own) {
+                const int2 e = g.list[(int64_t)ts.t * g.cap + (j - np)];
+                p = e.x;
+                home = e.y;
+            }
+            int c[3], l[3];
+            T f[3], u[3], f1[3], w = T(0);
+            unsigned char st = 0, gn = 0;
+            bool moved = true;
+            if (G && own && g.flag && g.flag[p]) {
+                // a guest of another tile this step: that tile moves it
+                moved = false;
+            } else if (!load_particle(in, p, pc.n, c, f, u, err)) {
+                copy_particle(in, out, p);
+            } else if (!tile_local(tg, pc.n, ts.t0, c, l)) {
+                if (own) {
+                    moved = false;
+                    st = 1;
+                } else {
+                    atomicOr(err, 2);
+                    copy_particle(in, out, p);
+                }
+            } else {
+                int kap[3];
+                if (particle_advance<T, O, true, false>(pc, in, out, lf, p, c, f, u, l, tg.lo_f, sf, f1, kap, w, err)) {
+                    if ((kap[0] | kap[1] | kap[2]) == 0) {
+#pragma unroll
+                        for (int d = 0; d < 3; ++d)
+                            f1s.o[d][p] = f1[d];
+                        const bool in_tile = l[0] >= 0 && l[0] < tg.t[0] && l[1] >= 0 && l[1] < tg.t[1] &&
+                                             l[2] >= 0 && l[2] < tg.t[2];
+                        const int slot = in_tile ? l[0] + tg.t[0] * (l[1] + tg.t[1] * l[2]) : tc;
+                        key = (slot << 16) | atomicAdd(ccnt + slot, 1);
+                    } else {
+#pragma unroll
+                        for (int d = 0; d < 3; ++d)
+                            out.off[d][p] = f1[d];
+                        if (!cq.push((int)(p - ts.ps), l, kap, f, f1))
+                            deposit_global_full<T, O>(pc, fp, c, f, f1, kap, w);
+                    }
+                    if (G && ((kap[0] | kap[1] | kap[2]) || !own)) {
+                        int c1[3], ht0[3] = {ts.t0[0], ts.t0[1], ts.t0[2]};
+#pragma unroll
+                        for (int d = 0; d < 3; ++d)
+                            c1[d] = wrap_any(c[d] + kap[d], pc.n[d]);
+                        if (!own)
+                            tile_origin(tg, home, ht0);
+                        gn = guest_next(g, tg, pc.n, p, home, ht0, c1);
+                    }
+                }
+            }
+            if (own)
+                stray[p] = st;
+            if (G && moved)
+                g.flag_next[p] = gn;
+            keys[j - jb] = key;
+        }
+        __syncthreads();
+        block_exclusive_scan(ccnt, cstart, tc + 1, sh);
+        __syncthreads();
+        for (int j = jb + tid; j < je; j += nth) {
+            const int key = keys[j - jb];
+            if (key >= 0)
+                list[cstart[key >> 16] + (key & 0xffff)] = j;
+        }
+        __syncthreads();
+        // phase B
+        const int nq = *cq.cnt < cq.cap ? *cq.cnt : cq.cap;
+        // threads per cell: each adds its sum with a row update per cell, so
+        // a second thread per cell pays only from about 6 particles per cell
+        // on (the chunk's count over 4 per cell, rounded)
+        int groups = 1;
+        if (tc < nth) {
+            const int dense = (je - jb + 2 * tc) / (4 * tc);
+            groups = nth / tc < dense ? nth / tc : (dense > 1 ? dense : 1);
+        }
+#pragma unroll
+        for (int m = 0; m < 3; ++m) {
+            if (m == 0)
+                cells_component<T, O, 0>(pc, tg, ts, g, np, in, out, f1s, list, cstart, ccnt, tc, cq, nq, sA, sj, false,
+                                         groups);
+            else if (m == 1)
+                cells_component<T, O, 1>(pc, tg, ts, g, np, in, out, f1s, list, cstart, ccnt, tc, cq, nq, sA, sj, false,
+                                         groups);
+            else
+                cells_component<T, O, 2>(pc, tg, ts, g, np, in, out, f1s, list, cstart, ccnt, tc, cq, nq, sA, sj, true,
+                                         groups);
+            __syncthreads();
+            for (int r = tid; r < rjvol; r += nth) {
+                const T v = (T)sA[r];
+                sA[r] = 0.0;
+                const int rx = r % jpx;
+                if (v != T(0) && rx < rjx) {
+                    const int gi = region_global(pc.n, ts.t0, tg.lo_j, rx, (r / jpx) % rjy, r / (jpx * rjy));
+                    gatomic_add(fp.J[m] + gi, v);
+                }
+            }
+            __syncthreads();
         }
     }
 }
@@ -1853,41 +2354,6 @@ __global__ void __launch_bounds__(AdjThreads<T>::value) k_adjoint_scatter_tile(P
 // accumulator, so the LDS holds one component at a time.
 constexpr int CELL_THREADS = 512;
 
-// exclusive prefix sum of in[0..n) into out[0..n) by the whole workgroup;
-// sh: LDS scratch of blockDim.x / 64 + 1 ints
-__device__ inline void block_exclusive_scan(const int *in, int *out, int n, int *sh)
-{
-    const int tid = threadIdx.x, nth = blockDim.x, lane = tid & 63, wv = tid >> 6;
-    const int per = (n + nth - 1) / nth, b = tid * per, e = b + per < n ? b + per : n;
-    int sum = 0;
-    for (int i = b; i < e; ++i)
-        sum += in[i];
-    int incl = sum;
-    for (int off = 1; off < 64; off <<= 1) {
-        const int v = __shfl_up(incl, off, 64);
-        if (lane >= off)
-            incl += v;
-    }
-    if (lane == 63)
-        sh[wv] = incl;
-    __syncthreads();
-    if (tid == 0) {
-        int acc = 0;
-        for (int w = 0; w < nth / 64; ++w) {
-            const int v = sh[w];
-            sh[w] = acc;
-            acc += v;
-        }
-    }
-    __syncthreads();
-    int run = sh[wv] + incl - sum;
-    for (int i = b; i < e; ++i) {
-        const int v = in[i];
-        out[i] = run;
-        run += v;
-    }
-}
-
 // One component (staggering SX, SY, SZ) of the per-cell scatter into the
 // LDS accumulator sA, then its slack-cell particles one lane each.
 template <typename T, int O, int SX, int SY, int SZ>
@@ -1917,13 +2383,28 @@ __device__ __attribute__((always_inline)) inline void cell_scatter_component(
 #pragma unroll
                 for (int a = 0; a < NX; ++a)
                     acc[c][b][a] = T(0);
+        // the next particle's loads are issued before this one's arithmetic
+        T fn[3] = {T(0), T(0), T(0)}, vn = T(0);
+        if (k > 0) {
+            const int64_t p = ts.ps + list[s];
+#pragma unroll
+            for (int d = 0; d < 3; ++d)
+                fn[d] = sp.off[d][p];
+            vn = vbm[p];
+        }
         for (int i = 0; i < k; ++i) {
-            const int64_t p = ts.ps + list[s + i];
+            const T f[3] = {fn[0], fn[1], fn[2]}, v = vn;
+            if (i + 1 < k) {
+                const int64_t p = ts.ps + list[s + i + 1];
+#pragma unroll
+                for (int d = 0; d < 3; ++d)
+                    fn[d] = sp.off[d][p];
+                vn = vbm[p];
+            }
             AxisW<O, T> aw[3];
 #pragma unroll
             for (int d = 0; d < 3; ++d)
-                axis_weights<O>(sp.off[d][p], aw[d]);
-            const T v = vbm[p];
+                axis_weights<O>(f[d], aw[d]);
             T wx[NX], wy[NY], wz[NZ];
             scatter_axis<O, T, SX, SM_WIDE>(aw[0], wx);
             scatter_axis<O, T, SY, SM_WIDE>(aw[1], wy);
@@ -2072,14 +2553,65 @@ static void allow_big_lds(K *kernel, bool &done)
     }
 }
 
+// the two-phase tile kernel's queue entries and the list capacity left by
+// its LDS; 0 when the list would hold fewer than 1024 particles
+template <typename T>
+int cells_chunk(const TileGeo &tg, TileGeo &tq)
+{
+    tq = tg;
+    tq.qcap = sizeof(T) == 4 ? 512 : 256;
+    const size_t fixed = cells_lds(tq, TileThreads<T>::value, 0, (int)sizeof(T)).total;
+    const size_t limit = 160 * 1024;
+    if (fixed >= limit)
+        return 0;
+    const size_t kc = (limit - fixed) / 8;
+    if (kc < 1024)
+        return 0;
+    return (int)(kc < 16384 ? kc : 16384);
+}
+
 template <typename T, int O>
 static hipError_t launch_tile_o(const PConst<T> &pc, const TileGeo &tg, const PArr<T> &in, const PArr<T> &out,
                                 const FieldPtrs<T> &f, const int *tile_start, unsigned char *stray,
-                                const GuestArgs &g, int *err, hipStream_t st)
+                                const GuestArgs &g, T *const scratch[3], int *err, hipStream_t st)
 {
-    static bool attr_plain = false, attr_guests = false;
-    const size_t lds = tile_lds_bytes<T>(O, tg);
+    static bool attr_plain = false, attr_guests = false, attr_cp = false, attr_cg = false;
     const unsigned ntiles = (unsigned)(tg.nt[0] * tg.nt[1] * tg.nt[2]);
+    // The per-cell deposit pays where cells hold many particles, which share
+    // one row update per cell, and where the deposit is the wide order-3
+    // window in FP32: 256^3, 8 per cell, 21.2 -> 16.6 ms.  It loses at low
+    // densities (the laser box, 2 per cell: 4.65 -> 5.0 ms; 512^3, 2 per
+    // cell: 76.4 -> 78.2 ms), at order 1 (32^3 FP64: 0.049 -> 0.069 ms) and
+    // in FP64 (213 registers: 31.0 against 30.9 ms at 256^3, 0.35 -> 0.38 ms
+    // at 64^3 / 4 per cell).
+    if constexpr (sizeof(T) == 4 && O == 3) {
+        const int64_t ncell = (int64_t)tg.nt[0] * tg.t[0] * tg.nt[1] * tg.t[1] * tg.nt[2] * tg.t[2];
+        TileGeo tq;
+        const int kc = cells_chunk<T>(tg, tq);
+        if (kc > 0 && in.n >= 6 * ncell) {
+            // the new offsets of the particles that stay in their cells wait
+            // in scratch when the step runs in place
+            Off3<T> f1s;
+            for (int d = 0; d < 3; ++d)
+                f1s.o[d] = in.off[d] == out.off[d] ? scratch[d] : out.off[d];
+            const size_t l = cells_lds(tq, TileThreads<T>::value, kc, (int)sizeof(T)).total;
+            if (g.flag_next) {
+                allow_big_lds(&k_particles_cells<T, O, true>, attr_cg);
+                hipLaunchKernelGGL((k_particles_cells<T, O, true>), dim3(ntiles), dim3(TileThreads<T>::value), l, st,
+                                   pc, tq, in, out, f, tile_start, stray, g, f1s, kc, err);
+            } else {
+                allow_big_lds(&k_particles_cells<T, O, false>, attr_cp);
+                hipLaunchKernelGGL((k_particles_cells<T, O, false>), dim3(ntiles), dim3(TileThreads<T>::value), l, st,
+                                   pc, tq, in, out, f, tile_start, stray, g, f1s, kc, err);
+            }
+            return hipGetLastError();
+        }
+    } else {
+        (void)scratch;
+        (void)attr_cp;
+        (void)attr_cg;
+    }
+    const size_t lds = tile_lds_bytes<T>(O, tg);
     if (g.flag_next) {
         allow_big_lds(&k_particles_tile<T, O, true>, attr_guests);
         hipLaunchKernelGGL((k_particles_tile<T, O, true>), dim3(ntiles), dim3(TileThreads<T>::value), lds, st, pc, tg,
@@ -2095,10 +2627,11 @@ static hipError_t launch_tile_o(const PConst<T> &pc, const TileGeo &tg, const PA
 template <typename T>
 hipError_t launch_particles_tile(int order, const PConst<T> &pc, const TileGeo &tg, const PArr<T> &in,
                                  const PArr<T> &out, const FieldPtrs<T> &f, const int *tile_start,
-                                 unsigned char *stray, const GuestArgs &g, int *err, hipStream_t st)
+                                 unsigned char *stray, const GuestArgs &g, T *const scratch[3], int *err,
+                                 hipStream_t st)
 {
-    return order == 1 ? launch_tile_o<T, 1>(pc, tg, in, out, f, tile_start, stray, g, err, st)
-                      : launch_tile_o<T, 3>(pc, tg, in, out, f, tile_start, stray, g, err, st);
+    return order == 1 ? launch_tile_o<T, 1>(pc, tg, in, out, f, tile_start, stray, g, scratch, err, st)
+                      : launch_tile_o<T, 3>(pc, tg, in, out, f, tile_start, stray, g, scratch, err, st);
 }
 
 template <typename T>
@@ -2310,7 +2843,8 @@ hipError_t launch_adjoint_tile(int order, const PConst<T> &pc, const TileGeo &tg
     template size_t tile_lds_bytes<T>(int, const TileGeo &);                                                       \
     template hipError_t launch_particles_tile<T>(int, const PConst<T> &, const TileGeo &, const PArr<T> &,         \
                                                  const PArr<T> &, const FieldPtrs<T> &, const int *,               \
-                                                 unsigned char *, const GuestArgs &, int *, hipStream_t);          \
+                                                 unsigned char *, const GuestArgs &, T *const[3], int *,           \
+                                                 hipStream_t);                                                     \
     template hipError_t launch_particles_strays<T>(int, const PConst<T> &, const TileGeo &, const PArr<T> &,       \
                                                    const PArr<T> &, const FieldPtrs<T> &, const int *,             \
                                                    const unsigned char *, const GuestArgs &, int *, hipStream_t);                     \

@@ -96,11 +96,14 @@ struct GuestArgs {
 // launchers (return hipSuccess or the launch error)
 
 // stray: per-particle scratch (uint8[n]) marking the particles that the tile
-// kernel leaves to the stray kernel
+// kernel leaves to the stray kernel; scratch: three T[n] arrays that hold
+// new offsets between the kernel's two phases when in and out are the same
+// arrays
 template <typename T>
 hipError_t launch_particles_tile(int order, const PConst<T> &pc, const TileGeo &tg, const PArr<T> &in,
                                  const PArr<T> &out, const FieldPtrs<T> &f, const int *tile_start,
-                                 unsigned char *stray, const GuestArgs &g, int *err, hipStream_t st);
+                                 unsigned char *stray, const GuestArgs &g, T *const scratch[3], int *err,
+                                 hipStream_t st);
 // the particles the tile kernel marked in `stray`, on global memory
 template <typename T>
 hipError_t launch_particles_strays(int order, const PConst<T> &pc, const TileGeo &tg, const PArr<T> &in,
