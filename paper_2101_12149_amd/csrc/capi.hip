@@ -751,9 +751,10 @@ pic_status step_t(const pic_grid *g, const GridInfo &gi, pic_species *sp, pic_fi
     const PArr<T> user = parr<T>(sp);
     // the fields the particle kernels gather from (filtered copies with a filter)
     const FieldPtrs<T> fpp = gather_view<T>(gi, fp, w, L);
-    // per-particle stray marks of the tile kernels, in the sort's key buffer
-    // (free once the sort of the step is done)
-    unsigned char *stray = reinterpret_cast<unsigned char *>(w + L.key);
+    // the list of the tile kernels' strays, in the sort's rank buffer (free
+    // once the sort of the step is done), and its count
+    int *stray_list = reinterpret_cast<int *>(w + L.rank);
+    int *stray_cnt = reinterpret_cast<int *>(w + L.err + 64);
     // guest buffers by step parity: the lists a step builds are the next
     // step's; none are read at the first step of a call or after a sort
     // (a sort renumbers the particles)
@@ -806,19 +807,19 @@ pic_status step_t(const pic_grid *g, const GridInfo &gi, pic_species *sp, pic_fi
             }
             {
                 TimedScope ts(1, st);
-                PIC_HIP(launch_particles_tile<T>(gi.order, pc, gi.tg, sorted, user, fpp, tile_start, stray, ga, scratch,
-                                                 err, st));
+                PIC_HIP(launch_particles_tile<T>(gi.order, pc, gi.tg, sorted, user, fpp, tile_start, stray_list,
+                                                 stray_cnt, ga, scratch, err, st));
             }
             TimedScope ts(6, st);
-            PIC_HIP(launch_particles_strays<T>(gi.order, pc, gi.tg, sorted, user, fpp, tile_start, stray, ga, err, st));
+            PIC_HIP(launch_particles_strays<T>(gi.order, pc, sorted, user, fpp, stray_list, stray_cnt, ga, err, st));
         } else if (tile_start && sp->n > 0) {
             {
                 TimedScope ts(1, st);
-                PIC_HIP(launch_particles_tile<T>(gi.order, pc, gi.tg, user, user, fpp, tile_start, stray, ga, scratch,
-                                                 err, st));
+                PIC_HIP(launch_particles_tile<T>(gi.order, pc, gi.tg, user, user, fpp, tile_start, stray_list,
+                                                 stray_cnt, ga, scratch, err, st));
             }
             TimedScope ts(6, st);
-            PIC_HIP(launch_particles_strays<T>(gi.order, pc, gi.tg, user, user, fpp, tile_start, stray, ga, err, st));
+            PIC_HIP(launch_particles_strays<T>(gi.order, pc, user, user, fpp, stray_list, stray_cnt, ga, err, st));
         } else {
             TimedScope ts(1, st);
             PIC_HIP(launch_particles_global<T>(gi.order, pc, user, fpp, err, st));
@@ -952,7 +953,8 @@ pic_status adjoint_t(const pic_grid *g, const GridInfo &gi, const pic_species *s
         }
         if (tile_start && tiled_ok)
             PIC_HIP(launch_adjoint_tile<T>(gi.order, pc, adjoint_geo(gi), parr<T>(sp), fpv, hat, lx, lu, glE, glB,
-                                           vb, tile_start, err, st));
+                                           vb, tile_start, reinterpret_cast<int *>(w + L.rank),
+                                           reinterpret_cast<int *>(w + L.err + 64), err, st));
         else
             PIC_HIP(launch_adjoint_particles<T>(gi.order, pc, parr<T>(sp), fpv, hat, lx, lu, glE, glB, vb, tile_start,
                                                 gi.ntiles, err, st));

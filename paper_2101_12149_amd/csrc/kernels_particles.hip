@@ -226,6 +226,34 @@ __device__ inline int collect_strays(const TileSpan &ts, int j0, int *list, int 
     return k;
 }
 
+// A list of strays on the device, appended to by the tile kernels (one
+// atomic per wave) and worked through by the stray kernels; cnt is cleared
+// before the tile kernel runs.  cap >= the particle count.
+struct StrayList {
+    int *p;
+    int *cnt;
+    int cap;
+};
+
+// appends p for every lane with `want`; call with the whole wave converged
+__device__ inline void stray_append(bool want, int p, const StrayList &sl)
+{
+    const int lane = threadIdx.x & 63;
+    const unsigned long long m = __ballot(want);
+    if (m == 0)
+        return;   // uniform across the wave
+    const int leader = __ffsll((long long)m) - 1;
+    int base = 0;
+    if (lane == leader)
+        base = atomicAdd(sl.cnt, __popcll(m));
+    base = __shfl(base, leader);
+    if (want) {
+        const int i = base + __popcll(m & ((1ull << lane) - 1ull));
+        if (i < sl.cap)
+            sl.p[i] = p;
+    }
+}
+
 // stray test from the cell (for kernels that do not move particles); an
 // invalid cell is not a stray, the tile kernel flags it
 template <typename T>
@@ -629,13 +657,13 @@ __device__ __attribute__((always_inline)) inline void deposit_still_shared(const
 }
 
 // ---------------------------------------------------------------------------
-// stray[p] records whether particle p was left to k_particles_strays: when
-// the step runs in place the cells are overwritten, so the stray kernel
-// cannot tell the strays from the cells any more.
+// The particles left to k_particles_strays are listed (`strays`) before they
+// move: when the step runs in place their cells are overwritten, so the
+// stray kernel could not tell them from the cells any more.
 template <typename T, int O, bool G>
 __global__ void __launch_bounds__(TileThreads<T>::value) k_particles_tile(PConst<T> pc, TileGeo tg, PArr<T> in, PArr<T> out,
                                                         FieldPtrs<T> fp, const int *__restrict__ tile_start,
-                                                        unsigned char *__restrict__ stray, GuestArgs g, int *err)
+                                                        StrayList strays, GuestArgs g, int *err)
 {
     extern __shared__ __align__(16) unsigned char smem_raw[];
     T *sF = reinterpret_cast<T *>(smem_raw);
@@ -691,6 +719,8 @@ __global__ void __launch_bounds__(TileThreads<T>::value) k_particles_tile(PConst
         int key = 0;   // non-zero: a particle that stays in its cell, deposited below
         int l[3] = {0, 0, 0};
         T f[3] = {T(0), T(0), T(0)}, f1[3] = {T(0), T(0), T(0)}, w = T(0);
+        bool is_stray = false;
+        int pst = 0;
         if (j < np + ng) {
             const bool own = j < np;
             int64_t p = ts.ps + j;
@@ -741,12 +771,13 @@ __global__ void __launch_bounds__(TileThreads<T>::value) k_particles_tile(PConst
                     }
                 }
             }
-            if (own)
-                stray[p] = st;
+            is_stray = own && st;
+            pst = (int)p;
             if (G && moved)
                 g.flag_next[p] = gn;
         }
-        // the wave is converged here: find the runs, then deposit
+        // the wave is converged here: list the strays, find the runs, then deposit
+        stray_append(is_stray, pst, strays);
         const XRun xr = xrun(key);
         if (key != 0)
             deposit_still_shared<T, O>(pc, f, f1, l, tg.lo_j, sj, w, sJ, rjvol, xr);
@@ -1125,9 +1156,8 @@ template <typename T, int O, bool G>
 __global__ void __launch_bounds__(TileThreads<T>::value) k_particles_cells(PConst<T> pc, TileGeo tg, PArr<T> in,
                                                                            PArr<T> out, FieldPtrs<T> fp,
                                                                            const int *__restrict__ tile_start,
-                                                                           unsigned char *__restrict__ stray,
-                                                                           GuestArgs g, Off3<T> f1s, int kc,
-                                                                           int *err)
+                                                                           StrayList strays, GuestArgs g,
+                                                                           Off3<T> f1s, int kc, int *err)
 {
     extern __shared__ __align__(16) unsigned char smem_raw[];
     const int tid = threadIdx.x, nth = blockDim.x;
@@ -1180,7 +1210,11 @@ __global__ void __launch_bounds__(TileThreads<T>::value) k_particles_cells(PCons
             *cq.cnt = 0;
         __syncthreads();   // also: the field tile is staged
         // phase A
-        for (int j = jb + tid; j < je; j += nth) {
+        for (int j0 = jb; j0 < je; j0 += nth) {
+          const int j = j0 + tid;
+          bool is_stray = false;
+          int pst = 0;
+          if (j < je) {
             int key = -1;
             const bool own = j < np;
             int64_t p = ts.ps + j;
@@ -1236,11 +1270,14 @@ __global__ void __launch_bounds__(TileThreads<T>::value) k_particles_cells(PCons
                     }
                 }
             }
-            if (own)
-                stray[p] = st;
+            is_stray = own && st;
+            pst = (int)p;
             if (G && moved)
                 g.flag_next[p] = gn;
             keys[j - jb] = key;
+          }
+          // the wave is converged here
+          stray_append(is_stray, pst, strays);
         }
         __syncthreads();
         block_exclusive_scan(ccnt, cstart, tc + 1, sh);
@@ -1287,33 +1324,23 @@ __global__ void __launch_bounds__(TileThreads<T>::value) k_particles_cells(PCons
     }
 }
 
-// the fused step for the strays of each tile, on global memory
+// the fused step for the listed strays, on global memory
 template <typename T, int O>
-__global__ void __launch_bounds__(STRAY_THREADS) k_particles_strays(PConst<T> pc, TileGeo tg, PArr<T> in, PArr<T> out,
-                                                                    FieldPtrs<T> fp, const int *__restrict__ tile_start,
-                                                                    const unsigned char *__restrict__ stray,
-                                                                    GuestArgs g, int *err)
+__global__ void __launch_bounds__(STRAY_THREADS) k_particles_strays(PConst<T> pc, PArr<T> in, PArr<T> out,
+                                                                    FieldPtrs<T> fp, StrayList strays, GuestArgs g,
+                                                                    int *err)
 {
-    __shared__ int list[STRAY_CHUNK];
-    __shared__ int cnt;
-    const TileSpan ts = tile_span(tg, tile_start, in.n);
-    const int np = (int)(ts.pe - ts.ps);
-    FieldSrc<T> gf = global_fields(fp);
-    const int z3[3] = {0, 0, 0};
-    for (int j0 = 0; j0 < np; j0 += STRAY_CHUNK) {
-        const int k = collect_strays(ts, j0, list, &cnt, [&](int64_t p) { return stray[p] != 0; });
-        for (int i = threadIdx.x; i < k; i += blockDim.x) {
-            const int64_t p = ts.ps + list[i];
-            int c[3];
-            T f[3], u[3];
-            if (!load_particle(in, p, pc.n, c, f, u, err))
-                copy_particle(in, out, p);
-            else
-                particle_step_global<T, O>(pc, in, out, fp, p, c, f, u, err);
-            if (g.flag_next)
-                g.flag_next[p] = 0;   // next step: the home tile's again, or a stray
-        }
-        __syncthreads();   // the list is rewritten by the next chunk
+    const int k = *strays.cnt < strays.cap ? *strays.cnt : strays.cap;
+    for (int i = blockIdx.x * blockDim.x + threadIdx.x; i < k; i += gridDim.x * blockDim.x) {
+        const int64_t p = strays.p[i];
+        int c[3];
+        T f[3], u[3];
+        if (!load_particle(in, p, pc.n, c, f, u, err))
+            copy_particle(in, out, p);
+        else
+            particle_step_global<T, O>(pc, in, out, fp, p, c, f, u, err);
+        if (g.flag_next)
+            g.flag_next[p] = 0;   // next step: the home tile's again, or a stray
     }
 }
 
@@ -2118,22 +2145,26 @@ struct AdjThreads {
 
 // threads of the tiled pass 1: 512 leaves the order-3 FP32 pass 256
 // registers (1024 capped it at 128 and spilled 29 to scratch; 25.9 against
-// 27.1 ms at 256^3 / 8 ppc).  768 (a cap of 170, of which the pass takes
-// 159) saved 0.2-0.5 ms per adjoint step at 8 ppc but cost 1 ms on the
-// laser box, whose tiles hold about 1024 particles: a second batch of 768
-// threads runs a third full.
+// 27.1 ms at 256^3 / 8 ppc).  768 (a cap of 170, of which the FP32 pass
+// takes 164) saves time at 8 ppc but costs 1 ms on the laser box, whose
+// tiles hold about 1024 particles: a second batch of 768 threads runs a
+// third full.  So FP32 takes 768 from 6 particles per cell on (`dense`),
+// else 512, each its own instantiation (the kernel built for 768 ran the
+// sparse workloads 8-20 % slower at 512 threads); FP64 (205 registers at
+// order 1) stays at 512.
 template <typename T>
 struct PushThreads {
     static constexpr int value = 512;
+    static constexpr int dense = sizeof(T) == 4 ? 768 : 512;
 };
 
 // pass 1, tiled: LDS holds E, B with the gather halo and hatE with the
 // deposit halo; strays are left to k_adjoint_push_strays
-template <typename T, int O>
-__global__ void __launch_bounds__(PushThreads<T>::value) k_adjoint_push_tile(PConst<T> pc, TileGeo tg, PArr<T> sp,
+template <typename T, int O, int NTH>
+__global__ void __launch_bounds__(NTH) k_adjoint_push_tile(PConst<T> pc, TileGeo tg, PArr<T> sp,
                                                                            FieldPtrs<T> fp, AdjPtrs<T> ap,
                                                                            const int *__restrict__ tile_start,
-                                                                           int *err)
+                                                                           StrayList strays, int *err)
 {
     extern __shared__ __align__(16) unsigned char smem_raw[];
     const int rfx = tg.rf[0], rfy = tg.rf[1];
@@ -2171,6 +2202,7 @@ __global__ void __launch_bounds__(PushThreads<T>::value) k_adjoint_push_tile(PCo
     const int np = (int)(ts.pe - ts.ps);
     for (int j0 = 0; j0 < np; j0 += nth) {
         const int j = j0 + tid;
+        bool stray = false;
         if (j < np) {
             const int64_t p = ts.ps + j;
             int c[3];
@@ -2182,59 +2214,47 @@ __global__ void __launch_bounds__(PushThreads<T>::value) k_adjoint_push_tile(PCo
                 if (tile_local(tg, pc.n, ts.t0, c, l))
                     adjoint_push_particle<T, O, true>(pc, sp, ap, lf, lh, p, c, f, u, l, tg.lo_f, sf, tg.lo_j, sj,
                                                       err);
+                else
+                    stray = true;
             }
         }
+        // the wave is converged here
+        stray_append(stray, (int)(ts.ps + j), strays);
     }
 }
 
-// pass 1 for the strays of each tile, on global memory
+// pass 1 for the listed strays, on global memory
 template <typename T, int O>
-__global__ void __launch_bounds__(STRAY_THREADS) k_adjoint_push_strays(PConst<T> pc, TileGeo tg, PArr<T> sp,
-                                                                       FieldPtrs<T> fp, AdjPtrs<T> ap,
-                                                                       const int *__restrict__ tile_start, int *err)
+__global__ void __launch_bounds__(STRAY_THREADS) k_adjoint_push_strays(PConst<T> pc, PArr<T> sp, FieldPtrs<T> fp,
+                                                                       AdjPtrs<T> ap, StrayList strays, int *err)
 {
-    __shared__ int list[STRAY_CHUNK];
-    __shared__ int cnt;
-    const TileSpan ts = tile_span(tg, tile_start, sp.n);
-    const int np = (int)(ts.pe - ts.ps);
     const FieldSrc<T> gf = global_fields(fp);
     const int z3[3] = {0, 0, 0};
-    for (int j0 = 0; j0 < np; j0 += STRAY_CHUNK) {
-        const int k = collect_strays(ts, j0, list, &cnt, CellStray<T>{tg, pc.n, ts, sp});
-        for (int i = threadIdx.x; i < k; i += blockDim.x) {
-            const int64_t p = ts.ps + list[i];
-            int c[3];
-            T f[3], u[3];
-            if (!load_particle(sp, p, pc.n, c, f, u, err))
-                clear_vb(ap, p);
-            else
-                adjoint_push_particle<T, O, false>(pc, sp, ap, gf, ap.hat, p, c, f, u, z3, 0, z3, 0, z3, err);
-        }
-        __syncthreads();
+    const int k = *strays.cnt < strays.cap ? *strays.cnt : strays.cap;
+    for (int i = blockIdx.x * blockDim.x + threadIdx.x; i < k; i += gridDim.x * blockDim.x) {
+        const int64_t p = strays.p[i];
+        int c[3];
+        T f[3], u[3];
+        if (!load_particle(sp, p, pc.n, c, f, u, err))
+            clear_vb(ap, p);
+        else
+            adjoint_push_particle<T, O, false>(pc, sp, ap, gf, ap.hat, p, c, f, u, z3, 0, z3, 0, z3, err);
     }
 }
 
-// pass 2 for the strays of each tile, both groups, on global memory
+// pass 2 for the listed strays, both groups, on global memory
 template <typename T, int O>
-__global__ void __launch_bounds__(STRAY_THREADS) k_adjoint_scatter_strays(PConst<T> pc, TileGeo tg, PArr<T> sp,
-                                                                          FieldPtrs<T> fp, AdjPtrs<T> ap,
-                                                                          const int *__restrict__ tile_start)
+__global__ void __launch_bounds__(STRAY_THREADS) k_adjoint_scatter_strays(PConst<T> pc, PArr<T> sp, AdjPtrs<T> ap,
+                                                                          StrayList strays)
 {
-    __shared__ int list[STRAY_CHUNK];
-    __shared__ int cnt;
-    const TileSpan ts = tile_span(tg, tile_start, sp.n);
-    const int np = (int)(ts.pe - ts.ps);
     const int z3[3] = {0, 0, 0};
-    for (int j0 = 0; j0 < np; j0 += STRAY_CHUNK) {
-        const int k = collect_strays(ts, j0, list, &cnt, CellStray<T>{tg, pc.n, ts, sp});
-        for (int i = threadIdx.x; i < k; i += blockDim.x) {
-            const int64_t p = ts.ps + list[i];
-            int c[3];
-            T f[3];
-            if (load_position(sp, p, pc.n, c, f))
-                adjoint_scatter_particle<T, O, false, 2>(pc, ap, p, c, f, z3, 0, z3, nullptr, 0, nullptr);
-        }
-        __syncthreads();
+    const int k = *strays.cnt < strays.cap ? *strays.cnt : strays.cap;
+    for (int i = blockIdx.x * blockDim.x + threadIdx.x; i < k; i += gridDim.x * blockDim.x) {
+        const int64_t p = strays.p[i];
+        int c[3];
+        T f[3];
+        if (load_position(sp, p, pc.n, c, f))
+            adjoint_scatter_particle<T, O, false, 2>(pc, ap, p, c, f, z3, 0, z3, nullptr, 0, nullptr);
     }
 }
 
@@ -2572,7 +2592,7 @@ int cells_chunk(const TileGeo &tg, TileGeo &tq)
 
 template <typename T, int O>
 static hipError_t launch_tile_o(const PConst<T> &pc, const TileGeo &tg, const PArr<T> &in, const PArr<T> &out,
-                                const FieldPtrs<T> &f, const int *tile_start, unsigned char *stray,
+                                const FieldPtrs<T> &f, const int *tile_start, const StrayList &stray,
                                 const GuestArgs &g, T *const scratch[3], int *err, hipStream_t st)
 {
     static bool attr_plain = false, attr_guests = false, attr_cp = false, attr_cg = false;
@@ -2627,25 +2647,33 @@ static hipError_t launch_tile_o(const PConst<T> &pc, const TileGeo &tg, const PA
 template <typename T>
 hipError_t launch_particles_tile(int order, const PConst<T> &pc, const TileGeo &tg, const PArr<T> &in,
                                  const PArr<T> &out, const FieldPtrs<T> &f, const int *tile_start,
-                                 unsigned char *stray, const GuestArgs &g, T *const scratch[3], int *err,
+                                 int *stray_list, int *stray_cnt, const GuestArgs &g, T *const scratch[3], int *err,
                                  hipStream_t st)
 {
-    return order == 1 ? launch_tile_o<T, 1>(pc, tg, in, out, f, tile_start, stray, g, scratch, err, st)
-                      : launch_tile_o<T, 3>(pc, tg, in, out, f, tile_start, stray, g, scratch, err, st);
+    const StrayList sl{stray_list, stray_cnt, (int)in.n};
+    const hipError_t e0 = launch_fill<int>(stray_cnt, 1, 0, st);
+    if (e0 != hipSuccess)
+        return e0;
+    return order == 1 ? launch_tile_o<T, 1>(pc, tg, in, out, f, tile_start, sl, g, scratch, err, st)
+                      : launch_tile_o<T, 3>(pc, tg, in, out, f, tile_start, sl, g, scratch, err, st);
 }
 
 template <typename T>
-hipError_t launch_particles_strays(int order, const PConst<T> &pc, const TileGeo &tg, const PArr<T> &in,
-                                   const PArr<T> &out, const FieldPtrs<T> &f, const int *tile_start,
-                                   const unsigned char *stray, const GuestArgs &g, int *err, hipStream_t st)
+hipError_t launch_particles_strays(int order, const PConst<T> &pc, const PArr<T> &in, const PArr<T> &out,
+                                   const FieldPtrs<T> &f, int *stray_list, int *stray_cnt, const GuestArgs &g,
+                                   int *err, hipStream_t st)
 {
-    const unsigned ntiles = (unsigned)(tg.nt[0] * tg.nt[1] * tg.nt[2]);
+    if (in.n == 0)
+        return hipSuccess;
+    // a fixed grid that strides over the list (it is usually short)
+    const StrayList sl{stray_list, stray_cnt, (int)in.n};
+    const unsigned nb = (unsigned)(in.n < 1024 * STRAY_THREADS ? (in.n + STRAY_THREADS - 1) / STRAY_THREADS : 1024);
     if (order == 1)
-        hipLaunchKernelGGL((k_particles_strays<T, 1>), dim3(ntiles), dim3(STRAY_THREADS), 0, st, pc, tg, in, out, f,
-                           tile_start, stray, g, err);
+        hipLaunchKernelGGL((k_particles_strays<T, 1>), dim3(nb), dim3(STRAY_THREADS), 0, st, pc, in, out, f, sl, g,
+                           err);
     else
-        hipLaunchKernelGGL((k_particles_strays<T, 3>), dim3(ntiles), dim3(STRAY_THREADS), 0, st, pc, tg, in, out, f,
-                           tile_start, stray, g, err);
+        hipLaunchKernelGGL((k_particles_strays<T, 3>), dim3(nb), dim3(STRAY_THREADS), 0, st, pc, in, out, f, sl, g,
+                           err);
     return hipGetLastError();
 }
 
@@ -2775,10 +2803,12 @@ size_t adjoint_lds_bytes(int, const TileGeo &tg)
 
 template <typename T, int O>
 static hipError_t launch_adj_tile_o(const PConst<T> &pc, const TileGeo &tg, const PArr<T> &sp, const FieldPtrs<T> &f,
-                                    const AdjPtrs<T> &ap, const int *tile_start, int *err, hipStream_t st)
+                                    const AdjPtrs<T> &ap, const int *tile_start, const StrayList &sl, int *err,
+                                    hipStream_t st)
 {
-    static bool a1 = false, a2 = false;
-    allow_big_lds(&k_adjoint_push_tile<T, O>, a1);
+    static bool a1 = false, a1d = false, a2 = false;
+    allow_big_lds(&k_adjoint_push_tile<T, O, PushThreads<T>::value>, a1);
+    allow_big_lds(&k_adjoint_push_tile<T, O, PushThreads<T>::dense>, a1d);
     allow_big_lds(&k_adjoint_scatter_tile<T, O>, a2);
     const unsigned ntiles = (unsigned)(tg.nt[0] * tg.nt[1] * tg.nt[2]);
     const unsigned nth = AdjThreads<T>::value;
@@ -2788,10 +2818,20 @@ static hipError_t launch_adj_tile_o(const PConst<T> &pc, const TileGeo &tg, cons
     const size_t room = l2 + 16 < ADJ_QUEUE_LDS ? (ADJ_QUEUE_LDS - l2 - 16) / 4 : 0;
     const int qcap = (int)(room < 16384 ? room : 16384);
     const size_t l2q = l2 + 16 + 4 * (size_t)qcap;
-    hipLaunchKernelGGL((k_adjoint_push_tile<T, O>), dim3(ntiles), dim3(PushThreads<T>::value), l1, st, pc, tg, sp,
-                       f, ap, tile_start, err);
-    hipLaunchKernelGGL((k_adjoint_push_strays<T, O>), dim3(ntiles), dim3(STRAY_THREADS), 0, st, pc, tg, sp, f, ap,
-                       tile_start, err);
+    // strays: listed by pass 1, taken by the stray kernels of both passes
+    // (a fixed grid that strides over the list; it is usually short)
+    const unsigned nsb = (unsigned)(sp.n < 1024 * STRAY_THREADS ? (sp.n + STRAY_THREADS - 1) / STRAY_THREADS : 1024);
+    const hipError_t e0 = launch_fill<int>(sl.cnt, 1, 0, st);
+    if (e0 != hipSuccess)
+        return e0;
+    const int64_t ncell = (int64_t)tg.nt[0] * tg.t[0] * tg.nt[1] * tg.t[1] * tg.nt[2] * tg.t[2];
+    if (sp.n >= 6 * ncell)
+        hipLaunchKernelGGL((k_adjoint_push_tile<T, O, PushThreads<T>::dense>), dim3(ntiles), dim3(PushThreads<T>::dense),
+                           l1, st, pc, tg, sp, f, ap, tile_start, sl, err);
+    else
+        hipLaunchKernelGGL((k_adjoint_push_tile<T, O, PushThreads<T>::value>), dim3(ntiles), dim3(PushThreads<T>::value),
+                           l1, st, pc, tg, sp, f, ap, tile_start, sl, err);
+    hipLaunchKernelGGL((k_adjoint_push_strays<T, O>), dim3(nsb), dim3(STRAY_THREADS), 0, st, pc, sp, f, ap, sl, err);
     bool cells = false;
     if constexpr (sizeof(T) == 4) {
         // per-cell accumulation: one component's accumulators, the cell
@@ -2815,39 +2855,38 @@ static hipError_t launch_adj_tile_o(const PConst<T> &pc, const TileGeo &tg, cons
     if (!cells)
         hipLaunchKernelGGL((k_adjoint_scatter_tile<T, O>), dim3(ntiles), dim3(nth), l2q, st, pc, tg, sp, f, ap,
                            tile_start, qcap);
-    hipLaunchKernelGGL((k_adjoint_scatter_strays<T, O>), dim3(ntiles), dim3(STRAY_THREADS), 0, st, pc, tg, sp, f, ap,
-                       tile_start);
+    hipLaunchKernelGGL((k_adjoint_scatter_strays<T, O>), dim3(nsb), dim3(STRAY_THREADS), 0, st, pc, sp, ap, sl);
     return hipGetLastError();
 }
 
 template <typename T>
 hipError_t launch_adjoint_tile(int order, const PConst<T> &pc, const TileGeo &tg, const PArr<T> &sp,
                                const FieldPtrs<T> &f, T *const hatE[3], T *const lx[3], T *const lu[3],
-                               T *const lE[3], T *const lB[3], T *const vb[6], const int *tile_start, int *err,
-                               hipStream_t st)
+                               T *const lE[3], T *const lB[3], T *const vb[6], const int *tile_start,
+                               int *stray_list, int *stray_cnt, int *err, hipStream_t st)
 {
+    const StrayList sl{stray_list, stray_cnt, (int)sp.n};
     if (sp.n == 0)
         return hipSuccess;
     const AdjPtrs<T> ap = adj_ptrs<T>(hatE, lx, lu, lE, lB, vb);
     if (order == 1)
-        return launch_adj_tile_o<T, 1>(pc, tg, sp, f, ap, tile_start, err, st);
+        return launch_adj_tile_o<T, 1>(pc, tg, sp, f, ap, tile_start, sl, err, st);
     // FP64 order 3 has no tiled form (its pass 1 needs 256 registers and
     // spills; the caller runs the per-particle kernels with the binning)
     if constexpr (sizeof(T) == 8)
         return hipErrorNotSupported;
     else
-        return launch_adj_tile_o<T, 3>(pc, tg, sp, f, ap, tile_start, err, st);
+        return launch_adj_tile_o<T, 3>(pc, tg, sp, f, ap, tile_start, sl, err, st);
 }
 
 #define PIC_INST(T)                                                                                               \
     template size_t tile_lds_bytes<T>(int, const TileGeo &);                                                       \
     template hipError_t launch_particles_tile<T>(int, const PConst<T> &, const TileGeo &, const PArr<T> &,         \
-                                                 const PArr<T> &, const FieldPtrs<T> &, const int *,               \
-                                                 unsigned char *, const GuestArgs &, T *const[3], int *,           \
-                                                 hipStream_t);                                                     \
-    template hipError_t launch_particles_strays<T>(int, const PConst<T> &, const TileGeo &, const PArr<T> &,       \
-                                                   const PArr<T> &, const FieldPtrs<T> &, const int *,             \
-                                                   const unsigned char *, const GuestArgs &, int *, hipStream_t);                     \
+                                                 const PArr<T> &, const FieldPtrs<T> &, const int *, int *, int *, \
+                                                 const GuestArgs &, T *const[3], int *, hipStream_t);              \
+    template hipError_t launch_particles_strays<T>(int, const PConst<T> &, const PArr<T> &, const PArr<T> &,       \
+                                                   const FieldPtrs<T> &, int *, int *, const GuestArgs &, int *,   \
+                                                   hipStream_t);                                                   \
     template hipError_t launch_particles_global<T>(int, const PConst<T> &, const PArr<T> &, const FieldPtrs<T> &,  \
                                                    int *, hipStream_t);                                            \
     template hipError_t launch_gather<T>(int, const PConst<T> &, const PArr<T> &, const FieldPtrs<T> &,            \
@@ -2863,8 +2902,8 @@ hipError_t launch_adjoint_tile(int order, const PConst<T> &pc, const TileGeo &tg
     template size_t adjoint_lds_bytes<T>(int, const TileGeo &);                                                    \
     template hipError_t launch_adjoint_tile<T>(int, const PConst<T> &, const TileGeo &, const PArr<T> &,           \
                                                const FieldPtrs<T> &, T *const[3], T *const[3], T *const[3],        \
-                                               T *const[3], T *const[3], T *const[6], const int *, int *,          \
-                                               hipStream_t);
+                                               T *const[3], T *const[3], T *const[6], const int *, int *, int *,   \
+                                               int *, hipStream_t);
 
 PIC_INST(float)
 PIC_INST(double)

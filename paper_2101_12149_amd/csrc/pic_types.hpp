@@ -95,20 +95,20 @@ struct GuestArgs {
 // ---------------------------------------------------------------------------
 // launchers (return hipSuccess or the launch error)
 
-// stray: per-particle scratch (uint8[n]) marking the particles that the tile
-// kernel leaves to the stray kernel; scratch: three T[n] arrays that hold
-// new offsets between the kernel's two phases when in and out are the same
-// arrays
+// stray_list (int[n]) and stray_cnt (one int, cleared by the launcher):
+// the particles the tile kernel leaves to the stray kernel; scratch: three
+// T[n] arrays that hold new offsets between the two-phase kernel's phases
+// when in and out are the same arrays
 template <typename T>
 hipError_t launch_particles_tile(int order, const PConst<T> &pc, const TileGeo &tg, const PArr<T> &in,
                                  const PArr<T> &out, const FieldPtrs<T> &f, const int *tile_start,
-                                 unsigned char *stray, const GuestArgs &g, T *const scratch[3], int *err,
+                                 int *stray_list, int *stray_cnt, const GuestArgs &g, T *const scratch[3], int *err,
                                  hipStream_t st);
-// the particles the tile kernel marked in `stray`, on global memory
+// the particles the tile kernel listed, on global memory
 template <typename T>
-hipError_t launch_particles_strays(int order, const PConst<T> &pc, const TileGeo &tg, const PArr<T> &in,
-                                   const PArr<T> &out, const FieldPtrs<T> &f, const int *tile_start,
-                                   const unsigned char *stray, const GuestArgs &g, int *err, hipStream_t st);
+hipError_t launch_particles_strays(int order, const PConst<T> &pc, const PArr<T> &in, const PArr<T> &out,
+                                   const FieldPtrs<T> &f, int *stray_list, int *stray_cnt, const GuestArgs &g,
+                                   int *err, hipStream_t st);
 template <typename T>
 hipError_t launch_particles_global(int order, const PConst<T> &pc, const PArr<T> &sp, const FieldPtrs<T> &f,
                                    int *err, hipStream_t st);
@@ -134,11 +134,14 @@ template <typename T>
 size_t tile_lds_bytes(int order, const TileGeo &tg);
 template <typename T>
 size_t adjoint_lds_bytes(int order, const TileGeo &tg);
+// stray_list: int[n] scratch, stray_cnt: one int of scratch (cleared by the
+// launcher): the particles outside their tile's region, listed by the first
+// pass for the stray kernels
 template <typename T>
 hipError_t launch_adjoint_tile(int order, const PConst<T> &pc, const TileGeo &tg, const PArr<T> &sp,
                                const FieldPtrs<T> &f, T *const hatE[3], T *const lx[3], T *const lu[3],
-                               T *const lE[3], T *const lB[3], T *const vb[6], const int *tile_start, int *err,
-                               hipStream_t st);
+                               T *const lE[3], T *const lB[3], T *const vb[6], const int *tile_start,
+                               int *stray_list, int *stray_cnt, int *err, hipStream_t st);
 
 template <typename T>
 hipError_t launch_curl(bool forward, const CurlArgs<T> &a, hipStream_t st);
