@@ -766,7 +766,7 @@ pic_status step_t(const pic_grid *g, const GridInfo &gi, pic_species *sp, pic_fi
         glist[b] = reinterpret_cast<int2 *>(w + L.glist + b * al(2 * sizeof(int) * (size_t)gi.ntiles * GUEST_CAP));
         gflag[b] = reinterpret_cast<unsigned char *>(w + L.gflag + b * al((size_t)(sp->n > 0 ? sp->n : 0)));
     }
-    // new offsets between the tile kernel's phases when it runs in place:
+    // old offsets between the tile kernel's phases when it runs in place:
     // the sorted copy's offset arrays, free on a step without a sort
     T *scratch[3];
     for (int d = 0; d < 3; ++d)

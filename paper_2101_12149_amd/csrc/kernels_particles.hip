@@ -862,8 +862,9 @@ __device__ inline void block_exclusive_scan(const int *in, int *out, int n, int 
 // crossing queue (its full-window current is added per component in phase
 // B; when the queue is full, at once to global memory), one that stayed is
 // listed under its cell (an LDS counting sort: count per cell, scan, list)
-// and its new offsets go to `f1s` (the caller's offsets when the step does
-// not run in place, else scratch, since phase B still reads the old ones).
+// and when the step runs in place its old offsets are kept in scratch
+// (`f0s`; else they stay in `in`) for phase B, which reads them with the
+// new ones from `out`.
 //
 // Phase B, per current component: one thread per cell of the tile (two or
 // more per cell when the workgroup has more threads than the tile has
@@ -1037,17 +1038,15 @@ __device__ __attribute__((always_inline)) inline void deposit_global_full(const 
 
 // Phase B for component M: the per-cell sums of the listed still particles,
 // the still particles of the slack cells, the queued crossers; `last`
-// copies the new offsets of the listed particles from scratch to `out`.
 template <typename T, int O, int M>
 __device__ __attribute__((always_inline)) inline void cells_component(
     const PConst<T> &pc, const TileGeo &tg, const TileSpan &ts, const GuestArgs &g, int np, const PArr<T> &in,
-    const PArr<T> &out, const Off3<T> &f1s, const int *list, const int *cstart, const int *ccnt, int tc,
-    const CrossQueue<T> &cq, int nq, double *sA, const int *sj, bool last, int groups)
+    const PArr<T> &out, const Off3<T> &f0s, const int *list, const int *cstart, const int *ccnt, int tc,
+    const CrossQueue<T> &cq, int nq, double *sA, const int *sj, int groups)
 {
     using R = StillRows<T, O, M>;
     constexpr int NB = Shape<O, T>::NB;
     const int nth = blockDim.x, tid = threadIdx.x;
-    const bool copy = last && f1s.o[0] != out.off[0];
     for (int lc0 = 0; lc0 < tc; lc0 += nth) {
         const int part = tc < nth ? tid / tc : 0;
         const int lc = lc0 + (tc < nth ? tid % tc : tid);
@@ -1075,8 +1074,8 @@ __device__ __attribute__((always_inline)) inline void cells_component(
             pn = tile_particle(ts, g, np, list[s + part]);
 #pragma unroll
             for (int d = 0; d < 3; ++d) {
-                f0n[d] = in.off[d][pn];
-                f1n[d] = f1s.o[d][pn];
+                f0n[d] = f0s.o[d][pn];
+                f1n[d] = out.off[d][pn];
             }
             if (in.w)
                 wn = in.w[pn];
@@ -1088,18 +1087,13 @@ __device__ __attribute__((always_inline)) inline void cells_component(
                 pn = tile_particle(ts, g, np, list[s + i + groups]);
 #pragma unroll
                 for (int d = 0; d < 3; ++d) {
-                    f0n[d] = in.off[d][pn];
-                    f1n[d] = f1s.o[d][pn];
+                    f0n[d] = f0s.o[d][pn];
+                    f1n[d] = out.off[d][pn];
                 }
                 if (in.w)
                     wn = in.w[pn];
             }
             R::apply(pc, f0, f1, w, [&](int c, int b, int a, T v) { acc[c][b][a] += v; });
-            if (copy) {
-#pragma unroll
-                for (int d = 0; d < 3; ++d)
-                    out.off[d][p] = f1[d];
-            }
         }
         // the wave is converged here: runs of consecutive cells along x
         const XRun xr = xrun(cell ? xrun_key(l) : 0);
@@ -1121,8 +1115,8 @@ __device__ __attribute__((always_inline)) inline void cells_component(
 #pragma unroll
         for (int d = 0; d < 3; ++d) {
             c[d] = in.cell[d][p];
-            f0[d] = in.off[d][p];
-            f1[d] = f1s.o[d][p];
+            f0[d] = f0s.o[d][p];
+            f1[d] = out.off[d][p];
         }
         tile_local(tg, pc.n, ts.t0, c, l);
         const T w = in.w ? in.w[p] : pc.w0;
@@ -1130,11 +1124,6 @@ __device__ __attribute__((always_inline)) inline void cells_component(
         R::apply(pc, f0, f1, w, [&](int cc, int b, int a, T v) {
             latomic_add(sA + x0 + a + sj[1] * (y0 + b) + sj[2] * (z0 + cc), (double)v);
         });
-        if (copy) {
-#pragma unroll
-            for (int d = 0; d < 3; ++d)
-                out.off[d][p] = f1[d];
-        }
     }
     // the queued crossers of this chunk, one lane each
     for (int k = tid; k < nq; k += nth) {
@@ -1157,7 +1146,7 @@ __global__ void __launch_bounds__(TileThreads<T>::value) k_particles_cells(PCons
                                                                            PArr<T> out, FieldPtrs<T> fp,
                                                                            const int *__restrict__ tile_start,
                                                                            StrayList strays, GuestArgs g,
-                                                                           Off3<T> f1s, int kc, int *err)
+                                                                           Off3<T> f0s, int kc, int *err)
 {
     extern __shared__ __align__(16) unsigned char smem_raw[];
     const int tid = threadIdx.x, nth = blockDim.x;
@@ -1246,8 +1235,11 @@ __global__ void __launch_bounds__(TileThreads<T>::value) k_particles_cells(PCons
                 if (particle_advance<T, O, true, false>(pc, in, out, lf, p, c, f, u, l, tg.lo_f, sf, f1, kap, w, err)) {
                     if ((kap[0] | kap[1] | kap[2]) == 0) {
 #pragma unroll
-                        for (int d = 0; d < 3; ++d)
-                            f1s.o[d][p] = f1[d];
+                        for (int d = 0; d < 3; ++d) {
+                            out.off[d][p] = f1[d];
+                            if (f0s.o[d] != in.off[d])
+                                f0s.o[d][p] = f[d];
+                        }
                         const bool in_tile = l[0] >= 0 && l[0] < tg.t[0] && l[1] >= 0 && l[1] < tg.t[1] &&
                                              l[2] >= 0 && l[2] < tg.t[2];
                         const int slot = in_tile ? l[0] + tg.t[0] * (l[1] + tg.t[1] * l[2]) : tc;
@@ -1301,13 +1293,13 @@ __global__ void __launch_bounds__(TileThreads<T>::value) k_particles_cells(PCons
 #pragma unroll
         for (int m = 0; m < 3; ++m) {
             if (m == 0)
-                cells_component<T, O, 0>(pc, tg, ts, g, np, in, out, f1s, list, cstart, ccnt, tc, cq, nq, sA, sj, false,
+                cells_component<T, O, 0>(pc, tg, ts, g, np, in, out, f0s, list, cstart, ccnt, tc, cq, nq, sA, sj,
                                          groups);
             else if (m == 1)
-                cells_component<T, O, 1>(pc, tg, ts, g, np, in, out, f1s, list, cstart, ccnt, tc, cq, nq, sA, sj, false,
+                cells_component<T, O, 1>(pc, tg, ts, g, np, in, out, f0s, list, cstart, ccnt, tc, cq, nq, sA, sj,
                                          groups);
             else
-                cells_component<T, O, 2>(pc, tg, ts, g, np, in, out, f1s, list, cstart, ccnt, tc, cq, nq, sA, sj, true,
+                cells_component<T, O, 2>(pc, tg, ts, g, np, in, out, f0s, list, cstart, ccnt, tc, cq, nq, sA, sj,
                                          groups);
             __syncthreads();
             for (int r = tid; r < rjvol; r += nth) {
@@ -2609,20 +2601,20 @@ static hipError_t launch_tile_o(const PConst<T> &pc, const TileGeo &tg, const PA
         TileGeo tq;
         const int kc = cells_chunk<T>(tg, tq);
         if (kc > 0 && in.n >= 6 * ncell) {
-            // the new offsets of the particles that stay in their cells wait
+            // the old offsets of the particles that stay in their cells wait
             // in scratch when the step runs in place
-            Off3<T> f1s;
+            Off3<T> f0s;
             for (int d = 0; d < 3; ++d)
-                f1s.o[d] = in.off[d] == out.off[d] ? scratch[d] : out.off[d];
+                f0s.o[d] = in.off[d] == out.off[d] ? scratch[d] : in.off[d];
             const size_t l = cells_lds(tq, TileThreads<T>::value, kc, (int)sizeof(T)).total;
             if (g.flag_next) {
                 allow_big_lds(&k_particles_cells<T, O, true>, attr_cg);
                 hipLaunchKernelGGL((k_particles_cells<T, O, true>), dim3(ntiles), dim3(TileThreads<T>::value), l, st,
-                                   pc, tq, in, out, f, tile_start, stray, g, f1s, kc, err);
+                                   pc, tq, in, out, f, tile_start, stray, g, f0s, kc, err);
             } else {
                 allow_big_lds(&k_particles_cells<T, O, false>, attr_cp);
                 hipLaunchKernelGGL((k_particles_cells<T, O, false>), dim3(ntiles), dim3(TileThreads<T>::value), l, st,
-                                   pc, tq, in, out, f, tile_start, stray, g, f1s, kc, err);
+                                   pc, tq, in, out, f, tile_start, stray, g, f0s, kc, err);
             }
             return hipGetLastError();
         }

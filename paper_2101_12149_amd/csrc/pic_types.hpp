@@ -97,7 +97,7 @@ struct GuestArgs {
 
 // stray_list (int[n]) and stray_cnt (one int, cleared by the launcher):
 // the particles the tile kernel leaves to the stray kernel; scratch: three
-// T[n] arrays that hold new offsets between the two-phase kernel's phases
+// T[n] arrays that hold old offsets between the two-phase kernel's phases
 // when in and out are the same arrays
 template <typename T>
 hipError_t launch_particles_tile(int order, const PConst<T> &pc, const TileGeo &tg, const PArr<T> &in,
