@@ -33,10 +33,10 @@ VALU_PEAK_TFLOPS = 78.6
 # 6 x 14 FMA = 168, Boris 68, position 28, Esirkepov shapes 12, products and
 # sums 126
 FLOPS_PER_PARTICLE = {3: 2028, 1: 411}
-# calibrated HBM bytes per launch of the FP32 tile kernel at 256^3 / 8 ppc,
-# from the FETCH_SIZE / WRITE_SIZE passes (scaled by a 1 GiB copy); only
-# figures taken on the current kernel are listed
-MEASURED_TRAFFIC = {"uniform256_o3_f32": 12.50e9}
+# calibrated HBM bytes per launch of the FP32 two-phase tile kernel at
+# 256^3 / 8 ppc, from the FETCH_SIZE / WRITE_SIZE passes (scaled by a 1 GiB
+# copy); only figures taken on the current kernel are listed
+MEASURED_TRAFFIC = {"uniform256_o3_f32": 17.19e9}
 
 
 def log(*a):
@@ -124,6 +124,12 @@ def run_adjoint(w, nrep, tile_start):
     return dict(ms=e0.elapsed_time(e1), kernels=kt)
 
 
+def tile_kernel_name(npart, ncell, tsize, order):
+    """The fused particle kernel the library runs: the two-phase one for
+    FP32 order 3 at 6 or more particles per cell, else the one-pass one."""
+    return "k_particles_cells" if tsize == 4 and order == 3 and npart >= 6 * ncell else "k_particles_tile"
+
+
 def kernel_roofs(kernels, npart, ncell, tsize, has_w, order):
     """The fused tile kernel's mean launch time and its HBM and ALU
     fractions from the algorithmic bytes and flops per particle-step."""
@@ -132,7 +138,8 @@ def kernel_roofs(kernels, npart, ncell, tsize, has_w, order):
     alg_bytes = particle_bytes(npart, tsize, has_w) + field_bytes(ncell, tsize)
     gbs = alg_bytes / (avg * 1e-3) / 1e9
     tfs = FLOPS_PER_PARTICLE[order] * npart / (avg * 1e-3) / 1e12
-    return {"kernel": "k_particles_tile", "avg_ms": round(avg, 4), "alg_bytes_per_particle": round(alg_bytes / npart, 2),
+    return {"kernel": tile_kernel_name(npart, ncell, tsize, order), "avg_ms": round(avg, 4),
+            "alg_bytes_per_particle": round(alg_bytes / npart, 2),
             "hbm_GBps": round(gbs, 1), "hbm_frac": round(gbs / HBM_PEAK_GBS, 4), "alu_TFLOPs": round(tfs, 2),
             "alu_frac": round(tfs / VALU_PEAK_TFLOPS, 4)}
 
@@ -427,7 +434,7 @@ def main():
     hbm_gbs = alg_bytes / (pk_avg * 1e-3) / 1e9
     roofline = {"bound": "alu", "achieved": round(achieved_tf, 2), "peak": VALU_PEAK_TFLOPS, "unit": "TFLOP/s",
                 "frac": round(achieved_tf / VALU_PEAK_TFLOPS, 4), "traffic": MEASURED_TRAFFIC.get(w.name),
-                "kernel": "k_particles_tile", "avg_ms": round(pk_avg, 4),
+                "kernel": tile_kernel_name(npart, ncell, tsize, g.order), "avg_ms": round(pk_avg, 4),
                 "alg_flops_per_particle": FLOPS_PER_PARTICLE[g.order],
                 "hbm_achieved_GBps": round(hbm_gbs, 1), "hbm_frac": round(hbm_gbs / HBM_PEAK_GBS, 4),
                 "alg_bytes_per_launch": int(alg_bytes),

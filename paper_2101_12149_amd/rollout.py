@@ -2,21 +2,23 @@
 hand-written reverse sweep (pic_step_adjoint) and checkpointing every k steps.
 
 Forward: nsteps PIC steps from the initial momenta u0 with the source map
-`amp` on the plane k_plane; the state is stored every k steps.  The loss is
-the field energy U_E + U_B after the last step (pic_energy_loss).
-Backward: for each checkpoint segment, last first, the segment is replayed
-from its checkpoint keeping every step's input state, then the steps are
-reversed with pic_step_adjoint.  Returns dL/du0 and dL/damp.
+`amp` on the plane k_plane; the loss is the field energy U_E + U_B after the
+last step (pic_energy_loss).  The steps run in segments of k: each segment
+stores its input state (the checkpoint), bins the particles by tile
+(pic_sort_tiles, keeping the permutation and the binning) and takes its k
+steps on that binning, so that no step runs on a binning more than k steps
+old.
+Backward: for each segment, last first, the checkpoint is put in the
+segment's binned order with the stored permutation and replayed keeping
+every step's input state, then the steps are reversed with
+pic_step_adjoint on the same binning.  The particle adjoints arrive in the
+binned order of the segment (its steps do not reorder particles) and leave
+in the order of its checkpoint, which is the order at the end of the
+previous segment.  Returns dL/du0 and dL/damp.
 
-With `tiled` (the default) the particles are binned by tile once, before the
-first step (pic_sort_tiles, keeping the permutation), and the forward steps
-run the tile kernels on that binning.  Each replay segment of the reverse
-sweep bins its checkpoint afresh, so that the adjoint steps never run on a
-binning more than k steps old: the particle adjoints are gathered into the
-segment's order before its steps and scattered back after them, and dL/du0
-is scattered back to the order of u0 at the end.  All arithmetic runs in the
-library's kernels; this module only orders the calls and holds device
-buffers.
+With `tiled` False the particles are never binned and every kernel runs per
+particle.  All arithmetic runs in the library's kernels; this module only
+orders the calls and holds device buffers.
 """
 import torch
 
@@ -39,10 +41,7 @@ class Problem:
         self.dtype = dtype
         self.ws = _lib.workspace(grid, dtype, species.n)
         self.tiled = bool(tiled) and species.n > 0
-        self.tile_start = None
-        if self.tiled:
-            self.tile_start = torch.zeros(_lib.pic_tile_count(grid, dtype) + 1, dtype=torch.int32,
-                                          device=species.off.device)
+        self.ntiles = _lib.pic_tile_count(grid, dtype) if self.tiled else 0
 
     def source_with(self, amp):
         if self.source is None:
@@ -58,9 +57,10 @@ class _Adjoint:
         self.lB = torch.zeros_like(fields.B)
 
 
-def _advance(pb, sp, f, src, step0, nsteps):
-    if nsteps > 0:
-        _lib.pic_step(pb.grid, sp, f, src, step0, nsteps, 0, pb.tile_start, pb.ws)
+def _permute(sp, perm):
+    """The species with particle j taken from index perm[j]."""
+    return wl.Species(sp.cell[:, perm].contiguous(), sp.off[:, perm].contiguous(), sp.u[:, perm].contiguous(),
+                      None if sp.w is None else sp.w[perm].contiguous(), sp.w0, sp.q, sp.m)
 
 
 class PICRollout(torch.autograd.Function):
@@ -68,27 +68,28 @@ class PICRollout(torch.autograd.Function):
     def forward(ctx, u0, amp, pb):
         sp = pb.species.clone()
         sp.u = u0.detach().clone().contiguous()
-        perm = None
-        if pb.tiled:
-            perm = torch.empty(sp.n, dtype=torch.int32, device=sp.off.device)
-            _lib.pic_sort_tiles(pb.grid, sp, pb.tile_start, pb.ws, perm=perm)
         f = pb.fields.clone()
         src = pb.source_with(amp) if amp is not None else None
-        checkpoints = []
+        segments = []   # (first step, checkpoint species, fields, permutation, binning)
         s = 0
         while s < pb.nsteps:
-            checkpoints.append((s, sp.clone(), f.clone()))
             n = min(pb.k, pb.nsteps - s)
-            _advance(pb, sp, f, src, s, n)
+            cp = (sp.clone(), f.clone())
+            perm = ts = None
+            if pb.tiled:
+                perm = torch.empty(sp.n, dtype=torch.int32, device=sp.off.device)
+                ts = torch.zeros(pb.ntiles + 1, dtype=torch.int32, device=sp.off.device)
+                _lib.pic_sort_tiles(pb.grid, sp, ts, pb.ws, perm=perm)
+            segments.append((s, cp[0], cp[1], perm, ts))
+            _lib.pic_step(pb.grid, sp, f, src, s, n, 0, ts, pb.ws)
             s += n
         lam = _Adjoint(sp.n, f)
         loss = _lib.pic_energy_loss(pb.grid, f, lam, pb.ws)
         ctx.pb = pb
         ctx.src = src
-        ctx.checkpoints = checkpoints
+        ctx.segments = segments
         ctx.final_fields = f
         ctx.has_amp = amp is not None
-        ctx.perm = perm
         return loss[0].clone()
 
     @staticmethod
@@ -100,37 +101,28 @@ class PICRollout(torch.autograd.Function):
         dA = None
         if ctx.has_amp and src is not None:
             dA = torch.zeros(src.amp.shape, dtype=torch.float64, device=src.amp.device)
-        for (s0, sp0, f0) in reversed(ctx.checkpoints):
+        for (s0, sp0, f0, perm, ts) in reversed(ctx.segments):
             n = min(pb.k, pb.nsteps - s0)
-            sp, f = sp0.clone(), f0.clone()
-            seg = None
-            if pb.tiled:
-                # a fresh binning for the segment; the particle adjoints follow
-                # the particles into its order (new j <- old seg[j])
-                seg = torch.empty(sp.n, dtype=torch.int32, device=sp.off.device)
-                _lib.pic_sort_tiles(pb.grid, sp, pb.tile_start, pb.ws, perm=seg)
-                seg = seg.long()
-                lam.lx = lam.lx[:, seg].contiguous()
-                lam.lu = lam.lu[:, seg].contiguous()
+            # the segment's state in its binned order; lam is in that order
+            pl = perm.long() if perm is not None else None
+            sp = _permute(sp0, pl) if pl is not None else sp0.clone()
+            f = f0.clone()
             # replay the segment, keeping the input state of every step
             states = []
             for i in range(n):
                 states.append((sp.clone(), f.clone()))
-                _advance(pb, sp, f, src, s0 + i, 1)
+                _lib.pic_step(pb.grid, sp, f, src, s0 + i, 1, 0, ts, pb.ws)
             for i in reversed(range(n)):
                 sp_n, f_n = states[i]
-                _lib.pic_step_adjoint(pb.grid, sp_n, f_n, src, s0 + i, lam, dA, pb.ws, tile_start=pb.tile_start)
-            if seg is not None:
+                _lib.pic_step_adjoint(pb.grid, sp_n, f_n, src, s0 + i, lam, dA, pb.ws, tile_start=ts)
+            if pl is not None:
+                # back to the checkpoint's order (new j <- old perm[j])
                 for name in ("lx", "lu"):
                     back = torch.empty_like(getattr(lam, name))
-                    back[:, seg] = getattr(lam, name)
+                    back[:, pl] = getattr(lam, name)
                     setattr(lam, name, back)
-        ctx.checkpoints = None
-        if ctx.perm is not None:
-            du0 = torch.empty_like(lam.lu)
-            du0[:, ctx.perm.long()] = lam.lu      # back to the order of u0
-        else:
-            du0 = lam.lu.clone()
+        ctx.segments = None
+        du0 = lam.lu.clone()
         damp = dA.to(src.amp.dtype) if dA is not None else None
         return du0, damp, None
 
