@@ -1542,6 +1542,52 @@ __device__ __attribute__((always_inline)) inline void gather_grad(const T *F, T 
     lxa[2] += vb * gz;
 }
 
+// The gathered value of one component and its gradient in the particle's
+// offsets (in cells) in one sweep over the window: the pass-1 kernel that
+// keeps the gradients in LDS reads each field value once, for the forward
+// recomputation and for the position part of the gather transpose.
+template <int O, typename T, int SX, int SY, int SZ>
+__device__ __attribute__((always_inline)) inline T gather_value_grad(const T *F, const AxisW<O, T> *aw,
+                                      const T (*dn)[Shape<O, T>::NW], const T (*ds)[Shape<O, T>::NW],
+                                      const int (*on)[Shape<O, T>::NW], const int (*os)[Shape<O, T>::NW], T *g)
+{
+    constexpr int NW = Shape<O, T>::NW;
+    const T *wx = SX ? aw[0].ws : aw[0].wn;
+    const T *wy = SY ? aw[1].ws : aw[1].wn;
+    const T *wz = SZ ? aw[2].ws : aw[2].wn;
+    const T *dx = SX ? ds[0] : dn[0];
+    const T *dy = SY ? ds[1] : dn[1];
+    const T *dz = SZ ? ds[2] : dn[2];
+    const int *xo = SX ? os[0] : on[0];
+    const int *yo = SY ? os[1] : on[1];
+    const int *zo = SZ ? os[2] : on[2];
+    T v = T(0), gx = T(0), gy = T(0), gz = T(0);
+#pragma unroll
+    for (int k = 0; k < NW; ++k)
+#pragma unroll
+        for (int j = 0; j < NW; ++j) {
+            const int rowo = yo[j] + zo[k];
+            T ax = T(0), adx = T(0);
+#pragma unroll
+            for (int i = 0; i < NW; ++i) {
+                const T val = F[rowo + xo[i]];
+                ax += wx[i] * val;
+                adx += dx[i] * val;
+            }
+            const T ayz = ax * wz[k];
+            v += ayz * wy[j];
+            gx += adx * wy[j] * wz[k];
+            gy += ayz * dy[j];
+            gz += ax * wy[j] * dz[k];
+            asm volatile("" : "+v"(v), "+v"(gx), "+v"(gy), "+v"(gz));
+            __builtin_amdgcn_sched_barrier(0);
+        }
+    g[0] = gx;
+    g[1] = gy;
+    g[2] = gz;
+    return v;
+}
+
 // How the LDS scatter of a component shares rows between lanes:
 //   SM_RUNS   the component's own window (its start on a staggered axis
 //             depends on the half of the cell the particle is in), rows
@@ -1683,11 +1729,17 @@ __device__ inline void clear_vb(const AdjPtrs<T> &ap, int64_t p)
 }
 
 // pass 1 for one particle
-template <typename T, int O, bool LOCAL>
+//
+// SST > 0: st points at this thread's slot of an LDS stash of 18 values with
+// stride SST; the forward gather then also evaluates the gradients of the six
+// gathered components in the particle's offsets and parks them there, and
+// the position part of the gather transpose reads them back (one sweep over
+// the field windows instead of two).  SST = 0: the windows are swept twice.
+template <typename T, int O, bool LOCAL, int SST = 0>
 __device__ __attribute__((always_inline)) inline void adjoint_push_particle(const PConst<T> &pc, const PArr<T> &sp, const AdjPtrs<T> &ap,
                                              const FieldSrc<T> &fsrc, const T *const *hsrc, int64_t p, const int *c,
                                              const T *f, const T *u, const int *l, int lo_f, const int *sf, int lo_j,
-                                             const int *sj, int *err)
+                                             const int *sj, int *err, T *st = nullptr)
 {
     constexpr int NW = Shape<O, T>::NW;
     const int gs[3] = {1, pc.n[0], pc.n[0] * pc.n[1]};
@@ -1697,7 +1749,33 @@ __device__ __attribute__((always_inline)) inline void adjoint_push_particle(cons
         AxisW<O, T> aw[3];
         int on[3][NW], os[3][NW];
         adjoint_offsets<T, O, LOCAL>(pc, c, f, l, lo_f, sf, aw, on, os);
-        gather_eb<O>(fsrc, aw, on, os, E, B);
+        if constexpr (SST > 0) {
+            T dn[3][NW], ds[3][NW];
+#pragma unroll
+            for (int d = 0; d < 3; ++d)
+                axis_dweights<O>(f[d], dn[d], ds[d]);
+            T g[3];
+            auto park = [&](int m) {
+#pragma unroll
+                for (int k = 0; k < 3; ++k)
+                    st[(3 * m + k) * SST] = g[k];
+            };
+            // staggering: E_x(s,n,n) E_y(n,s,n) E_z(n,n,s) B_x(n,s,s) B_y(s,n,s) B_z(s,s,n)
+            E[0] = gather_value_grad<O, T, 1, 0, 0>(fsrc.c[0], aw, dn, ds, on, os, g);
+            park(0);
+            E[1] = gather_value_grad<O, T, 0, 1, 0>(fsrc.c[1], aw, dn, ds, on, os, g);
+            park(1);
+            E[2] = gather_value_grad<O, T, 0, 0, 1>(fsrc.c[2], aw, dn, ds, on, os, g);
+            park(2);
+            B[0] = gather_value_grad<O, T, 0, 1, 1>(fsrc.c[3], aw, dn, ds, on, os, g);
+            park(3);
+            B[1] = gather_value_grad<O, T, 1, 0, 1>(fsrc.c[4], aw, dn, ds, on, os, g);
+            park(4);
+            B[2] = gather_value_grad<O, T, 1, 1, 0>(fsrc.c[5], aw, dn, ds, on, os, g);
+            park(5);
+        } else {
+            gather_eb<O>(fsrc, aw, on, os, E, B);
+        }
     }
     T f1[3];
     int kap[3];
@@ -1775,10 +1853,15 @@ __device__ __attribute__((always_inline)) inline void adjoint_push_particle(cons
         ap.vb[3 + d][p] = Bb[d];
     }
     // the position part of the gather transpose: vb . grad(gathered fields).
-    // The weights and offsets are evaluated again; the register operands keep
-    // the compiler from carrying those of the first gather across the
-    // deposit transpose.
-    {
+    if constexpr (SST > 0) {
+#pragma unroll
+        for (int k = 0; k < 3; ++k)
+            lxa[k] += Eb[0] * st[k * SST] + Eb[1] * st[(3 + k) * SST] + Eb[2] * st[(6 + k) * SST] +
+                      Bb[0] * st[(9 + k) * SST] + Bb[1] * st[(12 + k) * SST] + Bb[2] * st[(15 + k) * SST];
+    } else {
+        // The weights and offsets are evaluated again; the register operands
+        // keep the compiler from carrying those of the first gather across
+        // the deposit transpose.
         T fr[3] = {f[0], f[1], f[2]};
         int cr[3] = {c[0], c[1], c[2]}, lr[3] = {l[0], l[1], l[2]};
         asm volatile("" : "+v"(fr[0]), "+v"(fr[1]), "+v"(fr[2]));
@@ -2151,8 +2234,9 @@ struct PushThreads {
 };
 
 // pass 1, tiled: LDS holds E, B with the gather halo and hatE with the
-// deposit halo; strays are left to k_adjoint_push_strays
-template <typename T, int O, int NTH>
+// deposit halo (and, with STASH, each thread's 18 gathered-field gradients
+// after them); strays are left to k_adjoint_push_strays
+template <typename T, int O, int NTH, bool STASH>
 __global__ void __launch_bounds__(NTH) k_adjoint_push_tile(PConst<T> pc, TileGeo tg, PArr<T> sp,
                                                                            FieldPtrs<T> fp, AdjPtrs<T> ap,
                                                                            const int *__restrict__ tile_start,
@@ -2204,8 +2288,9 @@ __global__ void __launch_bounds__(NTH) k_adjoint_push_tile(PConst<T> pc, TileGeo
             } else {
                 int l[3];
                 if (tile_local(tg, pc.n, ts.t0, c, l))
-                    adjoint_push_particle<T, O, true>(pc, sp, ap, lf, lh, p, c, f, u, l, tg.lo_f, sf, tg.lo_j, sj,
-                                                      err);
+                    adjoint_push_particle<T, O, true, STASH ? NTH : 0>(pc, sp, ap, lf, lh, p, c, f, u, l, tg.lo_f,
+                                                                        sf, tg.lo_j, sj, err,
+                                                                        sH + 3 * rjvol + tid);
                 else
                     stray = true;
             }
@@ -2799,8 +2884,8 @@ static hipError_t launch_adj_tile_o(const PConst<T> &pc, const TileGeo &tg, cons
                                     hipStream_t st)
 {
     static bool a1 = false, a1d = false, a2 = false;
-    allow_big_lds(&k_adjoint_push_tile<T, O, PushThreads<T>::value>, a1);
-    allow_big_lds(&k_adjoint_push_tile<T, O, PushThreads<T>::dense>, a1d);
+    allow_big_lds(&k_adjoint_push_tile<T, O, PushThreads<T>::value, false>, a1);
+    allow_big_lds(&k_adjoint_push_tile<T, O, PushThreads<T>::dense, false>, a1d);
     allow_big_lds(&k_adjoint_scatter_tile<T, O>, a2);
     const unsigned ntiles = (unsigned)(tg.nt[0] * tg.nt[1] * tg.nt[2]);
     const unsigned nth = AdjThreads<T>::value;
@@ -2817,12 +2902,34 @@ static hipError_t launch_adj_tile_o(const PConst<T> &pc, const TileGeo &tg, cons
     if (e0 != hipSuccess)
         return e0;
     const int64_t ncell = (int64_t)tg.nt[0] * tg.t[0] * tg.nt[1] * tg.t[1] * tg.nt[2] * tg.t[2];
-    if (sp.n >= 6 * ncell)
-        hipLaunchKernelGGL((k_adjoint_push_tile<T, O, PushThreads<T>::dense>), dim3(ntiles), dim3(PushThreads<T>::dense),
-                           l1, st, pc, tg, sp, f, ap, tile_start, sl, err);
-    else
-        hipLaunchKernelGGL((k_adjoint_push_tile<T, O, PushThreads<T>::value>), dim3(ntiles), dim3(PushThreads<T>::value),
-                           l1, st, pc, tg, sp, f, ap, tile_start, sl, err);
+    const bool dense = sp.n >= 6 * ncell;
+    bool stashed = false;
+    if constexpr (sizeof(T) == 4) {
+        // the gradient stash: 18 values per thread after the field regions
+        static bool s1 = false, s1d = false;
+        const int nt = dense ? PushThreads<T>::dense : PushThreads<T>::value;
+        const size_t ls = l1 + 18 * sizeof(T) * (size_t)nt;
+        if (ls <= 160 * 1024) {
+            if (dense) {
+                allow_big_lds(&k_adjoint_push_tile<T, O, PushThreads<T>::dense, true>, s1d);
+                hipLaunchKernelGGL((k_adjoint_push_tile<T, O, PushThreads<T>::dense, true>), dim3(ntiles),
+                                   dim3(PushThreads<T>::dense), ls, st, pc, tg, sp, f, ap, tile_start, sl, err);
+            } else {
+                allow_big_lds(&k_adjoint_push_tile<T, O, PushThreads<T>::value, true>, s1);
+                hipLaunchKernelGGL((k_adjoint_push_tile<T, O, PushThreads<T>::value, true>), dim3(ntiles),
+                                   dim3(PushThreads<T>::value), ls, st, pc, tg, sp, f, ap, tile_start, sl, err);
+            }
+            stashed = true;
+        }
+    }
+    if (!stashed) {
+        if (dense)
+            hipLaunchKernelGGL((k_adjoint_push_tile<T, O, PushThreads<T>::dense, false>), dim3(ntiles),
+                               dim3(PushThreads<T>::dense), l1, st, pc, tg, sp, f, ap, tile_start, sl, err);
+        else
+            hipLaunchKernelGGL((k_adjoint_push_tile<T, O, PushThreads<T>::value, false>), dim3(ntiles),
+                               dim3(PushThreads<T>::value), l1, st, pc, tg, sp, f, ap, tile_start, sl, err);
+    }
     hipLaunchKernelGGL((k_adjoint_push_strays<T, O>), dim3(nsb), dim3(STRAY_THREADS), 0, st, pc, sp, f, ap, sl, err);
     bool cells = false;
     if constexpr (sizeof(T) == 4) {
