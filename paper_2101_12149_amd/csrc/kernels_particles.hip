@@ -2013,6 +2013,9 @@ template <typename T, int O>
 __global__ void __launch_bounds__(256) k_adjoint_push(PConst<T> pc, PArr<T> sp, FieldPtrs<T> fp, AdjPtrs<T> ap,
                                                       int *err)
 {
+    // the gathered-field gradients wait in LDS across the deposit transpose
+    // (one sweep over the field windows in global memory instead of two)
+    __shared__ T stash[18 * 256];
     const int64_t p = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (p >= sp.n)
         return;
@@ -2023,7 +2026,8 @@ __global__ void __launch_bounds__(256) k_adjoint_push(PConst<T> pc, PArr<T> sp, 
         return;
     }
     const int z3[3] = {0, 0, 0};
-    adjoint_push_particle<T, O, false>(pc, sp, ap, global_fields(fp), ap.hat, p, c, f, u, z3, 0, z3, 0, z3, err);
+    adjoint_push_particle<T, O, false, 256>(pc, sp, ap, global_fields(fp), ap.hat, p, c, f, u, z3, 0, z3, 0, z3, err,
+                                            stash + threadIdx.x);
 }
 
 // Pass 2 without a binning: a workgroup takes BOX_CHUNK consecutive
