@@ -191,12 +191,50 @@ __device__ __attribute__((always_inline)) inline unsigned char guest_next(const 
     return 1;
 }
 
-__device__ inline int region_global(const int *n, const int *t0, int lo, int rx, int ry, int rz)
+// Walk of a tile region (ex x ey x ez cells from t0 - lo, x fastest, LDS row
+// pitch px >= ex) by the whole workgroup without integer divisions in the
+// loop: a thread keeps one x (its position in a group of LX lanes, LX the
+// power of two >= ex) and steps over the rows (y, z) by blockDim.x / LX,
+// carrying y into z.  fn(local index, global index) runs once per cell.
+// With once, every axis of the region wraps at most once around the grid
+// (see region_wraps_once), else each row takes the general wrap.
+template <typename Fn>
+__device__ __attribute__((always_inline)) inline void region_walk(const int *n, const int *t0, int lo, int ex,
+                                                                   int ey, int ez, int px, bool once, Fn &&fn)
 {
-    const int gx = wrap_any(t0[0] - lo + rx, n[0]);
-    const int gy = wrap_any(t0[1] - lo + ry, n[1]);
-    const int gz = wrap_any(t0[2] - lo + rz, n[2]);
-    return gx + n[0] * (gy + n[1] * gz);
+    const int lb = ex > 1 ? 32 - __clz(ex - 1) : 0;
+    const int x = (int)threadIdx.x & ((1 << lb) - 1);
+    const int step = (int)blockDim.x >> lb;   // >= 1: regions are at most 64 cells wide
+    if (x >= ex || step == 0)
+        return;
+    int row = (int)threadIdx.x >> lb;
+    int y = row % ey, z = row / ey;
+    const int sy = step % ey, sz = step / ey;
+    const int gx = wrap_any(t0[0] - lo + x, n[0]);
+    const int nrow = ey * ez;
+    for (; row < nrow; row += step) {
+        const int vy = t0[1] - lo + y, vz = t0[2] - lo + z;
+        const int gy = once ? wrap_once(vy, n[1]) : wrap_any(vy, n[1]);
+        const int gz = once ? wrap_once(vz, n[2]) : wrap_any(vz, n[2]);
+        fn(x + px * (y + ey * z), gx + n[0] * (gy + n[1] * gz));
+        y += sy;
+        z += sz;
+        if (y >= ey) {
+            y -= ey;
+            ++z;
+        }
+    }
+}
+
+// true when the region of extents e starting lo cells below a tile of
+// extents t wraps each axis of the grid at most once (wrap_once suffices)
+__device__ inline bool region_wraps_once(const int *n, const int *t, int lo, const int *e)
+{
+    bool ok = true;
+#pragma unroll
+    for (int d = 0; d < 3; ++d)
+        ok = ok && lo <= n[d] && e[d] - t[d] - lo <= n[d];
+    return ok;
 }
 
 // Particles of a tile whose cell lies outside the tile's regions (they
@@ -688,14 +726,14 @@ __global__ void __launch_bounds__(TileThreads<T>::value) k_particles_tile(PConst
         return;   // uniform across the workgroup
 
     const int tid = threadIdx.x, nth = blockDim.x;
-    for (int r = tid; r < rfvol; r += nth) {
-        const int gi = region_global(pc.n, ts.t0, tg.lo_f, r % rfx, (r / rfx) % rfy, r / (rfx * rfy));
+    region_walk(pc.n, ts.t0, tg.lo_f, rfx, rfy, tg.rf[2], rfx, region_wraps_once(pc.n, tg.t, tg.lo_f, tg.rf),
+                [&](int r, int gi) {
 #pragma unroll
-        for (int m = 0; m < 3; ++m) {
-            sF[m * rfvol + r] = fp.E[m][gi];
-            sF[(3 + m) * rfvol + r] = fp.B[m][gi];
-        }
-    }
+                    for (int m = 0; m < 3; ++m) {
+                        sF[m * rfvol + r] = fp.E[m][gi];
+                        sF[(3 + m) * rfvol + r] = fp.B[m][gi];
+                    }
+                });
     for (int r = tid; r < 3 * rjvol; r += nth)
         sJ[r] = 0.0;
     if (tid == 0)
@@ -807,15 +845,15 @@ __global__ void __launch_bounds__(TileThreads<T>::value) k_particles_tile(PConst
             deposit_local_full<T, O, 2>(pc, f0, f1, kap, l, tg.lo_j, sj, w, sJ, rjvol);
     }
     __syncthreads();
-    for (int r = tid; r < 3 * rjvol; r += nth) {
-        const T v = (T)sJ[r];
-        const int m = r / rjvol, rr = r - m * rjvol;
-        const int rx = rr % jpx;
-        if (v != T(0) && rx < rjx) {
-            const int gi = region_global(pc.n, ts.t0, tg.lo_j, rx, (rr / jpx) % rjy, rr / (jpx * rjy));
-            gatomic_add(fp.J[m] + gi, v);
-        }
-    }
+    region_walk(pc.n, ts.t0, tg.lo_j, rjx, rjy, tg.rj[2], jpx, region_wraps_once(pc.n, tg.t, tg.lo_j, tg.rj),
+                [&](int r, int gi) {
+#pragma unroll
+                    for (int m = 0; m < 3; ++m) {
+                        const T v = (T)sJ[m * rjvol + r];
+                        if (v != T(0))
+                            gatomic_add(fp.J[m] + gi, v);
+                    }
+                });
 }
 
 // exclusive prefix sum of in[0..n) into out[0..n) by the whole workgroup;
@@ -1174,14 +1212,14 @@ __global__ void __launch_bounds__(TileThreads<T>::value) k_particles_cells(PCons
     const int ng = (G && g.cnt) ? (g.cnt[ts.t] < g.cap ? g.cnt[ts.t] : g.cap) : 0;
     if (ts.pe <= ts.ps && ng == 0)
         return;   // uniform across the workgroup
-    for (int r = tid; r < rfvol; r += nth) {
-        const int gi = region_global(pc.n, ts.t0, tg.lo_f, r % rfx, (r / rfx) % rfy, r / (rfx * rfy));
+    region_walk(pc.n, ts.t0, tg.lo_f, rfx, rfy, tg.rf[2], rfx, region_wraps_once(pc.n, tg.t, tg.lo_f, tg.rf),
+                [&](int r, int gi) {
 #pragma unroll
-        for (int m = 0; m < 3; ++m) {
-            sF[m * rfvol + r] = fp.E[m][gi];
-            sF[(3 + m) * rfvol + r] = fp.B[m][gi];
-        }
-    }
+                    for (int m = 0; m < 3; ++m) {
+                        sF[m * rfvol + r] = fp.E[m][gi];
+                        sF[(3 + m) * rfvol + r] = fp.B[m][gi];
+                    }
+                });
     for (int r = tid; r < rjvol; r += nth)
         sA[r] = 0.0;
     FieldSrc<T> lf;
@@ -1290,6 +1328,7 @@ __global__ void __launch_bounds__(TileThreads<T>::value) k_particles_cells(PCons
             const int dense = (je - jb + 2 * tc) / (4 * tc);
             groups = nth / tc < dense ? nth / tc : (dense > 1 ? dense : 1);
         }
+        const bool jonce = region_wraps_once(pc.n, tg.t, tg.lo_j, tg.rj);
 #pragma unroll
         for (int m = 0; m < 3; ++m) {
             if (m == 0)
@@ -1302,15 +1341,12 @@ __global__ void __launch_bounds__(TileThreads<T>::value) k_particles_cells(PCons
                 cells_component<T, O, 2>(pc, tg, ts, g, np, in, out, f0s, list, cstart, ccnt, tc, cq, nq, sA, sj,
                                          groups);
             __syncthreads();
-            for (int r = tid; r < rjvol; r += nth) {
+            region_walk(pc.n, ts.t0, tg.lo_j, rjx, rjy, tg.rj[2], jpx, jonce, [&](int r, int gi) {
                 const T v = (T)sA[r];
                 sA[r] = 0.0;
-                const int rx = r % jpx;
-                if (v != T(0) && rx < rjx) {
-                    const int gi = region_global(pc.n, ts.t0, tg.lo_j, rx, (r / jpx) % rjy, r / (jpx * rjy));
+                if (v != T(0))
                     gatomic_add(fp.J[m] + gi, v);
-                }
-            }
+            });
             __syncthreads();
         }
     }
@@ -2187,14 +2223,14 @@ __global__ void __launch_bounds__(BOX_THREADS) k_adjoint_scatter_box(PConst<T> p
             }
             __syncthreads();
             const int org[3] = {ref[0] + lo[0], ref[1] + lo[1], ref[2] + lo[2]};
-            for (int r = tid; r < 6 * rfvol; r += BOX_THREADS) {
-                const T v = (T)sL[r];
-                if (v != T(0)) {
-                    const int m = r / rfvol, rr = r - m * rfvol;
-                    const int gi = region_global(pc.n, org, gl, rr % rf[0], (rr / rf[0]) % rf[1], rr / sf[2]);
-                    gatomic_add((m < 3 ? ap.lE[m] : ap.lB[m - 3]) + gi, v);
+            region_walk(pc.n, org, gl, rf[0], rf[1], rf[2], rf[0], false, [&](int r, int gi) {
+#pragma unroll
+                for (int m = 0; m < 6; ++m) {
+                    const T v = (T)sL[m * rfvol + r];
+                    if (v != T(0))
+                        gatomic_add((m < 3 ? ap.lE[m] : ap.lB[m - 3]) + gi, v);
                 }
-            }
+            });
             __syncthreads();   // sL is cleared by the next segment
         } else {
             for (int j0 = 0; j0 < seg; j0 += BOX_THREADS) {
@@ -2257,20 +2293,20 @@ __global__ void __launch_bounds__(NTH) k_adjoint_push_tile(PConst<T> pc, TileGeo
     if (ts.pe <= ts.ps)
         return;   // uniform across the workgroup
     const int tid = threadIdx.x, nth = blockDim.x;
-    for (int r = tid; r < rfvol; r += nth) {
-        const int gi = region_global(pc.n, ts.t0, tg.lo_f, r % rfx, (r / rfx) % rfy, r / (rfx * rfy));
+    region_walk(pc.n, ts.t0, tg.lo_f, rfx, rfy, tg.rf[2], rfx, region_wraps_once(pc.n, tg.t, tg.lo_f, tg.rf),
+                [&](int r, int gi) {
 #pragma unroll
-        for (int m = 0; m < 3; ++m) {
-            sF[m * rfvol + r] = fp.E[m][gi];
-            sF[(3 + m) * rfvol + r] = fp.B[m][gi];
-        }
-    }
-    for (int r = tid; r < rjvol; r += nth) {
-        const int gi = region_global(pc.n, ts.t0, tg.lo_j, r % rjx, (r / rjx) % rjy, r / (rjx * rjy));
+                    for (int m = 0; m < 3; ++m) {
+                        sF[m * rfvol + r] = fp.E[m][gi];
+                        sF[(3 + m) * rfvol + r] = fp.B[m][gi];
+                    }
+                });
+    region_walk(pc.n, ts.t0, tg.lo_j, rjx, rjy, tg.rj[2], rjx, region_wraps_once(pc.n, tg.t, tg.lo_j, tg.rj),
+                [&](int r, int gi) {
 #pragma unroll
-        for (int m = 0; m < 3; ++m)
-            sH[m * rjvol + r] = ap.hat[m][gi];
-    }
+                    for (int m = 0; m < 3; ++m)
+                        sH[m * rjvol + r] = ap.hat[m][gi];
+                });
     __syncthreads();
     FieldSrc<T> lf;
 #pragma unroll
@@ -2421,14 +2457,15 @@ __global__ void __launch_bounds__(AdjThreads<T>::value) k_adjoint_scatter_tile(P
                                                                nullptr);
     }
     __syncthreads();
-    for (int r = tid; r < 6 * rfvol; r += nth) {
-        const T v = (T)sL[r];
-        if (v != T(0)) {
-            const int m = r / rfvol, rr = r - m * rfvol;
-            const int gi = region_global(pc.n, ts.t0, tg.lo_f, rr % rfx, (rr / rfx) % rfy, rr / (rfx * rfy));
-            gatomic_add((m < 3 ? ap.lE[m] : ap.lB[m - 3]) + gi, v);
-        }
-    }
+    region_walk(pc.n, ts.t0, tg.lo_f, rfx, rfy, tg.rf[2], rfx, region_wraps_once(pc.n, tg.t, tg.lo_f, tg.rf),
+                [&](int r, int gi) {
+#pragma unroll
+                    for (int m = 0; m < 6; ++m) {
+                        const T v = (T)sL[m * rfvol + r];
+                        if (v != T(0))
+                            gatomic_add((m < 3 ? ap.lE[m] : ap.lB[m - 3]) + gi, v);
+                    }
+                });
     (void)fp;
 }
 
@@ -2599,6 +2636,7 @@ __global__ void __launch_bounds__(CELL_THREADS) __attribute__((amdgpu_waves_per_
                 list[cstart[key >> 16] + (key & 0xffff)] = j;
         }
         __syncthreads();
+        const bool fonce = region_wraps_once(pc.n, tg.t, tg.lo_f, tg.rf);
         for (int m = 0; m < 6; ++m) {
             const T *vbm = ap.vb[m];
             // staggering: E_x(s,n,n) E_y(n,s,n) E_z(n,n,s) B_x(n,s,s) B_y(s,n,s) B_z(s,s,n)
@@ -2613,14 +2651,12 @@ __global__ void __launch_bounds__(CELL_THREADS) __attribute__((amdgpu_waves_per_
             __syncthreads();
             // flush the component and clear the accumulator for the next
             T *dst = m < 3 ? ap.lE[m] : ap.lB[m - 3];
-            for (int r = tid; r < rfvol; r += nth) {
+            region_walk(pc.n, ts.t0, tg.lo_f, rfx, rfy, tg.rf[2], rfx, fonce, [&](int r, int gi) {
                 const T v = (T)sA[r];
                 sA[r] = 0.0;
-                if (v != T(0)) {
-                    const int gi = region_global(pc.n, ts.t0, tg.lo_f, r % rfx, (r / rfx) % rfy, r / (rfx * rfy));
+                if (v != T(0))
                     gatomic_add(dst + gi, v);
-                }
-            }
+            });
             __syncthreads();
         }
     }
