@@ -299,17 +299,25 @@ __global__ void __launch_bounds__(BC_T) k_bin_count_tile(PArr<T> sp, TileGeo tg,
     const int rx = tg.t[0] + 2 * BC_MARGIN, ry = tg.t[1] + 2 * BC_MARGIN, rz = tg.t[2] + 2 * BC_MARGIN;
     const int rvol = rx * ry * rz;
     const int t = blockIdx.x;
-    const int tx = t % tg.nt[0], ty = (t / tg.nt[0]) % tg.nt[1], tz = t / (tg.nt[0] * tg.nt[1]);
-    const int t0[3] = {tx * tg.t[0], ty * tg.t[1], tz * tg.t[2]};
+    const int tc[3] = {t % tg.nt[0], (t / tg.nt[0]) % tg.nt[1], t / (tg.nt[0] * tg.nt[1])};
+    const int t0[3] = {tc[0] * tg.t[0], tc[1] * tg.t[1], tc[2] * tg.t[2]};
     const int tcells = tg.t[0] * tg.t[1] * tg.t[2];
     const int64_t N = sp.n;
     int64_t ps = tile_start[t], pe = tile_start[t + 1];
     ps = ps < 0 ? 0 : (ps > N ? N : ps);
     pe = pe < ps ? ps : (pe > N ? N : pe);
+    // A particle inside the margin region lies in this tile or a neighbour
+    // (tiles at least BC_MARGIN cells wide), so its key needs no division.
+    // Its region cell and local rank are packed into the rank word (region
+    // cells below 2^rb, ranks below 2^(31 - rb): at most 2^(31 - rb)
+    // particles in the segment), so that the second pass reads nothing else.
+    const int rb = 32 - __clz(rvol - 1);
+    const bool packed = rb <= 20 && pe - ps <= ((int64_t)1 << (31 - rb));
+    const bool nodiv = tg.t[0] >= BC_MARGIN && tg.t[1] >= BC_MARGIN && tg.t[2] >= BC_MARGIN;
     for (int r = threadIdx.x; r < rvol; r += blockDim.x)
         lc[r] = 0;
     __syncthreads();
-    // pass 1: keys; local ranks (stored as -(rank+1)) or global ranks.  The
+    // pass 1: keys; local ranks (stored negative) or global ranks.  The
     // chunks of blockDim.x particles are ranked one after the other (a
     // barrier between them), so particles that kept their cell keep their
     // order and the scatter below writes long runs of consecutive slots.
@@ -318,32 +326,49 @@ __global__ void __launch_bounds__(BC_T) k_bin_count_tile(PArr<T> sp, TileGeo tg,
         if (p < pe) {
             int c[3] = {sp.cell[0][p], sp.cell[1][p], sp.cell[2][p]};
             bool ok = true;
-            int l[3];
+            int v[3];
             bool inside = true;
 #pragma unroll
             for (int d = 0; d < 3; ++d) {
                 const T f = sp.off[d][p];
                 ok = ok && c[d] >= 0 && c[d] < n[d] && f >= T(0) && f < T(1);
                 c[d] = c[d] < 0 ? 0 : (c[d] >= n[d] ? n[d] - 1 : c[d]);
-                int v = c[d] - t0[d];
-                if (v < -BC_MARGIN)
-                    v += n[d];
-                else if (v >= tg.t[d] + BC_MARGIN)
-                    v -= n[d];
-                l[d] = v + BC_MARGIN;
-                inside = inside && v >= -BC_MARGIN && v < tg.t[d] + BC_MARGIN;
+                int w = c[d] - t0[d];
+                if (w < -BC_MARGIN)
+                    w += n[d];
+                else if (w >= tg.t[d] + BC_MARGIN)
+                    w -= n[d];
+                v[d] = w;
+                inside = inside && w >= -BC_MARGIN && w < tg.t[d] + BC_MARGIN;
             }
             if (!ok)
                 atomicOr(err, 1);
-            const int cx = c[0] / tg.t[0], cy = c[1] / tg.t[1], cz = c[2] / tg.t[2];
-            const int tile = cx + tg.nt[0] * (cy + tg.nt[1] * cz);
-            const int kk = tile * tcells + (c[0] - cx * tg.t[0]) + tg.t[0] * ((c[1] - cy * tg.t[1]) +
-                                                                             tg.t[1] * (c[2] - cz * tg.t[2]));
+            int kk;
+            if (inside && nodiv) {
+                int tile = 0, loc = 0;
+#pragma unroll
+                for (int d = 2; d >= 0; --d) {
+                    const int o = v[d] < 0 ? -1 : (v[d] >= tg.t[d] ? 1 : 0);
+                    int td = tc[d] + o;
+                    td = td < 0 ? td + tg.nt[d] : (td >= tg.nt[d] ? td - tg.nt[d] : td);
+                    tile = tile * tg.nt[d] + td;
+                    loc = loc * tg.t[d] + (v[d] - o * tg.t[d]);
+                }
+                kk = tile * tcells + loc;
+            } else {
+                const int cx = c[0] / tg.t[0], cy = c[1] / tg.t[1], cz = c[2] / tg.t[2];
+                const int tile = cx + tg.nt[0] * (cy + tg.nt[1] * cz);
+                kk = tile * tcells + (c[0] - cx * tg.t[0]) +
+                     tg.t[0] * ((c[1] - cy * tg.t[1]) + tg.t[1] * (c[2] - cz * tg.t[2]));
+            }
             key[p] = kk;
-            if (inside)
-                rank[p] = -1 - atomicAdd(lc + l[0] + rx * (l[1] + ry * l[2]), 1);
-            else
+            if (inside) {
+                const int r = (v[0] + BC_MARGIN) + rx * ((v[1] + BC_MARGIN) + ry * (v[2] + BC_MARGIN));
+                const int lr = atomicAdd(lc + r, 1);
+                rank[p] = packed ? -1 - ((lr << rb) | r) : -1 - lr;
+            } else {
                 rank[p] = atomicAdd(counts + kk, 1);
+            }
         }
         __syncthreads();   // uniform: every thread runs every chunk
     }
@@ -366,19 +391,24 @@ __global__ void __launch_bounds__(BC_T) k_bin_count_tile(PArr<T> sp, TileGeo tg,
     for (int64_t p = ps + threadIdx.x; p < pe; p += blockDim.x) {
         const int rk = rank[p];
         if (rk < 0) {
-            int l[3];
+            const int v = -1 - rk;
+            if (packed) {
+                rank[p] = lc[v & ((1 << rb) - 1)] + (v >> rb);
+            } else {
+                int l[3];
 #pragma unroll
-            for (int d = 0; d < 3; ++d) {
-                int c = sp.cell[d][p];
-                c = c < 0 ? 0 : (c >= n[d] ? n[d] - 1 : c);
-                int v = c - t0[d];
-                if (v < -BC_MARGIN)
-                    v += n[d];
-                else if (v >= tg.t[d] + BC_MARGIN)
-                    v -= n[d];
-                l[d] = v + BC_MARGIN;
+                for (int d = 0; d < 3; ++d) {
+                    int c = sp.cell[d][p];
+                    c = c < 0 ? 0 : (c >= n[d] ? n[d] - 1 : c);
+                    int w = c - t0[d];
+                    if (w < -BC_MARGIN)
+                        w += n[d];
+                    else if (w >= tg.t[d] + BC_MARGIN)
+                        w -= n[d];
+                    l[d] = w + BC_MARGIN;
+                }
+                rank[p] = lc[l[0] + rx * (l[1] + ry * l[2])] + v;
             }
-            rank[p] = lc[l[0] + rx * (l[1] + ry * l[2])] + (-1 - rk);
         }
     }
 }

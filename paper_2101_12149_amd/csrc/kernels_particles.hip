@@ -802,7 +802,7 @@ __global__ void __launch_bounds__(TileThreads<T>::value) k_particles_tile(PConst
                         int c1[3], ht0[3] = {ts.t0[0], ts.t0[1], ts.t0[2]};
 #pragma unroll
                         for (int d = 0; d < 3; ++d)
-                            c1[d] = wrap_any(c[d] + kap[d], pc.n[d]);
+                            c1[d] = wrap_once(c[d] + kap[d], pc.n[d]);
                         if (!own)
                             tile_origin(tg, home, ht0);
                         gn = guest_next(g, tg, pc.n, p, home, ht0, c1);
@@ -1293,7 +1293,7 @@ __global__ void __launch_bounds__(TileThreads<T>::value) k_particles_cells(PCons
                         int c1[3], ht0[3] = {ts.t0[0], ts.t0[1], ts.t0[2]};
 #pragma unroll
                         for (int d = 0; d < 3; ++d)
-                            c1[d] = wrap_any(c[d] + kap[d], pc.n[d]);
+                            c1[d] = wrap_once(c[d] + kap[d], pc.n[d]);
                         if (!own)
                             tile_origin(tg, home, ht0);
                         gn = guest_next(g, tg, pc.n, p, home, ht0, c1);
