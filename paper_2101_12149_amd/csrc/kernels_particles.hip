@@ -2046,8 +2046,10 @@ __device__ inline bool load_position(const PArr<T> &in, int64_t p, const int *n,
 }
 
 template <typename T, int O>
-__global__ void __launch_bounds__(256) k_adjoint_push(PConst<T> pc, PArr<T> sp, FieldPtrs<T> fp, AdjPtrs<T> ap,
-                                                      int *err)
+// (at least two waves per SIMD: the FP64 order-3 pass sits at the 256
+// registers that allow two, and one register more would halve them)
+__global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2)))
+k_adjoint_push(PConst<T> pc, PArr<T> sp, FieldPtrs<T> fp, AdjPtrs<T> ap, int *err)
 {
     // the gathered-field gradients wait in LDS across the deposit transpose
     // (one sweep over the field windows in global memory instead of two)

@@ -646,20 +646,12 @@ __device__ __attribute__((always_inline)) inline void esk_gather_adjoint(const E
 #pragma unroll
         for (int a = 0; a < NW; ++a)
             G[a] = T(0);
-        // the two combinations of S0 and DS each transverse axis enters with
-        T Ap[NW + 1], Bp[NW + 1], Aq[NW + 1], Bq[NW + 1];
-#pragma unroll
-        for (int b = 0; b <= NW; ++b) {
-            Ap[b] = e[p].S0[b] + half * e[p].DS[b];
-            Bp[b] = half * e[p].S0[b] + third * e[p].DS[b];
-            Aq[b] = e[q].S0[b] + half * e[q].DS[b];
-            Bq[b] = half * e[q].S0[b] + third * e[q].DS[b];
-        }
 #pragma unroll
         for (int c = 0; c <= NW; ++c) {
 #pragma unroll
             for (int b = 0; b <= NW; ++b) {
-                const T C = e[p].S0[b] * Aq[c] + e[p].DS[b] * Bq[c];
+                const T C = e[p].S0[b] * (e[q].S0[c] + half * e[q].DS[c]) +
+                            e[p].DS[b] * (half * e[q].S0[c] + third * e[q].DS[c]);
                 const int base = jo[p][b] + jo[q][c];
                 // the window values enter unscaled: K_m multiplies H here and
                 // G after the window
@@ -672,10 +664,10 @@ __device__ __attribute__((always_inline)) inline void esk_gather_adjoint(const E
                 }
                 H *= K[m];
                 // dC/dS0p, dC/dDSp, dC/dS0q, dC/dDSq
-                gS0[p][b] += H * Aq[c];
-                gDS[p][b] += H * Bq[c];
-                gS0[q][c] += H * Ap[b];
-                gDS[q][c] += H * Bp[b];
+                gS0[p][b] += H * (e[q].S0[c] + half * e[q].DS[c]);
+                gDS[p][b] += H * (half * e[q].S0[c] + third * e[q].DS[c]);
+                gS0[q][c] += H * (e[p].S0[b] + half * e[p].DS[b]);
+                gDS[q][c] += H * (half * e[p].S0[b] + third * e[p].DS[b]);
                 // Finish this window entry's arithmetic here: without the
                 // register operands below the compiler issues every window
                 // load first and parks the values in scratch memory.
