@@ -72,21 +72,38 @@ __device__ inline bool finite3(const T *u)
 
 // Load a particle and check its state; returns false (and flags err) for a
 // cell outside [0,n), an offset outside [0,1) or a non-finite momentum.
+// the state words of particle p, unchecked
 template <typename T>
-__device__ inline bool load_particle(const PArr<T> &in, int64_t p, const int *n, int *c, T *f, T *u, int *err)
+__device__ __attribute__((always_inline)) inline void load_state(const PArr<T> &in, int64_t p, int *c, T *f, T *u)
 {
-    bool ok = true;
 #pragma unroll
     for (int d = 0; d < 3; ++d) {
         c[d] = in.cell[d][p];
         f[d] = in.off[d][p];
         u[d] = in.u[d][p];
-        ok = ok && c[d] >= 0 && c[d] < n[d] && f[d] >= T(0) && f[d] < T(1);
     }
+}
+
+// true for a valid state (cell in the grid, offsets in [0,1), finite
+// momentum); an invalid one sets bit 0 of the error word
+template <typename T>
+__device__ inline bool check_state(const int *n, const int *c, const T *f, const T *u, int *err)
+{
+    bool ok = true;
+#pragma unroll
+    for (int d = 0; d < 3; ++d)
+        ok = ok && c[d] >= 0 && c[d] < n[d] && f[d] >= T(0) && f[d] < T(1);
     ok = ok && finite3(u);
     if (!ok)
         atomicOr(err, 1);
     return ok;
+}
+
+template <typename T>
+__device__ inline bool load_particle(const PArr<T> &in, int64_t p, const int *n, int *c, T *f, T *u, int *err)
+{
+    load_state(in, p, c, f, u);
+    return check_state(n, c, f, u, err);
 }
 
 template <typename T>
@@ -772,12 +789,15 @@ __global__ void __launch_bounds__(TileThreads<T>::value) k_particles_tile(PConst
             T u[3];
             unsigned char st = 0, gn = 0;   // stray mark; guest status next step
             bool moved = true;             // this launch writes the particle's next status
-            if (G && own && g.flag && g.flag[p]) {
-                // listed as a guest of another tile this step: that tile moves
-                // it, possibly before this one runs (the step is in place), so
-                // its cell must not be read here at all
+            // The state is read together with the guest flag (one memory
+            // round trip, not two).  A particle listed as a guest of another
+            // tile this step is moved by that tile, possibly while this one
+            // runs (the step is in place): what was read of it is dropped.
+            load_state(in, p, c, f, u);
+            const bool flagged = G && own && g.flag && g.flag[p];
+            if (flagged) {
                 moved = false;
-            } else if (!load_particle(in, p, pc.n, c, f, u, err)) {
+            } else if (!check_state(pc.n, c, f, u, err)) {
                 copy_particle(in, out, p);
             } else if (!tile_local(tg, pc.n, ts.t0, c, l)) {
                 if (own) {
@@ -1255,10 +1275,14 @@ __global__ void __launch_bounds__(TileThreads<T>::value) k_particles_cells(PCons
             T f[3], u[3], f1[3], w = T(0);
             unsigned char st = 0, gn = 0;
             bool moved = true;
-            if (G && own && g.flag && g.flag[p]) {
-                // a guest of another tile this step: that tile moves it
+            // the state is read together with the guest flag; a guest of
+            // another tile this step is moved by that tile (what was read of
+            // it is dropped)
+            load_state(in, p, c, f, u);
+            const bool flagged = G && own && g.flag && g.flag[p];
+            if (flagged) {
                 moved = false;
-            } else if (!load_particle(in, p, pc.n, c, f, u, err)) {
+            } else if (!check_state(pc.n, c, f, u, err)) {
                 copy_particle(in, out, p);
             } else if (!tile_local(tg, pc.n, ts.t0, c, l)) {
                 if (own) {
