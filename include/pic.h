@@ -107,7 +107,9 @@ typedef struct {
     int32_t order;    /* shape-function order: 1 (cloud in cell) or 3 (cubic) */
     int32_t dtype;    /* pic_dtype */
     int32_t tile[3];  /* sort/tile size in cells, each in [1,16] dividing n;
-                         0 = the largest divisor of n not above 8 */
+                         0 = automatic: the largest divisor of n not above 8,
+                         halved (not below 4) while the tile's LDS regions do
+                         not fit or the grid holds fewer than 512 tiles */
     int32_t slack;    /* cells of halo slack around a tile for particles that
                          drifted since the last sort; -1 = automatic */
     int32_t pusher;   /* pic_pusher; anything else is PIC_E_UNSUPPORTED */

@@ -350,6 +350,25 @@ pic_status check_grid(const pic_grid *g, GridInfo &gi)
     }
     if (lds_bytes(gi) > limit)
         return fail(PIC_E_UNSUPPORTED, "tile plus halo does not fit in LDS; use a smaller tile or slack");
+    // On a small grid the automatic tiles halve further (not below 4 cells)
+    // until there are two per CU: one workgroup per tile would otherwise
+    // leave most of the 256 CUs idle.
+    for (;;) {
+        int64_t ntl = 1;
+        for (int d = 0; d < 3; ++d)
+            ntl *= gi.n[d] / gi.tg.t[d];
+        if (ntl >= 512)
+            break;
+        int dmax = -1;
+        for (int d = 0; d < 3; ++d)
+            if (auto_tile[d] && gi.tg.t[d] >= 8 && gi.tg.t[d] % 2 == 0 &&
+                (dmax < 0 || gi.tg.t[d] > gi.tg.t[dmax] || (gi.tg.t[d] == gi.tg.t[dmax] && d > dmax)))
+                dmax = d;
+        if (dmax < 0)
+            break;
+        gi.tg.t[dmax] /= 2;
+        region_extents(gi.order, gi.tg);
+    }
     // the LDS left over holds the forward tile kernel's queue of
     // cell-crossing particles (up to 1024 entries)
     {

@@ -53,12 +53,17 @@ def test_workspace_bytes_grows_with_particles_and_rejects_bad_grids():
 def test_tile_shape_resolves_the_automatic_choices():
     """The automatic tile is the largest divisor of n not above 8 with one
     cell of slack; while the LDS regions do not fit, the largest tile edge
-    halves before the slack is dropped; a fixed tile that cannot hold the
+    halves before the slack is dropped; on a grid of fewer than 512 tiles an
+    automatic edge of 8 or more halves (largest first) until there are 512
+    or none is left to halve; a fixed tile that cannot hold the
     slack keeps the tile and drops the slack."""
     big = wl.plasma_grid((256, 256, 256), 3)
     assert _lib.pic_tile_shape(big, "f32") == ((8, 8, 8), 1)
     assert _lib.pic_tile_shape(big, "f64") == ((8, 8, 4), 1)
-    assert _lib.pic_tile_shape(wl.plasma_grid((12, 16, 20), 3), "f32") == ((6, 8, 5), 1)
+    assert _lib.pic_tile_shape(wl.plasma_grid((12, 16, 20), 3), "f32") == ((6, 4, 5), 1)
+    assert _lib.pic_tile_shape(wl.plasma_grid((32, 32, 32), 1), "f64") == ((4, 4, 4), 1)
+    assert _lib.pic_tile_shape(wl.plasma_grid((64, 64, 64), 3), "f64") == ((8, 8, 4), 1)
+    assert _lib.pic_tile_shape(wl.plasma_grid((16, 16, 16), 3), "f32") == ((4, 4, 4), 1)
     fixed = wl.plasma_grid((16, 16, 16), 3)
     fixed.tile = (8, 8, 8)
     assert _lib.pic_tile_shape(fixed, "f64") == ((8, 8, 8), 0)

@@ -275,7 +275,7 @@ def test_sort_tiles_is_a_binning_permutation():
     assert torch.equal(d.w.cpu(), sp.w[p])
     # tiles are contiguous and in order; inside a tile the order is rank-major:
     # (occurrence of the particle's cell so far, local cell) strictly increases
-    tx, ty, tz = 8, 8, 8
+    (tx, ty, tz), _ = _lib.pic_tile_shape(g, "f32")
     c = d.cell.cpu().numpy().astype(np.int64)
     tile = (c[0] // tx) + (g.n[0] // tx) * ((c[1] // ty) + (g.n[1] // ty) * (c[2] // tz))
     local = (c[0] % tx) + tx * ((c[1] % ty) + ty * (c[2] % tz))
