@@ -688,6 +688,44 @@ def test_guests_that_step_back_home_on_many_tiles():
     assert rel_l2(gt[:, 3:], ot[:, 3:]) < F64_TOL
 
 
+def test_resort_of_a_tile_holding_over_a_million_particles():
+    """The re-sort's counting pass packs each particle's region cell and
+    local rank into one word while a tile's segment holds at most 2^20
+    particles (8^3 tiles: 2^11 region cells); beyond that it keeps the rank
+    alone and reads the cell again.  One fixed 8^3 tile holding 1,100,000
+    particles (FP64, order 3), two steps with a sort at each (the second a
+    re-sort of the binned particles), against the oracle within 1e-12."""
+    w = wl.uniform_plasma((8, 8, 8), 2149, 0.02, 3, 2, "f64", 97, 1)
+    w.grid.tile = (8, 8, 8)
+    assert w.species.n > (1 << 20)
+    assert _lib.pic_tile_count(w.grid, "f64") == 1
+    gsp, gf, _ = _run_gpu_steps(w, 2, 1)
+    osp, of, _ = _run_oracle(w, 2)
+    for name in ("E", "B", "J"):
+        assert rel_l2(_cpu(getattr(gf, name)), getattr(of, name)) < F64_TOL, name
+    gt, ot = particle_table(gsp), particle_table(osp)
+    assert np.array_equal(gt[:, :3], ot[:, :3])
+    assert rel_l2(gt[:, 3:], ot[:, 3:]) < F64_TOL
+
+
+def test_regions_that_wrap_more_than_once_with_two_cells_of_slack():
+    """A 4-cell axis with two cells of slack: the current region (4 + 2 * 2 +
+    5 = 13 cells) wraps the axis more than once, so the tile kernels' region
+    walks take the general wrap; order 3, FP64, six steps sorted every 3,
+    against the oracle within 1e-12."""
+    w = wl.uniform_plasma((4, 8, 12), 6, 0.1, 3, 6, "f64", 98, 3)
+    w.grid.slack = 2
+    tile, slack = _lib.pic_tile_shape(w.grid, "f64")
+    assert slack == 2 and tile[0] == 4
+    gsp, gf, _ = _run_gpu_steps(w, w.nsteps, w.sort_every)
+    osp, of, _ = _run_oracle(w, w.nsteps)
+    for name in ("E", "B", "J"):
+        assert rel_l2(_cpu(getattr(gf, name)), getattr(of, name)) < F64_TOL, name
+    gt, ot = particle_table(gsp), particle_table(osp)
+    assert np.array_equal(gt[:, :3], ot[:, :3])
+    assert rel_l2(gt[:, 3:], ot[:, 3:]) < F64_TOL
+
+
 def test_laser_plasma_reduced_with_empty_tiles_and_source():
     """Laser workload shape at reduced size: vacuum tiles without particles,
     a density up-ramp with per-particle weights, the soft source."""
