@@ -231,7 +231,7 @@ size_t adj_lds_for(const GridInfo &gi, const TileGeo &a)
 {
     const size_t rf = (size_t)a.rf[0] * a.rf[1] * a.rf[2];
     const size_t rj = (size_t)a.rj[0] * a.rj[1] * a.rj[2];
-    const size_t push = 6 * rf * gi.tsize + 3 * rj * gi.tsize;
+    const size_t push = 6 * rf * gi.tsize + 3 * rj * gi.tsize + 16;
     const size_t scatter = 6 * rf * sizeof(double);
     return push > scatter ? push : scatter;
 }
@@ -970,13 +970,29 @@ pic_status adjoint_t(const pic_grid *g, const GridInfo &gi, const pic_species *s
                 PIC_HIP(launch_fill<T>(glB[d], gi.ncell, T(0), st));
             }
         }
-        if (tile_start && tiled_ok)
+        if (tile_start && tiled_ok) {
+            // Below 6 particles per cell, the particles that change cells are
+            // split off (the others take the narrow window of the deposit
+            // transpose) only when few do: sampled from the momenta, under 2 %
+            // (a few leftover crossers per tile run alone at its end).
+            bool split_sparse = false;
+            if (gi.dtype == PIC_F32 && sp->n > 0 && sp->n < 6 * gi.ncell) {
+                int *cnt = reinterpret_cast<int *>(w + L.err + 128);
+                int64_t taken = 0;
+                PIC_HIP(launch_cross_estimate<T>(pc, parr<T>(sp), int64_t(1) << 20, cnt, st, &taken));
+                int hc = 0;
+                PIC_HIP(hipMemcpyAsync(&hc, cnt, sizeof(int), hipMemcpyDeviceToHost, st));
+                PIC_HIP(hipStreamSynchronize(st));
+                split_sparse = (int64_t)hc * 50 < taken;
+            }
             PIC_HIP(launch_adjoint_tile<T>(gi.order, pc, adjoint_geo(gi), parr<T>(sp), fpv, hat, lx, lu, glE, glB,
                                            vb, tile_start, reinterpret_cast<int *>(w + L.rank),
-                                           reinterpret_cast<int *>(w + L.err + 64), err, st));
-        else
+                                           reinterpret_cast<int *>(w + L.err + 64),
+                                           reinterpret_cast<int *>(w + L.key), split_sparse, err, st));
+        } else {
             PIC_HIP(launch_adjoint_particles<T>(gi.order, pc, parr<T>(sp), fpv, hat, lx, lu, glE, glB, vb, tile_start,
                                                 gi.ntiles, err, st));
+        }
         if (gi.filt) {
             FieldPtrs<T> lsrc{}, ldst{};
             for (int d = 0; d < 3; ++d) {

@@ -1795,12 +1795,19 @@ __device__ inline void clear_vb(const AdjPtrs<T> &ap, int64_t p)
 // gathered components in the particle's offsets and parks them there, and
 // the position part of the gather transpose reads them back (one sweep over
 // the field windows instead of two).  SST = 0: the windows are swept twice.
-template <typename T, int O, bool LOCAL, int SST = 0>
-__device__ __attribute__((always_inline)) inline void adjoint_push_particle(const PConst<T> &pc, const PArr<T> &sp, const AdjPtrs<T> &ap,
+//
+// STILL (tile kernels only): a particle that stays in its cell along every
+// axis takes the narrow-window deposit transpose (the transpose of the
+// forward step's still-particle deposit); one that changes cells is left
+// untouched and the call returns false (the caller runs it again without
+// STILL).  Otherwise the call returns true.
+template <typename T, int O, bool LOCAL, int SST = 0, bool STILL = false>
+__device__ __attribute__((always_inline)) inline bool adjoint_push_particle(const PConst<T> &pc, const PArr<T> &sp, const AdjPtrs<T> &ap,
                                              const FieldSrc<T> &fsrc, const T *const *hsrc, int64_t p, const int *c,
                                              const T *f, const T *u, const int *l, int lo_f, const int *sf, int lo_j,
                                              const int *sj, int *err, T *st = nullptr)
 {
+    static_assert(LOCAL || !STILL, "the narrow path reads tile regions");
     constexpr int NW = Shape<O, T>::NW;
     const int gs[3] = {1, pc.n[0], pc.n[0] * pc.n[1]};
     // forward recomputation: gather, Boris, position
@@ -1854,12 +1861,26 @@ __device__ __attribute__((always_inline)) inline void adjoint_push_particle(cons
     if (!ok) {
         atomicOr(err, 2);
         clear_vb(ap, p);
-        return;
+        return true;
+    }
+    if constexpr (STILL) {
+        if ((kap[0] | kap[1] | kap[2]) != 0)
+            return false;
     }
     // deposit transpose: phi = <lJ, J_p>, lJ = (-dt/eps0) hatE
     T g0[3], g1[3];
-    {
-        const T w = sp.w ? sp.w[p] : pc.w0;
+    const T w = sp.w ? sp.w[p] : pc.w0;
+    if constexpr (STILL) {
+        T S0[3][NW], DS[3][NW], K[3];
+        int jo[3][NW];
+#pragma unroll
+        for (int d = 0; d < 3; ++d) {
+            esk_axis_still<O>(f[d], f1[d], S0[d], DS[d]);
+            K[d] = pc.jk[d] * w * pc.lj;
+            axis_offsets_local<NW>(l[d] + lo_j, Shape<O, T>::NB, sj[d], jo[d]);
+        }
+        esk_gather_adjoint_still<O>(S0, DS, f, f1, jo, K, [&](int m, int idx) { return hsrc[m][idx]; }, g0, g1);
+    } else {
         EskAxis<O, T> e[3];
         T K[3];
         int jo[3][NW + 1];
@@ -1944,6 +1965,7 @@ __device__ __attribute__((always_inline)) inline void adjoint_push_particle(cons
 #pragma unroll
     for (int d = 0; d < 3; ++d)
         ap.lx[d][p] = lxa[d];
+    return true;
 }
 
 // pass 2 for one particle: the scatter of the gather transpose for the
@@ -2301,12 +2323,19 @@ struct PushThreads {
 
 // pass 1, tiled: LDS holds E, B with the gather halo and hatE with the
 // deposit halo (and, with STASH, each thread's 18 gathered-field gradients
-// after them); strays are left to k_adjoint_push_strays
-template <typename T, int O, int NTH, bool STASH>
+// after them); strays are left to k_adjoint_push_strays.  The particles that
+// stay in their cells take the narrow-window deposit transpose in the loop
+// and those that change cells are listed in the tile's segment of crossq
+// and run after it in full waves with the full window (STILL: dense tiles,
+// and sparse ones where almost no particle changes cells).  Without STILL
+// every particle takes the full window: in a sparse tile the leftover
+// crossers would run alone at its end (512^3, 2 ppc, u_th 0.1c: 120.5 ->
+// 126.1 ms per adjoint step with the split).
+template <typename T, int O, int NTH, bool STASH, bool STILL>
 __global__ void __launch_bounds__(NTH) k_adjoint_push_tile(PConst<T> pc, TileGeo tg, PArr<T> sp,
                                                                            FieldPtrs<T> fp, AdjPtrs<T> ap,
                                                                            const int *__restrict__ tile_start,
-                                                                           StrayList strays, int *err)
+                                                                           StrayList strays, int *crossq, int *err)
 {
     extern __shared__ __align__(16) unsigned char smem_raw[];
     const int rfx = tg.rf[0], rfy = tg.rf[1];
@@ -2342,9 +2371,16 @@ __global__ void __launch_bounds__(NTH) k_adjoint_push_tile(PConst<T> pc, TileGeo
     const int sf[3] = {1, rfx, rfx * rfy};
     const int sj[3] = {1, rjx, rjx * rjy};
     const int np = (int)(ts.pe - ts.ps);
+    // the count of the tile's cell-changing particles, after the stash
+    int *ncross = reinterpret_cast<int *>(sH + 3 * rjvol + (STASH ? 18 * NTH : 0));
+    if (tid == 0)
+        *ncross = 0;
+    __syncthreads();
+    const StrayList cross{crossq + ts.ps, ncross, np};
+    T *const stash = sH + 3 * rjvol + tid;
     for (int j0 = 0; j0 < np; j0 += nth) {
         const int j = j0 + tid;
-        bool stray = false;
+        bool stray = false, crosser = false;
         if (j < np) {
             const int64_t p = ts.ps + j;
             int c[3];
@@ -2354,15 +2390,28 @@ __global__ void __launch_bounds__(NTH) k_adjoint_push_tile(PConst<T> pc, TileGeo
             } else {
                 int l[3];
                 if (tile_local(tg, pc.n, ts.t0, c, l))
-                    adjoint_push_particle<T, O, true, STASH ? NTH : 0>(pc, sp, ap, lf, lh, p, c, f, u, l, tg.lo_f,
-                                                                        sf, tg.lo_j, sj, err,
-                                                                        sH + 3 * rjvol + tid);
+                    crosser = !adjoint_push_particle<T, O, true, STASH ? NTH : 0, STILL>(
+                        pc, sp, ap, lf, lh, p, c, f, u, l, tg.lo_f, sf, tg.lo_j, sj, err, stash);
                 else
                     stray = true;
             }
         }
         // the wave is converged here
         stray_append(stray, (int)(ts.ps + j), strays);
+        stray_append(crosser, j, cross);
+    }
+    if constexpr (!STILL)
+        return;
+    __syncthreads();   // the list and its count are complete
+    const int nc = *ncross;
+    for (int k = tid; k < nc; k += nth) {
+        const int64_t p = ts.ps + crossq[ts.ps + k];
+        int c[3], l[3];
+        T f[3], u[3];
+        load_state(sp, p, c, f, u);   // checked in the loop above
+        tile_local(tg, pc.n, ts.t0, c, l);
+        adjoint_push_particle<T, O, true, STASH ? NTH : 0>(pc, sp, ap, lf, lh, p, c, f, u, l, tg.lo_f, sf, tg.lo_j,
+                                                            sj, err, stash);
     }
 }
 
@@ -2924,7 +2973,7 @@ size_t adjoint_push_lds(const TileGeo &tg)
 {
     const size_t rf = (size_t)tg.rf[0] * tg.rf[1] * tg.rf[2];
     const size_t rj = (size_t)tg.rj[0] * tg.rj[1] * tg.rj[2];
-    return 6 * rf * sizeof(T) + 3 * rj * sizeof(T);
+    return 6 * rf * sizeof(T) + 3 * rj * sizeof(T) + 16;   // and the count of cell-changing particles
 }
 
 // dynamic LDS one workgroup of the tiled adjoint scatter may take
@@ -2944,14 +2993,61 @@ size_t adjoint_lds_bytes(int, const TileGeo &tg)
     return a > b ? a : b;
 }
 
+// Particles that would change cells at their present momenta, among runs
+// of 64 consecutive particles every `stride` particles (whole cache lines
+// read, one run in stride / 64): an estimate of the share of cell-changing
+// particles in an adjoint step, which decides whether sparse tiles split
+// them off.
+template <typename T>
+__global__ void __launch_bounds__(256) k_cross_estimate(PConst<T> pc, PArr<T> sp, int64_t stride, int *count)
+{
+    int mine = 0;
+    for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;; i += (int64_t)gridDim.x * blockDim.x) {
+        const int64_t p = (i >> 6) * stride + (i & 63);
+        if (p >= sp.n)
+            break;
+        const T u[3] = {sp.u[0][p], sp.u[1][p], sp.u[2][p]};
+        const T ig = T(1) / sqrt(T(1) + (u[0] * u[0] + u[1] * u[1] + u[2] * u[2]) * pc.inv_c2);
+        bool cross = false;
+#pragma unroll
+        for (int d = 0; d < 3; ++d) {
+            const T x = sp.off[d][p] + pc.dtd[d] * u[d] * ig;
+            cross = cross || !(x >= T(0) && x < T(1));
+        }
+        mine += cross ? 1 : 0;
+    }
+    for (int off = 32; off > 0; off >>= 1)
+        mine += __shfl_down(mine, off, 64);
+    if ((threadIdx.x & 63) == 0 && mine > 0)
+        atomicAdd(count, mine);
+}
+
+template <typename T>
+hipError_t launch_cross_estimate(const PConst<T> &pc, const PArr<T> &sp, int64_t samples, int *count,
+                                 hipStream_t st, int64_t *taken)
+{
+    // runs of 64 at a stride that takes about `samples` particles
+    const int64_t runs = (samples + 63) / 64;
+    int64_t stride = runs > 0 ? (sp.n + runs - 1) / runs : sp.n;
+    stride = stride < 64 ? 64 : (stride + 63) / 64 * 64;
+    *taken = sp.n / stride * 64 + (sp.n % stride < 64 ? sp.n % stride : 64);
+    const int64_t ns = *taken;
+    const unsigned nb = (unsigned)(ns < 1024 * 256 ? (ns + 255) / 256 : 1024);
+    const hipError_t e = launch_fill<int>(count, 1, 0, st);
+    if (e != hipSuccess || ns == 0)
+        return e;
+    hipLaunchKernelGGL((k_cross_estimate<T>), dim3(nb), dim3(256), 0, st, pc, sp, stride, count);
+    return hipGetLastError();
+}
+
 template <typename T, int O>
 static hipError_t launch_adj_tile_o(const PConst<T> &pc, const TileGeo &tg, const PArr<T> &sp, const FieldPtrs<T> &f,
-                                    const AdjPtrs<T> &ap, const int *tile_start, const StrayList &sl, int *err,
-                                    hipStream_t st)
+                                    const AdjPtrs<T> &ap, const int *tile_start, const StrayList &sl, int *crossq,
+                                    bool split_sparse, int *err, hipStream_t st)
 {
     static bool a1 = false, a1d = false, a2 = false;
-    allow_big_lds(&k_adjoint_push_tile<T, O, PushThreads<T>::value, false>, a1);
-    allow_big_lds(&k_adjoint_push_tile<T, O, PushThreads<T>::dense, false>, a1d);
+    allow_big_lds(&k_adjoint_push_tile<T, O, PushThreads<T>::value, false, false>, a1);
+    allow_big_lds(&k_adjoint_push_tile<T, O, PushThreads<T>::dense, false, true>, a1d);
     allow_big_lds(&k_adjoint_scatter_tile<T, O>, a2);
     const unsigned ntiles = (unsigned)(tg.nt[0] * tg.nt[1] * tg.nt[2]);
     const unsigned nth = AdjThreads<T>::value;
@@ -2977,24 +3073,29 @@ static hipError_t launch_adj_tile_o(const PConst<T> &pc, const TileGeo &tg, cons
         const size_t ls = l1 + 18 * sizeof(T) * (size_t)nt;
         if (ls <= 160 * 1024) {
             if (dense) {
-                allow_big_lds(&k_adjoint_push_tile<T, O, PushThreads<T>::dense, true>, s1d);
-                hipLaunchKernelGGL((k_adjoint_push_tile<T, O, PushThreads<T>::dense, true>), dim3(ntiles),
-                                   dim3(PushThreads<T>::dense), ls, st, pc, tg, sp, f, ap, tile_start, sl, err);
+                allow_big_lds(&k_adjoint_push_tile<T, O, PushThreads<T>::dense, true, true>, s1d);
+                hipLaunchKernelGGL((k_adjoint_push_tile<T, O, PushThreads<T>::dense, true, true>), dim3(ntiles),
+                                   dim3(PushThreads<T>::dense), ls, st, pc, tg, sp, f, ap, tile_start, sl, crossq, err);
+            } else if (split_sparse) {
+                static bool s1s = false;
+                allow_big_lds(&k_adjoint_push_tile<T, O, PushThreads<T>::value, true, true>, s1s);
+                hipLaunchKernelGGL((k_adjoint_push_tile<T, O, PushThreads<T>::value, true, true>), dim3(ntiles),
+                                   dim3(PushThreads<T>::value), ls, st, pc, tg, sp, f, ap, tile_start, sl, crossq, err);
             } else {
-                allow_big_lds(&k_adjoint_push_tile<T, O, PushThreads<T>::value, true>, s1);
-                hipLaunchKernelGGL((k_adjoint_push_tile<T, O, PushThreads<T>::value, true>), dim3(ntiles),
-                                   dim3(PushThreads<T>::value), ls, st, pc, tg, sp, f, ap, tile_start, sl, err);
+                allow_big_lds(&k_adjoint_push_tile<T, O, PushThreads<T>::value, true, false>, s1);
+                hipLaunchKernelGGL((k_adjoint_push_tile<T, O, PushThreads<T>::value, true, false>), dim3(ntiles),
+                                   dim3(PushThreads<T>::value), ls, st, pc, tg, sp, f, ap, tile_start, sl, crossq, err);
             }
             stashed = true;
         }
     }
     if (!stashed) {
         if (dense)
-            hipLaunchKernelGGL((k_adjoint_push_tile<T, O, PushThreads<T>::dense, false>), dim3(ntiles),
-                               dim3(PushThreads<T>::dense), l1, st, pc, tg, sp, f, ap, tile_start, sl, err);
+            hipLaunchKernelGGL((k_adjoint_push_tile<T, O, PushThreads<T>::dense, false, true>), dim3(ntiles),
+                               dim3(PushThreads<T>::dense), l1, st, pc, tg, sp, f, ap, tile_start, sl, crossq, err);
         else
-            hipLaunchKernelGGL((k_adjoint_push_tile<T, O, PushThreads<T>::value, false>), dim3(ntiles),
-                               dim3(PushThreads<T>::value), l1, st, pc, tg, sp, f, ap, tile_start, sl, err);
+            hipLaunchKernelGGL((k_adjoint_push_tile<T, O, PushThreads<T>::value, false, false>), dim3(ntiles),
+                               dim3(PushThreads<T>::value), l1, st, pc, tg, sp, f, ap, tile_start, sl, crossq, err);
     }
     hipLaunchKernelGGL((k_adjoint_push_strays<T, O>), dim3(nsb), dim3(STRAY_THREADS), 0, st, pc, sp, f, ap, sl, err);
     bool cells = false;
@@ -3028,20 +3129,21 @@ template <typename T>
 hipError_t launch_adjoint_tile(int order, const PConst<T> &pc, const TileGeo &tg, const PArr<T> &sp,
                                const FieldPtrs<T> &f, T *const hatE[3], T *const lx[3], T *const lu[3],
                                T *const lE[3], T *const lB[3], T *const vb[6], const int *tile_start,
-                               int *stray_list, int *stray_cnt, int *err, hipStream_t st)
+                               int *stray_list, int *stray_cnt, int *crossq, bool split_sparse, int *err,
+                               hipStream_t st)
 {
     const StrayList sl{stray_list, stray_cnt, (int)sp.n};
     if (sp.n == 0)
         return hipSuccess;
     const AdjPtrs<T> ap = adj_ptrs<T>(hatE, lx, lu, lE, lB, vb);
     if (order == 1)
-        return launch_adj_tile_o<T, 1>(pc, tg, sp, f, ap, tile_start, sl, err, st);
+        return launch_adj_tile_o<T, 1>(pc, tg, sp, f, ap, tile_start, sl, crossq, split_sparse, err, st);
     // FP64 order 3 has no tiled form (its pass 1 needs 256 registers and
     // spills; the caller runs the per-particle kernels with the binning)
     if constexpr (sizeof(T) == 8)
         return hipErrorNotSupported;
     else
-        return launch_adj_tile_o<T, 3>(pc, tg, sp, f, ap, tile_start, sl, err, st);
+        return launch_adj_tile_o<T, 3>(pc, tg, sp, f, ap, tile_start, sl, crossq, split_sparse, err, st);
 }
 
 #define PIC_INST(T)                                                                                               \
@@ -3068,7 +3170,9 @@ hipError_t launch_adjoint_tile(int order, const PConst<T> &pc, const TileGeo &tg
     template hipError_t launch_adjoint_tile<T>(int, const PConst<T> &, const TileGeo &, const PArr<T> &,           \
                                                const FieldPtrs<T> &, T *const[3], T *const[3], T *const[3],        \
                                                T *const[3], T *const[3], T *const[6], const int *, int *, int *,   \
-                                               int *, hipStream_t);
+                                               int *, bool, int *, hipStream_t);                                   \
+    template hipError_t launch_cross_estimate<T>(const PConst<T> &, const PArr<T> &, int64_t, int *, hipStream_t,   \
+                                                 int64_t *);
 
 PIC_INST(float)
 PIC_INST(double)

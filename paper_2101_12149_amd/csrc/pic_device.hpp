@@ -614,6 +614,91 @@ __device__ __attribute__((always_inline)) inline void esk_scatter_still(const T 
     }
 }
 
+// Transpose of esk_scatter_still (a particle that stays in its cell along
+// every axis): the NW x NW cross-section and the NW - 1 nodes along m that
+// carry current.  S0, DS and jo as for esk_scatter_still; returns
+// d phi / d d0 and d phi / d d1 per axis for phi = <lJ, J_particle>.
+template <int O, typename T, typename GetFn>
+__device__ __attribute__((always_inline)) inline void esk_gather_adjoint_still(
+    const T (*S0)[Shape<O, T>::NW], const T (*DS)[Shape<O, T>::NW], const T *d0, const T *d1,
+    const int (*jo)[Shape<O, T>::NW], const T *K, GetFn &&get, T *g0, T *g1)
+{
+    constexpr int NW = Shape<O, T>::NW;
+    const T half = T(0.5), third = T(1) / T(3);
+    T gS0[3][NW], gDS[3][NW];
+#pragma unroll
+    for (int d = 0; d < 3; ++d)
+#pragma unroll
+        for (int a = 0; a < NW; ++a) {
+            gS0[d][a] = T(0);
+            gDS[d][a] = T(0);
+        }
+#pragma unroll
+    for (int m = 0; m < 3; ++m) {
+        const int p = (m + 1) % 3, q = (m + 2) % 3;
+        T P[NW - 1];
+        T run = T(0);
+#pragma unroll
+        for (int a = 0; a < NW - 1; ++a) {
+            run += DS[m][a];
+            P[a] = run;
+        }
+        T G[NW - 1];
+#pragma unroll
+        for (int a = 0; a < NW - 1; ++a)
+            G[a] = T(0);
+#pragma unroll
+        for (int c = 0; c < NW; ++c) {
+#pragma unroll
+            for (int b = 0; b < NW; ++b) {
+                const T C = S0[p][b] * (S0[q][c] + half * DS[q][c]) + DS[p][b] * (half * S0[q][c] + third * DS[q][c]);
+                const int base = jo[p][b] + jo[q][c];
+                T H = T(0);
+#pragma unroll
+                for (int a = 0; a < NW - 1; ++a) {
+                    const T l = get(m, base + jo[m][a]);
+                    G[a] += l * C;
+                    H += l * P[a];
+                }
+                H *= K[m];
+                gS0[p][b] += H * (S0[q][c] + half * DS[q][c]);
+                gDS[p][b] += H * (half * S0[q][c] + third * DS[q][c]);
+                gS0[q][c] += H * (S0[p][b] + half * DS[p][b]);
+                gDS[q][c] += H * (half * S0[p][b] + third * DS[p][b]);
+                // finish this entry here (see esk_gather_adjoint)
+#pragma unroll
+                for (int a = 0; a < NW - 1; ++a)
+                    asm volatile("" : "+v"(G[a]));
+                asm volatile("" : "+v"(gS0[p][b]), "+v"(gDS[p][b]), "+v"(gS0[q][c]), "+v"(gDS[q][c]));
+                __builtin_amdgcn_sched_barrier(0);
+            }
+        }
+        // P[a] = sum_{a' <= a} DS[a'] -> dphi/dDS[a'] = sum_{a' <= a < NW-1} G[a]
+        T suf = T(0);
+#pragma unroll
+        for (int a = NW - 2; a >= 0; --a) {
+            suf += G[a];
+            gDS[m][a] += K[m] * suf;
+        }
+    }
+    // chain rule: S0 = w(d0) and DS = w(d1) - w(d0) on the same nodes
+    using S = Shape<O, T>;
+#pragma unroll
+    for (int d = 0; d < 3; ++d) {
+        T w0[NW], w1[NW];
+        S::dw(d0[d], w0);
+        S::dw(d1[d], w1);
+        T s0 = T(0), s1 = T(0);
+#pragma unroll
+        for (int a = 0; a < NW; ++a) {
+            s0 += (gS0[d][a] - gDS[d][a]) * w0[a];
+            s1 += gDS[d][a] * w1[a];
+        }
+        g0[d] = s0;
+        g1[d] = s1;
+    }
+}
+
 // Transpose of esk_scatter: given the current adjoint lJ (read through
 // `get(m, index)`), return d phi / d d0 and d phi / d d1 per axis for
 // phi = <lJ, J_particle>.

@@ -136,12 +136,22 @@ template <typename T>
 size_t adjoint_lds_bytes(int order, const TileGeo &tg);
 // stray_list: int[n] scratch, stray_cnt: one int of scratch (cleared by the
 // launcher): the particles outside their tile's region, listed by the first
-// pass for the stray kernels
+// pass for the stray kernels; crossq: int[n] scratch, where the first pass
+// lists each tile's particles that change cells (in the tile's segment);
+// split_sparse: below 6 particles per cell too, run those separately (the
+// particles that stay in their cells take the narrow window)
 template <typename T>
 hipError_t launch_adjoint_tile(int order, const PConst<T> &pc, const TileGeo &tg, const PArr<T> &sp,
                                const FieldPtrs<T> &f, T *const hatE[3], T *const lx[3], T *const lu[3],
                                T *const lE[3], T *const lB[3], T *const vb[6], const int *tile_start,
-                               int *stray_list, int *stray_cnt, int *err, hipStream_t st);
+                               int *stray_list, int *stray_cnt, int *crossq, bool split_sparse, int *err,
+                               hipStream_t st);
+// count[0] = the particles, among about `samples` of them (runs of 64
+// spread over the arrays; *taken = how many), whose offsets would leave
+// [0,1) after a move with their present momenta (count cleared first)
+template <typename T>
+hipError_t launch_cross_estimate(const PConst<T> &pc, const PArr<T> &sp, int64_t samples, int *count,
+                                 hipStream_t st, int64_t *taken);
 
 template <typename T>
 hipError_t launch_curl(bool forward, const CurlArgs<T> &a, hipStream_t st);
