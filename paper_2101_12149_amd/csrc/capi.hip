@@ -594,9 +594,12 @@ void ckc_weights(const pic_grid *g, CurlArgs<T> &a)
 // One field step: B -= dt/2 curlE; E += dt (c^2 curlB - J/eps0) + source;
 // B -= dt/2 curlE (with the CKC solver the curl of E averages transversely).
 // zero_j clears J as it is consumed.
+// With bh (Yee solver only): the steps of one call chained through the
+// half-step B in bh, first and last marking the call's first and last step.
 template <typename T>
 pic_status yee_step(const pic_grid *g, const GridInfo &gi, const FieldPtrs<T> &f, const pic_source *src,
-                    int64_t step, bool zero_j, hipStream_t st)
+                    int64_t step, bool zero_j, hipStream_t st, T *const *bh = nullptr, bool first = true,
+                    bool last = true)
 {
     CurlArgs<T> b{};
     for (int d = 0; d < 3; ++d) {
@@ -631,9 +634,31 @@ pic_status yee_step(const pic_grid *g, const GridInfo &gi, const FieldPtrs<T> &f
         e.amp = static_cast<const T *>(src->amp);
         e.ag = (T)src_g(src, step);
     }
-    PIC_HIP(launch_curl<T>(true, b, st));
+    if (!bh) {
+        PIC_HIP(launch_curl<T>(true, b, st));
+        PIC_HIP(launch_curl<T>(false, e, st));
+        PIC_HIP(launch_curl<T>(true, b, st));
+        return PIC_OK;
+    }
+    // Chained steps of one call: the second B half step of a step and the
+    // first of the next use the same curl of E, so one pass writes both
+    // B^{n+1} (into B, for the gather and the diagnostics) and B^{n+3/2}
+    // (into bh, for the next E update) with the same arithmetic as two
+    // passes; only the first step of a call computes its B^{n+1/2} alone.
+    CurlArgs<T> bf = b;
+    for (int d = 0; d < 3; ++d) {
+        if (first) {
+            b.out[d] = bh[d];
+        }
+        e.src[d] = bh[d];
+        bf.in[d] = bh[d];
+        bf.out[d] = f.B[d];
+        bf.out2[d] = last ? nullptr : bh[d];
+    }
+    if (first)
+        PIC_HIP(launch_curl<T>(true, b, st));
     PIC_HIP(launch_curl<T>(false, e, st));
-    PIC_HIP(launch_curl<T>(true, b, st));
+    PIC_HIP(launch_curl<T>(true, bf, st));
     return PIC_OK;
 }
 
@@ -790,6 +815,12 @@ pic_status step_t(const pic_grid *g, const GridInfo &gi, pic_species *sp, pic_fi
     T *scratch[3];
     for (int d = 0; d < 3; ++d)
         scratch[d] = reinterpret_cast<T *>(w + L.soff + d * al(gi.tsize * (size_t)(sp->n > 0 ? sp->n : 0)));
+    // the half-step B of chained Yee steps, in the adjoint's hatE scratch
+    // (unused by the forward step)
+    T *bh[3];
+    for (int d = 0; d < 3; ++d)
+        bh[d] = reinterpret_cast<T *>(w + L.hatE + d * al(sizeof(T) * (size_t)gi.ncell));
+    const bool chain = g->solver == PIC_SOLVER_YEE;
     PIC_HIP(launch_fill<int>(err, 1, 0, st));
     for (int d = 0; d < 3; ++d)
         PIC_HIP(launch_fill<T>(fp.J[d], gi.ncell, T(0), st));
@@ -846,7 +877,8 @@ pic_status step_t(const pic_grid *g, const GridInfo &gi, pic_species *sp, pic_fi
         pic_status s;
         {
             TimedScope ts(2, st);
-            s = yee_step<T>(g, gi, fp, src, step, it + 1 < nsteps, st);
+            s = yee_step<T>(g, gi, fp, src, step, it + 1 < nsteps, st, chain ? bh : nullptr, it == 0,
+                            it + 1 == nsteps);
         }
         if (s != PIC_OK)
             return s;

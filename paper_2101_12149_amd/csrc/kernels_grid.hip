@@ -20,9 +20,12 @@ template <typename T>
 __device__ inline void curl_finish(const CurlArgs<T> &a, int i, int j, int k, int64_t o, T dx_sy, T dx_sz, T dy_sx,
                                    T dy_sz, T dz_sx, T dz_sy)
 {
-    T vx = a.in[0][o] + (a.cy * dy_sz - a.cz * dz_sy);
-    T vy = a.in[1][o] + (a.cz * dz_sx - a.cx * dx_sz);
-    T vz = a.in[2][o] + (a.cx * dx_sy - a.cy * dy_sx);
+    const T tx = a.cy * dy_sz - a.cz * dz_sy;
+    const T ty = a.cz * dz_sx - a.cx * dx_sz;
+    const T tz = a.cx * dx_sy - a.cy * dy_sx;
+    T vx = a.in[0][o] + tx;
+    T vy = a.in[1][o] + ty;
+    T vz = a.in[2][o] + tz;
     if (a.J[0]) {
         vx += a.jc * a.J[0][o];
         vy += a.jc * a.J[1][o];
@@ -42,6 +45,11 @@ __device__ inline void curl_finish(const CurlArgs<T> &a, int i, int j, int k, in
     a.out[0][o] = vx;
     a.out[1][o] = vy;
     a.out[2][o] = vz;
+    if (a.out2[0]) {   // the same update again from the result (two B half steps around one E)
+        a.out2[0][o] = vx + tx;
+        a.out2[1][o] = vy + ty;
+        a.out2[2][o] = vz + tz;
+    }
 }
 
 template <typename T, bool FWD>

@@ -61,6 +61,7 @@ struct TileGeo {
 template <typename T>
 struct CurlArgs {
     T *out[3];
+    T *out2[3];       // non-null: out2 = out + the same curl terms (no J or source)
     const T *in[3];
     const T *src[3];
     T cx, cy, cz;
