@@ -267,7 +267,8 @@ PIC_API pic_status pic_step_noalloc(const pic_grid *grid, pic_species *sp, pic_f
  * position update, of the Boris push and of the gather (a scatter).
  * tile_start (int32[ntiles+1], or NULL): a binning of state_n's particles
  * from pic_sort_tiles or pic_step (running from 0 to n, else
- * PIC_E_INVALID); with it the particle part runs one
+ * PIC_E_INVALID, found on the device and returned at the end of the call:
+ * lam and dA are then unspecified); with it the particle part runs one
  * workgroup per tile with the fields, the field adjoint and the scatter
  * accumulators in LDS, without it one thread per particle on global memory.
  * The result does not depend on the choice beyond rounding. */

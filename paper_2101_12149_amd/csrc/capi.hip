@@ -980,6 +980,11 @@ pic_status adjoint_t(const pic_grid *g, const GridInfo &gi, const pic_species *s
         ckc_weights<T>(g, e);
     }
     PIC_HIP(launch_fill<int>(err, 1, 0, st));
+    // the binning is checked on the device and reported with the state
+    // errors at the end (no read-back before the launches)
+    constexpr int bad_binning = 1 << 8;
+    if (tile_start && sp->n > 0)
+        PIC_HIP(launch_check_binning(tile_start, gi.ntiles, sp->n, err, bad_binning, st));
     {
         TimedScope tf(4, st);
         PIC_HIP(launch_curl<T>(false, a, st));   // hatE
@@ -1039,6 +1044,9 @@ pic_status adjoint_t(const pic_grid *g, const GridInfo &gi, const pic_species *s
     int herr = 0;
     PIC_HIP(hipMemcpyAsync(&herr, err, sizeof(int), hipMemcpyDeviceToHost, st));
     PIC_HIP(hipStreamSynchronize(st));
+    if (herr & bad_binning)
+        return fail(PIC_E_INVALID, "tile_start is not a binning of these particles (it must run from 0 to n); "
+                                   "sort them first (lam and dA are unspecified)");
     if (herr)
         return fail(PIC_E_STATE, "corrupt particle state (cell, offset, momentum or a displacement >= 1 cell)");
     return PIC_OK;
@@ -1371,8 +1379,6 @@ pic_status pic_step_adjoint(const pic_grid *grid, const pic_species *state_n, co
                 return fail(PIC_E_INVALID, "NULL adjoint array");
         PIC_TRY(check_ws(gi, state_n->n, ws, ws_bytes, L));
         hipStream_t st = static_cast<hipStream_t>(stream);
-        if (tile_start && state_n->n > 0)
-            PIC_TRY(check_binning(gi, tile_start, state_n->n, st));
         if (gi.dtype == PIC_F64)
             return adjoint_t<double>(grid, gi, state_n, fields_n, tile_start, src, step, lam, dA, ws, L, st);
         return adjoint_t<float>(grid, gi, state_n, fields_n, tile_start, src, step, lam, dA, ws, L, st);

@@ -213,6 +213,20 @@ __global__ void k_fill(T *p, int64_t n, T v)
         p[i] = v;
 }
 
+// Sets `bit` in *err when tile_start does not run from 0 to n (a binning of
+// other particles, or an array never filled).
+__global__ void k_check_binning(const int *tile_start, int ntiles, int64_t n, int *err, int bit)
+{
+    if (threadIdx.x == 0 && blockIdx.x == 0 && (tile_start[0] != 0 || (int64_t)tile_start[ntiles] != n))
+        atomicOr(err, bit);
+}
+
+hipError_t launch_check_binning(const int *tile_start, int ntiles, int64_t n, int *err, int bit, hipStream_t st)
+{
+    hipLaunchKernelGGL(k_check_binning, dim3(1), dim3(64), 0, st, tile_start, ntiles, n, err, bit);
+    return hipGetLastError();
+}
+
 template <typename T>
 hipError_t launch_fill(T *p, int64_t n, T v, hipStream_t st)
 {

@@ -156,6 +156,8 @@ hipError_t launch_cross_estimate(const PConst<T> &pc, const PArr<T> &sp, int64_t
 
 template <typename T>
 hipError_t launch_curl(bool forward, const CurlArgs<T> &a, hipStream_t st);
+// sets `bit` in *err when tile_start[0] != 0 or tile_start[ntiles] != n
+hipError_t launch_check_binning(const int *tile_start, int ntiles, int64_t n, int *err, int bit, hipStream_t st);
 // out = (add ? out : 0) + symmetric z filter of in with taps w[0..3] (periodic)
 template <typename T>
 hipError_t launch_filter_z(const T *in, T *out, const T w[4], bool add, const int n[3], hipStream_t st);

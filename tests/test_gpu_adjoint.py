@@ -263,6 +263,20 @@ def test_untiled_adjoint_box_segments_match_oracle(order, dtype):
     assert rel_l2(dA.cpu().numpy(), odA) < tol
 
 
+def test_adjoint_rejects_a_binning_that_does_not_span_the_particles():
+    """A tile_start never filled (all zeros) is found on the device (every
+    tile's range clamps to empty, so nothing is read out of bounds) and the
+    call returns PIC_E_INVALID at its end."""
+    g = wl.plasma_grid((16, 16, 16), 3)
+    sp, f = dev(random_species(g, 2000, 131)), dev(random_fields(g, 132))
+    ts = torch.zeros(_lib.pic_tile_count(g, "f64") + 1, dtype=torch.int32, device="cuda")
+    lam = NS(lx=torch.zeros_like(sp.off), lu=torch.zeros_like(sp.u), lE=f.E.clone(), lB=f.B.clone())
+    ws = _lib.workspace(g, "f64", sp.n)
+    with pytest.raises(_lib.PicError) as ei:
+        _lib.pic_step_adjoint(g, sp, f, None, 0, lam, None, ws, tile_start=ts)
+    assert ei.value.name == "PIC_E_INVALID"
+
+
 def test_energy_loss_and_seed():
     g = wl.plasma_grid((8, 12, 16), 3)
     f = random_fields(g, 111, scale=0.4)
