@@ -310,6 +310,7 @@ __global__ void __launch_bounds__(256) k_bin_count(PArr<T> sp, TileGeo tg, int n
 // and keys mean exactly what k_bin_count produces.
 static constexpr int BC_T = 512;
 static constexpr int BC_MARGIN = 2;
+static constexpr int BC_GROUP = 4;   // chunks loaded ahead of their ranking
 
 template <typename T>
 __global__ void __launch_bounds__(BC_T) k_bin_count_tile(PArr<T> sp, TileGeo tg, int n0, int n1, int n2,
@@ -343,56 +344,87 @@ __global__ void __launch_bounds__(BC_T) k_bin_count_tile(PArr<T> sp, TileGeo tg,
     // chunks of blockDim.x particles are ranked one after the other (a
     // barrier between them), so particles that kept their cell keep their
     // order and the scatter below writes long runs of consecutive slots.
-    for (int64_t p0 = ps; p0 < pe; p0 += blockDim.x) {
-        const int64_t p = p0 + threadIdx.x;
-        if (p < pe) {
-            int c[3] = {sp.cell[0][p], sp.cell[1][p], sp.cell[2][p]};
-            bool ok = true;
-            int v[3];
-            bool inside = true;
+    // The loads and keys of BC_GROUP chunks are taken first, so the barriers
+    // separate only the LDS ranking steps.
+    // (indices fit 32 bits: a species holds fewer than 2^31 particles)
+    const unsigned ue = (unsigned)pe;
+    for (unsigned g0 = (unsigned)ps; g0 < ue; g0 += BC_GROUP * blockDim.x) {
+        // every load of the group first (no store between them, so they are
+        // all in flight together), then the keys
+        int cg[BC_GROUP][3];
+        T fg[BC_GROUP][3];
 #pragma unroll
-            for (int d = 0; d < 3; ++d) {
-                const T f = sp.off[d][p];
-                ok = ok && c[d] >= 0 && c[d] < n[d] && f >= T(0) && f < T(1);
-                c[d] = c[d] < 0 ? 0 : (c[d] >= n[d] ? n[d] - 1 : c[d]);
-                int w = c[d] - t0[d];
-                if (w < -BC_MARGIN)
-                    w += n[d];
-                else if (w >= tg.t[d] + BC_MARGIN)
-                    w -= n[d];
-                v[d] = w;
-                inside = inside && w >= -BC_MARGIN && w < tg.t[d] + BC_MARGIN;
-            }
-            if (!ok)
-                atomicOr(err, 1);
-            int kk;
-            if (inside && nodiv) {
-                int tile = 0, loc = 0;
+        for (int j = 0; j < BC_GROUP; ++j) {
+            const unsigned p = g0 + j * blockDim.x + threadIdx.x;
+            if (p < ue) {
 #pragma unroll
-                for (int d = 2; d >= 0; --d) {
-                    const int o = v[d] < 0 ? -1 : (v[d] >= tg.t[d] ? 1 : 0);
-                    int td = tc[d] + o;
-                    td = td < 0 ? td + tg.nt[d] : (td >= tg.nt[d] ? td - tg.nt[d] : td);
-                    tile = tile * tg.nt[d] + td;
-                    loc = loc * tg.t[d] + (v[d] - o * tg.t[d]);
+                for (int d = 0; d < 3; ++d) {
+                    cg[j][d] = sp.cell[d][p];
+                    fg[j][d] = sp.off[d][p];
                 }
-                kk = tile * tcells + loc;
-            } else {
-                const int cx = c[0] / tg.t[0], cy = c[1] / tg.t[1], cz = c[2] / tg.t[2];
-                const int tile = cx + tg.nt[0] * (cy + tg.nt[1] * cz);
-                kk = tile * tcells + (c[0] - cx * tg.t[0]) +
-                     tg.t[0] * ((c[1] - cy * tg.t[1]) + tg.t[1] * (c[2] - cz * tg.t[2]));
-            }
-            key[p] = kk;
-            if (inside) {
-                const int r = (v[0] + BC_MARGIN) + rx * ((v[1] + BC_MARGIN) + ry * (v[2] + BC_MARGIN));
-                const int lr = atomicAdd(lc + r, 1);
-                rank[p] = packed ? -1 - ((lr << rb) | r) : -1 - lr;
-            } else {
-                rank[p] = atomicAdd(counts + kk, 1);
             }
         }
-        __syncthreads();   // uniform: every thread runs every chunk
+        int reg[BC_GROUP];   // region cell of the chunk's particle, or -1
+#pragma unroll
+        for (int j = 0; j < BC_GROUP; ++j) {
+            const unsigned p = g0 + j * blockDim.x + threadIdx.x;
+            reg[j] = -1;
+            if (p < ue) {
+                int c[3] = {cg[j][0], cg[j][1], cg[j][2]};
+                bool ok = true;
+                int v[3];
+                bool inside = true;
+#pragma unroll
+                for (int d = 0; d < 3; ++d) {
+                    const T f = fg[j][d];
+                    ok = ok & (c[d] >= 0) & (c[d] < n[d]) & (f >= T(0)) & (f < T(1));
+                    c[d] = c[d] < 0 ? 0 : (c[d] >= n[d] ? n[d] - 1 : c[d]);
+                    int w = c[d] - t0[d];
+                    if (w < -BC_MARGIN)
+                        w += n[d];
+                    else if (w >= tg.t[d] + BC_MARGIN)
+                        w -= n[d];
+                    v[d] = w;
+                    inside = inside & (w >= -BC_MARGIN) & (w < tg.t[d] + BC_MARGIN);
+                }
+                if (!ok)
+                    atomicOr(err, 1);
+                int kk;
+                if (inside && nodiv) {
+                    int tile = 0, loc = 0;
+#pragma unroll
+                    for (int d = 2; d >= 0; --d) {
+                        const int o = v[d] < 0 ? -1 : (v[d] >= tg.t[d] ? 1 : 0);
+                        int td = tc[d] + o;
+                        td = td < 0 ? td + tg.nt[d] : (td >= tg.nt[d] ? td - tg.nt[d] : td);
+                        tile = tile * tg.nt[d] + td;
+                        loc = loc * tg.t[d] + (v[d] - o * tg.t[d]);
+                    }
+                    kk = tile * tcells + loc;
+                } else {
+                    const int cx = c[0] / tg.t[0], cy = c[1] / tg.t[1], cz = c[2] / tg.t[2];
+                    const int tile = cx + tg.nt[0] * (cy + tg.nt[1] * cz);
+                    kk = tile * tcells + (c[0] - cx * tg.t[0]) +
+                         tg.t[0] * ((c[1] - cy * tg.t[1]) + tg.t[1] * (c[2] - cz * tg.t[2]));
+                }
+                key[p] = kk;
+                if (inside)
+                    reg[j] = (v[0] + BC_MARGIN) + rx * ((v[1] + BC_MARGIN) + ry * (v[2] + BC_MARGIN));
+                else
+                    rank[p] = atomicAdd(counts + kk, 1);
+            }
+        }
+#pragma unroll
+        for (int j = 0; j < BC_GROUP; ++j) {
+            if (g0 + j * blockDim.x >= ue)
+                break;   // uniform across the workgroup
+            const unsigned p = g0 + j * blockDim.x + threadIdx.x;
+            if (reg[j] >= 0) {
+                const int lr = atomicAdd(lc + reg[j], 1);
+                rank[p] = packed ? -1 - ((lr << rb) | reg[j]) : -1 - lr;
+            }
+            __syncthreads();
+        }
     }
     // reserve each region cell's range in the global counts
     for (int r = threadIdx.x; r < rvol; r += blockDim.x) {
