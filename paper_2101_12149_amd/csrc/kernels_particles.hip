@@ -1984,19 +1984,25 @@ __device__ __attribute__((always_inline)) inline void adjoint_scatter_particle(c
     adjoint_offsets<T, O, LOCAL>(pc, c, f, l, lo_f, sf, aw, on, os);
     constexpr int b = G == 1 ? 3 : 0;
     auto run = [&](int k) { return xrun_unpack(runs ? runs[k] : XRUN_ALONE); };
+    // the group's values first: a load after a component's global atomics
+    // would wait for them
+    T vb[6];
+#pragma unroll
+    for (int m = 0; m < 6; ++m)
+        if ((m < 3 && G != 1) || (m >= 3 && G != 0))
+            vb[m] = ap.vb[m][p];
     // staggering: E_x(s,n,n) E_y(n,s,n) E_z(n,n,s) B_x(n,s,s) B_y(s,n,s) B_z(s,s,n)
     if (G != 1) {
-        scatter_component<O, T, LOCAL, SM, 1, 0, 0>(ap.lE[0], sL + (0 - b) * rfvol, ap.vb[0][p], aw, on, os, sf, run(0));
-        scatter_component<O, T, LOCAL, SM, 0, 1, 0>(ap.lE[1], sL + (1 - b) * rfvol, ap.vb[1][p], aw, on, os, sf, run(1));
-        scatter_component<O, T, LOCAL, SM, 0, 0, 1>(ap.lE[2], sL + (2 - b) * rfvol, ap.vb[2][p], aw, on, os, sf, run(2));
+        scatter_component<O, T, LOCAL, SM, 1, 0, 0>(ap.lE[0], sL + (0 - b) * rfvol, vb[0], aw, on, os, sf, run(0));
+        scatter_component<O, T, LOCAL, SM, 0, 1, 0>(ap.lE[1], sL + (1 - b) * rfvol, vb[1], aw, on, os, sf, run(1));
+        scatter_component<O, T, LOCAL, SM, 0, 0, 1>(ap.lE[2], sL + (2 - b) * rfvol, vb[2], aw, on, os, sf, run(2));
     }
     if (G != 0) {
         const int k0 = G == 2 ? 3 : 0;
-        scatter_component<O, T, LOCAL, SM, 0, 1, 1>(ap.lB[0], sL + (3 - b) * rfvol, ap.vb[3][p], aw, on, os, sf,
-                                                    run(k0));
-        scatter_component<O, T, LOCAL, SM, 1, 0, 1>(ap.lB[1], sL + (4 - b) * rfvol, ap.vb[4][p], aw, on, os, sf,
+        scatter_component<O, T, LOCAL, SM, 0, 1, 1>(ap.lB[0], sL + (3 - b) * rfvol, vb[3], aw, on, os, sf, run(k0));
+        scatter_component<O, T, LOCAL, SM, 1, 0, 1>(ap.lB[1], sL + (4 - b) * rfvol, vb[4], aw, on, os, sf,
                                                     run(k0 + 1));
-        scatter_component<O, T, LOCAL, SM, 1, 1, 0>(ap.lB[2], sL + (5 - b) * rfvol, ap.vb[5][p], aw, on, os, sf,
+        scatter_component<O, T, LOCAL, SM, 1, 1, 0>(ap.lB[2], sL + (5 - b) * rfvol, vb[5], aw, on, os, sf,
                                                     run(k0 + 2));
     }
 }
@@ -2081,13 +2087,17 @@ __device__ inline bool queue_push_wave(bool want, int j, int *qcnt, int *qj, int
 template <typename T>
 __device__ inline bool load_position(const PArr<T> &in, int64_t p, const int *n, int *c, T *f)
 {
-    bool ok = true;
+    // all six loads first, then a check without short-circuit branches (a
+    // branch between them would make each load wait for the one before)
 #pragma unroll
     for (int d = 0; d < 3; ++d) {
         c[d] = in.cell[d][p];
         f[d] = in.off[d][p];
-        ok = ok && c[d] >= 0 && c[d] < n[d] && f[d] >= T(0) && f[d] < T(1);
     }
+    bool ok = true;
+#pragma unroll
+    for (int d = 0; d < 3; ++d)
+        ok = ok & (c[d] >= 0) & (c[d] < n[d]) & (f[d] >= T(0)) & (f[d] < T(1));
     return ok;
 }
 
