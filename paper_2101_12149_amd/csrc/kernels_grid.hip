@@ -896,6 +896,7 @@ hipError_t launch_tile_start(const int *offsets, int tile_cells, int ntiles, int
 // block order (deterministic) and applies the physical scale factors.
 
 static constexpr int RED_T = 256;
+static constexpr int RED_U = 4;   // elements per thread and iteration of k_reduce
 static constexpr int RED_MAX_BLOCKS = 4096;
 
 int reduce_max_blocks()
@@ -934,25 +935,79 @@ __global__ void __launch_bounds__(RED_T) k_reduce(PArr<T> sp, int has_sp, FieldP
 {
     __shared__ double sh[(RED_T / 64) * 5];
     double v[5] = {0, 0, 0, 0, 0};
+    // RED_U strided elements per iteration, all loaded before any is used
+    // (one element per iteration leaves too few loads in flight); the last
+    // fewer than RED_U one at a time
     if ((int)blockIdx.x < nbf) {
-        for (int64_t i = (int64_t)blockIdx.x * RED_T + threadIdx.x; i < ncell; i += (int64_t)nbf * RED_T) {
+        const int64_t stride = (int64_t)nbf * RED_T;
+        auto add = [&](const T *e, const T *b) {
 #pragma unroll
             for (int m = 0; m < 3; ++m) {
-                const double e = (double)f.E[m][i], b = (double)f.B[m][i];
-                v[0] += e * e;
-                v[1] += b * b;
+                const double ed = (double)e[m], bd = (double)b[m];
+                v[0] += ed * ed;
+                v[1] += bd * bd;
             }
+        };
+        int64_t i = (int64_t)blockIdx.x * RED_T + threadIdx.x;
+        for (; i + (RED_U - 1) * stride < ncell; i += RED_U * stride) {
+            T e[RED_U][3], b[RED_U][3];
+#pragma unroll
+            for (int k = 0; k < RED_U; ++k)
+#pragma unroll
+                for (int m = 0; m < 3; ++m) {
+                    e[k][m] = f.E[m][i + k * stride];
+                    b[k][m] = f.B[m][i + k * stride];
+                }
+#pragma unroll
+            for (int k = 0; k < RED_U; ++k)
+                add(e[k], b[k]);
+        }
+        for (; i < ncell; i += stride) {
+            const T e[3] = {f.E[0][i], f.E[1][i], f.E[2][i]}, b[3] = {f.B[0][i], f.B[1][i], f.B[2][i]};
+            add(e, b);
         }
     } else if (has_sp) {
         const int bb = blockIdx.x - nbf;
-        for (int64_t p = (int64_t)bb * RED_T + threadIdx.x; p < sp.n; p += (int64_t)nbp * RED_T) {
-            const double ux = sp.u[0][p], uy = sp.u[1][p], uz = sp.u[2][p];
-            const double w = sp.w ? (double)sp.w[p] : w0;
+        const int64_t stride = (int64_t)nbp * RED_T;
+        auto add = [&](const T *u, double w) {
+            const double ux = u[0], uy = u[1], uz = u[2];
             const double uu = (ux * ux + uy * uy + uz * uz) * inv_c2;
             const double gm = sqrt(1.0 + uu);
             v[2] += w * uu / (gm + 1.0);   // gamma - 1 without cancellation
             v[3] += w;
             v[4] += w * uz;
+        };
+        int64_t p = (int64_t)bb * RED_T + threadIdx.x;
+        if (sp.w) {
+            for (; p + (RED_U - 1) * stride < sp.n; p += RED_U * stride) {
+                T u[RED_U][3], w[RED_U];
+#pragma unroll
+                for (int k = 0; k < RED_U; ++k) {
+#pragma unroll
+                    for (int d = 0; d < 3; ++d)
+                        u[k][d] = sp.u[d][p + k * stride];
+                    w[k] = sp.w[p + k * stride];
+                }
+#pragma unroll
+                for (int k = 0; k < RED_U; ++k)
+                    add(u[k], (double)w[k]);
+            }
+        } else {
+            for (; p + (RED_U - 1) * stride < sp.n; p += RED_U * stride) {
+                T u[RED_U][3];
+#pragma unroll
+                for (int k = 0; k < RED_U; ++k)
+#pragma unroll
+                    for (int d = 0; d < 3; ++d)
+                        u[k][d] = sp.u[d][p + k * stride];
+#pragma unroll
+                for (int k = 0; k < RED_U; ++k)
+                    add(u[k], w0);
+            }
+        }
+        for (; p < sp.n; p += stride) {
+            const T u[3] = {sp.u[0][p], sp.u[1][p], sp.u[2][p]};
+            add(u, sp.w ? (double)sp.w[p] : w0);
         }
     }
     block_sum5(v, sh, partials + 5 * (int64_t)blockIdx.x);

@@ -67,7 +67,7 @@ __device__ inline void push_momentum(const PConst<T> &pc, const T *u, const T *E
 template <typename T>
 __device__ inline bool finite3(const T *u)
 {
-    return isfinite(u[0]) && isfinite(u[1]) && isfinite(u[2]);
+    return isfinite(u[0]) & isfinite(u[1]) & isfinite(u[2]);
 }
 
 // Load a particle and check its state; returns false (and flags err) for a
@@ -89,11 +89,13 @@ __device__ __attribute__((always_inline)) inline void load_state(const PArr<T> &
 template <typename T>
 __device__ inline bool check_state(const int *n, const int *c, const T *f, const T *u, int *err)
 {
+    // no short-circuit branches: a branch between the loads of load_state
+    // and their uses lets the compiler move later loads behind earlier checks
     bool ok = true;
 #pragma unroll
     for (int d = 0; d < 3; ++d)
-        ok = ok && c[d] >= 0 && c[d] < n[d] && f[d] >= T(0) && f[d] < T(1);
-    ok = ok && finite3(u);
+        ok = ok & (c[d] >= 0) & (c[d] < n[d]) & (f[d] >= T(0)) & (f[d] < T(1));
+    ok = ok & finite3(u);
     if (!ok)
         atomicOr(err, 1);
     return ok;
