@@ -36,7 +36,7 @@ FLOPS_PER_PARTICLE = {3: 2028, 1: 411}
 # calibrated HBM bytes per launch of the FP32 two-phase tile kernel at
 # 256^3 / 8 ppc, from the FETCH_SIZE / WRITE_SIZE passes (scaled by a 1 GiB
 # copy); only figures taken on the current kernel are listed
-MEASURED_TRAFFIC = {"uniform256_o3_f32": 17.15e9}
+MEASURED_TRAFFIC = {"uniform256_o3_f32": 17.49e9}
 
 
 def log(*a):
