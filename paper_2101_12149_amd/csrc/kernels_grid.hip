@@ -534,6 +534,9 @@ __device__ inline int block_excl_scan_512(int v, int *sh, int &total)
     return res;
 }
 
+// PER cells per thread, contiguous (a compile-time count, so that the
+// per-cell registers are indexed statically in the loop over rank levels)
+template <int PER>
 __global__ void __launch_bounds__(IL_T) k_interleave(const int *offsets, const int *tile_start, int tile_cells,
                                                      int *slot_of)
 {
@@ -541,11 +544,12 @@ __global__ void __launch_bounds__(IL_T) k_interleave(const int *offsets, const i
     __shared__ int smax;
     const int t = blockIdx.x;
     const int64_t c0 = (int64_t)t * tile_cells;
-    const int per = (tile_cells + IL_T - 1) / IL_T;   // cells per thread, contiguous
+    constexpr int per = PER;
     const int tend = tile_start[t + 1];
-    int cnt[8], off[8];
+    int cnt[PER], off[PER];
     int mymax = 0;
-    for (int i = 0; i < per && i < 8; ++i) {
+#pragma unroll
+    for (int i = 0; i < per; ++i) {
         const int lc = threadIdx.x * per + i;
         cnt[i] = 0;
         off[i] = 0;
@@ -565,11 +569,13 @@ __global__ void __launch_bounds__(IL_T) k_interleave(const int *offsets, const i
     int base = 0;
     for (int r = 0; r < levels; ++r) {
         int mine = 0;
-        for (int i = 0; i < per && i < 8; ++i)
+#pragma unroll
+        for (int i = 0; i < per; ++i)
             mine += cnt[i] > r ? 1 : 0;
         int total = 0;
         int pos = block_excl_scan_512(mine, sh, total) + base;
-        for (int i = 0; i < per && i < 8; ++i)
+#pragma unroll
+        for (int i = 0; i < per; ++i)
             if (cnt[i] > r)
                 slot_of[off[i] + r] = pos++;
         base += total;
@@ -581,8 +587,15 @@ hipError_t launch_interleave(const int *offsets, const int *tile_start, int tile
 {
     if (tile_cells > 8 * IL_T)
         return hipErrorInvalidValue;
-    hipLaunchKernelGGL(k_interleave, dim3((unsigned)ntiles), dim3(IL_T), 0, st, offsets, tile_start, tile_cells,
-                       slot_of);
+    const dim3 g((unsigned)ntiles), b(IL_T);
+    if (tile_cells <= IL_T)
+        hipLaunchKernelGGL(k_interleave<1>, g, b, 0, st, offsets, tile_start, tile_cells, slot_of);
+    else if (tile_cells <= 2 * IL_T)
+        hipLaunchKernelGGL(k_interleave<2>, g, b, 0, st, offsets, tile_start, tile_cells, slot_of);
+    else if (tile_cells <= 4 * IL_T)
+        hipLaunchKernelGGL(k_interleave<4>, g, b, 0, st, offsets, tile_start, tile_cells, slot_of);
+    else
+        hipLaunchKernelGGL(k_interleave<8>, g, b, 0, st, offsets, tile_start, tile_cells, slot_of);
     return hipGetLastError();
 }
 
