@@ -2673,10 +2673,16 @@ __device__ __attribute__((always_inline)) inline void cell_scatter_component(
     }
 }
 
+// With merge = 2 a workgroup takes two tiles adjacent along x (their
+// particles are adjacent in the binning) and tg is the merged geometry
+// (twice as wide, the same halo): at low densities the region flushed per
+// particle shrinks.  A particle is placed only when it lies in the region
+// of its own tile, the test by which pass 1 listed the strays.
 template <typename T, int O>
 __global__ void __launch_bounds__(CELL_THREADS) __attribute__((amdgpu_waves_per_eu(4))) k_adjoint_scatter_cells(PConst<T> pc, TileGeo tg, PArr<T> sp,
                                                                         AdjPtrs<T> ap,
-                                                                        const int *__restrict__ tile_start, int cap)
+                                                                        const int *__restrict__ tile_start, int cap,
+                                                                        int merge)
 {
     extern __shared__ __align__(16) unsigned char smem_raw[];
     const int rfx = tg.rf[0], rfy = tg.rf[1];
@@ -2688,7 +2694,21 @@ __global__ void __launch_bounds__(CELL_THREADS) __attribute__((amdgpu_waves_per_
     int *keys = cstart + (tc + 1);                        // cap
     int *list = keys + cap;                               // cap
     int *sh = list + cap;                                 // scan scratch
-    const TileSpan ts = tile_span(tg, tile_start, sp.n);
+    TileSpan ts = tile_span(tg, tile_start, sp.n);
+    // the merged tiles' particles, and where the second tile's begin
+    TileGeo to = tg;   // the geometry of one binning tile
+    to.t[0] = tg.t[0] / merge;
+    int64_t mid = ts.pe;
+    if (merge > 1) {
+        const int64_t N = sp.n;
+        auto clampN = [&](int64_t v) { return v < 0 ? int64_t(0) : (v > N ? N : v); };
+        ts.ps = clampN(tile_start[merge * ts.t]);
+        mid = clampN(tile_start[merge * ts.t + 1]);
+        ts.pe = clampN(tile_start[merge * ts.t + merge]);
+        mid = mid < ts.ps ? ts.ps : (mid > ts.pe ? ts.pe : mid);
+        if (ts.pe < ts.ps)
+            ts.pe = ts.ps;
+    }
     if (ts.pe <= ts.ps)
         return;
     const int tid = threadIdx.x, nth = blockDim.x;
@@ -2706,7 +2726,10 @@ __global__ void __launch_bounds__(CELL_THREADS) __attribute__((amdgpu_waves_per_
             int c[3], l[3];
             T f[3];
             int key = -1;
-            if (load_position(sp, ts.ps + j, pc.n, c, f) && tile_local(tg, pc.n, ts.t0, c, l)) {
+            const int sub = ts.ps + j >= mid ? 1 : 0;   // which of the merged tiles
+            const int t0s[3] = {ts.t0[0] + sub * to.t[0], ts.t0[1], ts.t0[2]};
+            if (load_position(sp, ts.ps + j, pc.n, c, f) && tile_local(to, pc.n, t0s, c, l)) {
+                l[0] += sub * to.t[0];
                 const bool in = l[0] >= 0 && l[0] < tg.t[0] && l[1] >= 0 && l[1] < tg.t[1] && l[2] >= 0 &&
                                 l[2] < tg.t[2];
                 const int slot = in ? l[0] + tg.t[0] * (l[1] + tg.t[1] * l[2]) : tc;
@@ -3116,17 +3139,30 @@ static hipError_t launch_adj_tile_o(const PConst<T> &pc, const TileGeo &tg, cons
         // counts and starts, and the chunk's keys and lists, within half the
         // LDS of a CU so that two workgroups share it
         static bool a3 = false;
-        const size_t rf = (size_t)tg.rf[0] * tg.rf[1] * tg.rf[2];
-        const size_t tc = (size_t)tg.t[0] * tg.t[1] * tg.t[2];
-        const size_t fixed = rf * sizeof(double) + 4 * (2 * (tc + 1) + CELL_THREADS / 64 + 4);
-        const size_t half = 80 * 1024;
-        const size_t cap = fixed < half ? (half - fixed) / 8 : 0;
+        auto lds_of = [](const TileGeo &g, size_t &fixed) {
+            const size_t rf = (size_t)g.rf[0] * g.rf[1] * g.rf[2];
+            const size_t tc = (size_t)g.t[0] * g.t[1] * g.t[2];
+            fixed = rf * sizeof(double) + 4 * (2 * (tc + 1) + CELL_THREADS / 64 + 4);
+            const size_t half = 80 * 1024;
+            return fixed < half ? (half - fixed) / 8 : size_t(0);
+        };
+        // below 6 particles per cell, pairs of tiles adjacent along x share
+        // a workgroup when their regions and a chunk of 2048 fit
+        TileGeo tm = tg;
+        tm.t[0] = 2 * tg.t[0];
+        tm.nt[0] = tg.nt[0] / 2;
+        tm.rf[0] = tg.rf[0] + tg.t[0];
+        tm.xcd_map = ((ntiles / 2) % 8 == 0) ? 1 : 0;
+        size_t fixed = 0, fixed_m = 0;
+        const size_t cap1 = lds_of(tg, fixed), cap_m = lds_of(tm, fixed_m);
+        const bool merge = !dense && tg.nt[0] >= 4 && tg.nt[0] % 2 == 0 && tm.rf[0] <= 64 && cap_m >= 2048;
+        const size_t cap = merge ? cap_m : cap1;
         if (cap >= 1024) {
             const int c = (int)(cap < 16384 ? cap : 16384);
-            const size_t l3 = fixed + 8 * (size_t)c;
+            const size_t l3 = (merge ? fixed_m : fixed) + 8 * (size_t)c;
             allow_big_lds(&k_adjoint_scatter_cells<T, O>, a3);
-            hipLaunchKernelGGL((k_adjoint_scatter_cells<T, O>), dim3(ntiles), dim3(CELL_THREADS), l3, st, pc, tg, sp,
-                               ap, tile_start, c);
+            hipLaunchKernelGGL((k_adjoint_scatter_cells<T, O>), dim3(merge ? ntiles / 2 : ntiles), dim3(CELL_THREADS),
+                               l3, st, pc, merge ? tm : tg, sp, ap, tile_start, c, merge ? 2 : 1);
             cells = true;
         }
     }

@@ -115,6 +115,53 @@ def test_adjoint_step_matches_oracle(order, dtype, tiled, pusher, solver, filt):
     assert rel_l2(dA.cpu().numpy(), odA) < tol
 
 
+@pytest.mark.parametrize("stale", [False, True])
+def test_tiled_adjoint_with_merged_tile_pairs_matches_oracle(stale):
+    """FP32, order 3, 2 particles per cell on 32x16x16 (4^3 tiles, 8 along
+    x): below 6 per cell the per-cell scatter takes two tiles adjacent along
+    x per workgroup.  With a stale binning a third of the particles moved
+    1-3 cells: those outside their own tile's region are the stray pass's
+    even when they lie in the merged region (placing them there as well
+    would count them twice), the others scatter from the merged tile."""
+    g = wl.plasma_grid((32, 16, 16), 3)
+    geo = _lib.tile_geometry(g, "f32")
+    assert geo["ntiles_xyz"][0] % 2 == 0 and geo["ntiles_xyz"][0] >= 4
+    n = 2 * 32 * 16 * 16
+    sp = random_species(g, n, 211, u_th=0.2, dtype="f32")
+    f = random_fields(g, 212, scale=0.3, dtype="f32")
+    amp = torch.randn((16, 32), dtype=torch.float64, generator=torch.Generator().manual_seed(213))
+    src = wl.Source(4, amp.to(torch.float32), np.array([0.2, -0.7, 1.1, 0.4]))
+    lam = _random_lambda(g, n, 214, "f32")
+    olam = _oracle_lambda(lam)
+    dsp = dev(sp)
+    dlam = NS(lx=dev(lam.lx), lu=dev(lam.lu), lE=dev(lam.lE), lB=dev(lam.lB))
+    dA = torch.zeros((16, 32), dtype=torch.float64, device="cuda")
+    ws = _lib.workspace(g, "f32", n)
+    ts = torch.zeros(_lib.pic_tile_count(g, "f32") + 1, dtype=torch.int32, device="cuda")
+    perm = torch.empty(n, dtype=torch.int32, device="cuda")
+    _lib.pic_sort_tiles(g, dsp, ts, ws, perm=perm)
+    pl = perm.long()
+    dlam.lx = dlam.lx[:, pl].contiguous()
+    dlam.lu = dlam.lu[:, pl].contiguous()
+    if stale:
+        assert _stale(dsp, g, 215) > n // 5
+        back = torch.empty_like(dsp.cell)
+        back[:, pl] = dsp.cell
+        sp.cell = back.cpu()
+    _lib.pic_step_adjoint(g, dsp, dev(f), src.to(device="cuda"), 2, dlam, dA, ws, tile_start=ts)
+    torch.cuda.synchronize()
+    for name in ("lx", "lu"):
+        back = torch.empty_like(getattr(dlam, name))
+        back[:, pl] = getattr(dlam, name)
+        setattr(dlam, name, back)
+    odA = np.zeros((16, 32))
+    oracle.step_adjoint(g, sp.numpy(), f.numpy(), src.numpy(), 2, olam, odA)
+    for name in ("lx", "lu", "lE", "lB"):
+        r = rel_l2(_cpu(getattr(dlam, name)), getattr(olam, name))
+        assert r < 1e-4, (name, r)
+    assert rel_l2(dA.cpu().numpy(), odA) < 1e-4
+
+
 def _dense_species(g, ppc, seed, dtype, layout):
     """ppc particles per cell.  "lattice": every cell holds ppc = 8 particles
     on a 2x2x2 sub-lattice with a small jitter, so that the rank-major order
